@@ -1,0 +1,225 @@
+"""The solver the GPU library computes, written out plainly (FP64, CPU).
+
+TEST INFRASTRUCTURE ONLY (see ``oracle/__init__.py``).
+
+The paper's multi-iterative method (Sec. 6.1), used as preconditioner of a
+conjugate-gradient iteration (Remark 6.1 and the P_MIM label of Sec. 6.2),
+with these readings, each also listed with its reason in the design notes:
+
+1. Grid hierarchy.  Level 0 is A^{p,alpha,beta}_n.  Coarse operators are the
+   Galerkin products P^T A P with the block prolongator I_d (x) P (x) ... (x) P
+   (Sec. 6.1); because every block of A is a sum of Kronecker products of 1D
+   matrices, the coarse operator has the same form with the 1D matrices
+   P^T M P, P^T A P, P^T S P.  P is either the knot-insertion prolongator
+   (n -> n/2, default) or the paper's (1/2)[1 2 1] stencil.  Coarsening stops
+   when the level has at most ``coarse_max_dofs`` unknowns or cannot be
+   coarsened further; that coarsest level is solved exactly.
+2. Smoother.  The paper's Gauss-Seidel sweeps are sequential; this method uses
+   Chebyshev smoothing of degree ``nu`` on D^{-1} A_l (D = diag A_l), on the
+   interval [hi/ratio, hi], hi = 1.1 * lambda_est.  lambda_est is the pencil
+   Rayleigh quotient v^T A v / v^T D v after ``power_iters`` steps of the
+   power method on D^{-1} A_l started from v0 = (-1)^{i_1+...+i_d} in every
+   component.  One smoothing application (degree nu) replaces each of the
+   paper's Gauss-Seidel sweeps: before the coarse correction on every level,
+   and after it on all levels but the finest.
+3. Finest-level post-smoother: ``krylov_steps`` (default p) steps of GMRES on
+   the error equation with zero initial guess, right-preconditioned by
+   T = I_d (x) T_m(m_{p-1})^{(x) d} (Sec. 6.1), Arnoldi by classical
+   Gram-Schmidt, update T^{-1}(V y) with y the least-squares solution of the
+   (s+1) x s Hessenberg problem.
+4. Outer iteration: flexible CG with one stored direction (Notay's FCG(1)),
+   x_0 = 0, stop when ||r_k||_2 / ||r_0||_2 < tol (Sec. 6.2).  FCG(1) equals
+   PCG for a fixed SPD preconditioner; the GMRES post-smoother makes the
+   preconditioner nonlinear.
+"""
+import numpy as np
+import scipy.linalg as sla
+import scipy.sparse as sp
+import scipy.sparse.linalg as spla
+
+from .assembly import curl_div_matrix
+from .matrices import mass_adv_stiff, toeplitz_T
+from .transfer import knot_insertion_prolongator, paper_prolongator
+
+
+def _kron(*mats):
+    out = sp.csr_matrix(mats[0])
+    for X in mats[1:]:
+        out = sp.kron(out, sp.csr_matrix(X), format="csr")
+    return out
+
+
+class Level:
+    def __init__(self, d, p, n, alpha, beta, mats):
+        self.d, self.p, self.n = d, p, n
+        self.M, self.A, self.S = mats
+        self.m = self.M.shape[0]
+        self.K = curl_div_matrix(d, p, n, alpha, beta, mats=mats)
+        self.D = self.K.diagonal().copy()
+        self.P = None  # 1D prolongator from the next level to this one
+        self.lam = None
+
+
+def build_hierarchy(d, p, n, alpha, beta, transfer="knot", coarse_max_dofs=1000,
+                    power_iters=10, nu=3, ratio=30.0):
+    """List of Level objects, finest first."""
+    mats = mass_adv_stiff(n, p)
+    levels = [Level(d, p, n, alpha, beta, mats)]
+    while True:
+        L = levels[-1]
+        if d * L.m**d <= coarse_max_dofs:
+            break
+        if transfer == "knot":
+            if L.n % 2 or L.n // 2 + p - 2 < 1:
+                break
+            P = knot_insertion_prolongator(L.n, p)
+            nc = L.n // 2
+        elif transfer == "paper":
+            if L.m // 2 < 1:
+                break
+            P = paper_prolongator(L.m)
+            nc = None
+        else:
+            raise ValueError(transfer)
+        L.P = P
+        cm = tuple(P.T @ X @ P for X in (L.M, L.A, L.S))
+        levels.append(Level(d, p, nc, alpha, beta, cm))
+    for L in levels[:-1]:
+        L.lam = power_estimate(L, power_iters)
+        L.hi = 1.1 * L.lam
+        L.lo = L.hi / ratio
+        L.nu = nu
+    C = levels[-1]
+    C.coarse_factor = sla.cho_factor(C.K.toarray())
+    return levels
+
+
+def start_vector(d, m):
+    """v0 = (-1)^{i_1+...+i_d}, the same in every component."""
+    idx = np.indices((m,) * d).sum(axis=0)
+    v = np.where(idx % 2 == 0, 1.0, -1.0).ravel()
+    return np.tile(v, d)
+
+
+def power_estimate(L, iters):
+    """Pencil Rayleigh quotient after ``iters`` power steps on D^{-1} K."""
+    v = start_vector(L.d, L.m)
+    for _ in range(iters):
+        w = (L.K @ v) / L.D
+        v = w / np.linalg.norm(w)
+    return (v @ (L.K @ v)) / (v @ (L.D * v))
+
+
+def chebyshev(L, x, b, nu=None):
+    """``nu`` steps of Chebyshev iteration for K x = b preconditioned by D,
+    on the interval [L.lo, L.hi] (three-term recurrence on the update)."""
+    nu = L.nu if nu is None else nu
+    theta = 0.5 * (L.hi + L.lo)
+    delta = 0.5 * (L.hi - L.lo)
+    sigma = theta / delta
+    rho = 1.0 / sigma
+    x = x.copy()
+    r = b - L.K @ x
+    upd = r / L.D / theta
+    x += upd
+    for _ in range(nu - 1):
+        r = b - L.K @ x
+        rho_new = 1.0 / (2.0 * sigma - rho)
+        upd = rho_new * rho * upd + (2.0 * rho_new / delta) * (r / L.D)
+        x += upd
+        rho = rho_new
+    return x
+
+
+def t_operator(d, p, m):
+    """Sparse T = I_d (x) T_m(m_{p-1})^{(x) d} (Sec. 6.1) and a solver for it
+    (sparse LU of the assembled Kronecker product)."""
+    T1 = toeplitz_T(m, p)
+    T = _kron(*([np.eye(d)] + [T1] * d))
+    lu = spla.splu(T.tocsc())
+    return T, lu.solve
+
+
+def gmres_T(K, Tsolve, r, steps):
+    """``steps`` GMRES steps on K e = r from e = 0, right preconditioner T."""
+    beta0 = np.linalg.norm(r)
+    if beta0 == 0.0:
+        return np.zeros_like(r)
+    V = [r / beta0]
+    H = np.zeros((steps + 1, steps))
+    s = steps
+    for j in range(steps):
+        w = K @ Tsolve(V[j])
+        h = np.array([vi @ w for vi in V])  # classical Gram-Schmidt
+        w = w - sum(hi * vi for hi, vi in zip(h, V))
+        H[: j + 1, j] = h
+        H[j + 1, j] = np.linalg.norm(w)
+        if H[j + 1, j] == 0.0:
+            s = j + 1
+            break
+        V.append(w / H[j + 1, j])
+    rhs = np.zeros(s + 1)
+    rhs[0] = beta0
+    y = np.linalg.lstsq(H[: s + 1, :s], rhs, rcond=None)[0]
+    return Tsolve(sum(yi * vi for yi, vi in zip(y, V[:s])))
+
+
+class Method:
+    """Hierarchy plus the finest-level T solver; ``vcycle`` is one application
+    of the preconditioner, ``solve`` the outer flexible CG."""
+
+    def __init__(self, d, p, n, alpha, beta, transfer="knot", coarse_max_dofs=1000,
+                 nu=3, ratio=30.0, power_iters=10, krylov_steps=None):
+        self.d, self.p, self.n = d, p, n
+        self.levels = build_hierarchy(d, p, n, alpha, beta, transfer, coarse_max_dofs,
+                                      power_iters, nu, ratio)
+        self.krylov_steps = p if krylov_steps is None else krylov_steps
+        self.T, self.Tsolve = t_operator(d, p, self.levels[0].m)
+        self.K = self.levels[0].K
+
+    def _prolong_block(self, l):
+        P = self.levels[l].P
+        return _kron(*([np.eye(self.d)] + [P] * self.d))
+
+    def vcycle(self, b, l=0):
+        L = self.levels[l]
+        if l == len(self.levels) - 1:
+            return sla.cho_solve(L.coarse_factor, b)
+        x = chebyshev(L, np.zeros_like(b), b)
+        r = b - L.K @ x
+        Pb = self._prolong_block(l)
+        x = x + Pb @ self.vcycle(Pb.T @ r, l + 1)
+        if l == 0 and self.krylov_steps > 0:
+            x = x + gmres_T(L.K, self.Tsolve, b - L.K @ x, self.krylov_steps)
+        else:
+            x = chebyshev(L, x, b)
+        return x
+
+    def solve(self, b, tol, maxiter=10000):
+        """FCG(1).  Returns (x, iterations, history of ||r_k||_2)."""
+        K = self.K
+        x = np.zeros_like(b)
+        r = b.copy()
+        r0 = np.linalg.norm(r)
+        hist = [r0]
+        if r0 == 0.0:
+            return x, 0, hist
+        dprev = qprev = dq_prev = None
+        k = 0
+        while k < maxiter:
+            z = self.vcycle(r)
+            if dprev is None:
+                dk = z
+            else:
+                dk = z - (z @ qprev) / dq_prev * dprev
+            q = K @ dk
+            dq = dk @ q
+            a = (dk @ r) / dq
+            x += a * dk
+            r -= a * q
+            k += 1
+            hist.append(np.linalg.norm(r))
+            if hist[-1] < tol * r0:
+                break
+            dprev, qprev, dq_prev = dk, q, dq
+        return x, k, hist
