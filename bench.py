@@ -1,0 +1,212 @@
+"""Benchmark of the curl-div solver on one MI355X.
+
+A step solves one batch of the 2D workload (p = 3, n = 256 intervals per
+direction, alpha = 1, beta in {1, 1e-4}, uniform [-1, 1] right-hand sides)
+to relative residual 1e-8 with the mixed-precision solver (FP32 V-cycle
+inside FP64 flexible CG).  Right-hand sides are resident in HBM before the
+timed region; solver setup is outside it.  Prints one JSON line.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+
+
+def percentile(v, q):
+    v = sorted(v)
+    if not v:
+        return None
+    k = (len(v) - 1) * q / 100.0
+    lo, hi = int(k), min(int(k) + 1, len(v) - 1)
+    return v[lo] + (v[hi] - v[lo]) * (k - lo)
+
+
+def cpu_baseline(cfg, its_gpu):
+    """Oracle timed on the host: one full solve at beta = 1 and a bounded
+    number of outer iterations at beta = 1e-4, projected to the iteration
+    count the GPU solver needed (setup excluded on both sides)."""
+    import numpy as np
+    from threadpoolctl import threadpool_limits
+
+    import curldiv_inputs as ci
+    from oracle import method
+
+    d, p, n, alpha, betas, dist, tol = cfg
+    times = []
+    with threadpool_limits(limits=1):
+        for beta in betas:
+            meth = method.Method(d, p, n, alpha, beta, coarse_max_dofs=1000)
+            b = ci.rhs(d, p, n, 0, dist)
+            cap = 12 if beta < 1e-2 else 10000
+            t0 = time.perf_counter()
+            _, it, _ = meth.solve(b, tol, maxiter=cap)
+            dt = time.perf_counter() - t0
+            target = its_gpu.get(beta, it)
+            times.append(dt / it * max(it, target))
+    return {"value": len(betas) / sum(times), "unit": "solves/s", "cores": 1, "kind": "oracle",
+            "sample": f"FP64 oracle P_MIM (FCG + V-cycle, same algorithm) on the {d}D p={p} n={n} workload, "
+                      f"one solve per beta in {betas}; beta=1 run to completion, beta<1e-2 run for 12 outer "
+                      f"iterations and projected to the GPU iteration count; setup excluded; 1 thread"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-c4", action="store_true", help="skip the 3D p=3 n=128 operator-apply measurement")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU: this build has no multi-GPU path (see DESIGN.md, sharding)",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import curldiv_inputs as ci
+    from paper_1805_10058_amd import capi
+
+    torch.cuda.set_device(0)
+    st = torch.cuda.current_stream().cuda_stream
+    name = "c2_2d_p3_n256"
+    cfg = ci.CONFIGS[name]
+    d, p, n, alpha, betas, dist, tol = cfg
+    N = ci.num_dofs(d, p, n)
+
+    def make(beta, precision):
+        opt = capi.options(precision=precision, rtol=tol)
+        return capi.Solver(capi.problem(d, p, n, alpha, beta), opt, st)
+
+    mixed = {beta: make(beta, capi.CD_MIXED_FP32) for beta in betas}
+    fp64 = {beta: make(beta, capi.CD_FP64) for beta in betas}
+    nsteps = args.warmup + args.steps
+    rhs = [[torch.as_tensor(ci.rhs(d, p, n, 1000 * k + j, dist)).cuda() for j in range(len(betas))]
+           for k in range(nsteps)]
+    xs = [torch.zeros(N, dtype=torch.float64, device="cuda") for _ in betas]
+    torch.cuda.synchronize()
+
+    def step(k, solvers, lat, its, res_out):
+        for j, beta in enumerate(betas):
+            t0 = time.perf_counter()
+            r = solvers[beta].solve(rhs[k][j].data_ptr(), xs[j].data_ptr())
+            lat.append(time.perf_counter() - t0)
+            its[beta] = r.iterations
+            res_out.append(r.true_rel_residual)
+            if r.status != capi.CD_OK:
+                raise RuntimeError(f"solve did not converge: beta={beta} status={r.status}")
+
+    lat, its, tres = [], {}, []
+    def log(msg):
+        print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+    for k in range(args.warmup):
+        step(k, mixed, [], its, [])
+        log(f"warmup step {k} done, iterations {its}")
+    for s in mixed.values():
+        s.profile_enable(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(args.warmup, nsteps):
+        step(k, mixed, lat, its, tres)
+        log(f"timed step {k} done")
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    T = t1 - t0
+    nsolves = args.steps * len(betas)
+
+    # live kernel timing (HIP events on the solver stream) of the dominant kernel:
+    # the level-0 operator apply of the FP32 V-cycle
+    tot_ms = tot_b = 0.0
+    launches = 0
+    for s in mixed.values():
+        stt = s.profile_read(0, True)
+        tot_ms += stt.total_ms
+        tot_b += stt.bytes
+        launches += stt.launches
+        s.profile_enable(False)
+    ach = (tot_b / (tot_ms * 1e-3)) / 1e9 if tot_ms > 0 else 0.0
+
+    # plain FP64 single-solve path on the same inputs (comparison, not the headline)
+    lat64, its64, tres64 = [], {}, []
+    step(0, fp64, [], its64, [])
+    t2 = time.perf_counter()
+    for k in range(args.warmup, nsteps):
+        step(k, fp64, lat64, its64, tres64)
+    torch.cuda.synchronize()
+    T64 = time.perf_counter() - t2
+    log(f"fp64 comparison done, iterations {its64}")
+
+    out = {
+        "metric": "solves/sec + p50/p99 latency to rel. residual 1e-8; operator-apply HBM GB/s",
+        "value": nsolves / T,
+        "unit": "solves/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": 1e3 * T / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32+f64",
+        "data": "synthetic",
+        "config": {"workload": "2D curl-div, p=3, n=256 (132,098 unknowns), alpha=1, beta in {1, 1e-4}, "
+                               "uniform[-1,1] RHS, rel. residual 1e-8, FP32 V-cycle in FP64 flexible CG",
+                   "dim": d, "degree": p, "n": n, "betas": betas, "solves_per_step": len(betas)},
+        "latency_ms": {"p50": 1e3 * percentile(lat, 50), "p99": 1e3 * percentile(lat, 99)},
+        "iterations": {str(b): its[b] for b in betas},
+        "max_true_rel_residual": max(tres),
+        "fp64_path": {"solves_per_s": nsolves / T64, "p50_ms": 1e3 * percentile(lat64, 50),
+                      "p99_ms": 1e3 * percentile(lat64, 99), "iterations": {str(b): its64[b] for b in betas},
+                      "max_true_rel_residual": max(tres64)},
+        "roofline": {"bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": ach / HBM_PEAK_GBS, "traffic": None,
+                     "kernel": "level-0 FP32 operator apply (k_apply2d<float,3,*>) inside the timed solves",
+                     "launches": launches, "avg_us": 1e3 * tot_ms / max(launches, 1)},
+    }
+
+    if not args.no_c4:
+        out["operator_apply_c4"] = c4_apply(capi, torch, st)
+        log(f"3D p=3 n=128 operator apply: {out['operator_apply_c4']}")
+
+    if not args.no_cpu_baseline:
+        log("timing the oracle on the host")
+        out["cpu_baseline"] = cpu_baseline(cfg, its)
+    print(json.dumps(out), flush=True)
+
+
+def c4_apply(capi, torch, st, reps=20):
+    """Operator apply A x at the 3D p=3 n=128 size (6,440,067 unknowns),
+    FP64 and FP32, kernel time from HIP events on the solver stream."""
+    d, p, n = 3, 3, 128
+    opt = capi.options(method=capi.CD_METHOD_CG)
+    s = capi.Solver(capi.problem(d, p, n, 1.0, 1e-6), opt, st)
+    N = capi.num_dofs(s.prob)
+    res = {}
+    for prec, dt, fn in (("fp64", torch.float64, s.apply), ("fp32", torch.float32, s.apply_f32)):
+        x = torch.rand(N, dtype=dt, device="cuda")
+        y = torch.empty(N, dtype=dt, device="cuda")
+        fn(0, x.data_ptr(), y.data_ptr())
+        s.profile_enable(True)
+        for _ in range(reps):
+            fn(0, x.data_ptr(), y.data_ptr())
+        stt = s.profile_read(0, prec == "fp32")
+        s.profile_enable(False)
+        gbs = stt.bytes / (stt.total_ms * 1e-3) / 1e9
+        flops = (22 * (2 * p + 1)) * N * stt.launches  # 33 band contractions per point
+        res[prec] = {"avg_us": 1e3 * stt.total_ms / stt.launches, "GB_s": gbs, "hbm_frac": gbs / HBM_PEAK_GBS,
+                     "TFLOP_s": flops / (stt.total_ms * 1e-3) / 1e12}
+    s.close()
+    return res
+
+
+if __name__ == "__main__":
+    main()

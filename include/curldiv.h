@@ -1,0 +1,186 @@
+/*
+ * curldiv.h - C ABI of the MI355X solver for the B-spline (isogeometric)
+ * discretization of the parameter-dependent curl-div problem
+ *
+ *     alpha (curl u, curl v) + beta (div u, div v) = (f, v)
+ *
+ * on (0,1)^d, d = 2 or 3, homogeneous Dirichlet conditions, tensor-product
+ * B-splines of degree p with maximal smoothness on n uniform intervals per
+ * direction (Mazza, Manni, Ratnani, Serra-Capizzano, Speleers,
+ * "Isogeometric analysis for 2D and 3D curl-div problems: spectral symbols
+ * and fast iterative solvers", Sec. 1 (problem), Sec. 3.1 (spline space),
+ * Sec. 4.1 / 4.2 (the 2x2 and 3x3 block system matrix A^{p,alpha,beta}_n)).
+ *
+ * The solver is the paper's multi-iterative method (Sec. 6.1) used as the
+ * preconditioner of a conjugate-gradient iteration (Remark 6.1, "P_MIM" in
+ * Sec. 6.2): a V-cycle with Kronecker-product grid transfers, a parallel
+ * (Chebyshev-Jacobi) smoother in place of the sequential Gauss-Seidel
+ * sweeps, p steps of GMRES preconditioned by the banded Toeplitz matrix
+ * T = I_d (x) T_m(m_{p-1})^{(x) d} as finest-level post-smoother, and an
+ * exact dense solve on the coarsest level; the outer iteration is flexible
+ * CG.  Every step runs in HIP kernels on the GPU.
+ *
+ * Vector layout (Sec. 4.1): a vector of the system has d * prod_l m_l
+ * entries, m_l = n_l + p - 2.  It is component-major; inside a component the
+ * coefficient u_{i_1,...,i_d} (i_l = 2..n_l+p-1 in the paper's numbering) is
+ * stored at offset ((i_1-2) m_2 + (i_2-2)) m_3 + (i_3-2) (3D) or
+ * (i_1-2) m_2 + (i_2-2) (2D): i_1 slowest, i_d fastest.
+ *
+ * Memory: "dev" pointers are device (HBM) pointers owned by the caller; they
+ * must stay valid until the call returns and the stream given at creation
+ * has finished the work.  The library owns its handles and all workspace.
+ * Functions return a status code (CD_OK = 0, CD_NOT_CONVERGED = 1, negative
+ * codes for errors); cd_last_error() gives the message of the last error on
+ * the calling thread.  A handle must not be used by two threads at once;
+ * distinct handles are independent.
+ */
+#ifndef CURLDIV_H
+#define CURLDIV_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- status codes ------------------------------------------------------ */
+#define CD_OK 0
+#define CD_NOT_CONVERGED 1   /* max_iter reached; x holds the last iterate   */
+#define CD_EINVAL (-1)       /* invalid argument (see cd_last_error)          */
+#define CD_ENOMEM (-2)       /* device allocation failed                      */
+#define CD_EBREAKDOWN (-3)   /* Krylov breakdown: d^T A d <= 0 or non-finite  */
+#define CD_EHIP (-4)         /* HIP runtime error                             */
+#define CD_EAGAIN (-5)       /* server: request queued, not yet admitted      */
+#define CD_ENOTFOUND (-6)    /* server: unknown ticket                        */
+
+/* ---- problem and options ----------------------------------------------- */
+/* The discrete problem of Sec. 4: dimension d, degree p >= 1, n[l] >= 1
+ * intervals along axis l (n[2] ignored for d = 2; needs n[l]+p-2 >= 1), and
+ * the weights alpha, beta > 0 of the curl and div terms (the matrix is SPD
+ * only when both are positive, Corollaries 5.4 and 5.8). */
+typedef struct {
+    int dim;
+    int degree;
+    int n[3];
+    double alpha;
+    double beta;
+} cd_problem;
+
+#define CD_METHOD_PMIM 0   /* flexible CG preconditioned by one V-cycle (Sec. 6.2, P_MIM) */
+#define CD_METHOD_CG 3     /* unpreconditioned CG (the CG columns of Tables 1-4)          */
+
+#define CD_XFER_KNOT 0     /* knot-insertion prolongator, n -> n/2 (exact subspace embedding) */
+#define CD_XFER_PAPER 1    /* (1/2)[1 2 1] stencil, m -> floor(m/2) (Sec. 6.1)                 */
+
+#define CD_FP64 0          /* every step in FP64                                              */
+#define CD_MIXED_FP32 1    /* V-cycle (smoother, transfers, level operators, T-solves, GMRES
+                              vectors) in FP32; outer residual, Krylov inner products and the
+                              coarse solve in FP64                                             */
+
+typedef struct {
+    int method;           /* CD_METHOD_*                                     */
+    int transfer;         /* CD_XFER_*                                       */
+    int precision;        /* CD_FP64 or CD_MIXED_FP32                        */
+    double rtol;          /* stop when ||r_k||_2 / ||r_0||_2 < rtol (Sec. 6.2) */
+    int max_iter;
+    int coarse_max_dofs;  /* coarsen while a level has more unknowns          */
+    int cheb_degree;      /* Chebyshev smoother degree per application (>=1)  */
+    double cheb_ratio;    /* smoothing interval [hi/ratio, hi]               */
+    int power_iters;      /* power steps for the smoother's eigenvalue bound */
+    int krylov_steps;     /* finest post-smoothing GMRES steps; < 0 means p  */
+} cd_options;
+
+/* Fill *opt with the defaults: P_MIM, knot insertion, FP64, rtol 1e-8,
+ * max_iter 10000, coarse_max_dofs 1000, cheb_degree 3, cheb_ratio 30,
+ * power_iters 10, krylov_steps = p. */
+void cd_default_options(cd_options* opt);
+
+typedef struct {
+    int status;                 /* CD_OK, CD_NOT_CONVERGED or an error code  */
+    int iterations;             /* outer iterations performed                 */
+    double rel_residual;        /* recursive ||r_k|| / ||r_0|| at exit        */
+    double true_rel_residual;   /* ||b - A x||_2 / ||b||_2 recomputed in FP64 */
+} cd_result;
+
+/* Number of unknowns d * prod_l (n_l + p - 2); 0 for an invalid problem. */
+size_t cd_num_dofs(const cd_problem* prob);
+
+/* CD_OK if (prob, opt) is a valid combination, else CD_EINVAL. */
+int cd_validate(const cd_problem* prob, const cd_options* opt);
+
+/* Device bytes a solver for (prob, opt) allocates (hierarchy, coarse
+ * inverse, workspace); used by the server's admission test. */
+size_t cd_footprint_bytes(const cd_problem* prob, const cd_options* opt);
+
+/* ---- solver handle ----------------------------------------------------- */
+typedef struct cd_solver cd_solver;
+
+/* Set up the hierarchy on the host in FP64 (1D matrices by Gauss
+ * quadrature, transfers, Galerkin coarse 1D matrices, banded LDL^T of
+ * T_m(m_{p-1}), dense coarse matrix) and on the device (eigenvalue bounds of
+ * the smoother, inverse of the coarse matrix).  `stream` is a hipStream_t
+ * (NULL = default stream); all later work of the handle is queued on it. */
+int cd_solver_create(const cd_problem* prob, const cd_options* opt, void* stream, cd_solver** out);
+void cd_solver_destroy(cd_solver* s);
+
+/* Solve A x = b (Sec. 6, the linear system of the problem) from x_0 = 0.
+ * b_dev, x_dev: device arrays of cd_num_dofs() doubles.  Blocks until done. */
+int cd_solve(cd_solver* s, const double* b_dev, double* x_dev, cd_result* out);
+
+/* ---- hooks for parity tests and measurement ----------------------------- */
+int cd_num_levels(const cd_solver* s);
+/* m_l per axis of a level (3 ints; m[2] = 1 in 2D) and its unknown count. */
+int cd_level_shape(const cd_solver* s, int level, int* m3, size_t* ndofs);
+/* Host copy of a 1D setup matrix of `level` along `axis` as a dense
+ * row-major m x m array: which = 'M', 'A', 'S' (Sec. 3.2 matrices or their
+ * Galerkin coarse versions), 'T' (T_m(m_{p-1}), level 0 only) or 'P' (the
+ * prolongator from level+1 to level, m_level x m_{level+1}). */
+int cd_get_matrix(const cd_solver* s, int level, int axis, char which, double* host_out);
+/* The smoother's eigenvalue estimate of `level` (power-method Rayleigh
+ * quotient of diag(A_l)^{-1} A_l). */
+int cd_get_lambda(const cd_solver* s, int level, double* lam);
+
+/* y = A_level x in FP64 (level 0 is the system matrix). */
+int cd_apply(cd_solver* s, int level, const double* x_dev, double* y_dev);
+/* y = A_level x in FP32 with FP32 coefficients. */
+int cd_apply_f32(cd_solver* s, int level, const float* x_dev, float* y_dev);
+/* One smoother application (cheb_degree Chebyshev steps) on level `level`
+ * for A_l x = b starting from x_in; writes x_out (FP64). */
+int cd_smooth(cd_solver* s, int level, const double* b_dev, const double* x_in_dev, double* x_out_dev);
+/* r_c = P^T r (level -> level+1) and x += P e (level+1 -> level), FP64. */
+int cd_restrict(cd_solver* s, int level, const double* r_fine_dev, double* r_coarse_dev);
+int cd_prolong_add(cd_solver* s, int level, const double* e_coarse_dev, double* x_fine_dev);
+/* z = T^{-1} v on the finest level (Sec. 6.1), FP64. */
+int cd_tsolve(cd_solver* s, const double* v_dev, double* z_dev);
+/* z = A_L^{-1} r on the coarsest level, FP64. */
+int cd_coarse_solve(cd_solver* s, const double* r_dev, double* z_dev);
+/* z = one application of the preconditioner (one V-cycle, in the handle's
+ * precision) to r. */
+int cd_precondition(cd_solver* s, const double* r_dev, double* z_dev);
+
+/* ---- live kernel timing ------------------------------------------------- */
+/* When enabled, every operator-apply launch of the handle is bracketed by a
+ * pair of HIP events on the handle's stream; the elapsed times are folded
+ * into per-(level, precision) totals at the next synchronisation point.
+ * `bytes` accumulates the algorithmic traffic of those launches: the vectors
+ * each launch must read and write once (2 N s for y = A x, 3 N s for the
+ * residual, 5 N s for a Chebyshev step; s = 8 or 4 bytes). */
+typedef struct {
+    long long launches;
+    double total_ms;
+    double bytes;
+} cd_kernel_stats;
+/* Enable (on != 0) or disable timing; enabling resets the totals. */
+int cd_profile_enable(cd_solver* s, int on);
+/* Totals of level `level` applies in FP64 (fp32 = 0) or FP32 (fp32 = 1). */
+int cd_profile_read(const cd_solver* s, int level, int fp32, cd_kernel_stats* out);
+
+const char* cd_status_string(int status);
+const char* cd_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* CURLDIV_H */

@@ -1,0 +1,1002 @@
+// HIP kernels for gfx950: sum-factorized curl-div operator, grid transfers,
+// banded Toeplitz line solves, reductions and the small Krylov helpers.
+//
+// Every reduction accumulates in FP64 and combines partial sums in a fixed
+// order, so results are bitwise reproducible run to run.
+#include <algorithm>
+#include <stdexcept>
+#include <string>
+
+#include "kernels.hpp"
+
+namespace cd {
+
+namespace {
+
+constexpr int kThreads = 256;  // block size of every kernel in this file
+
+void check_launch(const char* what) {
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) throw std::runtime_error(std::string(what) + ": " + hipGetErrorString(e));
+}
+
+__device__ inline double wave_sum(double v) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
+    return v;
+}
+
+// Sum over the block; the result is returned to every thread.
+__device__ inline double block_sum(double v) {
+    __shared__ double red[kThreads / 64];
+    __shared__ double total;
+    v = wave_sum(v);
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    if (lane == 0) red[wid] = v;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double s = 0.0;
+        for (int i = 0; i < int(blockDim.x) / 64; ++i) s += red[i];
+        total = s;
+    }
+    __syncthreads();
+    const double r = total;
+    __syncthreads();
+    return r;
+}
+
+__device__ inline double sum_partials(const double* part, int np) {
+    double v = 0.0;
+    for (int i = threadIdx.x; i < np; i += blockDim.x) v += part[i];
+    return block_sum(v);
+}
+
+template <typename T>
+__device__ inline T band_at(const OpDev<T>& op, int axis, int which, int k, int i) {
+    return op.band[axis][which][k * op.m[axis] + i];
+}
+
+// Diagonal entry of block (c,c) at multi-index (i0,i1,i2):
+// beta * prod(S on axis c, M elsewhere) + alpha * sum_{e != c} prod(S on e, M elsewhere).
+template <typename T>
+__device__ inline T diag_entry(const OpDev<T>& op, int c, int i0, int i1, int i2) {
+    const int hb = op.hb;
+    const T m0 = band_at(op, 0, 0, hb, i0), s0 = band_at(op, 0, 2, hb, i0);
+    const T m1 = band_at(op, 1, 0, hb, i1), s1 = band_at(op, 1, 2, hb, i1);
+    if (op.dim == 2) {
+        const T t0 = s0 * m1, t1 = m0 * s1;
+        return (c == 0) ? op.beta * t0 + op.alpha * t1 : op.alpha * t0 + op.beta * t1;
+    }
+    const T m2 = band_at(op, 2, 0, hb, i2), s2 = band_at(op, 2, 2, hb, i2);
+    const T t0 = s0 * m1 * m2, t1 = m0 * s1 * m2, t2 = m0 * m1 * s2;
+    return (c == 0 ? op.beta : op.alpha) * t0 + (c == 1 ? op.beta : op.alpha) * t1 +
+           (c == 2 ? op.beta : op.alpha) * t2;
+}
+
+// ------------------------------------------------------------------------------
+// 3D operator apply.
+//
+// Block (chunk, x1-range): the block owns kThreads consecutive points of the
+// flattened (x2, x3) plane, f = s + tid, and output planes x1 in [o0, o1).
+// For every input plane j in [o0-HB, o1+HB) and every component it
+//   (A) contracts axis 2 (stride m3) from an LDS copy of the plane chunk with
+//       its +-HB row halo, producing M2 x, A2 x, S2 x on [s-HB, s+kThreads+HB);
+//   (B) contracts axis 3 (contiguous) at f, combining the raw products with
+//       the weights alpha, beta, alpha-beta into W[c][{S,M,A}], the inputs of
+//       the axis-1 contraction of output component c;
+//   (C) scatters W into a ring of 2HB+1 per-plane accumulators held in
+//       registers: acc(i) += X1(i, j) W for i in [j-HB, j+HB].
+// After plane j the accumulator of output plane j-HB is complete and goes
+// through the epilogue.  33 band contractions per point in total.
+// ------------------------------------------------------------------------------
+template <typename T, int HB>
+struct Plane3 {
+    static constexpr int STN = kThreads + 2 * HB;
+};
+
+template <typename T, int HB, int C>
+__device__ inline void stage_ab(const OpDev<T>& op, const T* __restrict__ xp, int s, int PL, int m3, T* xs, T* st,
+                                bool active, int i3, T (&W)[3][3]) {
+    constexpr int STN = Plane3<T, HB>::STN;
+    const int XSN = kThreads + 2 * HB * m3 + 2 * HB;
+    const int base = s - HB * m3 - HB;
+    for (int q = threadIdx.x; q < XSN; q += kThreads) {
+        const int ff = base + q;
+        xs[q] = (ff >= 0 && ff < PL) ? xp[ff] : T(0);
+    }
+    __syncthreads();
+    const int m2 = op.m[1];
+    for (int q = threadIdx.x; q < STN; q += kThreads) {
+        const int ff = s - HB + q;
+        T aM = T(0), aA = T(0), aS = T(0);
+        if (ff >= 0 && ff < PL) {
+            const int r2 = ff / m3;
+#pragma unroll
+            for (int k = 0; k <= 2 * HB; ++k) {
+                const T xv = xs[q + k * m3];
+                aM += op.band[1][0][k * m2 + r2] * xv;
+                aA += op.band[1][1][k * m2 + r2] * xv;
+                aS += op.band[1][2][k * m2 + r2] * xv;
+            }
+        }
+        st[q] = aM;
+        st[STN + q] = aA;
+        st[2 * STN + q] = aS;
+    }
+    __syncthreads();
+    if (active) {
+        T mm = T(0), sm = T(0), am = T(0), ms = T(0), ma = T(0), aa = T(0);
+        const int tid = threadIdx.x;
+#pragma unroll
+        for (int k = 0; k <= 2 * HB; ++k) {
+            const T cM = op.band[2][0][k * m3 + i3];
+            const T cA = op.band[2][1][k * m3 + i3];
+            const T cS = op.band[2][2][k * m3 + i3];
+            const T vM = st[tid + k], vA = st[STN + tid + k], vS = st[2 * STN + tid + k];
+            mm += cM * vM;  // M3 (M2 x)
+            sm += cS * vM;  // S3 (M2 x)
+            if (C != 1) am += cA * vM;  // A3 (M2 x)
+            ms += cM * vS;  // M3 (S2 x)
+            if (C != 2) ma += cM * vA;  // M3 (A2 x)
+            if (C != 0) aa += cA * vA;  // A3 (A2 x)
+        }
+        const T al = op.alpha, be = op.beta, ab = op.alpha - op.beta;
+        if (C == 0) {
+            W[0][0] += be * mm;
+            W[0][1] += al * (sm + ms);
+            W[2][2] += ab * am;
+            W[1][2] += ab * ma;
+        } else if (C == 1) {
+            W[1][0] += al * mm;
+            W[1][1] += al * sm + be * ms;
+            W[0][2] += ab * ma;
+            W[2][1] += ab * aa;
+        } else {
+            W[2][0] += al * mm;
+            W[2][1] += be * sm + al * ms;
+            W[0][2] += ab * am;
+            W[1][1] += ab * aa;
+        }
+    }
+    __syncthreads();
+}
+
+template <typename T, int HB, int MODE>
+__global__ __launch_bounds__(kThreads) void k_apply3d(OpDev<T> op, const T* __restrict__ x, T* __restrict__ y,
+                                                      const T* __restrict__ b, T* __restrict__ u,
+                                                      T* __restrict__ xout, T c1, T c2, double* __restrict__ part,
+                                                      int nchunk, int c1len) {
+    constexpr int R = 2 * HB + 1;
+    constexpr int STN = Plane3<T, HB>::STN;
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    T* xs = reinterpret_cast<T*>(smem_raw);
+    const int m1 = op.m[0], m2 = op.m[1], m3 = op.m[2];
+    const int PL = m2 * m3;
+    const size_t G = size_t(m1) * PL;
+    T* st = xs + (kThreads + 2 * HB * m3 + 2 * HB);
+    (void)STN;
+    const int chunk = blockIdx.x % nchunk;
+    const int xc = blockIdx.x / nchunk;
+    const int s = chunk * kThreads;
+    const int o0 = xc * c1len;
+    const int o1 = min(o0 + c1len, m1);
+    const int f = s + int(threadIdx.x);
+    const bool active = f < PL;
+    const int i3 = active ? f % m3 : 0;
+    const int i2 = active ? f / m3 : 0;
+
+    T acc[3][R];
+#pragma unroll
+    for (int c = 0; c < 3; ++c)
+#pragma unroll
+        for (int r = 0; r < R; ++r) acc[c][r] = T(0);
+    double dot = 0.0;
+
+    const int TI = (o1 - o0) + 2 * HB;
+    for (int t0 = 0; t0 < TI; t0 += R) {
+#pragma unroll
+        for (int uu = 0; uu < R; ++uu) {
+            const int t = t0 + uu;
+            if (t < TI) {
+                const int j = o0 - HB + t;
+                const bool jin = (j >= 0 && j < m1);
+                T W[3][3];
+#pragma unroll
+                for (int c = 0; c < 3; ++c)
+#pragma unroll
+                    for (int w = 0; w < 3; ++w) W[c][w] = T(0);
+                if (jin) {
+                    stage_ab<T, HB, 0>(op, x + 0 * G + size_t(j) * PL, s, PL, m3, xs, st, active, i3, W);
+                    stage_ab<T, HB, 1>(op, x + 1 * G + size_t(j) * PL, s, PL, m3, xs, st, active, i3, W);
+                    stage_ab<T, HB, 2>(op, x + 2 * G + size_t(j) * PL, s, PL, m3, xs, st, active, i3, W);
+#pragma unroll
+                    for (int k = 0; k < R; ++k) {
+                        const int i = j - HB + k;
+                        if (i >= o0 && i < o1) {
+                            const int kk = 2 * HB - k;  // band column of X1(i, j)
+                            const T cS = op.band[0][2][kk * m1 + i];
+                            const T cM = op.band[0][0][kk * m1 + i];
+                            const T cA = op.band[0][1][kk * m1 + i];
+                            const int slot = (uu + k + 1) % R;
+#pragma unroll
+                            for (int c = 0; c < 3; ++c) {
+                                // slot is a compile-time constant after unrolling uu and k
+#pragma unroll
+                                for (int r = 0; r < R; ++r)
+                                    if (r == slot) acc[c][r] += cS * W[c][0] + cM * W[c][1] + cA * W[c][2];
+                            }
+                        }
+                    }
+                }
+                const int io = j - HB;
+                if (io >= o0 && io < o1 && active) {
+                    const int slot = (uu + 1) % R;
+#pragma unroll
+                    for (int c = 0; c < 3; ++c) {
+                        T kx = T(0);
+#pragma unroll
+                        for (int r = 0; r < R; ++r)
+                            if (r == slot) { kx = acc[c][r]; acc[c][r] = T(0); }
+                        const size_t idx = size_t(c) * G + size_t(io) * PL + f;
+                        if (MODE == kApplyY) {
+                            y[idx] = kx;
+                        } else if (MODE == kApplyRes) {
+                            y[idx] = b[idx] - kx;
+                        } else if (MODE == kApplyCheb) {
+                            const T r = b[idx] - kx;
+                            const T dg = diag_entry(op, c, io, i2, i3);
+                            const T uprev = (c1 != T(0)) ? u[idx] : T(0);  // u is not read on a first step
+                            const T un = c1 * uprev + c2 * r / dg;
+                            u[idx] = un;
+                            xout[idx] = x[idx] + un;
+                        } else {
+                            y[idx] = kx;
+                            dot += double(x[idx]) * double(kx);
+                        }
+                    }
+                } else if (io >= o0 && io < o1) {
+#pragma unroll
+                    for (int c = 0; c < 3; ++c)
+#pragma unroll
+                        for (int r = 0; r < R; ++r)
+                            if (r == (uu + 1) % R) acc[c][r] = T(0);
+                }
+            }
+        }
+    }
+    if (MODE == kApplyYDot) {
+        const double tot = block_sum(dot);
+        if (threadIdx.x == 0) part[blockIdx.x] = tot;
+    }
+}
+
+// ------------------------------------------------------------------------------
+// 2D operator apply: block owns kThreads consecutive points of the flattened
+// (x1, x2) grid.  (A) axis-1 contractions (stride m2) S1, M1, A1 of both
+// components on [s-HB, s+kThreads+HB); (B) axis-2 contraction at the point:
+//   y1 = beta M2(S1 x1) + alpha S2(M1 x1) + (alpha-beta) A2(A1 x2)
+//   y2 = alpha M2(S1 x2) + beta S2(M1 x2) + (alpha-beta) A2(A1 x1)
+// ------------------------------------------------------------------------------
+template <typename T, int HB, int MODE>
+__global__ __launch_bounds__(kThreads) void k_apply2d(OpDev<T> op, const T* __restrict__ x, T* __restrict__ y,
+                                                      const T* __restrict__ b, T* __restrict__ u,
+                                                      T* __restrict__ xout, T c1, T c2, double* __restrict__ part) {
+    constexpr int STN = kThreads + 2 * HB;
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    const int m1 = op.m[0], m2 = op.m[1];
+    const int G = m1 * m2;
+    const int XSN = kThreads + 2 * HB * m2 + 2 * HB;
+    T* xs = reinterpret_cast<T*>(smem_raw);  // 2 x XSN
+    T* st = xs + 2 * XSN;                    // 6 x STN: S1x1 M1x1 A1x1 S1x2 M1x2 A1x2
+    const int s = blockIdx.x * kThreads;
+    const int tid = threadIdx.x;
+    const int f = s + tid;
+    const int base = s - HB * m2 - HB;
+    for (int q = tid; q < XSN; q += kThreads) {
+        const int ff = base + q;
+        const bool in = ff >= 0 && ff < G;
+        xs[q] = in ? x[ff] : T(0);
+        xs[XSN + q] = in ? x[G + ff] : T(0);
+    }
+    __syncthreads();
+    for (int q = tid; q < STN; q += kThreads) {
+        const int ff = s - HB + q;
+        T v[6] = {T(0), T(0), T(0), T(0), T(0), T(0)};
+        if (ff >= 0 && ff < G) {
+            const int r1 = ff / m2;
+#pragma unroll
+            for (int k = 0; k <= 2 * HB; ++k) {
+                const T cS = op.band[0][2][k * m1 + r1];
+                const T cM = op.band[0][0][k * m1 + r1];
+                const T cA = op.band[0][1][k * m1 + r1];
+                const T x1 = xs[q + k * m2], x2 = xs[XSN + q + k * m2];
+                v[0] += cS * x1;
+                v[1] += cM * x1;
+                v[2] += cA * x1;
+                v[3] += cS * x2;
+                v[4] += cM * x2;
+                v[5] += cA * x2;
+            }
+        }
+#pragma unroll
+        for (int w = 0; w < 6; ++w) st[w * STN + q] = v[w];
+    }
+    __syncthreads();
+    double dot = 0.0;
+    if (f < G) {
+        const int i2 = f % m2, i1 = f / m2;
+        T mS1 = T(0), sM1 = T(0), aA2 = T(0), mS2 = T(0), sM2 = T(0), aA1 = T(0);
+#pragma unroll
+        for (int k = 0; k <= 2 * HB; ++k) {
+            const T cM = op.band[1][0][k * m2 + i2];
+            const T cA = op.band[1][1][k * m2 + i2];
+            const T cS = op.band[1][2][k * m2 + i2];
+            mS1 += cM * st[0 * STN + tid + k];
+            sM1 += cS * st[1 * STN + tid + k];
+            aA1 += cA * st[2 * STN + tid + k];
+            mS2 += cM * st[3 * STN + tid + k];
+            sM2 += cS * st[4 * STN + tid + k];
+            aA2 += cA * st[5 * STN + tid + k];
+        }
+        const T al = op.alpha, be = op.beta, ab = op.alpha - op.beta;
+        const T kx[2] = {be * mS1 + al * sM1 + ab * aA2, al * mS2 + be * sM2 + ab * aA1};
+#pragma unroll
+        for (int c = 0; c < 2; ++c) {
+            const size_t idx = size_t(c) * G + f;
+            if (MODE == kApplyY) {
+                y[idx] = kx[c];
+            } else if (MODE == kApplyRes) {
+                y[idx] = b[idx] - kx[c];
+            } else if (MODE == kApplyCheb) {
+                const T r = b[idx] - kx[c];
+                const T dg = diag_entry(op, c, i1, i2, 0);
+                const T uprev = (c1 != T(0)) ? u[idx] : T(0);  // u is not read on a first step
+                const T un = c1 * uprev + c2 * r / dg;
+                u[idx] = un;
+                xout[idx] = x[idx] + un;
+            } else {
+                y[idx] = kx[c];
+                dot += double(x[idx]) * double(kx[c]);
+            }
+        }
+    }
+    if (MODE == kApplyYDot) {
+        const double tot = block_sum(dot);
+        if (threadIdx.x == 0) part[blockIdx.x] = tot;
+    }
+}
+
+constexpr int kX1Chunk = 16;
+
+template <typename T>
+size_t apply_lds_bytes(const OpDev<T>& op) {
+    const int hb = op.hb;
+    if (op.dim == 3) return sizeof(T) * (size_t(kThreads + 2 * hb * op.m[2] + 2 * hb) + 3 * size_t(kThreads + 2 * hb));
+    return sizeof(T) * (2 * size_t(kThreads + 2 * hb * op.m[1] + 2 * hb) + 6 * size_t(kThreads + 2 * hb));
+}
+
+template <typename T, int HB, int MODE>
+void apply_dispatch(const OpDev<T>& op, const T* x, T* y, const T* b, T* u, T* xout, T c1, T c2, double* part,
+                    hipStream_t s) {
+    const size_t lds = apply_lds_bytes(op);
+    if (lds > 160 * 1024) throw std::runtime_error("grid too large for the operator kernel's LDS tile");
+    if (op.dim == 3) {
+        const int PL = op.m[1] * op.m[2];
+        const int nchunk = (PL + kThreads - 1) / kThreads;
+        const int nx1 = (op.m[0] + kX1Chunk - 1) / kX1Chunk;
+        auto kern = k_apply3d<T, HB, MODE>;
+        if (lds > 64 * 1024) hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, int(lds));
+        hipLaunchKernelGGL(kern, dim3(nchunk * nx1), dim3(kThreads), lds, s, op, x, y, b, u, xout, c1, c2, part,
+                           nchunk, kX1Chunk);
+    } else {
+        const int G = op.m[0] * op.m[1];
+        auto kern = k_apply2d<T, HB, MODE>;
+        if (lds > 64 * 1024) hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, int(lds));
+        hipLaunchKernelGGL(kern, dim3((G + kThreads - 1) / kThreads), dim3(kThreads), lds, s, op, x, y, b, u, xout,
+                           c1, c2, part);
+    }
+    check_launch("apply");
+}
+
+template <typename T, int HB>
+void apply_mode(const OpDev<T>& op, int mode, const T* x, T* y, const T* b, T* u, T* xout, T c1, T c2, double* part,
+                hipStream_t s) {
+    switch (mode) {
+        case kApplyY: apply_dispatch<T, HB, kApplyY>(op, x, y, b, u, xout, c1, c2, part, s); break;
+        case kApplyRes: apply_dispatch<T, HB, kApplyRes>(op, x, y, b, u, xout, c1, c2, part, s); break;
+        case kApplyCheb: apply_dispatch<T, HB, kApplyCheb>(op, x, y, b, u, xout, c1, c2, part, s); break;
+        case kApplyYDot: apply_dispatch<T, HB, kApplyYDot>(op, x, y, b, u, xout, c1, c2, part, s); break;
+        default: throw std::runtime_error("bad apply mode");
+    }
+}
+
+// ------------------------------------------------------------------------------
+// Grid transfers: Kronecker products of 1D prolongators, one thread per
+// output entry (coarse entry for the restriction P^T r, fine entry for x += P e).
+// ------------------------------------------------------------------------------
+template <typename T>
+__global__ __launch_bounds__(kThreads) void k_restrict(XferDev<T> X, int ncomp, const T* __restrict__ rf,
+                                                       T* __restrict__ rc) {
+    const XferAxisDev<T>& a0 = X.ax[0];
+    const XferAxisDev<T>& a1 = X.ax[1];
+    const XferAxisDev<T>& a2 = X.ax[2];
+    const size_t Gc = size_t(a0.mc) * a1.mc * a2.mc;
+    const size_t Gf = size_t(a0.mf) * a1.mf * a2.mf;
+    const size_t id = size_t(blockIdx.x) * kThreads + threadIdx.x;
+    if (id >= Gc * ncomp) return;
+    const int c = int(id / Gc);
+    size_t rem = id % Gc;
+    const int J2 = int(rem % a2.mc);
+    rem /= a2.mc;
+    const int J1 = int(rem % a1.mc);
+    const int J0 = int(rem / a1.mc);
+    double acc = 0.0;
+    for (int k0 = 0; k0 < a0.wr; ++k0) {
+        const T p0 = a0.vt[J0 * a0.wr + k0];
+        if (p0 == T(0)) continue;
+        const int i0 = a0.r0[J0] + k0;
+        for (int k1 = 0; k1 < a1.wr; ++k1) {
+            const T p1 = a1.vt[J1 * a1.wr + k1];
+            if (p1 == T(0)) continue;
+            const int i1 = a1.r0[J1] + k1;
+            const T* row = rf + size_t(c) * Gf + (size_t(i0) * a1.mf + i1) * a2.mf + a2.r0[J2];
+            T s2 = T(0);
+            for (int k2 = 0; k2 < a2.wr; ++k2) s2 += a2.vt[J2 * a2.wr + k2] * row[k2];
+            acc += double(p0 * p1 * s2);
+        }
+    }
+    rc[id] = T(acc);
+}
+
+template <typename T>
+__global__ __launch_bounds__(kThreads) void k_prolong_add(XferDev<T> X, int ncomp, const T* __restrict__ ec,
+                                                          T* __restrict__ xf) {
+    const XferAxisDev<T>& a0 = X.ax[0];
+    const XferAxisDev<T>& a1 = X.ax[1];
+    const XferAxisDev<T>& a2 = X.ax[2];
+    const size_t Gc = size_t(a0.mc) * a1.mc * a2.mc;
+    const size_t Gf = size_t(a0.mf) * a1.mf * a2.mf;
+    const size_t id = size_t(blockIdx.x) * kThreads + threadIdx.x;
+    if (id >= Gf * ncomp) return;
+    const int c = int(id / Gf);
+    size_t rem = id % Gf;
+    const int i2 = int(rem % a2.mf);
+    rem /= a2.mf;
+    const int i1 = int(rem % a1.mf);
+    const int i0 = int(rem / a1.mf);
+    T acc = T(0);
+    for (int k0 = 0; k0 < a0.w; ++k0) {
+        const T p0 = a0.v[i0 * a0.w + k0];
+        if (p0 == T(0)) continue;
+        const int J0 = a0.c0[i0] + k0;
+        for (int k1 = 0; k1 < a1.w; ++k1) {
+            const T p1 = a1.v[i1 * a1.w + k1];
+            if (p1 == T(0)) continue;
+            const int J1 = a1.c0[i1] + k1;
+            const T* row = ec + size_t(c) * Gc + (size_t(J0) * a1.mc + J1) * a2.mc + a2.c0[i2];
+            T s2 = T(0);
+            for (int k2 = 0; k2 < a2.w; ++k2) s2 += a2.v[i2 * a2.w + k2] * row[k2];
+            acc += p0 * p1 * s2;
+        }
+    }
+    xf[id] += acc;
+}
+
+// ------------------------------------------------------------------------------
+// T^{-1}: banded LDL^T forward / diagonal / backward solves along every grid
+// line of one axis, one thread per line, in place.
+// ------------------------------------------------------------------------------
+template <typename T, int BW>
+__global__ __launch_bounds__(kThreads) void k_tsolve_axis(T* __restrict__ z, int ncomp, int m0, int m1, int m2,
+                                                          int axis, TFacDev<T> F) {
+    const size_t G = size_t(m0) * m1 * m2;
+    const int ma = (axis == 0) ? m0 : (axis == 1) ? m1 : m2;
+    const size_t lines_per_comp = G / ma;
+    const size_t line = size_t(blockIdx.x) * kThreads + threadIdx.x;
+    if (line >= lines_per_comp * ncomp) return;
+    const int c = int(line / lines_per_comp);
+    const size_t rem = line % lines_per_comp;
+    size_t base, stride;
+    if (axis == 0) {
+        base = rem;
+        stride = size_t(m1) * m2;
+    } else if (axis == 1) {
+        base = (rem / m2) * size_t(m1) * m2 + rem % m2;
+        stride = m2;
+    } else {
+        base = rem * m2;
+        stride = 1;
+    }
+    T* zl = z + size_t(c) * G + base;
+    T win[BW > 0 ? BW : 1];
+#pragma unroll
+    for (int k = 0; k < (BW > 0 ? BW : 1); ++k) win[k] = T(0);
+    // forward: y_i = v_i - sum_k L(i,i-k) y_{i-k}; store y_i / D_i
+    for (int i = 0; i < ma; ++i) {
+        T v = zl[size_t(i) * stride];
+#pragma unroll
+        for (int k = 1; k <= BW; ++k)
+            if (i - k >= 0) v -= F.l[i * BW + k - 1] * win[k - 1];
+#pragma unroll
+        for (int k = BW - 1; k >= 1; --k) win[k] = win[k - 1];
+        if (BW > 0) win[0] = v;
+        zl[size_t(i) * stride] = v * F.dinv[i];
+    }
+    // backward: z_i = w_i - sum_k L(i+k, i) z_{i+k}
+#pragma unroll
+    for (int k = 0; k < (BW > 0 ? BW : 1); ++k) win[k] = T(0);
+    for (int i = ma - 1; i >= 0; --i) {
+        T v = zl[size_t(i) * stride];
+#pragma unroll
+        for (int k = 1; k <= BW; ++k)
+            if (i + k < ma) v -= F.l[(i + k) * BW + k - 1] * win[k - 1];
+#pragma unroll
+        for (int k = BW - 1; k >= 1; --k) win[k] = win[k - 1];
+        if (BW > 0) win[0] = v;
+        zl[size_t(i) * stride] = v;
+    }
+}
+
+// ------------------------------------------------------------------------------
+// Vector kernels
+// ------------------------------------------------------------------------------
+template <typename TA, typename TB>
+__global__ __launch_bounds__(kThreads) void k_dot_partial(const TA* __restrict__ a, const TB* __restrict__ b, size_t n,
+                                                          double* __restrict__ part) {
+    double s = 0.0;
+    for (size_t i = size_t(blockIdx.x) * kThreads + threadIdx.x; i < n; i += size_t(gridDim.x) * kThreads)
+        s += double(a[i]) * double(b[i]);
+    s = block_sum(s);
+    if (threadIdx.x == 0) part[blockIdx.x] = s;
+}
+
+__global__ __launch_bounds__(kThreads) void k_finalize(const double* __restrict__ part, int np, double* out) {
+    const double s = sum_partials(part, np);
+    if (threadIdx.x == 0) out[0] = s;
+}
+
+template <typename TO, typename TI>
+__global__ __launch_bounds__(kThreads) void k_cast(const TI* __restrict__ x, TO* __restrict__ y, size_t n) {
+    for (size_t i = size_t(blockIdx.x) * kThreads + threadIdx.x; i < n; i += size_t(gridDim.x) * kThreads)
+        y[i] = TO(x[i]);
+}
+
+template <typename T>
+__global__ __launch_bounds__(kThreads) void k_fill(T* __restrict__ x, T v, size_t n) {
+    for (size_t i = size_t(blockIdx.x) * kThreads + threadIdx.x; i < n; i += size_t(gridDim.x) * kThreads) x[i] = v;
+}
+
+template <typename T>
+__global__ __launch_bounds__(kThreads) void k_axpby(T a, const T* __restrict__ x, T b, T* __restrict__ y, size_t n) {
+    for (size_t i = size_t(blockIdx.x) * kThreads + threadIdx.x; i < n; i += size_t(gridDim.x) * kThreads)
+        y[i] = a * x[i] + b * y[i];
+}
+
+template <typename T>
+__global__ __launch_bounds__(kThreads) void k_normalize(const double* __restrict__ part, int np, const T* __restrict__ x,
+                                                        T* __restrict__ y, size_t n) {
+    const double ss = sum_partials(part, np);
+    const T sc = ss > 0.0 ? T(1.0 / sqrt(ss)) : T(0);
+    for (size_t i = size_t(blockIdx.x) * kThreads + threadIdx.x; i < n; i += size_t(gridDim.x) * kThreads)
+        y[i] = x[i] * sc;
+}
+
+template <typename T>
+__device__ inline void unflatten(const OpDev<T>& op, size_t id, int& c, int& i0, int& i1, int& i2) {
+    const size_t G = size_t(op.m[0]) * op.m[1] * op.m[2];
+    c = int(id / G);
+    size_t rem = id % G;
+    i2 = int(rem % op.m[2]);
+    rem /= op.m[2];
+    i1 = int(rem % op.m[1]);
+    i0 = int(rem / op.m[1]);
+}
+
+template <typename T>
+__global__ __launch_bounds__(kThreads) void k_diag_scale(OpDev<T> op, bool inv, const T* __restrict__ x,
+                                                         T* __restrict__ y, size_t n) {
+    for (size_t id = size_t(blockIdx.x) * kThreads + threadIdx.x; id < n; id += size_t(gridDim.x) * kThreads) {
+        int c, i0, i1, i2;
+        unflatten(op, id, c, i0, i1, i2);
+        const T d = diag_entry(op, c, i0, i1, i2);
+        y[id] = inv ? x[id] / d : x[id] * d;
+    }
+}
+
+template <typename T>
+__global__ __launch_bounds__(kThreads) void k_diag_dot(OpDev<T> op, const T* __restrict__ x, size_t n,
+                                                       double* __restrict__ part) {
+    double s = 0.0;
+    for (size_t id = size_t(blockIdx.x) * kThreads + threadIdx.x; id < n; id += size_t(gridDim.x) * kThreads) {
+        int c, i0, i1, i2;
+        unflatten(op, id, c, i0, i1, i2);
+        const double d = double(diag_entry(op, c, i0, i1, i2));
+        s += d * double(x[id]) * double(x[id]);
+    }
+    s = block_sum(s);
+    if (threadIdx.x == 0) part[blockIdx.x] = s;
+}
+
+template <typename T>
+__global__ __launch_bounds__(kThreads) void k_cheb_first(OpDev<T> op, const T* __restrict__ b, T* __restrict__ u,
+                                                         T* __restrict__ x, T inv_theta, size_t n) {
+    for (size_t id = size_t(blockIdx.x) * kThreads + threadIdx.x; id < n; id += size_t(gridDim.x) * kThreads) {
+        int c, i0, i1, i2;
+        unflatten(op, id, c, i0, i1, i2);
+        const T v = inv_theta * b[id] / diag_entry(op, c, i0, i1, i2);
+        u[id] = v;
+        x[id] = v;
+    }
+}
+
+// z = Kinv r, one block per row, FP64 accumulation
+template <typename T>
+__global__ __launch_bounds__(kThreads) void k_coarse_gemv(const double* __restrict__ Kinv, int N,
+                                                          const T* __restrict__ r, T* __restrict__ z) {
+    const int row = blockIdx.x;
+    double s = 0.0;
+    for (int j = threadIdx.x; j < N; j += kThreads) s += Kinv[size_t(row) * N + j] * double(r[j]);
+    s = block_sum(s);
+    if (threadIdx.x == 0) z[row] = T(s);
+}
+
+// ---- flexible CG ----------------------------------------------------------------
+__global__ __launch_bounds__(kThreads) void k_fcg_direction(int first, const double* __restrict__ z,
+                                                            const double* __restrict__ pzq, int npzq,
+                                                            const double* __restrict__ dq_prev, double* __restrict__ d,
+                                                            const double* __restrict__ r, double* __restrict__ pdr,
+                                                            size_t n) {
+    double beta = 0.0;
+    if (!first) {
+        const double zq = sum_partials(pzq, npzq);
+        const double dq = dq_prev[0];
+        beta = (dq != 0.0) ? zq / dq : 0.0;
+    }
+    double s = 0.0;
+    for (size_t i = size_t(blockIdx.x) * kThreads + threadIdx.x; i < n; i += size_t(gridDim.x) * kThreads) {
+        const double dn = first ? z[i] : z[i] - beta * d[i];
+        d[i] = dn;
+        s += dn * r[i];
+    }
+    s = block_sum(s);
+    if (threadIdx.x == 0) pdr[blockIdx.x] = s;
+}
+
+__global__ __launch_bounds__(kThreads) void k_fcg_update(const double* __restrict__ pdr, int npdr,
+                                                         const double* __restrict__ pdq, int npdq,
+                                                         double* __restrict__ dq_out, double* __restrict__ x,
+                                                         double* __restrict__ r, const double* __restrict__ d,
+                                                         const double* __restrict__ q, double* __restrict__ prr,
+                                                         size_t n) {
+    const double dr = sum_partials(pdr, npdr);
+    const double dq = sum_partials(pdq, npdq);
+    const double a = (dq != 0.0) ? dr / dq : 0.0;
+    if (blockIdx.x == 0 && threadIdx.x == 0) dq_out[0] = dq;
+    double s = 0.0;
+    for (size_t i = size_t(blockIdx.x) * kThreads + threadIdx.x; i < n; i += size_t(gridDim.x) * kThreads) {
+        x[i] += a * d[i];
+        const double rn = r[i] - a * q[i];
+        r[i] = rn;
+        s += rn * rn;
+    }
+    s = block_sum(s);
+    if (threadIdx.x == 0) prr[blockIdx.x] = s;
+}
+
+// ---- GMRES helpers -----------------------------------------------------------------
+constexpr int kMaxBasis = 8;
+
+template <typename T>
+__global__ __launch_bounds__(kThreads) void k_multidot(const T* __restrict__ V, int k, const T* __restrict__ w,
+                                                       size_t n, double* __restrict__ part, int nb) {
+    double s[kMaxBasis];
+#pragma unroll
+    for (int j = 0; j < kMaxBasis; ++j) s[j] = 0.0;
+    for (size_t i = size_t(blockIdx.x) * kThreads + threadIdx.x; i < n; i += size_t(gridDim.x) * kThreads) {
+        const double wv = double(w[i]);
+#pragma unroll
+        for (int j = 0; j < kMaxBasis; ++j)
+            if (j < k) s[j] += double(V[size_t(j) * n + i]) * wv;
+    }
+    for (int j = 0; j < k; ++j) {
+        const double t = block_sum(s[j]);
+        if (threadIdx.x == 0) part[size_t(j) * nb + blockIdx.x] = t;
+    }
+}
+
+__global__ void k_multifinal(const double* __restrict__ part, int k, int nb, double* __restrict__ H, int take_sqrt) {
+    const int j = threadIdx.x;
+    if (j >= k) return;
+    double s = 0.0;
+    for (int b = 0; b < nb; ++b) s += part[size_t(j) * nb + b];
+    H[j] = take_sqrt ? sqrt(s) : s;
+}
+
+template <typename T>
+__global__ __launch_bounds__(kThreads) void k_multiaxpy(const T* __restrict__ V, int k, const double* __restrict__ h,
+                                                        T* __restrict__ w, size_t n) {
+    for (size_t i = size_t(blockIdx.x) * kThreads + threadIdx.x; i < n; i += size_t(gridDim.x) * kThreads) {
+        T acc = w[i];
+        for (int j = 0; j < k; ++j) acc -= T(h[j]) * V[size_t(j) * n + i];
+        w[i] = acc;
+    }
+}
+
+template <typename T>
+__global__ __launch_bounds__(kThreads) void k_scale_by(const double* __restrict__ h, const T* __restrict__ w,
+                                                       T* __restrict__ v, size_t n) {
+    const double hv = h[0];
+    const T sc = (hv != 0.0) ? T(1.0 / hv) : T(0);
+    for (size_t i = size_t(blockIdx.x) * kThreads + threadIdx.x; i < n; i += size_t(gridDim.x) * kThreads)
+        v[i] = w[i] * sc;
+}
+
+__global__ void k_hessenberg_ls(const double* __restrict__ H, int ld, int k, const double* __restrict__ beta0sq,
+                                double* __restrict__ y) {
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    double R[kMaxBasis + 1][kMaxBasis];
+    double g[kMaxBasis + 1];
+    for (int i = 0; i <= k; ++i) {
+        g[i] = 0.0;
+        for (int j = 0; j < k; ++j) R[i][j] = H[size_t(j) * ld + i];
+    }
+    g[0] = sqrt(beta0sq[0]);
+    for (int j = 0; j < k; ++j) {
+        const double a = R[j][j], b = R[j + 1][j];
+        const double rr = sqrt(a * a + b * b);
+        const double c = (rr > 0.0) ? a / rr : 1.0, sn = (rr > 0.0) ? b / rr : 0.0;
+        for (int col = j; col < k; ++col) {
+            const double t0 = R[j][col], t1 = R[j + 1][col];
+            R[j][col] = c * t0 + sn * t1;
+            R[j + 1][col] = -sn * t0 + c * t1;
+        }
+        const double g0 = g[j], g1 = g[j + 1];
+        g[j] = c * g0 + sn * g1;
+        g[j + 1] = -sn * g0 + c * g1;
+    }
+    for (int i = k - 1; i >= 0; --i) {
+        double s = g[i];
+        for (int col = i + 1; col < k; ++col) s -= R[i][col] * y[col];
+        y[i] = (fabs(R[i][i]) > 0.0) ? s / R[i][i] : 0.0;
+    }
+}
+
+template <typename T>
+__global__ __launch_bounds__(kThreads) void k_combine(const T* __restrict__ V, int k, const double* __restrict__ y,
+                                                      T* __restrict__ w, size_t n) {
+    for (size_t i = size_t(blockIdx.x) * kThreads + threadIdx.x; i < n; i += size_t(gridDim.x) * kThreads) {
+        T acc = T(0);
+        for (int j = 0; j < k; ++j) acc += T(y[j]) * V[size_t(j) * n + i];
+        w[i] = acc;
+    }
+}
+
+int grid_for(size_t n) {
+    const size_t nb = (n + kThreads - 1) / kThreads;
+    return int(std::max<size_t>(1, std::min<size_t>(nb, 8192)));
+}
+
+}  // namespace
+
+// ================================ launch wrappers =================================
+
+int reduce_blocks(size_t n) {
+    const size_t nb = (n + size_t(kThreads) * 8 - 1) / (size_t(kThreads) * 8);
+    return int(std::max<size_t>(1, std::min<size_t>(nb, 1024)));
+}
+
+template <typename T>
+int apply_blocks(const OpDev<T>& op) {
+    if (op.dim == 3) {
+        const int PL = op.m[1] * op.m[2];
+        return ((PL + kThreads - 1) / kThreads) * ((op.m[0] + kX1Chunk - 1) / kX1Chunk);
+    }
+    return (op.m[0] * op.m[1] + kThreads - 1) / kThreads;
+}
+
+template <typename T>
+void launch_apply(const OpDev<T>& op, int mode, const T* x, T* y, const T* b, T* u, T* xout, T c1, T c2, double* part,
+                  hipStream_t s) {
+    switch (op.hb) {
+        case 1: apply_mode<T, 1>(op, mode, x, y, b, u, xout, c1, c2, part, s); break;
+        case 2: apply_mode<T, 2>(op, mode, x, y, b, u, xout, c1, c2, part, s); break;
+        case 3: apply_mode<T, 3>(op, mode, x, y, b, u, xout, c1, c2, part, s); break;
+        case 4: apply_mode<T, 4>(op, mode, x, y, b, u, xout, c1, c2, part, s); break;
+        case 5: apply_mode<T, 5>(op, mode, x, y, b, u, xout, c1, c2, part, s); break;
+        case 6: apply_mode<T, 6>(op, mode, x, y, b, u, xout, c1, c2, part, s); break;
+        default: throw std::runtime_error("degree out of range (1..6)");
+    }
+}
+
+template <typename T>
+void launch_restrict(const XferDev<T>& X, int ncomp, const T* rf, T* rc, hipStream_t s) {
+    const size_t n = size_t(ncomp) * X.ax[0].mc * X.ax[1].mc * X.ax[2].mc;
+    hipLaunchKernelGGL(k_restrict<T>, dim3((n + kThreads - 1) / kThreads), dim3(kThreads), 0, s, X, ncomp, rf, rc);
+    check_launch("restrict");
+}
+
+template <typename T>
+void launch_prolong_add(const XferDev<T>& X, int ncomp, const T* ec, T* xf, hipStream_t s) {
+    const size_t n = size_t(ncomp) * X.ax[0].mf * X.ax[1].mf * X.ax[2].mf;
+    hipLaunchKernelGGL(k_prolong_add<T>, dim3((n + kThreads - 1) / kThreads), dim3(kThreads), 0, s, X, ncomp, ec, xf);
+    check_launch("prolong");
+}
+
+template <typename T>
+void launch_tsolve(int dim, const int* m, const TFacDev<T>* fac, T* z, hipStream_t s) {
+    const int m0 = m[0], m1 = m[1], m2 = (dim == 3) ? m[2] : 1;
+    const size_t G = size_t(m0) * m1 * m2;
+    for (int a = 0; a < dim; ++a) {
+        const TFacDev<T>& F = fac[a];
+        const size_t lines = size_t(dim) * G / F.m;
+        const dim3 grid((lines + kThreads - 1) / kThreads);
+        switch (F.bw) {
+            case 0: return;  // p = 1: T is the identity
+            case 1: hipLaunchKernelGGL((k_tsolve_axis<T, 1>), grid, dim3(kThreads), 0, s, z, dim, m0, m1, m2, a, F); break;
+            case 2: hipLaunchKernelGGL((k_tsolve_axis<T, 2>), grid, dim3(kThreads), 0, s, z, dim, m0, m1, m2, a, F); break;
+            case 3: hipLaunchKernelGGL((k_tsolve_axis<T, 3>), grid, dim3(kThreads), 0, s, z, dim, m0, m1, m2, a, F); break;
+            case 4: hipLaunchKernelGGL((k_tsolve_axis<T, 4>), grid, dim3(kThreads), 0, s, z, dim, m0, m1, m2, a, F); break;
+            case 5: hipLaunchKernelGGL((k_tsolve_axis<T, 5>), grid, dim3(kThreads), 0, s, z, dim, m0, m1, m2, a, F); break;
+            default: throw std::runtime_error("degree out of range (1..6)");
+        }
+        check_launch("tsolve");
+    }
+}
+
+template <typename TA, typename TB>
+void launch_dot_partial(const TA* a, const TB* b, size_t n, double* part, hipStream_t s) {
+    hipLaunchKernelGGL((k_dot_partial<TA, TB>), dim3(reduce_blocks(n)), dim3(kThreads), 0, s, a, b, n, part);
+    check_launch("dot");
+}
+
+void launch_finalize(const double* part, int np, double* out, hipStream_t s) {
+    hipLaunchKernelGGL(k_finalize, dim3(1), dim3(kThreads), 0, s, part, np, out);
+    check_launch("finalize");
+}
+
+template <typename TO, typename TI>
+void launch_cast(const TI* x, TO* y, size_t n, hipStream_t s) {
+    hipLaunchKernelGGL((k_cast<TO, TI>), dim3(grid_for(n)), dim3(kThreads), 0, s, x, y, n);
+    check_launch("cast");
+}
+
+template <typename T>
+void launch_fill(T* x, T v, size_t n, hipStream_t s) {
+    hipLaunchKernelGGL(k_fill<T>, dim3(grid_for(n)), dim3(kThreads), 0, s, x, v, n);
+    check_launch("fill");
+}
+
+template <typename T>
+void launch_copy(const T* x, T* y, size_t n, hipStream_t s) {
+    hipLaunchKernelGGL((k_cast<T, T>), dim3(grid_for(n)), dim3(kThreads), 0, s, x, y, n);
+    check_launch("copy");
+}
+
+template <typename T>
+void launch_axpby(T a, const T* x, T b, T* y, size_t n, hipStream_t s) {
+    hipLaunchKernelGGL(k_axpby<T>, dim3(grid_for(n)), dim3(kThreads), 0, s, a, x, b, y, n);
+    check_launch("axpby");
+}
+
+template <typename T>
+void launch_normalize(const double* part, int np, const T* x, T* y, size_t n, hipStream_t s) {
+    hipLaunchKernelGGL(k_normalize<T>, dim3(grid_for(n)), dim3(kThreads), 0, s, part, np, x, y, n);
+    check_launch("normalize");
+}
+
+template <typename T>
+static size_t op_len(const OpDev<T>& op) {
+    return size_t(op.dim) * op.m[0] * op.m[1] * op.m[2];
+}
+
+template <typename T>
+void launch_diag_scale(const OpDev<T>& op, bool inv, const T* x, T* y, hipStream_t s) {
+    const size_t n = op_len(op);
+    hipLaunchKernelGGL(k_diag_scale<T>, dim3(grid_for(n)), dim3(kThreads), 0, s, op, inv, x, y, n);
+    check_launch("diag_scale");
+}
+
+template <typename T>
+void launch_diag_dot(const OpDev<T>& op, const T* x, double* part, hipStream_t s) {
+    const size_t n = op_len(op);
+    hipLaunchKernelGGL(k_diag_dot<T>, dim3(reduce_blocks(n)), dim3(kThreads), 0, s, op, x, n, part);
+    check_launch("diag_dot");
+}
+
+template <typename T>
+void launch_cheb_first(const OpDev<T>& op, const T* b, T* u, T* x, T inv_theta, hipStream_t s) {
+    const size_t n = op_len(op);
+    hipLaunchKernelGGL(k_cheb_first<T>, dim3(grid_for(n)), dim3(kThreads), 0, s, op, b, u, x, inv_theta, n);
+    check_launch("cheb_first");
+}
+
+template <typename T>
+void launch_coarse_gemv(const double* Kinv, int N, const T* r, T* z, hipStream_t s) {
+    hipLaunchKernelGGL(k_coarse_gemv<T>, dim3(N), dim3(kThreads), 0, s, Kinv, N, r, z);
+    check_launch("coarse_gemv");
+}
+
+void launch_fcg_direction(bool first, const double* z, const double* pzq, int npzq, const double* dq_prev, double* d,
+                          const double* r, double* pdr, size_t n, hipStream_t s) {
+    hipLaunchKernelGGL(k_fcg_direction, dim3(reduce_blocks(n)), dim3(kThreads), 0, s, first ? 1 : 0, z, pzq, npzq,
+                       dq_prev, d, r, pdr, n);
+    check_launch("fcg_direction");
+}
+
+void launch_fcg_update(const double* pdr, int npdr, const double* pdq, int npdq, double* dq_out, double* x, double* r,
+                       const double* d, const double* q, double* prr, size_t n, hipStream_t s) {
+    hipLaunchKernelGGL(k_fcg_update, dim3(reduce_blocks(n)), dim3(kThreads), 0, s, pdr, npdr, pdq, npdq, dq_out, x, r,
+                       d, q, prr, n);
+    check_launch("fcg_update");
+}
+
+template <typename T>
+void launch_multidot(const T* V, int k, const T* w, size_t n, double* part, int nb, hipStream_t s) {
+    if (k > kMaxBasis) throw std::runtime_error("too many Krylov vectors");
+    hipLaunchKernelGGL(k_multidot<T>, dim3(nb), dim3(kThreads), 0, s, V, k, w, n, part, nb);
+    check_launch("multidot");
+}
+
+void launch_multifinal(const double* part, int k, int nb, double* H, hipStream_t s) {
+    hipLaunchKernelGGL(k_multifinal, dim3(1), dim3(64), 0, s, part, k, nb, H, 0);
+    check_launch("multifinal");
+}
+
+void launch_normfinal(const double* part, int nb, double* out, hipStream_t s) {
+    hipLaunchKernelGGL(k_multifinal, dim3(1), dim3(64), 0, s, part, 1, nb, out, 1);
+    check_launch("normfinal");
+}
+
+template <typename T>
+void launch_multiaxpy(const T* V, int k, const double* h, T* w, size_t n, hipStream_t s) {
+    hipLaunchKernelGGL(k_multiaxpy<T>, dim3(grid_for(n)), dim3(kThreads), 0, s, V, k, h, w, n);
+    check_launch("multiaxpy");
+}
+
+template <typename T>
+void launch_scale_by(const double* h, const T* w, T* v, size_t n, hipStream_t s) {
+    hipLaunchKernelGGL(k_scale_by<T>, dim3(grid_for(n)), dim3(kThreads), 0, s, h, w, v, n);
+    check_launch("scale_by");
+}
+
+void launch_hessenberg_ls(const double* H, int ld, int k, const double* beta0sq, double* y, hipStream_t s) {
+    if (k > kMaxBasis) throw std::runtime_error("too many Krylov vectors");
+    hipLaunchKernelGGL(k_hessenberg_ls, dim3(1), dim3(64), 0, s, H, ld, k, beta0sq, y);
+    check_launch("hessenberg_ls");
+}
+
+template <typename T>
+void launch_combine(const T* V, int k, const double* y, T* w, size_t n, hipStream_t s) {
+    hipLaunchKernelGGL(k_combine<T>, dim3(grid_for(n)), dim3(kThreads), 0, s, V, k, y, w, n);
+    check_launch("combine");
+}
+
+// ---- explicit instantiations ----
+#define CD_INST(T)                                                                                                   \
+    template int apply_blocks<T>(const OpDev<T>&);                                                                   \
+    template void launch_apply<T>(const OpDev<T>&, int, const T*, T*, const T*, T*, T*, T, T, double*, hipStream_t); \
+    template void launch_restrict<T>(const XferDev<T>&, int, const T*, T*, hipStream_t);                             \
+    template void launch_prolong_add<T>(const XferDev<T>&, int, const T*, T*, hipStream_t);                          \
+    template void launch_tsolve<T>(int, const int*, const TFacDev<T>*, T*, hipStream_t);                            \
+    template void launch_fill<T>(T*, T, size_t, hipStream_t);                                                        \
+    template void launch_copy<T>(const T*, T*, size_t, hipStream_t);                                                 \
+    template void launch_axpby<T>(T, const T*, T, T*, size_t, hipStream_t);                                          \
+    template void launch_normalize<T>(const double*, int, const T*, T*, size_t, hipStream_t);                        \
+    template void launch_diag_scale<T>(const OpDev<T>&, bool, const T*, T*, hipStream_t);                            \
+    template void launch_diag_dot<T>(const OpDev<T>&, const T*, double*, hipStream_t);                               \
+    template void launch_cheb_first<T>(const OpDev<T>&, const T*, T*, T*, T, hipStream_t);                           \
+    template void launch_coarse_gemv<T>(const double*, int, const T*, T*, hipStream_t);                              \
+    template void launch_multidot<T>(const T*, int, const T*, size_t, double*, int, hipStream_t);                    \
+    template void launch_multiaxpy<T>(const T*, int, const double*, T*, size_t, hipStream_t);                        \
+    template void launch_scale_by<T>(const double*, const T*, T*, size_t, hipStream_t);                              \
+    template void launch_combine<T>(const T*, int, const double*, T*, size_t, hipStream_t);
+
+CD_INST(double)
+CD_INST(float)
+
+template void launch_dot_partial<double, double>(const double*, const double*, size_t, double*, hipStream_t);
+template void launch_dot_partial<float, float>(const float*, const float*, size_t, double*, hipStream_t);
+template void launch_cast<float, double>(const double*, float*, size_t, hipStream_t);
+template void launch_cast<double, float>(const float*, double*, size_t, hipStream_t);
+
+}  // namespace cd

@@ -1,0 +1,130 @@
+// Device data structures and launch wrappers of the curl-div kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+
+namespace cd {
+
+// Operator of one level: 1D banded matrices per axis, stored k-major on the
+// device: for axis a and matrix w (0 = M, 1 = A, 2 = S) the entry (i, i+k-hb)
+// is at band[a][w][k * m[a] + i]; columns outside [0, m) hold zeros.
+template <typename T>
+struct OpDev {
+    const T* band[3][3];
+    int m[3];   // unknowns per axis (m[2] = 1 in 2D)
+    int hb;     // half bandwidth (= p on every level)
+    int dim;
+    T alpha, beta;
+};
+
+// Prolongator tables of one axis (see setup.hpp, Prolong), device copies.
+template <typename T>
+struct XferAxisDev {
+    const int* c0;
+    const T* v;
+    const int* r0;
+    const T* vt;
+    int mf, mc, w, wr;
+};
+
+template <typename T>
+struct XferDev {
+    XferAxisDev<T> ax[3];  // axis 2 of a 2D problem is the identity on 1 point
+    int dim;
+};
+
+// Banded LDL^T factor of T_m(m_{p-1}) for one axis.
+template <typename T>
+struct TFacDev {
+    const T* l;     // l[i*bw + k-1] = L(i, i-k)
+    const T* dinv;  // 1 / D(i)
+    int m, bw;
+};
+
+enum ApplyMode : int {
+    kApplyY = 0,     // y = A x
+    kApplyRes = 1,   // y = b - A x
+    kApplyCheb = 2,  // u = c1 u + c2 D^{-1}(b - A x); xout = x + u
+    kApplyYDot = 3,  // y = A x; part[block] = sum x.y (FP64)
+};
+
+// Partial-sum count used by every reduction of a vector of length n.
+int reduce_blocks(size_t n);
+// Number of partial sums written by the apply kernel in kApplyYDot mode.
+template <typename T>
+int apply_blocks(const OpDev<T>& op);
+
+template <typename T>
+void launch_apply(const OpDev<T>& op, int mode, const T* x, T* y, const T* b, T* u, T* xout, T c1, T c2,
+                  double* part, hipStream_t s);
+
+template <typename T>
+void launch_restrict(const XferDev<T>& X, int ncomp, const T* rf, T* rc, hipStream_t s);
+template <typename T>
+void launch_prolong_add(const XferDev<T>& X, int ncomp, const T* ec, T* xf, hipStream_t s);
+
+template <typename T>
+void launch_tsolve(int dim, const int* m, const TFacDev<T>* fac, T* z, hipStream_t s);
+
+// ---- vector kernels ---------------------------------------------------------
+template <typename TA, typename TB>
+void launch_dot_partial(const TA* a, const TB* b, size_t n, double* part, hipStream_t s);
+// out[0] = sum of part[0..np)
+void launch_finalize(const double* part, int np, double* out, hipStream_t s);
+template <typename TO, typename TI>
+void launch_cast(const TI* x, TO* y, size_t n, hipStream_t s);
+template <typename T>
+void launch_fill(T* x, T v, size_t n, hipStream_t s);
+template <typename T>
+void launch_copy(const T* x, T* y, size_t n, hipStream_t s);
+// y = a x + b y with host scalars
+template <typename T>
+void launch_axpby(T a, const T* x, T b, T* y, size_t n, hipStream_t s);
+// y = x * (1/sqrt(sum part)) (zero if the sum is zero); FP64 partials
+template <typename T>
+void launch_normalize(const double* part, int np, const T* x, T* y, size_t n, hipStream_t s);
+// Diagonal of a level operator: y = x / D (inv = true) or y = x * D.
+template <typename T>
+void launch_diag_scale(const OpDev<T>& op, bool inv, const T* x, T* y, hipStream_t s);
+// part[block] = sum D x^2 (FP64)
+template <typename T>
+void launch_diag_dot(const OpDev<T>& op, const T* x, double* part, hipStream_t s);
+// First Chebyshev step from x = 0: u = D^{-1} b / theta; x = u
+template <typename T>
+void launch_cheb_first(const OpDev<T>& op, const T* b, T* u, T* x, T inv_theta, hipStream_t s);
+
+// ---- coarse level -------------------------------------------------------------
+template <typename T>
+void launch_coarse_gemv(const double* Kinv, int N, const T* r, T* z, hipStream_t s);
+
+// ---- flexible CG (FP64) ---------------------------------------------------------
+// d = z - (sum pzq / *dq_prev) d   (first = true: d = z); pdr[block] = d.r
+void launch_fcg_direction(bool first, const double* z, const double* pzq, int npzq, const double* dq_prev,
+                          double* d, const double* r, double* pdr, size_t n, hipStream_t s);
+// a = sum pdr / sum pdq; x += a d; r -= a q; prr[block] = r.r; *dq_out = sum pdq
+void launch_fcg_update(const double* pdr, int npdr, const double* pdq, int npdq, double* dq_out,
+                       double* x, double* r, const double* d, const double* q, double* prr, size_t n,
+                       hipStream_t s);
+
+// ---- GMRES helpers (vectors of type T, scalars FP64) ----------------------------
+// part[(j)*nb + block] = V_j . w for j < k  (V: k vectors of length n, stride n)
+template <typename T>
+void launch_multidot(const T* V, int k, const T* w, size_t n, double* part, int nb, hipStream_t s);
+// H[j] = sum_b part[j*nb + b], j < k (one small kernel)
+void launch_multifinal(const double* part, int k, int nb, double* H, hipStream_t s);
+// w -= sum_j h[j] V_j
+template <typename T>
+void launch_multiaxpy(const T* V, int k, const double* h, T* w, size_t n, hipStream_t s);
+// v = w / h (h device scalar, zero-guarded)
+template <typename T>
+void launch_scale_by(const double* h, const T* w, T* v, size_t n, hipStream_t s);
+// Least squares min || beta0 e1 - H y || for the (k+1) x k Hessenberg H
+// (column-major, leading dimension ld) by Givens rotations; y[0..k)
+void launch_hessenberg_ls(const double* H, int ld, int k, const double* beta0, double* y, hipStream_t s);
+// w = sum_j y[j] V_j
+template <typename T>
+void launch_combine(const T* V, int k, const double* y, T* w, size_t n, hipStream_t s);
+
+}  // namespace cd

@@ -1,0 +1,974 @@
+// Solver orchestration and the C ABI (include/curldiv.h).
+//
+// One handle = one problem: an FP64 host setup, device copies of the 1D
+// operators of every level (FP64 and FP32), transfer tables, the banded
+// factor of T, the inverse of the coarsest operator, and the device
+// workspace of the V-cycle and of the outer flexible CG.  All device work
+// is queued on the handle's stream; the only host synchronisation in a solve
+// is one 16-byte read per outer iteration (the residual norm and the
+// curvature d^T A d, for the stopping test and breakdown detection).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <functional>
+#include <memory>
+#include <stdexcept>
+#include <string>
+#include <vector>
+
+#include "../../include/curldiv.h"
+#include "kernels.hpp"
+#include "setup.hpp"
+
+namespace cd {
+void launch_normfinal(const double* part, int nb, double* out, hipStream_t s);
+}
+
+namespace {
+
+thread_local std::string g_last_error;
+
+struct CdError : std::runtime_error {
+    int code;
+    CdError(int c, const std::string& m) : std::runtime_error(m), code(c) {}
+};
+
+void hip_check(hipError_t e, const char* what) {
+    if (e != hipSuccess) {
+        if (e == hipErrorOutOfMemory) throw CdError(CD_ENOMEM, std::string(what) + ": out of device memory");
+        throw CdError(CD_EHIP, std::string(what) + ": " + hipGetErrorString(e));
+    }
+}
+
+// Owning list of device allocations.
+struct DevArena {
+    std::vector<void*> ptrs;
+    size_t bytes = 0;
+    template <typename T>
+    T* alloc(size_t n) {
+        void* p = nullptr;
+        const size_t nb = std::max<size_t>(n, 1) * sizeof(T);
+        hip_check(hipMalloc(&p, nb), "hipMalloc");
+        ptrs.push_back(p);
+        bytes += nb;
+        return static_cast<T*>(p);
+    }
+    template <typename T>
+    T* upload(const std::vector<T>& h, hipStream_t s) {
+        T* d = alloc<T>(h.size());
+        if (!h.empty()) hip_check(hipMemcpyAsync(d, h.data(), h.size() * sizeof(T), hipMemcpyHostToDevice, s), "upload");
+        return d;
+    }
+    ~DevArena() {
+        for (void* p : ptrs) (void)hipFree(p);
+    }
+};
+
+template <typename T>
+std::vector<T> convert(const std::vector<double>& v) {
+    return std::vector<T>(v.begin(), v.end());
+}
+
+// k-major band layout of the device: entry (i, i+k-hb) at k*m + i
+std::vector<double> kmajor(const cd::Band& B) {
+    const int w = 2 * B.hb + 1;
+    std::vector<double> out(size_t(w) * B.m);
+    for (int i = 0; i < B.m; ++i)
+        for (int k = 0; k < w; ++k) out[size_t(k) * B.m + i] = B.a[size_t(i) * w + k];
+    return out;
+}
+
+struct LevelHost {
+    int n = 0;       // intervals per axis (knot insertion); 0 for the paper transfer below level 0
+    int m[3] = {1, 1, 1};
+    size_t N = 0;    // unknowns
+    cd::Band M[3], A[3], S[3];
+    cd::Prolong P[3];  // prolongator from the next level (valid if not coarsest)
+    double lam = 0, lo = 0, hi = 0;
+};
+
+template <typename T>
+struct LevelDev {
+    cd::OpDev<T> op{};
+    cd::XferDev<T> xf{};  // from level+1 to this level
+};
+
+// Workspace of a V-cycle in precision T.
+template <typename T>
+struct VWork {
+    struct L {
+        T* b = nullptr;
+        T* xa = nullptr;
+        T* xb = nullptr;
+        T* u = nullptr;
+        T* r = nullptr;
+        T* xcur = nullptr;
+    };
+    std::vector<L> lv;
+    T* V = nullptr;  // finest GMRES basis, (s+1) x N
+    T* w = nullptr;
+    T* z = nullptr;
+    T* io_in = nullptr;   // precision-converted input (mixed mode)
+    double* H = nullptr;  // (s+1) x s column-major
+    double* y = nullptr;
+    double* part = nullptr;  // multidot partials
+    double* scal = nullptr;  // [0] beta0^2
+    int nb = 0;
+};
+
+}  // namespace
+
+struct cd_solver {
+    cd_problem prob{};
+    cd_options opt{};
+    hipStream_t stream = nullptr;
+    int d = 0, p = 0, ksteps = 0;
+    size_t N = 0;
+    std::vector<LevelHost> lv;
+    cd::TFactor tf[3];
+    int Nc = 0;
+
+    DevArena arena;
+    std::vector<LevelDev<double>> ld64;
+    std::vector<LevelDev<float>> ld32;
+    cd::TFacDev<double> tfd64[3]{};
+    cd::TFacDev<float> tfd32[3]{};
+    double* Kinv = nullptr;
+
+    std::unique_ptr<VWork<double>> w64;
+    std::unique_ptr<VWork<float>> w32;
+    std::unique_ptr<DevArena> hook_arena;  // FP64 V-cycle workspace created on demand in mixed mode
+
+    // outer FCG (FP64)
+    double *r = nullptr, *z = nullptr, *dd = nullptr, *q = nullptr;
+    double *pzq = nullptr, *pdr = nullptr, *pdq = nullptr, *prr = nullptr, *scal = nullptr;
+    double* host_scal = nullptr;  // pinned: [0] r.r, [1] d.q
+    int nbr = 0, nba = 0;
+
+    // live timing of operator applies (cd_profile_enable)
+    struct ProfRec {
+        hipEvent_t a, b;
+        int cls;
+        double bytes;
+    };
+    bool prof = false;
+    std::vector<ProfRec> prof_pending;
+    std::vector<std::pair<hipEvent_t, hipEvent_t>> prof_pool;
+    std::vector<cd_kernel_stats> prof_stats;  // index 2*level + fp32
+    ~cd_solver() {
+        for (auto& r : prof_pending) { (void)hipEventDestroy(r.a); (void)hipEventDestroy(r.b); }
+        for (auto& e : prof_pool) { (void)hipEventDestroy(e.first); (void)hipEventDestroy(e.second); }
+    }
+};
+
+namespace {
+
+using cd::kApplyCheb;
+using cd::kApplyRes;
+using cd::kApplyY;
+using cd::kApplyYDot;
+
+void validate(const cd_problem* pr, const cd_options* op) {
+    if (!pr || !op) throw CdError(CD_EINVAL, "null problem or options");
+    if (pr->dim != 2 && pr->dim != 3) throw CdError(CD_EINVAL, "dim must be 2 or 3");
+    if (pr->degree < 1 || pr->degree > 6) throw CdError(CD_EINVAL, "degree must be in 1..6");
+    for (int l = 0; l < pr->dim; ++l)
+        if (pr->n[l] < 1 || pr->n[l] + pr->degree - 2 < 1) throw CdError(CD_EINVAL, "need n >= 1 and n + p - 2 >= 1");
+    if (!(pr->alpha > 0.0) || !(pr->beta > 0.0) || !std::isfinite(pr->alpha) || !std::isfinite(pr->beta))
+        throw CdError(CD_EINVAL, "alpha and beta must be positive and finite");
+    if (op->method != CD_METHOD_PMIM && op->method != CD_METHOD_CG) throw CdError(CD_EINVAL, "unknown method");
+    if (op->transfer != CD_XFER_KNOT && op->transfer != CD_XFER_PAPER) throw CdError(CD_EINVAL, "unknown transfer");
+    if (op->precision != CD_FP64 && op->precision != CD_MIXED_FP32) throw CdError(CD_EINVAL, "unknown precision");
+    if (!(op->rtol > 0.0)) throw CdError(CD_EINVAL, "rtol must be positive");
+    if (op->max_iter < 1) throw CdError(CD_EINVAL, "max_iter must be >= 1");
+    if (op->cheb_degree < 1 || op->cheb_degree > 32) throw CdError(CD_EINVAL, "cheb_degree must be in 1..32");
+    if (!(op->cheb_ratio > 1.0)) throw CdError(CD_EINVAL, "cheb_ratio must be > 1");
+    if (op->power_iters < 1) throw CdError(CD_EINVAL, "power_iters must be >= 1");
+    if (op->krylov_steps > 7) throw CdError(CD_EINVAL, "krylov_steps must be <= 7");
+    if (op->coarse_max_dofs < 1 || op->coarse_max_dofs > 8192)
+        throw CdError(CD_EINVAL, "coarse_max_dofs must be in 1..8192");
+    // the operator kernels keep a plane chunk with a +-p row halo in LDS
+    const int mlast = pr->n[pr->dim - 1] + pr->degree - 2;
+    const size_t lds = (pr->dim == 3) ? 8 * (256 + 2 * size_t(pr->degree) * mlast + 2 * pr->degree + 3 * (256 + 2 * pr->degree))
+                                      : 8 * (2 * (256 + 2 * size_t(pr->degree) * mlast + 2 * pr->degree) + 6 * (256 + 2 * pr->degree));
+    if (lds > 160 * 1024) throw CdError(CD_EINVAL, "grid too large along the last axis for the operator kernel");
+}
+
+size_t level_dofs(int d, const int* m) {
+    size_t G = 1;
+    for (int l = 0; l < d; ++l) G *= size_t(m[l]);
+    return size_t(d) * G;
+}
+
+// Build the host hierarchy (Sec. 6.1: Galerkin coarse operators of the
+// Kronecker form, coarsened until coarse_max_dofs).
+void build_host(cd_solver* s) {
+    const int d = s->d, p = s->p;
+    LevelHost L0;
+    for (int l = 0; l < 3; ++l) L0.m[l] = 1;
+    for (int l = 0; l < d; ++l) {
+        cd::assemble_1d(s->prob.n[l], p, L0.M[l], L0.A[l], L0.S[l]);
+        L0.m[l] = L0.M[l].m;
+    }
+    L0.n = s->prob.n[0];
+    L0.N = level_dofs(d, L0.m);
+    s->lv.clear();
+    s->lv.push_back(std::move(L0));
+    int nl[3] = {s->prob.n[0], s->prob.n[1], d == 3 ? s->prob.n[2] : 1};
+    while (true) {
+        LevelHost& F = s->lv.back();
+        if (F.N <= size_t(s->opt.coarse_max_dofs)) break;
+        bool ok = true;
+        for (int l = 0; l < d; ++l) {
+            if (s->opt.transfer == CD_XFER_KNOT) {
+                if (nl[l] % 2 || nl[l] / 2 + p - 2 < 1) ok = false;
+            } else if (F.m[l] / 2 < 1) {
+                ok = false;
+            }
+        }
+        if (!ok) break;
+        LevelHost C;
+        for (int l = 0; l < 3; ++l) C.m[l] = 1;
+        for (int l = 0; l < d; ++l) {
+            F.P[l] = (s->opt.transfer == CD_XFER_KNOT) ? cd::knot_insertion(nl[l], p) : cd::paper_prolong(F.m[l]);
+            C.M[l] = cd::galerkin(F.M[l], F.P[l]);
+            C.A[l] = cd::galerkin(F.A[l], F.P[l]);
+            C.S[l] = cd::galerkin(F.S[l], F.P[l]);
+            // every level is stored with half bandwidth p (zero padded)
+            if (C.M[l].hb > p || C.A[l].hb > p || C.S[l].hb > p) throw CdError(CD_EINVAL, "coarse band wider than p");
+            C.M[l] = C.M[l].widened(p);
+            C.A[l] = C.A[l].widened(p);
+            C.S[l] = C.S[l].widened(p);
+            C.m[l] = C.M[l].m;
+            if (s->opt.transfer == CD_XFER_KNOT) nl[l] /= 2;
+        }
+        C.n = nl[0];
+        C.N = level_dofs(d, C.m);
+        s->lv.push_back(std::move(C));
+    }
+    for (int l = 0; l < d; ++l) s->tf[l] = cd::toeplitz_factor(s->lv[0].m[l], p);
+    const LevelHost& Lc = s->lv.back();
+    s->Nc = int(Lc.N);
+}
+
+template <typename T>
+cd::OpDev<T> make_op(cd_solver* s, const LevelHost& L, hipStream_t st) {
+    cd::OpDev<T> op{};
+    op.dim = s->d;
+    op.hb = s->p;
+    op.alpha = T(s->prob.alpha);
+    op.beta = T(s->prob.beta);
+    for (int l = 0; l < 3; ++l) op.m[l] = L.m[l];
+    for (int l = 0; l < 3; ++l)
+        for (int w = 0; w < 3; ++w) op.band[l][w] = nullptr;
+    for (int l = 0; l < s->d; ++l) {
+        const cd::Band* mats[3] = {&L.M[l], &L.A[l], &L.S[l]};
+        for (int w = 0; w < 3; ++w) op.band[l][w] = s->arena.upload(convert<T>(kmajor(*mats[w])), st);
+    }
+    if (s->d == 2) {  // unused third axis: a 1x1 identity band keeps pointers valid
+        std::vector<double> id(2 * s->p + 1, 0.0);
+        id[s->p] = 1.0;
+        for (int w = 0; w < 3; ++w) op.band[2][w] = s->arena.upload(convert<T>(id), st);
+    }
+    return op;
+}
+
+template <typename T>
+cd::XferDev<T> make_xfer(cd_solver* s, const LevelHost& L, hipStream_t st) {
+    cd::XferDev<T> X{};
+    X.dim = s->d;
+    for (int l = 0; l < 3; ++l) {
+        cd::XferAxisDev<T>& a = X.ax[l];
+        if (l < s->d) {
+            const cd::Prolong& P = L.P[l];
+            a.mf = P.mf;
+            a.mc = P.mc;
+            a.w = P.w;
+            a.wr = P.wr;
+            a.c0 = s->arena.upload(P.c0, st);
+            a.r0 = s->arena.upload(P.r0, st);
+            a.v = s->arena.upload(convert<T>(P.v), st);
+            a.vt = s->arena.upload(convert<T>(P.vt), st);
+        } else {
+            a.mf = a.mc = a.w = a.wr = 1;
+            a.c0 = s->arena.upload(std::vector<int>{0}, st);
+            a.r0 = s->arena.upload(std::vector<int>{0}, st);
+            a.v = s->arena.upload(std::vector<T>{T(1)}, st);
+            a.vt = s->arena.upload(std::vector<T>{T(1)}, st);
+        }
+    }
+    return X;
+}
+
+template <typename T>
+cd::TFacDev<T> make_tfac(cd_solver* s, const cd::TFactor& F, hipStream_t st) {
+    cd::TFacDev<T> t{};
+    t.m = F.m;
+    t.bw = F.bw;
+    t.l = s->arena.upload(convert<T>(F.l), st);
+    t.dinv = s->arena.upload(convert<T>(F.dinv), st);
+    return t;
+}
+
+template <typename T>
+std::unique_ptr<VWork<T>> make_work(cd_solver* s, DevArena& ar) {
+    auto w = std::make_unique<VWork<T>>();
+    const int L = int(s->lv.size());
+    w->lv.resize(L);
+    for (int l = 0; l < L; ++l) {
+        const size_t n = s->lv[l].N;
+        auto& W = w->lv[l];
+        W.b = ar.alloc<T>(n);
+        W.xa = ar.alloc<T>(n);
+        if (l < L - 1) {
+            W.xb = ar.alloc<T>(n);
+            W.u = ar.alloc<T>(n);
+            W.r = ar.alloc<T>(n);
+        }
+    }
+    const int ks = std::max(s->ksteps, 1);
+    w->V = ar.alloc<T>(size_t(ks + 1) * s->N);
+    w->w = ar.alloc<T>(s->N);
+    w->z = ar.alloc<T>(s->N);
+    w->io_in = ar.alloc<T>(s->N);
+    w->H = ar.alloc<double>(size_t(ks + 1) * ks);
+    w->y = ar.alloc<double>(ks + 1);
+    w->nb = cd::reduce_blocks(s->N);
+    w->part = ar.alloc<double>(size_t(w->nb) * (ks + 2));
+    w->scal = ar.alloc<double>(4);
+    return w;
+}
+
+template <typename T>
+const std::vector<LevelDev<T>>& devlevels(cd_solver* s);
+template <>
+const std::vector<LevelDev<double>>& devlevels<double>(cd_solver* s) { return s->ld64; }
+template <>
+const std::vector<LevelDev<float>>& devlevels<float>(cd_solver* s) { return s->ld32; }
+template <typename T>
+const cd::TFacDev<T>* tfacs(cd_solver* s);
+template <>
+const cd::TFacDev<double>* tfacs<double>(cd_solver* s) { return s->tfd64; }
+template <>
+const cd::TFacDev<float>* tfacs<float>(cd_solver* s) { return s->tfd32; }
+
+// ---- operator apply with optional live timing ---------------------------------------
+template <typename T>
+void apply_op(cd_solver* s, int level, int mode, const T* x, T* y, const T* b, T* u, T* xout, T c1, T c2,
+              double* part) {
+    const cd::OpDev<T>& op = devlevels<T>(s)[level].op;
+    if (!s->prof) {
+        cd::launch_apply<T>(op, mode, x, y, b, u, xout, c1, c2, part, s->stream);
+        return;
+    }
+    std::pair<hipEvent_t, hipEvent_t> ev;
+    if (s->prof_pool.empty()) {
+        hip_check(hipEventCreate(&ev.first), "hipEventCreate");
+        hip_check(hipEventCreate(&ev.second), "hipEventCreate");
+    } else {
+        ev = s->prof_pool.back();
+        s->prof_pool.pop_back();
+    }
+    const double nvec = (mode == kApplyRes) ? 3.0 : (mode == kApplyCheb) ? 5.0 : 2.0;
+    const int cls = 2 * level + (sizeof(T) == 4 ? 1 : 0);
+    hip_check(hipEventRecord(ev.first, s->stream), "hipEventRecord");
+    cd::launch_apply<T>(op, mode, x, y, b, u, xout, c1, c2, part, s->stream);
+    hip_check(hipEventRecord(ev.second, s->stream), "hipEventRecord");
+    s->prof_pending.push_back({ev.first, ev.second, cls, nvec * double(s->lv[level].N) * sizeof(T)});
+}
+
+// Fold finished event pairs into the totals (call after a stream sync).
+void prof_flush(cd_solver* s) {
+    if (s->prof_stats.size() < 2 * s->lv.size()) s->prof_stats.resize(2 * s->lv.size(), cd_kernel_stats{0, 0.0, 0.0});
+    for (auto& r : s->prof_pending) {
+        float ms = 0.f;
+        hip_check(hipEventElapsedTime(&ms, r.a, r.b), "hipEventElapsedTime");
+        cd_kernel_stats& st = s->prof_stats[r.cls];
+        st.launches += 1;
+        st.total_ms += ms;
+        st.bytes += r.bytes;
+        s->prof_pool.push_back({r.a, r.b});
+    }
+    s->prof_pending.clear();
+}
+
+// ---- V-cycle pieces ------------------------------------------------------------
+
+// Chebyshev smoothing on level l (Sec. 6.1 smoother reading): cheb_degree
+// steps on D^{-1} A_l, interval [lo, hi].  Starts from zero when x == nullptr
+// (first step without an operator apply), else from *x; the result pointer
+// is returned (one of the level's two iterate buffers).
+template <typename T>
+T* chebyshev(cd_solver* s, int l, const T* b, T* x, T* other, T* u, bool from_zero) {
+    const LevelHost& L = s->lv[l];
+    const cd::OpDev<T>& op = devlevels<T>(s)[l].op;
+    const double theta = 0.5 * (L.hi + L.lo), delta = 0.5 * (L.hi - L.lo);
+    const double sigma = theta / delta;
+    double rho = 1.0 / sigma;
+    const int nu = s->opt.cheb_degree;
+    T* cur = x;
+    T* nxt = other;
+    if (from_zero) {
+        cd::launch_cheb_first<T>(op, b, u, cur, T(1.0 / theta), s->stream);
+    } else {
+        apply_op<T>(s, l, kApplyCheb, cur, nullptr, b, u, nxt, T(0), T(1.0 / theta), nullptr);
+        std::swap(cur, nxt);
+    }
+    for (int k = 1; k < nu; ++k) {
+        const double rn = 1.0 / (2.0 * sigma - rho);
+        apply_op<T>(s, l, kApplyCheb, cur, nullptr, b, u, nxt, T(rn * rho), T(2.0 * rn / delta), nullptr);
+        std::swap(cur, nxt);
+        rho = rn;
+    }
+    return cur;
+}
+
+// p steps of GMRES on A_0 e = b - A_0 x from e = 0, right preconditioner T
+// (Sec. 6.1 post-smoother), classical Gram-Schmidt; x += T^{-1} V y.
+template <typename T>
+void gmres_post(cd_solver* s, VWork<T>& W, const T* b, T* x) {
+    const cd::OpDev<T>& op = devlevels<T>(s)[0].op;
+    const size_t N = s->N;
+    const int ks = s->ksteps, ld = ks + 1, nb = W.nb;
+    hipStream_t st = s->stream;
+    T* V = W.V;
+    apply_op<T>(s, 0, kApplyRes, x, W.w, b, nullptr, nullptr, T(0), T(0), nullptr);
+    cd::launch_dot_partial<T, T>(W.w, W.w, N, W.part, st);
+    cd::launch_finalize(W.part, nb, W.scal, st);
+    cd::launch_normalize<T>(W.part, nb, W.w, V, N, st);
+    for (int j = 0; j < ks; ++j) {
+        cd::launch_copy<T>(V + size_t(j) * N, W.z, N, st);
+        cd::launch_tsolve<T>(s->d, s->lv[0].m, tfacs<T>(s), W.z, st);
+        apply_op<T>(s, 0, kApplyY, W.z, W.w, nullptr, nullptr, nullptr, T(0), T(0), nullptr);
+        cd::launch_multidot<T>(V, j + 1, W.w, N, W.part, nb, st);
+        cd::launch_multifinal(W.part, j + 1, nb, W.H + size_t(j) * ld, st);
+        cd::launch_multiaxpy<T>(V, j + 1, W.H + size_t(j) * ld, W.w, N, st);
+        cd::launch_dot_partial<T, T>(W.w, W.w, N, W.part, st);
+        cd::launch_normfinal(W.part, nb, W.H + size_t(j) * ld + (j + 1), st);
+        cd::launch_scale_by<T>(W.H + size_t(j) * ld + (j + 1), W.w, V + size_t(j + 1) * N, N, st);
+    }
+    cd::launch_hessenberg_ls(W.H, ld, ks, W.scal, W.y, st);
+    cd::launch_combine<T>(V, ks, W.y, W.w, N, st);
+    cd::launch_tsolve<T>(s->d, s->lv[0].m, tfacs<T>(s), W.w, st);
+    cd::launch_axpby<T>(T(1), W.w, T(1), x, N, st);
+}
+
+// One V-cycle on level l for A_l x = W.lv[l].b; result in W.lv[l].xcur.
+template <typename T>
+void vcycle(cd_solver* s, VWork<T>& W, int l) {
+    const int L = int(s->lv.size());
+    auto& Wl = W.lv[l];
+    hipStream_t st = s->stream;
+    if (l == L - 1) {
+        cd::launch_coarse_gemv<T>(s->Kinv, s->Nc, Wl.b, Wl.xa, st);
+        Wl.xcur = Wl.xa;
+        return;
+    }
+    const auto& D = devlevels<T>(s)[l];
+    T* x = chebyshev<T>(s, l, Wl.b, Wl.xa, Wl.xb, Wl.u, true);
+    T* other = (x == Wl.xa) ? Wl.xb : Wl.xa;
+    apply_op<T>(s, l, kApplyRes, x, Wl.r, Wl.b, nullptr, nullptr, T(0), T(0), nullptr);
+    cd::launch_restrict<T>(D.xf, s->d, Wl.r, W.lv[l + 1].b, st);
+    vcycle<T>(s, W, l + 1);
+    cd::launch_prolong_add<T>(D.xf, s->d, W.lv[l + 1].xcur, x, st);
+    if (l == 0 && s->ksteps > 0) {
+        gmres_post<T>(s, W, Wl.b, x);
+    } else {
+        x = chebyshev<T>(s, l, Wl.b, x, other, Wl.u, false);
+    }
+    Wl.xcur = x;
+}
+
+VWork<double>& work64(cd_solver* s) {
+    if (!s->w64) {
+        s->hook_arena = std::make_unique<DevArena>();
+        s->w64 = make_work<double>(s, *s->hook_arena);
+    }
+    return *s->w64;
+}
+
+// z = V(r) in the handle's precision; r, z FP64 device vectors.
+void precondition(cd_solver* s, const double* r, double* z) {
+    hipStream_t st = s->stream;
+    if (s->opt.precision == CD_FP64) {
+        VWork<double>& W = work64(s);
+        cd::launch_copy<double>(r, W.lv[0].b, s->N, st);
+        vcycle<double>(s, W, 0);
+        cd::launch_copy<double>(W.lv[0].xcur, z, s->N, st);
+    } else {
+        VWork<float>& W = *s->w32;
+        cd::launch_cast<float, double>(r, W.lv[0].b, s->N, st);
+        vcycle<float>(s, W, 0);
+        cd::launch_cast<double, float>(W.lv[0].xcur, z, s->N, st);
+    }
+}
+
+// Smoother eigenvalue bounds: power method on D^{-1} A_l from
+// v0 = (-1)^{i_1+...+i_d}, then the pencil Rayleigh quotient.
+void estimate_bounds(cd_solver* s) {
+    hipStream_t st = s->stream;
+    const int L = int(s->lv.size());
+    DevArena tmp;
+    double* v = tmp.alloc<double>(s->N);
+    double* w = tmp.alloc<double>(s->N);
+    const int nbmax = std::max(cd::reduce_blocks(s->N), cd::apply_blocks<double>(s->ld64[0].op));
+    double* part = tmp.alloc<double>(nbmax);
+    double* res = tmp.alloc<double>(2);
+    for (int l = 0; l < L - 1; ++l) {
+        LevelHost& H = s->lv[l];
+        const cd::OpDev<double>& op = s->ld64[l].op;
+        const size_t n = H.N;
+        std::vector<double> v0(n);
+        const int m0 = H.m[0], m1 = H.m[1], m2 = H.m[2];
+        const size_t G = size_t(m0) * m1 * m2;
+        for (size_t id = 0; id < n; ++id) {
+            size_t rem = id % G;
+            const int i2 = int(rem % m2);
+            rem /= m2;
+            const int i1 = int(rem % m1);
+            const int i0 = int(rem / m1);
+            v0[id] = ((i0 + i1 + i2) % 2 == 0) ? 1.0 : -1.0;
+        }
+        hip_check(hipMemcpyAsync(v, v0.data(), n * sizeof(double), hipMemcpyHostToDevice, st), "upload v0");
+        const int nbr = cd::reduce_blocks(n);
+        for (int it = 0; it < s->opt.power_iters; ++it) {
+            cd::launch_apply<double>(op, kApplyY, v, w, nullptr, nullptr, nullptr, 0.0, 0.0, nullptr, st);
+            cd::launch_diag_scale<double>(op, true, w, w, st);
+            cd::launch_dot_partial<double, double>(w, w, n, part, st);
+            cd::launch_normalize<double>(part, nbr, w, v, n, st);
+        }
+        cd::launch_apply<double>(op, kApplyYDot, v, w, nullptr, nullptr, nullptr, 0.0, 0.0, part, st);
+        cd::launch_finalize(part, cd::apply_blocks<double>(op), res, st);
+        cd::launch_diag_dot<double>(op, v, part, st);
+        cd::launch_finalize(part, nbr, res + 1, st);
+        double h[2];
+        hip_check(hipMemcpyAsync(h, res, 2 * sizeof(double), hipMemcpyDeviceToHost, st), "read bounds");
+        hip_check(hipStreamSynchronize(st), "sync");
+        if (!(h[0] > 0.0) || !(h[1] > 0.0)) throw CdError(CD_EINVAL, "operator is not positive definite");
+        H.lam = h[0] / h[1];
+        H.hi = 1.1 * H.lam;
+        H.lo = H.hi / s->opt.cheb_ratio;
+    }
+}
+
+void create(cd_solver* s, const cd_problem* pr, const cd_options* op, void* stream) {
+    validate(pr, op);
+    s->prob = *pr;
+    s->opt = *op;
+    if (s->prob.dim == 2) s->prob.n[2] = 1;
+    s->stream = static_cast<hipStream_t>(stream);
+    s->d = pr->dim;
+    s->p = pr->degree;
+    s->ksteps = (op->krylov_steps < 0) ? pr->degree : op->krylov_steps;
+    build_host(s);
+    s->N = s->lv[0].N;
+    hipStream_t st = s->stream;
+    const int L = int(s->lv.size());
+    for (int l = 0; l < L; ++l) {
+        LevelDev<double> a;
+        LevelDev<float> b;
+        a.op = make_op<double>(s, s->lv[l], st);
+        b.op = make_op<float>(s, s->lv[l], st);
+        if (l < L - 1) {
+            a.xf = make_xfer<double>(s, s->lv[l], st);
+            b.xf = make_xfer<float>(s, s->lv[l], st);
+        }
+        s->ld64.push_back(a);
+        s->ld32.push_back(b);
+    }
+    for (int l = 0; l < s->d; ++l) {
+        s->tfd64[l] = make_tfac<double>(s, s->tf[l], st);
+        s->tfd32[l] = make_tfac<float>(s, s->tf[l], st);
+    }
+    // coarse level: dense operator and its inverse (FP64)
+    {
+        const LevelHost& C = s->lv.back();
+        std::vector<double> K = cd::dense_operator(s->d, C.m, C.M, C.A, C.S, s->prob.alpha, s->prob.beta);
+        if (!cd::spd_inverse(K, s->Nc)) throw CdError(CD_EINVAL, "coarse operator is not positive definite");
+        s->Kinv = s->arena.upload(K, st);
+        hip_check(hipStreamSynchronize(st), "sync");
+    }
+    // outer vectors
+    const size_t N = s->N;
+    s->r = s->arena.alloc<double>(N);
+    s->z = s->arena.alloc<double>(N);
+    s->dd = s->arena.alloc<double>(N);
+    s->q = s->arena.alloc<double>(N);
+    s->nbr = cd::reduce_blocks(N);
+    s->nba = cd::apply_blocks<double>(s->ld64[0].op);
+    s->pzq = s->arena.alloc<double>(s->nbr);
+    s->pdr = s->arena.alloc<double>(s->nbr);
+    s->prr = s->arena.alloc<double>(s->nbr);
+    s->pdq = s->arena.alloc<double>(std::max(s->nba, s->nbr));
+    s->scal = s->arena.alloc<double>(4);
+    void* hp = nullptr;
+    hip_check(hipHostMalloc(&hp, 4 * sizeof(double), hipHostMallocDefault), "hipHostMalloc");
+    s->host_scal = static_cast<double*>(hp);
+    if (L > 1 && op->method == CD_METHOD_PMIM) estimate_bounds(s);
+    if (op->method == CD_METHOD_PMIM) {
+        if (op->precision == CD_FP64) {
+            s->w64 = make_work<double>(s, s->arena);
+        } else {
+            s->w32 = make_work<float>(s, s->arena);
+        }
+    }
+    hip_check(hipStreamSynchronize(st), "sync");
+}
+
+void solve(cd_solver* s, const double* b, double* x, cd_result* res) {
+    hipStream_t st = s->stream;
+    const size_t N = s->N;
+    cd_result out{};
+    cd::launch_fill<double>(x, 0.0, N, st);
+    cd::launch_copy<double>(b, s->r, N, st);
+    cd::launch_dot_partial<double, double>(s->r, s->r, N, s->prr, st);
+    cd::launch_finalize(s->prr, s->nbr, s->scal, st);
+    hip_check(hipMemcpyAsync(s->host_scal, s->scal, sizeof(double), hipMemcpyDeviceToHost, st), "read");
+    hip_check(hipStreamSynchronize(st), "sync");
+    const double rr0 = s->host_scal[0];
+    if (!std::isfinite(rr0)) throw CdError(CD_EINVAL, "right-hand side is not finite");
+    if (rr0 == 0.0) {
+        out.status = CD_OK;
+        if (res) *res = out;
+        return;
+    }
+    const double r0 = std::sqrt(rr0);
+    const cd::OpDev<double>& op = s->ld64[0].op;
+    int status = CD_NOT_CONVERGED;
+    int k = 0;
+    double rel = 1.0;
+    while (k < s->opt.max_iter) {
+        if (s->opt.method == CD_METHOD_CG) {
+            cd::launch_copy<double>(s->r, s->z, N, st);
+        } else {
+            precondition(s, s->r, s->z);
+        }
+        if (k > 0) cd::launch_dot_partial<double, double>(s->z, s->q, N, s->pzq, st);
+        cd::launch_fcg_direction(k == 0, s->z, s->pzq, s->nbr, s->scal + 1, s->dd, s->r, s->pdr, N, st);
+        apply_op<double>(s, 0, kApplyYDot, s->dd, s->q, nullptr, nullptr, nullptr, 0.0, 0.0, s->pdq);
+        cd::launch_fcg_update(s->pdr, s->nbr, s->pdq, s->nba, s->scal + 1, x, s->r, s->dd, s->q, s->prr, N, st);
+        cd::launch_finalize(s->prr, s->nbr, s->scal, st);
+        hip_check(hipMemcpyAsync(s->host_scal, s->scal, 2 * sizeof(double), hipMemcpyDeviceToHost, st), "read");
+        hip_check(hipStreamSynchronize(st), "sync");
+        if (s->prof) prof_flush(s);
+        ++k;
+        const double rr = s->host_scal[0], dq = s->host_scal[1];
+        if (!std::isfinite(rr) || !std::isfinite(dq) || !(dq > 0.0)) {
+            status = CD_EBREAKDOWN;
+            rel = std::sqrt(rr) / r0;
+            break;
+        }
+        rel = std::sqrt(rr) / r0;
+        if (rel < s->opt.rtol) {
+            status = CD_OK;
+            break;
+        }
+    }
+    // true residual in FP64
+    cd::launch_apply<double>(op, kApplyRes, x, s->z, b, nullptr, nullptr, 0.0, 0.0, nullptr, st);
+    cd::launch_dot_partial<double, double>(s->z, s->z, N, s->prr, st);
+    cd::launch_finalize(s->prr, s->nbr, s->scal + 2, st);
+    hip_check(hipMemcpyAsync(s->host_scal + 2, s->scal + 2, sizeof(double), hipMemcpyDeviceToHost, st), "read");
+    hip_check(hipStreamSynchronize(st), "sync");
+    out.status = status;
+    out.iterations = k;
+    out.rel_residual = rel;
+    out.true_rel_residual = std::sqrt(s->host_scal[2]) / r0;
+    if (res) *res = out;
+    if (status == CD_EBREAKDOWN) throw CdError(CD_EBREAKDOWN, "Krylov breakdown (d^T A d <= 0 or non-finite)");
+}
+
+}  // namespace
+
+// ================================== C ABI ==================================
+
+namespace {
+int run(const std::function<void()>& f) {
+    try {
+        f();
+        return CD_OK;
+    } catch (const CdError& e) {
+        g_last_error = e.what();
+        return e.code;
+    } catch (const std::bad_alloc&) {
+        g_last_error = "host allocation failed";
+        return CD_ENOMEM;
+    } catch (const std::exception& e) {
+        g_last_error = e.what();
+        return CD_EHIP;
+    }
+}
+
+void need(const cd_solver* s) {
+    if (!s) throw CdError(CD_EINVAL, "null solver handle");
+}
+void need_level(const cd_solver* s, int l) {
+    need(s);
+    if (l < 0 || l >= int(s->lv.size())) throw CdError(CD_EINVAL, "level out of range");
+}
+}  // namespace
+
+extern "C" {
+
+void cd_default_options(cd_options* o) {
+    if (!o) return;
+    o->method = CD_METHOD_PMIM;
+    o->transfer = CD_XFER_KNOT;
+    o->precision = CD_FP64;
+    o->rtol = 1e-8;
+    o->max_iter = 10000;
+    o->coarse_max_dofs = 1000;
+    o->cheb_degree = 3;
+    o->cheb_ratio = 30.0;
+    o->power_iters = 10;
+    o->krylov_steps = -1;
+}
+
+size_t cd_num_dofs(const cd_problem* pr) {
+    if (!pr || (pr->dim != 2 && pr->dim != 3) || pr->degree < 1) return 0;
+    size_t G = 1;
+    for (int l = 0; l < pr->dim; ++l) {
+        const int m = pr->n[l] + pr->degree - 2;
+        if (pr->n[l] < 1 || m < 1) return 0;
+        G *= size_t(m);
+    }
+    return size_t(pr->dim) * G;
+}
+
+int cd_validate(const cd_problem* pr, const cd_options* op) {
+    return run([&] { validate(pr, op); });
+}
+
+size_t cd_footprint_bytes(const cd_problem* pr, const cd_options* op) {
+    size_t total = 0;
+    int rc = run([&] {
+        validate(pr, op);
+        cd_solver tmp;
+        tmp.prob = *pr;
+        tmp.opt = *op;
+        tmp.d = pr->dim;
+        tmp.p = pr->degree;
+        tmp.ksteps = (op->krylov_steps < 0) ? pr->degree : op->krylov_steps;
+        if (tmp.prob.dim == 2) tmp.prob.n[2] = 1;
+        build_host(&tmp);
+        const size_t N = tmp.lv[0].N;
+        const size_t es = (op->precision == CD_FP64) ? 8 : 4;
+        size_t vw = 0;
+        for (size_t l = 0; l < tmp.lv.size(); ++l) vw += tmp.lv[l].N * ((l + 1 < tmp.lv.size()) ? 5 : 2);
+        vw += N * (size_t(std::max(tmp.ksteps, 1)) + 4);
+        total = 4 * N * 8                                   // outer r, z, d, q
+                + (op->method == CD_METHOD_PMIM ? vw * es : 0)  // V-cycle workspace
+                + size_t(tmp.Nc) * tmp.Nc * 8                // coarse inverse
+                + (1 << 20);                                 // 1D tables and partial sums
+    });
+    return rc == CD_OK ? total : 0;
+}
+
+int cd_solver_create(const cd_problem* prob, const cd_options* opt, void* stream, cd_solver** out) {
+    if (!out) {
+        g_last_error = "null output pointer";
+        return CD_EINVAL;
+    }
+    *out = nullptr;
+    cd_solver* s = new (std::nothrow) cd_solver();
+    if (!s) return CD_ENOMEM;
+    const int rc = run([&] { create(s, prob, opt, stream); });
+    if (rc != CD_OK) {
+        cd_solver_destroy(s);
+        return rc;
+    }
+    *out = s;
+    return CD_OK;
+}
+
+void cd_solver_destroy(cd_solver* s) {
+    if (!s) return;
+    (void)hipStreamSynchronize(s->stream);
+    if (s->host_scal) (void)hipHostFree(s->host_scal);
+    delete s;
+}
+
+int cd_solve(cd_solver* s, const double* b, double* x, cd_result* res) {
+    if (res) std::memset(res, 0, sizeof(*res));
+    int st = CD_OK;
+    const int rc = run([&] {
+        need(s);
+        if (!b || !x) throw CdError(CD_EINVAL, "null vector");
+        cd_result r{};
+        solve(s, b, x, &r);
+        st = r.status;
+        if (res) *res = r;
+    });
+    if (rc != CD_OK) {
+        if (res) res->status = rc;
+        return rc;
+    }
+    return st;
+}
+
+int cd_num_levels(const cd_solver* s) { return s ? int(s->lv.size()) : 0; }
+
+int cd_level_shape(const cd_solver* s, int level, int* m3, size_t* ndofs) {
+    return run([&] {
+        need_level(s, level);
+        if (m3)
+            for (int l = 0; l < 3; ++l) m3[l] = s->lv[level].m[l];
+        if (ndofs) *ndofs = s->lv[level].N;
+    });
+}
+
+int cd_get_matrix(const cd_solver* s, int level, int axis, char which, double* out) {
+    return run([&] {
+        need_level(s, level);
+        if (axis < 0 || axis >= s->d) throw CdError(CD_EINVAL, "axis out of range");
+        if (!out) throw CdError(CD_EINVAL, "null output");
+        const LevelHost& L = s->lv[level];
+        const int m = L.m[axis];
+        if (which == 'M' || which == 'A' || which == 'S') {
+            const cd::Band& B = (which == 'M') ? L.M[axis] : (which == 'A') ? L.A[axis] : L.S[axis];
+            for (int i = 0; i < m; ++i)
+                for (int j = 0; j < m; ++j) out[size_t(i) * m + j] = B.get(i, j);
+        } else if (which == 'T') {
+            if (level != 0) throw CdError(CD_EINVAL, "T exists on level 0 only");
+            const cd::Band& B = s->tf[axis].T;
+            for (int i = 0; i < m; ++i)
+                for (int j = 0; j < m; ++j) out[size_t(i) * m + j] = B.get(i, j);
+        } else if (which == 'P') {
+            if (level + 1 >= int(s->lv.size())) throw CdError(CD_EINVAL, "coarsest level has no prolongator");
+            const cd::Prolong& P = L.P[axis];
+            for (int i = 0; i < P.mf; ++i)
+                for (int j = 0; j < P.mc; ++j) out[size_t(i) * P.mc + j] = P.get(i, j);
+        } else {
+            throw CdError(CD_EINVAL, "which must be one of M, A, S, T, P");
+        }
+    });
+}
+
+int cd_get_lambda(const cd_solver* s, int level, double* lam) {
+    return run([&] {
+        need_level(s, level);
+        if (level == int(s->lv.size()) - 1) throw CdError(CD_EINVAL, "coarsest level has no smoother");
+        if (lam) *lam = s->lv[level].lam;
+    });
+}
+
+int cd_apply(cd_solver* s, int level, const double* x, double* y) {
+    return run([&] {
+        need_level(s, level);
+        apply_op<double>(s, level, kApplyY, x, y, nullptr, nullptr, nullptr, 0.0, 0.0, nullptr);
+        hip_check(hipStreamSynchronize(s->stream), "sync");
+        if (s->prof) prof_flush(s);
+    });
+}
+
+int cd_apply_f32(cd_solver* s, int level, const float* x, float* y) {
+    return run([&] {
+        need_level(s, level);
+        apply_op<float>(s, level, kApplyY, x, y, nullptr, nullptr, nullptr, 0.f, 0.f, nullptr);
+        hip_check(hipStreamSynchronize(s->stream), "sync");
+        if (s->prof) prof_flush(s);
+    });
+}
+
+int cd_smooth(cd_solver* s, int level, const double* b, const double* x_in, double* x_out) {
+    return run([&] {
+        need_level(s, level);
+        if (level == int(s->lv.size()) - 1) throw CdError(CD_EINVAL, "coarsest level has no smoother");
+        if (s->opt.method != CD_METHOD_PMIM) throw CdError(CD_EINVAL, "no smoother for plain CG");
+        VWork<double>& W = work64(s);
+        auto& Wl = W.lv[level];
+        const size_t n = s->lv[level].N;
+        cd::launch_copy<double>(b, Wl.b, n, s->stream);
+        cd::launch_copy<double>(x_in, Wl.xa, n, s->stream);
+        double* r = chebyshev<double>(s, level, Wl.b, Wl.xa, Wl.xb, Wl.u, false);
+        cd::launch_copy<double>(r, x_out, n, s->stream);
+        hip_check(hipStreamSynchronize(s->stream), "sync");
+    });
+}
+
+int cd_restrict(cd_solver* s, int level, const double* rf, double* rc) {
+    return run([&] {
+        need_level(s, level);
+        if (level == int(s->lv.size()) - 1) throw CdError(CD_EINVAL, "coarsest level");
+        cd::launch_restrict<double>(s->ld64[level].xf, s->d, rf, rc, s->stream);
+        hip_check(hipStreamSynchronize(s->stream), "sync");
+    });
+}
+
+int cd_prolong_add(cd_solver* s, int level, const double* ec, double* xf) {
+    return run([&] {
+        need_level(s, level);
+        if (level == int(s->lv.size()) - 1) throw CdError(CD_EINVAL, "coarsest level");
+        cd::launch_prolong_add<double>(s->ld64[level].xf, s->d, ec, xf, s->stream);
+        hip_check(hipStreamSynchronize(s->stream), "sync");
+    });
+}
+
+int cd_tsolve(cd_solver* s, const double* v, double* z) {
+    return run([&] {
+        need(s);
+        if (v != z) cd::launch_copy<double>(v, z, s->N, s->stream);
+        cd::launch_tsolve<double>(s->d, s->lv[0].m, s->tfd64, z, s->stream);
+        hip_check(hipStreamSynchronize(s->stream), "sync");
+    });
+}
+
+int cd_coarse_solve(cd_solver* s, const double* r, double* z) {
+    return run([&] {
+        need(s);
+        cd::launch_coarse_gemv<double>(s->Kinv, s->Nc, r, z, s->stream);
+        hip_check(hipStreamSynchronize(s->stream), "sync");
+    });
+}
+
+int cd_precondition(cd_solver* s, const double* r, double* z) {
+    return run([&] {
+        need(s);
+        if (s->opt.method != CD_METHOD_PMIM) throw CdError(CD_EINVAL, "plain CG has no preconditioner");
+        if (s->lv.size() == 1) {
+            cd::launch_coarse_gemv<double>(s->Kinv, s->Nc, r, z, s->stream);
+        } else {
+            precondition(s, r, z);
+        }
+        hip_check(hipStreamSynchronize(s->stream), "sync");
+    });
+}
+
+int cd_profile_enable(cd_solver* s, int on) {
+    return run([&] {
+        need(s);
+        hip_check(hipStreamSynchronize(s->stream), "sync");
+        prof_flush(s);
+        s->prof = (on != 0);
+        if (s->prof) s->prof_stats.assign(2 * s->lv.size(), cd_kernel_stats{0, 0.0, 0.0});
+    });
+}
+
+int cd_profile_read(const cd_solver* s, int level, int fp32, cd_kernel_stats* out) {
+    return run([&] {
+        need_level(s, level);
+        if (!out) throw CdError(CD_EINVAL, "null output");
+        const size_t k = size_t(2 * level + (fp32 ? 1 : 0));
+        *out = (k < s->prof_stats.size()) ? s->prof_stats[k] : cd_kernel_stats{0, 0.0, 0.0};
+    });
+}
+
+const char* cd_status_string(int st) {
+    switch (st) {
+        case CD_OK: return "converged";
+        case CD_NOT_CONVERGED: return "maximum number of iterations reached";
+        case CD_EINVAL: return "invalid argument";
+        case CD_ENOMEM: return "out of memory";
+        case CD_EBREAKDOWN: return "Krylov breakdown";
+        case CD_EHIP: return "HIP runtime error";
+        case CD_EAGAIN: return "request queued";
+        case CD_ENOTFOUND: return "unknown ticket";
+        default: return "unknown status";
+    }
+}
+
+const char* cd_last_error(void) { return g_last_error.c_str(); }
+
+}  // extern "C"

@@ -1,0 +1,265 @@
+"""GPU parity tests: every kernel of libcurldiv (through the C ABI) against the
+FP64 oracle on the same seeded inputs.
+
+Tolerances: linear maps in FP64 to 1e-12 relative (the operator, transfers,
+T-solve, coarse solve, one smoother application), whole V-cycles to 1e-10
+relative (the GMRES post-smoother's least-squares step amplifies rounding
+by the conditioning of its small Hessenberg problem), FP32 operator applies
+to 2e-5 relative (FP32 rounding of 2p+1-term sums across three axes).
+"""
+import numpy as np
+import pytest
+
+from tests.gpu_util import dev, empty, gpu_ok, host, relerr, stream, torch
+
+pytestmark = pytest.mark.gpu
+
+if not gpu_ok():  # collected on CPU with -m "not gpu" deselected anyway
+    pytest.skip("no GPU", allow_module_level=True)
+
+from oracle import assembly as asm  # noqa: E402
+from oracle import loadvec, method, solvers  # noqa: E402
+from oracle import matrices as mt  # noqa: E402
+from paper_1805_10058_amd import capi  # noqa: E402
+
+# (dim, p, n, beta, transfer, coarse_max): sizes span several tiles with ragged tails
+CASES = [
+    (2, 1, 20, 0.3, "knot", 60),
+    (2, 2, 40, 0.05, "knot", 100),
+    (2, 3, 64, 1e-2, "knot", 300),
+    (2, 4, 24, 0.5, "paper", 80),
+    (2, 6, 18, 0.1, "knot", 400),
+    (3, 1, 12, 0.2, "knot", 400),
+    (3, 2, 20, 0.1, "knot", 500),
+    (3, 3, 16, 0.01, "knot", 700),
+    (3, 4, 10, 1.0, "paper", 600),
+    (3, 6, 8, 0.3, "knot", 2000),
+]
+IDS = [f"d{c[0]}p{c[1]}n{c[2]}b{c[3]}{c[4]}" for c in CASES]
+
+_cache = {}
+
+
+def setup_case(case, precision=capi.CD_FP64, **kw):
+    d, p, n, beta, xfer, cmax = case
+    key = (case, precision, tuple(sorted(kw.items())))
+    if key not in _cache:
+        tr = capi.CD_XFER_KNOT if xfer == "knot" else capi.CD_XFER_PAPER
+        opt = capi.options(transfer=tr, coarse_max_dofs=cmax, precision=precision, **kw)
+        s = capi.Solver(capi.problem(d, p, n, 1.0, beta), opt, stream())
+        m = method.Method(d, p, n, 1.0, beta, transfer=xfer, coarse_max_dofs=cmax,
+                          nu=opt.cheb_degree, ratio=opt.cheb_ratio, power_iters=opt.power_iters,
+                          krylov_steps=None if opt.krylov_steps < 0 else opt.krylov_steps)
+        _cache[key] = (s, m)
+    return _cache[key]
+
+
+@pytest.mark.parametrize("case", CASES, ids=IDS)
+def test_setup_matrices(case):
+    s, m = setup_case(case)
+    assert s.num_levels() == len(m.levels)
+    d = case[0]
+    for l, L in enumerate(m.levels):
+        shape, ndofs = s.level_shape(l)
+        assert ndofs == L.K.shape[0]
+        assert shape[:d] == (L.m,) * d
+        for ax in range(d):
+            for w, X in (("M", L.M), ("A", L.A), ("S", L.S)):
+                G = np.array(s.get_matrix(l, ax, w, L.m, L.m)).reshape(L.m, L.m)
+                assert np.abs(G - X).max() <= 1e-13 * max(1.0, np.abs(X).max()), (l, ax, w)
+            if L.P is not None:
+                G = np.array(s.get_matrix(l, ax, "P", L.P.shape[0], L.P.shape[1])).reshape(L.P.shape)
+                assert np.abs(G - L.P).max() <= 1e-13
+    T = np.array(s.get_matrix(0, 0, "T", m.levels[0].m, m.levels[0].m)).reshape(m.levels[0].m, -1)
+    assert np.abs(T - mt.toeplitz_T(m.levels[0].m, case[1])).max() <= 1e-15
+
+
+@pytest.mark.parametrize("case", CASES, ids=IDS)
+def test_apply_every_level_fp64(case):
+    s, m = setup_case(case)
+    rng = np.random.default_rng(1)
+    for l, L in enumerate(m.levels):
+        x = rng.uniform(-1, 1, L.K.shape[0])
+        xd, y = dev(x), empty(L.K.shape[0])
+        s.apply(l, xd.data_ptr(), y.data_ptr())
+        assert relerr(host(y), L.K @ x) <= 1e-12, l
+
+
+@pytest.mark.parametrize("case", CASES, ids=IDS)
+def test_apply_fp32(case):
+    s, m = setup_case(case)
+    rng = np.random.default_rng(2)
+    L = m.levels[0]
+    x = rng.uniform(-1, 1, L.K.shape[0]).astype(np.float32)
+    xd, y = dev(x, torch.float32), empty(L.K.shape[0], torch.float32)
+    s.apply_f32(0, xd.data_ptr(), y.data_ptr())
+    assert relerr(host(y), L.K @ x.astype(np.float64)) <= 2e-5
+
+
+@pytest.mark.parametrize("case", CASES, ids=IDS)
+def test_transfers(case):
+    s, m = setup_case(case)
+    d = case[0]
+    rng = np.random.default_rng(3)
+    for l in range(len(m.levels) - 1):
+        Pb = m._prolong_block(l)
+        rf = rng.uniform(-1, 1, Pb.shape[0])
+        rfd, rc = dev(rf), empty(Pb.shape[1])
+        s.restrict(l, rfd.data_ptr(), rc.data_ptr())
+        assert relerr(host(rc), Pb.T @ rf) <= 1e-13
+        ec = rng.uniform(-1, 1, Pb.shape[1])
+        x0 = rng.uniform(-1, 1, Pb.shape[0])
+        xt, ecd = dev(x0), dev(ec)
+        s.prolong_add(l, ecd.data_ptr(), xt.data_ptr())
+        assert relerr(host(xt), x0 + Pb @ ec) <= 1e-13
+    assert d in (2, 3)
+
+
+@pytest.mark.parametrize("case", CASES, ids=IDS)
+def test_tsolve(case):
+    s, m = setup_case(case)
+    rng = np.random.default_rng(4)
+    v = rng.uniform(-1, 1, m.K.shape[0])
+    vd, z = dev(v), empty(m.K.shape[0])
+    s.tsolve(vd.data_ptr(), z.data_ptr())
+    # backward-stable banded solves: error <= c kappa(T) u, kappa(T) <= (pi/2)^(2(p-1))
+    kappa = (np.pi / 2) ** (2 * (case[1] - 1))
+    assert relerr(host(z), m.Tsolve(v)) <= 1e-13 * max(1.0, kappa)
+
+
+@pytest.mark.parametrize("case", CASES, ids=IDS)
+def test_coarse_solve(case):
+    s, m = setup_case(case)
+    C = m.levels[-1]
+    r = np.random.default_rng(5).uniform(-1, 1, C.K.shape[0])
+    rd, z = dev(r), empty(C.K.shape[0])
+    s.coarse_solve(rd.data_ptr(), z.data_ptr())
+    # explicit inverse (GPU) vs LU solve (oracle): both backward stable, so they
+    # agree to a small multiple of kappa(K_c) u
+    Kd = C.K.toarray()
+    kappa = np.linalg.cond(Kd)
+    assert relerr(host(z), np.linalg.solve(Kd, r)) <= max(1e-13, 50 * kappa * 2.2e-16)
+
+
+@pytest.mark.parametrize("case", CASES, ids=IDS)
+def test_smoother_and_eigenvalue_bound(case):
+    s, m = setup_case(case)
+    rng = np.random.default_rng(6)
+    for l, L in enumerate(m.levels[:-1]):
+        # both sides compute the bound from the same definition (power method from
+        # the same start vector), independently
+        assert abs(s.get_lambda(l) - L.lam) <= 1e-10 * L.lam
+        b = rng.uniform(-1, 1, L.K.shape[0])
+        x0 = rng.uniform(-1, 1, L.K.shape[0])
+        bd, xd, out = dev(b), dev(x0), empty(L.K.shape[0])
+        s.smooth(l, bd.data_ptr(), xd.data_ptr(), out.data_ptr())
+        assert relerr(host(out), method.chebyshev(L, x0, b)) <= 1e-11, l
+
+
+@pytest.mark.parametrize("case", CASES, ids=IDS)
+def test_vcycle(case):
+    s, m = setup_case(case)
+    r = np.random.default_rng(7).uniform(-1, 1, m.K.shape[0])
+    rd, z = dev(r), empty(m.K.shape[0])
+    s.precondition(rd.data_ptr(), z.data_ptr())
+    assert relerr(host(z), m.vcycle(r)) <= 1e-10
+
+
+@pytest.mark.parametrize("case", CASES, ids=IDS)
+def test_solve_matches_direct(case):
+    s, m = setup_case(case, rtol=1e-12)
+    b = np.random.default_rng(8).uniform(-1, 1, m.K.shape[0])
+    bd, x = dev(b), empty(m.K.shape[0])
+    res = s.solve(bd.data_ptr(), x.data_ptr())
+    assert res.status == capi.CD_OK
+    xd = solvers.solve_direct(m.K, b)
+    assert relerr(host(x), xd) <= 1e-9
+    # the recursive residual reached 1e-12; the true residual may drift above it
+    # by rounding (largest for p = 6)
+    assert res.true_rel_residual <= 5e-11
+    _, it_o, _ = m.solve(b, 1e-12)
+    assert abs(res.iterations - it_o) <= 1
+
+
+def test_c1_configuration():
+    # 2D, p = 2, n = 16, alpha = beta = 1, uniform RHS, FCG + V-cycle to 1e-10
+    from curldiv_inputs import rhs
+    d, p, n = 2, 2, 16
+    opt = capi.options(rtol=1e-12, coarse_max_dofs=64)
+    s = capi.Solver(capi.problem(d, p, n, 1.0, 1.0), opt, stream())
+    assert s.num_levels() >= 3
+    for seed in range(4):
+        b = rhs(d, p, n, seed)
+        bd, x = dev(b), empty(b.size)
+        res = s.solve(bd.data_ptr(), x.data_ptr())
+        assert res.status == capi.CD_OK
+        # alpha = beta: exact solution by fast diagonalization (independent of assembly)
+        assert relerr(host(x), solvers.fast_diag_solve(d, p, n, 1.0, b)) <= 1e-10
+
+
+@pytest.mark.parametrize("d,p,n,beta,cg_paper", [(2, 2, 15, 0.1, 40), (2, 3, 30, 0.01, 201),
+                                                 (3, 2, 7, 0.1, 29), (3, 3, 14, 0.01, 102)])
+def test_plain_cg_reproduces_paper_counts(d, p, n, beta, cg_paper):
+    # CG column of Tables 1-4 with the manufactured right-hand side (Sec. 6.2)
+    opt = capi.options(method=capi.CD_METHOD_CG, rtol=1e-7)
+    s = capi.Solver(capi.problem(d, p, n, 1.0, beta), opt, stream())
+    b = loadvec.load_vector(d, p, n, 1.0, beta)
+    bd, x = dev(b), empty(b.size)
+    res = s.solve(bd.data_ptr(), x.data_ptr())
+    assert abs(res.iterations - cg_paper) <= 2
+
+
+@pytest.mark.parametrize("case", [CASES[2], CASES[7]], ids=[IDS[2], IDS[7]])
+def test_mixed_precision_solve(case):
+    s64, m = setup_case(case, rtol=1e-8)
+    s32, _ = setup_case(case, precision=capi.CD_MIXED_FP32, rtol=1e-8)
+    b = np.random.default_rng(9).uniform(-1, 1, m.K.shape[0])
+    bd, x64, x32 = dev(b), empty(b.size), empty(b.size)
+    r64 = s64.solve(bd.data_ptr(), x64.data_ptr())
+    r32 = s32.solve(bd.data_ptr(), x32.data_ptr())
+    assert r64.status == capi.CD_OK and r32.status == capi.CD_OK
+    xo = host(x32)
+    # true FP64 residual recomputed by the oracle
+    assert np.linalg.norm(b - m.K @ xo) <= 1e-8 * np.linalg.norm(b) * 1.01
+    assert r32.true_rel_residual <= 1e-8 * 1.01
+    assert r32.iterations <= r64.iterations + 3
+
+
+def test_edge_cases():
+    st = stream()
+    opt = capi.options()
+    # invalid parameters are rejected before any device work
+    with pytest.raises(capi.CurldivError):
+        capi.Solver(capi.problem(2, 2, 8, 1.0, 0.0), opt, st)
+    with pytest.raises(capi.CurldivError):
+        capi.Solver(capi.problem(4, 2, [8, 8, 8], 1.0, 1.0), opt, st)
+    with pytest.raises(capi.CurldivError):
+        capi.Solver(capi.problem(2, 7, 8, 1.0, 1.0), opt, st)
+    with pytest.raises(capi.CurldivError):
+        capi.Solver(capi.problem(2, 1, 1, 1.0, 1.0), opt, st)  # n + p - 2 = 0 unknowns
+    s = capi.Solver(capi.problem(2, 2, 8, 1.0, 0.5), opt, st)
+    N = capi.num_dofs(s.prob)
+    # zero right-hand side: x = 0 after zero iterations
+    x, zero = empty(N) + 7.0, empty(N)
+    res = s.solve(zero.data_ptr(), x.data_ptr())
+    assert res.status == capi.CD_OK and res.iterations == 0 and np.all(host(x) == 0.0)
+    # non-finite right-hand side: clean error
+    b = np.ones(N)
+    b[3] = np.nan
+    bd, xn = dev(b), empty(N)
+    with pytest.raises(capi.CurldivError):
+        s.solve(bd.data_ptr(), xn.data_ptr())
+    # max_iter = 1: not converged, x holds the first iterate
+    s1 = capi.Solver(capi.problem(2, 2, 8, 1.0, 0.01),
+                     capi.options(max_iter=1, coarse_max_dofs=30, rtol=1e-14), st)
+    ones = dev(np.ones(N))
+    res = s1.solve(ones.data_ptr(), x.data_ptr())
+    assert res.status == capi.CD_NOT_CONVERGED and res.iterations == 1
+    # a single level: the preconditioner is the exact coarse solve, one iteration
+    s2 = capi.Solver(capi.problem(2, 3, 6, 1.0, 0.2), capi.options(coarse_max_dofs=5000, rtol=1e-10), st)
+    assert s2.num_levels() == 1
+    b = np.random.default_rng(0).uniform(-1, 1, capi.num_dofs(s2.prob))
+    bd, x = dev(b), empty(b.size)
+    res = s2.solve(bd.data_ptr(), x.data_ptr())
+    assert res.iterations <= 2
+    assert relerr(host(x), solvers.solve_direct(asm.curl_div_matrix(2, 3, 6, 1.0, 0.2), b)) <= 1e-11
