@@ -63,6 +63,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-c4", action="store_true", help="skip the 3D p=3 n=128 operator-apply measurement")
+    ap.add_argument("--only-c4", action="store_true", help="run only the 3D p=3 n=128 operator-apply measurement")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: this build has no multi-GPU path (see DESIGN.md, sharding)",
@@ -77,6 +78,9 @@ def main():
 
     torch.cuda.set_device(0)
     st = torch.cuda.current_stream().cuda_stream
+    if args.only_c4:
+        print(json.dumps({"operator_apply_c4": c4_apply(capi, torch, st)}), flush=True)
+        return
     name = "c2_2d_p3_n256"
     cfg = ci.CONFIGS[name]
     d, p, n, alpha, betas, dist, tol = cfg

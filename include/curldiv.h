@@ -176,6 +176,40 @@ int cd_profile_enable(cd_solver* s, int on);
 /* Totals of level `level` applies in FP64 (fp32 = 0) or FP32 (fp32 = 1). */
 int cd_profile_read(const cd_solver* s, int level, int fp32, cd_kernel_stats* out);
 
+/* ---- serving: continuous batching of independent solves ----------------- */
+/* A server keeps a FIFO of submitted solves and a set of active ones.  Each
+ * cd_server_step() admits queued requests while the sum of their footprints
+ * (cd_footprint_bytes) stays within the HBM budget and fewer than max_active
+ * are in flight, then enqueues one outer iteration of every active solve
+ * (each on one of the server's streams, so their kernels overlap on the
+ * device) and retires the ones that met their stopping rule.  A request's
+ * arithmetic never depends on the others: its result is bitwise the same
+ * alone or in a mix.  Callers keep b_dev and x_dev valid until the
+ * request's completion has been polled. */
+typedef struct cd_server cd_server;
+typedef struct {
+    size_t hbm_budget_bytes;  /* admission budget; 0 = 80% of the free HBM at creation */
+    int max_active;           /* solves in flight at once; 0 = 64 */
+    int num_streams;          /* HIP streams the active solves are spread over; 0 = 4 */
+} cd_server_options;
+typedef struct {
+    uint64_t ticket;
+    cd_result result;
+    double t_submit, t_admit, t_done;  /* seconds since server creation (host monotonic clock) */
+    size_t footprint_bytes;            /* device bytes the solve held */
+} cd_completion;
+void cd_server_default_options(cd_server_options* opt);
+int cd_server_create(const cd_server_options* opt, cd_server** out);
+/* Queue a solve of A x = b; CD_EINVAL for an invalid problem, CD_ENOMEM if
+ * its footprint exceeds the whole budget.  *ticket identifies it. */
+int cd_server_submit(cd_server* srv, const cd_problem* prob, const cd_options* opt, const double* b_dev,
+                     double* x_dev, uint64_t* ticket);
+/* One scheduling step (blocks until the step's iterations finished). */
+int cd_server_step(cd_server* srv, int* n_active, int* n_queued);
+/* Move up to `max` finished solves into out[]; *n_out = how many. */
+int cd_server_poll(cd_server* srv, cd_completion* out, int max, int* n_out);
+void cd_server_destroy(cd_server* srv);
+
 const char* cd_status_string(int status);
 const char* cd_last_error(void);
 

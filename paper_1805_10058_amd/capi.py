@@ -51,6 +51,15 @@ class cd_result(ctypes.Structure):
                 ("true_rel_residual", ctypes.c_double)]
 
 
+class cd_server_options(ctypes.Structure):
+    _fields_ = [("hbm_budget_bytes", ctypes.c_size_t), ("max_active", ctypes.c_int), ("num_streams", ctypes.c_int)]
+
+
+class cd_completion(ctypes.Structure):
+    _fields_ = [("ticket", ctypes.c_uint64), ("result", cd_result), ("t_submit", ctypes.c_double),
+                ("t_admit", ctypes.c_double), ("t_done", ctypes.c_double), ("footprint_bytes", ctypes.c_size_t)]
+
+
 # name -> (restype, argtypes); the exported symbol set of include/curldiv.h
 _P = ctypes.c_void_p
 _I = ctypes.c_int
@@ -76,6 +85,13 @@ SIGNATURES = {
     "cd_precondition": (_I, [_P, _P, _P]),
     "cd_profile_enable": (_I, [_P, _I]),
     "cd_profile_read": (_I, [_P, _I, _I, ctypes.POINTER(cd_kernel_stats)]),
+    "cd_server_default_options": (None, [ctypes.POINTER(cd_server_options)]),
+    "cd_server_create": (_I, [ctypes.POINTER(cd_server_options), ctypes.POINTER(_P)]),
+    "cd_server_submit": (_I, [_P, ctypes.POINTER(cd_problem), ctypes.POINTER(cd_options), _P, _P,
+                              ctypes.POINTER(ctypes.c_uint64)]),
+    "cd_server_step": (_I, [_P, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int)]),
+    "cd_server_poll": (_I, [_P, ctypes.POINTER(cd_completion), _I, ctypes.POINTER(ctypes.c_int)]),
+    "cd_server_destroy": (None, [_P]),
     "cd_status_string": (ctypes.c_char_p, [_I]),
     "cd_last_error": (ctypes.c_char_p, []),
 }
@@ -224,3 +240,47 @@ class Solver:
 
     def precondition(self, r_ptr, z_ptr):
         check(lib().cd_precondition(self._h, ctypes.c_void_p(r_ptr), ctypes.c_void_p(z_ptr)))
+
+
+class Server:
+    """Owner of a cd_server handle; methods forward to the C entry points."""
+
+    def __init__(self, hbm_budget_bytes=0, max_active=0, num_streams=0):
+        o = cd_server_options()
+        lib().cd_server_default_options(ctypes.byref(o))
+        if hbm_budget_bytes:
+            o.hbm_budget_bytes = hbm_budget_bytes
+        if max_active:
+            o.max_active = max_active
+        if num_streams:
+            o.num_streams = num_streams
+        self._h = ctypes.c_void_p()
+        check(lib().cd_server_create(ctypes.byref(o), ctypes.byref(self._h)))
+
+    def close(self):
+        if self._h:
+            lib().cd_server_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def submit(self, prob, opt, b_ptr, x_ptr):
+        t = ctypes.c_uint64()
+        check(lib().cd_server_submit(self._h, ctypes.byref(prob), ctypes.byref(opt), ctypes.c_void_p(b_ptr),
+                                     ctypes.c_void_p(x_ptr), ctypes.byref(t)))
+        return t.value
+
+    def step(self):
+        a, q = ctypes.c_int(), ctypes.c_int()
+        check(lib().cd_server_step(self._h, ctypes.byref(a), ctypes.byref(q)))
+        return a.value, q.value
+
+    def poll(self, max_n=256):
+        buf = (cd_completion * max_n)()
+        n = ctypes.c_int()
+        check(lib().cd_server_poll(self._h, buf, max_n, ctypes.byref(n)))
+        return [buf[i] for i in range(n.value)]

@@ -76,114 +76,64 @@ __device__ inline T diag_entry(const OpDev<T>& op, int c, int i0, int i1, int i2
 // ------------------------------------------------------------------------------
 // 3D operator apply.
 //
-// Block (chunk, x1-range): the block owns kThreads consecutive points of the
-// flattened (x2, x3) plane, f = s + tid, and output planes x1 in [o0, o1).
-// For every input plane j in [o0-HB, o1+HB) and every component it
-//   (A) contracts axis 2 (stride m3) from an LDS copy of the plane chunk with
-//       its +-HB row halo, producing M2 x, A2 x, S2 x on [s-HB, s+kThreads+HB);
-//   (B) contracts axis 3 (contiguous) at f, combining the raw products with
-//       the weights alpha, beta, alpha-beta into W[c][{S,M,A}], the inputs of
-//       the axis-1 contraction of output component c;
-//   (C) scatters W into a ring of 2HB+1 per-plane accumulators held in
-//       registers: acc(i) += X1(i, j) W for i in [j-HB, j+HB].
+// Block (chunk, x1-range): the block owns TPB = kThreads - 2HB consecutive
+// points f = s + tid of the flattened (x2, x3) plane and output planes x1 in
+// [o0, o1).  Every thread keeps the same in-plane position for the whole
+// march, so the band coefficients of its axis-2 row and axis-3 row are loaded
+// into registers once.  For every input plane j in [o0-HB, o1+HB):
+//   load    the three components' plane chunk with a +-HB row halo into LDS;
+//   (A)     contract axis 2 (stride m3): M2 x, A2 x, S2 x of all components at
+//           the kThreads stage positions s-HB .. s+TPB+HB-1;
+//   (B)     contract axis 3 (contiguous) at f and combine the raw products
+//           with alpha, beta, alpha-beta into W[c][{S,M,A}], the inputs of the
+//           axis-1 contraction of output component c;
+//   (C)     scatter W into a ring of 2HB+1 per-plane accumulators in
+//           registers: acc(i) += X1(i, j) W for i in [j-HB, j+HB] (X1 entries
+//           are block-uniform scalars).
 // After plane j the accumulator of output plane j-HB is complete and goes
-// through the epilogue.  33 band contractions per point in total.
+// through the epilogue.  33 band contractions per point.
 // ------------------------------------------------------------------------------
-template <typename T, int HB>
-struct Plane3 {
-    static constexpr int STN = kThreads + 2 * HB;
-};
-
-template <typename T, int HB, int C>
-__device__ inline void stage_ab(const OpDev<T>& op, const T* __restrict__ xp, int s, int PL, int m3, T* xs, T* st,
-                                bool active, int i3, T (&W)[3][3]) {
-    constexpr int STN = Plane3<T, HB>::STN;
-    const int XSN = kThreads + 2 * HB * m3 + 2 * HB;
-    const int base = s - HB * m3 - HB;
-    for (int q = threadIdx.x; q < XSN; q += kThreads) {
-        const int ff = base + q;
-        xs[q] = (ff >= 0 && ff < PL) ? xp[ff] : T(0);
-    }
-    __syncthreads();
-    const int m2 = op.m[1];
-    for (int q = threadIdx.x; q < STN; q += kThreads) {
-        const int ff = s - HB + q;
-        T aM = T(0), aA = T(0), aS = T(0);
-        if (ff >= 0 && ff < PL) {
-            const int r2 = ff / m3;
-#pragma unroll
-            for (int k = 0; k <= 2 * HB; ++k) {
-                const T xv = xs[q + k * m3];
-                aM += op.band[1][0][k * m2 + r2] * xv;
-                aA += op.band[1][1][k * m2 + r2] * xv;
-                aS += op.band[1][2][k * m2 + r2] * xv;
-            }
-        }
-        st[q] = aM;
-        st[STN + q] = aA;
-        st[2 * STN + q] = aS;
-    }
-    __syncthreads();
-    if (active) {
-        T mm = T(0), sm = T(0), am = T(0), ms = T(0), ma = T(0), aa = T(0);
-        const int tid = threadIdx.x;
-#pragma unroll
-        for (int k = 0; k <= 2 * HB; ++k) {
-            const T cM = op.band[2][0][k * m3 + i3];
-            const T cA = op.band[2][1][k * m3 + i3];
-            const T cS = op.band[2][2][k * m3 + i3];
-            const T vM = st[tid + k], vA = st[STN + tid + k], vS = st[2 * STN + tid + k];
-            mm += cM * vM;  // M3 (M2 x)
-            sm += cS * vM;  // S3 (M2 x)
-            if (C != 1) am += cA * vM;  // A3 (M2 x)
-            ms += cM * vS;  // M3 (S2 x)
-            if (C != 2) ma += cM * vA;  // M3 (A2 x)
-            if (C != 0) aa += cA * vA;  // A3 (A2 x)
-        }
-        const T al = op.alpha, be = op.beta, ab = op.alpha - op.beta;
-        if (C == 0) {
-            W[0][0] += be * mm;
-            W[0][1] += al * (sm + ms);
-            W[2][2] += ab * am;
-            W[1][2] += ab * ma;
-        } else if (C == 1) {
-            W[1][0] += al * mm;
-            W[1][1] += al * sm + be * ms;
-            W[0][2] += ab * ma;
-            W[2][1] += ab * aa;
-        } else {
-            W[2][0] += al * mm;
-            W[2][1] += be * sm + al * ms;
-            W[0][2] += ab * am;
-            W[1][1] += ab * aa;
-        }
-    }
-    __syncthreads();
-}
-
 template <typename T, int HB, int MODE>
 __global__ __launch_bounds__(kThreads) void k_apply3d(OpDev<T> op, const T* __restrict__ x, T* __restrict__ y,
                                                       const T* __restrict__ b, T* __restrict__ u,
                                                       T* __restrict__ xout, T c1, T c2, double* __restrict__ part,
                                                       int nchunk, int c1len) {
     constexpr int R = 2 * HB + 1;
-    constexpr int STN = Plane3<T, HB>::STN;
+    constexpr int TPB = kThreads - 2 * HB;
     extern __shared__ __align__(16) unsigned char smem_raw[];
-    T* xs = reinterpret_cast<T*>(smem_raw);
     const int m1 = op.m[0], m2 = op.m[1], m3 = op.m[2];
     const int PL = m2 * m3;
     const size_t G = size_t(m1) * PL;
-    T* st = xs + (kThreads + 2 * HB * m3 + 2 * HB);
-    (void)STN;
+    const int XSN = kThreads + 2 * HB * m3;
+    T* xs = reinterpret_cast<T*>(smem_raw);  // [3][XSN]
+    T* st = xs + 3 * XSN;                    // [9][kThreads]: M2x A2x S2x of components 0,1,2
     const int chunk = blockIdx.x % nchunk;
     const int xc = blockIdx.x / nchunk;
-    const int s = chunk * kThreads;
+    const int s = chunk * TPB;
     const int o0 = xc * c1len;
     const int o1 = min(o0 + c1len, m1);
-    const int f = s + int(threadIdx.x);
-    const bool active = f < PL;
+    const int tid = threadIdx.x;
+    const int base = s - HB - HB * m3;  // flat index of xs[0]
+
+    // stage-A position of this thread and its axis-2 band row
+    const int ffa = s - HB + tid;
+    const bool ina = (ffa >= 0 && ffa < PL);
+    const int r2 = ina ? ffa / m3 : 0;
+    T ca[3][R];
+#pragma unroll
+    for (int w = 0; w < 3; ++w)
+#pragma unroll
+        for (int k = 0; k < R; ++k) ca[w][k] = ina ? op.band[1][w][k * m2 + r2] : T(0);
+    // output point of this thread and its axis-3 band row
+    const int f = s + tid;
+    const bool active = (tid < TPB) && (f < PL);
     const int i3 = active ? f % m3 : 0;
     const int i2 = active ? f / m3 : 0;
+    T cb[3][R];
+#pragma unroll
+    for (int w = 0; w < 3; ++w)
+#pragma unroll
+        for (int k = 0; k < R; ++k) cb[w][k] = active ? op.band[2][w][k * m3 + i3] : T(0);
 
     T acc[3][R];
 #pragma unroll
@@ -191,6 +141,7 @@ __global__ __launch_bounds__(kThreads) void k_apply3d(OpDev<T> op, const T* __re
 #pragma unroll
         for (int r = 0; r < R; ++r) acc[c][r] = T(0);
     double dot = 0.0;
+    const T al = op.alpha, be = op.beta, ab = op.alpha - op.beta;
 
     const int TI = (o1 - o0) + 2 * HB;
     for (int t0 = 0; t0 < TI; t0 += R) {
@@ -199,16 +150,65 @@ __global__ __launch_bounds__(kThreads) void k_apply3d(OpDev<T> op, const T* __re
             const int t = t0 + uu;
             if (t < TI) {
                 const int j = o0 - HB + t;
-                const bool jin = (j >= 0 && j < m1);
-                T W[3][3];
+                if (j >= 0 && j < m1) {
+                    const T* xp = x + size_t(j) * PL;
+                    for (int q = tid; q < XSN; q += kThreads) {
+                        const int ff = base + q;
+                        const bool in = (ff >= 0 && ff < PL);
+                        xs[q] = in ? xp[ff] : T(0);
+                        xs[XSN + q] = in ? xp[G + ff] : T(0);
+                        xs[2 * XSN + q] = in ? xp[2 * G + ff] : T(0);
+                    }
+                    __syncthreads();
 #pragma unroll
-                for (int c = 0; c < 3; ++c)
+                    for (int c = 0; c < 3; ++c) {
+                        T aM = T(0), aA = T(0), aS = T(0);
 #pragma unroll
-                    for (int w = 0; w < 3; ++w) W[c][w] = T(0);
-                if (jin) {
-                    stage_ab<T, HB, 0>(op, x + 0 * G + size_t(j) * PL, s, PL, m3, xs, st, active, i3, W);
-                    stage_ab<T, HB, 1>(op, x + 1 * G + size_t(j) * PL, s, PL, m3, xs, st, active, i3, W);
-                    stage_ab<T, HB, 2>(op, x + 2 * G + size_t(j) * PL, s, PL, m3, xs, st, active, i3, W);
+                        for (int k = 0; k < R; ++k) {
+                            const T xv = xs[c * XSN + tid + k * m3];
+                            aM += ca[0][k] * xv;
+                            aA += ca[1][k] * xv;
+                            aS += ca[2][k] * xv;
+                        }
+                        st[(3 * c + 0) * kThreads + tid] = aM;
+                        st[(3 * c + 1) * kThreads + tid] = aA;
+                        st[(3 * c + 2) * kThreads + tid] = aS;
+                    }
+                    __syncthreads();
+                    T W[3][3];
+#pragma unroll
+                    for (int c = 0; c < 3; ++c)
+#pragma unroll
+                        for (int w = 0; w < 3; ++w) W[c][w] = T(0);
+                    if (active) {
+                        // raw products per input component c: M3(M2x), S3(M2x), A3(M2x), M3(S2x), M3(A2x), A3(A2x)
+                        T mm[3], sm[3], am[3], ms[3], ma[3], aa[3];
+#pragma unroll
+                        for (int c = 0; c < 3; ++c) {
+                            mm[c] = sm[c] = am[c] = ms[c] = ma[c] = aa[c] = T(0);
+#pragma unroll
+                            for (int k = 0; k < R; ++k) {
+                                const T vM = st[(3 * c + 0) * kThreads + tid + k];
+                                const T vA = st[(3 * c + 1) * kThreads + tid + k];
+                                const T vS = st[(3 * c + 2) * kThreads + tid + k];
+                                mm[c] += cb[0][k] * vM;
+                                sm[c] += cb[2][k] * vM;
+                                if (c != 1) am[c] += cb[1][k] * vM;
+                                ms[c] += cb[0][k] * vS;
+                                if (c != 2) ma[c] += cb[0][k] * vA;
+                                if (c != 0) aa[c] += cb[1][k] * vA;
+                            }
+                        }
+                        W[0][0] = be * mm[0];
+                        W[0][1] = al * (sm[0] + ms[0]);
+                        W[0][2] = ab * (ma[1] + am[2]);
+                        W[1][0] = al * mm[1];
+                        W[1][1] = al * sm[1] + be * ms[1] + ab * aa[2];
+                        W[1][2] = ab * ma[0];
+                        W[2][0] = al * mm[2];
+                        W[2][1] = be * sm[2] + al * ms[2] + ab * aa[1];
+                        W[2][2] = ab * am[0];
+                    }
 #pragma unroll
                     for (int k = 0; k < R; ++k) {
                         const int i = j - HB + k;
@@ -219,47 +219,45 @@ __global__ __launch_bounds__(kThreads) void k_apply3d(OpDev<T> op, const T* __re
                             const T cA = op.band[0][1][kk * m1 + i];
                             const int slot = (uu + k + 1) % R;
 #pragma unroll
-                            for (int c = 0; c < 3; ++c) {
-                                // slot is a compile-time constant after unrolling uu and k
+                            for (int c = 0; c < 3; ++c)
 #pragma unroll
                                 for (int r = 0; r < R; ++r)
                                     if (r == slot) acc[c][r] += cS * W[c][0] + cM * W[c][1] + cA * W[c][2];
-                            }
                         }
                     }
+                    __syncthreads();  // xs / st are overwritten by the next plane
                 }
                 const int io = j - HB;
-                if (io >= o0 && io < o1 && active) {
+                if (io >= o0 && io < o1) {
                     const int slot = (uu + 1) % R;
 #pragma unroll
                     for (int c = 0; c < 3; ++c) {
                         T kx = T(0);
 #pragma unroll
                         for (int r = 0; r < R; ++r)
-                            if (r == slot) { kx = acc[c][r]; acc[c][r] = T(0); }
-                        const size_t idx = size_t(c) * G + size_t(io) * PL + f;
-                        if (MODE == kApplyY) {
-                            y[idx] = kx;
-                        } else if (MODE == kApplyRes) {
-                            y[idx] = b[idx] - kx;
-                        } else if (MODE == kApplyCheb) {
-                            const T r = b[idx] - kx;
-                            const T dg = diag_entry(op, c, io, i2, i3);
-                            const T uprev = (c1 != T(0)) ? u[idx] : T(0);  // u is not read on a first step
-                            const T un = c1 * uprev + c2 * r / dg;
-                            u[idx] = un;
-                            xout[idx] = x[idx] + un;
-                        } else {
-                            y[idx] = kx;
-                            dot += double(x[idx]) * double(kx);
+                            if (r == slot) {
+                                kx = acc[c][r];
+                                acc[c][r] = T(0);
+                            }
+                        if (active) {
+                            const size_t idx = size_t(c) * G + size_t(io) * PL + f;
+                            if (MODE == kApplyY) {
+                                y[idx] = kx;
+                            } else if (MODE == kApplyRes) {
+                                y[idx] = b[idx] - kx;
+                            } else if (MODE == kApplyCheb) {
+                                const T r = b[idx] - kx;
+                                const T dg = diag_entry(op, c, io, i2, i3);
+                                const T uprev = (c1 != T(0)) ? u[idx] : T(0);  // u is not read on a first step
+                                const T un = c1 * uprev + c2 * r / dg;
+                                u[idx] = un;
+                                xout[idx] = x[idx] + un;
+                            } else {
+                                y[idx] = kx;
+                                dot += double(x[idx]) * double(kx);
+                            }
                         }
                     }
-                } else if (io >= o0 && io < o1) {
-#pragma unroll
-                    for (int c = 0; c < 3; ++c)
-#pragma unroll
-                        for (int r = 0; r < R; ++r)
-                            if (r == (uu + 1) % R) acc[c][r] = T(0);
                 }
             }
         }
@@ -271,9 +269,10 @@ __global__ __launch_bounds__(kThreads) void k_apply3d(OpDev<T> op, const T* __re
 }
 
 // ------------------------------------------------------------------------------
-// 2D operator apply: block owns kThreads consecutive points of the flattened
-// (x1, x2) grid.  (A) axis-1 contractions (stride m2) S1, M1, A1 of both
-// components on [s-HB, s+kThreads+HB); (B) axis-2 contraction at the point:
+// 2D operator apply: block owns TPB = kThreads - 2HB consecutive points of the
+// flattened (x1, x2) grid.  (A) axis-1 contractions (stride m2) S1, M1, A1 of
+// both components at the kThreads stage positions; (B) axis-2 contraction at
+// the point:
 //   y1 = beta M2(S1 x1) + alpha S2(M1 x1) + (alpha-beta) A2(A1 x2)
 //   y2 = alpha M2(S1 x2) + beta S2(M1 x2) + (alpha-beta) A2(A1 x1)
 // ------------------------------------------------------------------------------
@@ -281,17 +280,17 @@ template <typename T, int HB, int MODE>
 __global__ __launch_bounds__(kThreads) void k_apply2d(OpDev<T> op, const T* __restrict__ x, T* __restrict__ y,
                                                       const T* __restrict__ b, T* __restrict__ u,
                                                       T* __restrict__ xout, T c1, T c2, double* __restrict__ part) {
-    constexpr int STN = kThreads + 2 * HB;
+    constexpr int R = 2 * HB + 1;
+    constexpr int TPB = kThreads - 2 * HB;
     extern __shared__ __align__(16) unsigned char smem_raw[];
     const int m1 = op.m[0], m2 = op.m[1];
     const int G = m1 * m2;
-    const int XSN = kThreads + 2 * HB * m2 + 2 * HB;
-    T* xs = reinterpret_cast<T*>(smem_raw);  // 2 x XSN
-    T* st = xs + 2 * XSN;                    // 6 x STN: S1x1 M1x1 A1x1 S1x2 M1x2 A1x2
-    const int s = blockIdx.x * kThreads;
+    const int XSN = kThreads + 2 * HB * m2;
+    T* xs = reinterpret_cast<T*>(smem_raw);  // [2][XSN]
+    T* st = xs + 2 * XSN;                    // [6][kThreads]: S1x1 M1x1 A1x1 S1x2 M1x2 A1x2
+    const int s = blockIdx.x * TPB;
     const int tid = threadIdx.x;
-    const int f = s + tid;
-    const int base = s - HB * m2 - HB;
+    const int base = s - HB - HB * m2;
     for (int q = tid; q < XSN; q += kThreads) {
         const int ff = base + q;
         const bool in = ff >= 0 && ff < G;
@@ -299,17 +298,17 @@ __global__ __launch_bounds__(kThreads) void k_apply2d(OpDev<T> op, const T* __re
         xs[XSN + q] = in ? x[G + ff] : T(0);
     }
     __syncthreads();
-    for (int q = tid; q < STN; q += kThreads) {
-        const int ff = s - HB + q;
+    {
+        const int ffa = s - HB + tid;
         T v[6] = {T(0), T(0), T(0), T(0), T(0), T(0)};
-        if (ff >= 0 && ff < G) {
-            const int r1 = ff / m2;
+        if (ffa >= 0 && ffa < G) {
+            const int r1 = ffa / m2;
 #pragma unroll
-            for (int k = 0; k <= 2 * HB; ++k) {
+            for (int k = 0; k < R; ++k) {
                 const T cS = op.band[0][2][k * m1 + r1];
                 const T cM = op.band[0][0][k * m1 + r1];
                 const T cA = op.band[0][1][k * m1 + r1];
-                const T x1 = xs[q + k * m2], x2 = xs[XSN + q + k * m2];
+                const T x1 = xs[tid + k * m2], x2 = xs[XSN + tid + k * m2];
                 v[0] += cS * x1;
                 v[1] += cM * x1;
                 v[2] += cA * x1;
@@ -319,24 +318,25 @@ __global__ __launch_bounds__(kThreads) void k_apply2d(OpDev<T> op, const T* __re
             }
         }
 #pragma unroll
-        for (int w = 0; w < 6; ++w) st[w * STN + q] = v[w];
+        for (int w = 0; w < 6; ++w) st[w * kThreads + tid] = v[w];
     }
     __syncthreads();
     double dot = 0.0;
-    if (f < G) {
+    const int f = s + tid;
+    if (tid < TPB && f < G) {
         const int i2 = f % m2, i1 = f / m2;
         T mS1 = T(0), sM1 = T(0), aA2 = T(0), mS2 = T(0), sM2 = T(0), aA1 = T(0);
 #pragma unroll
-        for (int k = 0; k <= 2 * HB; ++k) {
+        for (int k = 0; k < R; ++k) {
             const T cM = op.band[1][0][k * m2 + i2];
             const T cA = op.band[1][1][k * m2 + i2];
             const T cS = op.band[1][2][k * m2 + i2];
-            mS1 += cM * st[0 * STN + tid + k];
-            sM1 += cS * st[1 * STN + tid + k];
-            aA1 += cA * st[2 * STN + tid + k];
-            mS2 += cM * st[3 * STN + tid + k];
-            sM2 += cS * st[4 * STN + tid + k];
-            aA2 += cA * st[5 * STN + tid + k];
+            mS1 += cM * st[0 * kThreads + tid + k];
+            sM1 += cS * st[1 * kThreads + tid + k];
+            aA1 += cA * st[2 * kThreads + tid + k];
+            mS2 += cM * st[3 * kThreads + tid + k];
+            sM2 += cS * st[4 * kThreads + tid + k];
+            aA2 += cA * st[5 * kThreads + tid + k];
         }
         const T al = op.alpha, be = op.beta, ab = op.alpha - op.beta;
         const T kx[2] = {be * mS1 + al * sM1 + ab * aA2, al * mS2 + be * sM2 + ab * aA1};
@@ -371,8 +371,8 @@ constexpr int kX1Chunk = 16;
 template <typename T>
 size_t apply_lds_bytes(const OpDev<T>& op) {
     const int hb = op.hb;
-    if (op.dim == 3) return sizeof(T) * (size_t(kThreads + 2 * hb * op.m[2] + 2 * hb) + 3 * size_t(kThreads + 2 * hb));
-    return sizeof(T) * (2 * size_t(kThreads + 2 * hb * op.m[1] + 2 * hb) + 6 * size_t(kThreads + 2 * hb));
+    if (op.dim == 3) return sizeof(T) * (3 * size_t(kThreads + 2 * hb * op.m[2]) + 9 * size_t(kThreads));
+    return sizeof(T) * (2 * size_t(kThreads + 2 * hb * op.m[1]) + 6 * size_t(kThreads));
 }
 
 template <typename T, int HB, int MODE>
@@ -382,7 +382,8 @@ void apply_dispatch(const OpDev<T>& op, const T* x, T* y, const T* b, T* u, T* x
     if (lds > 160 * 1024) throw std::runtime_error("grid too large for the operator kernel's LDS tile");
     if (op.dim == 3) {
         const int PL = op.m[1] * op.m[2];
-        const int nchunk = (PL + kThreads - 1) / kThreads;
+        const int tpb = kThreads - 2 * HB;
+        const int nchunk = (PL + tpb - 1) / tpb;
         const int nx1 = (op.m[0] + kX1Chunk - 1) / kX1Chunk;
         auto kern = k_apply3d<T, HB, MODE>;
         if (lds > 64 * 1024) hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, int(lds));
@@ -390,10 +391,11 @@ void apply_dispatch(const OpDev<T>& op, const T* x, T* y, const T* b, T* u, T* x
                            nchunk, kX1Chunk);
     } else {
         const int G = op.m[0] * op.m[1];
+        const int tpb = kThreads - 2 * HB;
         auto kern = k_apply2d<T, HB, MODE>;
         if (lds > 64 * 1024) hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, int(lds));
-        hipLaunchKernelGGL(kern, dim3((G + kThreads - 1) / kThreads), dim3(kThreads), lds, s, op, x, y, b, u, xout,
-                           c1, c2, part);
+        hipLaunchKernelGGL(kern, dim3((G + tpb - 1) / tpb), dim3(kThreads), lds, s, op, x, y, b, u, xout, c1, c2,
+                           part);
     }
     check_launch("apply");
 }
@@ -483,57 +485,115 @@ __global__ __launch_bounds__(kThreads) void k_prolong_add(XferDev<T> X, int ncom
 }
 
 // ------------------------------------------------------------------------------
-// T^{-1}: banded LDL^T forward / diagonal / backward solves along every grid
-// line of one axis, one thread per line, in place.
+// T^{-1}: banded LDL^T solves along every grid line of one axis, in two
+// out-of-place passes (forward L y = v with y scaled by D^{-1}, then backward
+// L^T z = y).  Each line is cut into chunks of `chunk` rows processed in
+// parallel; a chunk's recurrence starts `warm` rows before (forward) or after
+// (backward) the chunk from a zero state, which the recurrence forgets to
+// below rounding within `warm` rows (the factor of T_m(m_{p-1}) is well
+// conditioned), so every chunk reproduces the sequential solve.
+// Consecutive threads take consecutive lines of the same chunk.
 // ------------------------------------------------------------------------------
-template <typename T, int BW>
-__global__ __launch_bounds__(kThreads) void k_tsolve_axis(T* __restrict__ z, int ncomp, int m0, int m1, int m2,
-                                                          int axis, TFacDev<T> F) {
-    const size_t G = size_t(m0) * m1 * m2;
-    const int ma = (axis == 0) ? m0 : (axis == 1) ? m1 : m2;
-    const size_t lines_per_comp = G / ma;
-    const size_t line = size_t(blockIdx.x) * kThreads + threadIdx.x;
-    if (line >= lines_per_comp * ncomp) return;
-    const int c = int(line / lines_per_comp);
-    const size_t rem = line % lines_per_comp;
-    size_t base, stride;
-    if (axis == 0) {
-        base = rem;
-        stride = size_t(m1) * m2;
-    } else if (axis == 1) {
-        base = (rem / m2) * size_t(m1) * m2 + rem % m2;
-        stride = m2;
+struct LineGeom {
+    size_t G, lines_per_comp;
+    int ma, axis, m1, m2, nchunk, chunk;
+};
+
+__device__ inline void line_base(const LineGeom& g, size_t item, int& c, int& ch, size_t& base, size_t& stride) {
+    const size_t line = item % g.lines_per_comp;
+    const size_t rest = item / g.lines_per_comp;
+    ch = int(rest % g.nchunk);
+    c = int(rest / g.nchunk);
+    if (g.axis == 0) {
+        base = line;
+        stride = size_t(g.m1) * g.m2;
+    } else if (g.axis == 1) {
+        base = (line / g.m2) * size_t(g.m1) * g.m2 + line % g.m2;
+        stride = g.m2;
     } else {
-        base = rem * m2;
+        base = line * g.m2;
         stride = 1;
     }
-    T* zl = z + size_t(c) * G + base;
-    T win[BW > 0 ? BW : 1];
+    base += size_t(c) * g.G;
+}
+
+constexpr int kRowBatch = 8;  // rows whose loads are issued together in the line recurrences
+
+template <typename T, int BW>
+__global__ __launch_bounds__(kThreads) void k_tsolve_fwd(const T* __restrict__ in, T* __restrict__ out, size_t items,
+                                                         LineGeom g, const T* __restrict__ L,
+                                                         const T* __restrict__ dinv, int warm) {
+    const size_t item = size_t(blockIdx.x) * kThreads + threadIdx.x;
+    if (item >= items) return;
+    int c, ch;
+    size_t base, stride;
+    line_base(g, item, c, ch, base, stride);
+    const int r0 = ch * g.chunk, r1 = min(g.ma, r0 + g.chunk);
+    const int rs = max(0, r0 - warm);
+    T win[BW];
 #pragma unroll
-    for (int k = 0; k < (BW > 0 ? BW : 1); ++k) win[k] = T(0);
-    // forward: y_i = v_i - sum_k L(i,i-k) y_{i-k}; store y_i / D_i
-    for (int i = 0; i < ma; ++i) {
-        T v = zl[size_t(i) * stride];
+    for (int k = 0; k < BW; ++k) win[k] = T(0);
+    for (int rb = rs; rb < r1; rb += kRowBatch) {
+        T vin[kRowBatch], lc[kRowBatch][BW], dv[kRowBatch];
 #pragma unroll
-        for (int k = 1; k <= BW; ++k)
-            if (i - k >= 0) v -= F.l[i * BW + k - 1] * win[k - 1];
+        for (int q = 0; q < kRowBatch; ++q) {
+            const int r = min(rb + q, r1 - 1);  // clamped: rows past r1 are loaded but not used
+            vin[q] = in[base + size_t(r) * stride];
+            dv[q] = dinv[r];
 #pragma unroll
-        for (int k = BW - 1; k >= 1; --k) win[k] = win[k - 1];
-        if (BW > 0) win[0] = v;
-        zl[size_t(i) * stride] = v * F.dinv[i];
+            for (int k = 0; k < BW; ++k) lc[q][k] = L[r * BW + k];
+        }
+#pragma unroll
+        for (int q = 0; q < kRowBatch; ++q) {
+            const int r = rb + q;
+            if (r < r1) {
+                T v = vin[q];
+#pragma unroll
+                for (int k = 1; k <= BW; ++k) v -= lc[q][k - 1] * win[k - 1];
+#pragma unroll
+                for (int k = BW - 1; k >= 1; --k) win[k] = win[k - 1];
+                win[0] = v;
+                if (r >= r0) out[base + size_t(r) * stride] = v * dv[q];
+            }
+        }
     }
-    // backward: z_i = w_i - sum_k L(i+k, i) z_{i+k}
+}
+
+template <typename T, int BW>
+__global__ __launch_bounds__(kThreads) void k_tsolve_bwd(const T* __restrict__ in, T* __restrict__ out, size_t items,
+                                                         LineGeom g, const T* __restrict__ L, int warm) {
+    const size_t item = size_t(blockIdx.x) * kThreads + threadIdx.x;
+    if (item >= items) return;
+    int c, ch;
+    size_t base, stride;
+    line_base(g, item, c, ch, base, stride);
+    const int r0 = ch * g.chunk, r1 = min(g.ma, r0 + g.chunk);
+    const int re = min(g.ma, r1 + warm);
+    T win[BW];
 #pragma unroll
-    for (int k = 0; k < (BW > 0 ? BW : 1); ++k) win[k] = T(0);
-    for (int i = ma - 1; i >= 0; --i) {
-        T v = zl[size_t(i) * stride];
+    for (int k = 0; k < BW; ++k) win[k] = T(0);
+    for (int rb = re - 1; rb >= r0; rb -= kRowBatch) {
+        T vin[kRowBatch], lc[kRowBatch][BW];
 #pragma unroll
-        for (int k = 1; k <= BW; ++k)
-            if (i + k < ma) v -= F.l[(i + k) * BW + k - 1] * win[k - 1];
+        for (int q = 0; q < kRowBatch; ++q) {
+            const int r = max(rb - q, r0);  // clamped: rows below r0 are loaded but not used
+            vin[q] = in[base + size_t(r) * stride];
 #pragma unroll
-        for (int k = BW - 1; k >= 1; --k) win[k] = win[k - 1];
-        if (BW > 0) win[0] = v;
-        zl[size_t(i) * stride] = v;
+            for (int k = 1; k <= BW; ++k) lc[q][k - 1] = (r + k < g.ma) ? L[(r + k) * BW + k - 1] : T(0);
+        }
+#pragma unroll
+        for (int q = 0; q < kRowBatch; ++q) {
+            const int r = rb - q;
+            if (r >= r0) {
+                T v = vin[q];
+#pragma unroll
+                for (int k = 1; k <= BW; ++k) v -= lc[q][k - 1] * win[k - 1];
+#pragma unroll
+                for (int k = BW - 1; k >= 1; --k) win[k] = win[k - 1];
+                win[0] = v;
+                if (r < r1) out[base + size_t(r) * stride] = v;
+            }
+        }
     }
 }
 
@@ -704,12 +764,14 @@ __global__ __launch_bounds__(kThreads) void k_multidot(const T* __restrict__ V, 
     }
 }
 
-__global__ void k_multifinal(const double* __restrict__ part, int k, int nb, double* __restrict__ H, int take_sqrt) {
-    const int j = threadIdx.x;
-    if (j >= k) return;
-    double s = 0.0;
-    for (int b = 0; b < nb; ++b) s += part[size_t(j) * nb + b];
-    H[j] = take_sqrt ? sqrt(s) : s;
+// H[j] = sum of the nb partials of dot j, j < k; one block, partials read in
+// parallel and combined in a fixed order.
+__global__ __launch_bounds__(kThreads) void k_multifinal(const double* __restrict__ part, int k, int nb,
+                                                         double* __restrict__ H, int take_sqrt) {
+    for (int j = 0; j < k; ++j) {
+        const double s = sum_partials(part + size_t(j) * nb, nb);
+        if (threadIdx.x == 0) H[j] = take_sqrt ? sqrt(s) : s;
+    }
 }
 
 template <typename T>
@@ -787,11 +849,12 @@ int reduce_blocks(size_t n) {
 
 template <typename T>
 int apply_blocks(const OpDev<T>& op) {
+    const int tpb = kThreads - 2 * op.hb;
     if (op.dim == 3) {
         const int PL = op.m[1] * op.m[2];
-        return ((PL + kThreads - 1) / kThreads) * ((op.m[0] + kX1Chunk - 1) / kX1Chunk);
+        return ((PL + tpb - 1) / tpb) * ((op.m[0] + kX1Chunk - 1) / kX1Chunk);
     }
-    return (op.m[0] * op.m[1] + kThreads - 1) / kThreads;
+    return (op.m[0] * op.m[1] + tpb - 1) / tpb;
 }
 
 template <typename T>
@@ -822,24 +885,48 @@ void launch_prolong_add(const XferDev<T>& X, int ncomp, const T* ec, T* xf, hipS
     check_launch("prolong");
 }
 
+template <typename T, int BW>
+void tsolve_axis(const T* v, T* tmp, T* z, const LineGeom& g, const TFacDev<T>& F, size_t items, hipStream_t s) {
+    const dim3 grid((items + kThreads - 1) / kThreads);
+    hipLaunchKernelGGL((k_tsolve_fwd<T, BW>), grid, dim3(kThreads), 0, s, v, tmp, items, g, F.l, F.dinv, F.warm);
+    hipLaunchKernelGGL((k_tsolve_bwd<T, BW>), grid, dim3(kThreads), 0, s, tmp, z, items, g, F.l, F.warm);
+}
+
 template <typename T>
-void launch_tsolve(int dim, const int* m, const TFacDev<T>* fac, T* z, hipStream_t s) {
+void launch_tsolve(int dim, const int* m, const TFacDev<T>* fac, const T* v, T* tmp, T* z, hipStream_t s) {
     const int m0 = m[0], m1 = m[1], m2 = (dim == 3) ? m[2] : 1;
     const size_t G = size_t(m0) * m1 * m2;
+    if (fac[0].bw == 0) {  // p = 1: T is the identity
+        if (v != z) launch_copy<T>(v, z, size_t(dim) * G, s);
+        return;
+    }
+    const T* src = v;
     for (int a = 0; a < dim; ++a) {
         const TFacDev<T>& F = fac[a];
-        const size_t lines = size_t(dim) * G / F.m;
-        const dim3 grid((lines + kThreads - 1) / kThreads);
+        LineGeom g;
+        g.G = G;
+        g.ma = F.m;
+        g.axis = a;
+        g.m1 = m1;
+        g.m2 = m2;
+        g.lines_per_comp = G / F.m;
+        const size_t lines = size_t(dim) * g.lines_per_comp;
+        // enough independent chunks to fill the device, chunks no shorter than 16 rows
+        const size_t want = (size_t(1) << 17) / std::max<size_t>(lines, 1) + 1;
+        g.nchunk = int(std::max<size_t>(1, std::min<size_t>(want, size_t((F.m + 15) / 16))));
+        g.chunk = (F.m + g.nchunk - 1) / g.nchunk;
+        g.nchunk = (F.m + g.chunk - 1) / g.chunk;
+        const size_t items = lines * g.nchunk;
         switch (F.bw) {
-            case 0: return;  // p = 1: T is the identity
-            case 1: hipLaunchKernelGGL((k_tsolve_axis<T, 1>), grid, dim3(kThreads), 0, s, z, dim, m0, m1, m2, a, F); break;
-            case 2: hipLaunchKernelGGL((k_tsolve_axis<T, 2>), grid, dim3(kThreads), 0, s, z, dim, m0, m1, m2, a, F); break;
-            case 3: hipLaunchKernelGGL((k_tsolve_axis<T, 3>), grid, dim3(kThreads), 0, s, z, dim, m0, m1, m2, a, F); break;
-            case 4: hipLaunchKernelGGL((k_tsolve_axis<T, 4>), grid, dim3(kThreads), 0, s, z, dim, m0, m1, m2, a, F); break;
-            case 5: hipLaunchKernelGGL((k_tsolve_axis<T, 5>), grid, dim3(kThreads), 0, s, z, dim, m0, m1, m2, a, F); break;
+            case 1: tsolve_axis<T, 1>(src, tmp, z, g, F, items, s); break;
+            case 2: tsolve_axis<T, 2>(src, tmp, z, g, F, items, s); break;
+            case 3: tsolve_axis<T, 3>(src, tmp, z, g, F, items, s); break;
+            case 4: tsolve_axis<T, 4>(src, tmp, z, g, F, items, s); break;
+            case 5: tsolve_axis<T, 5>(src, tmp, z, g, F, items, s); break;
             default: throw std::runtime_error("degree out of range (1..6)");
         }
         check_launch("tsolve");
+        src = z;
     }
 }
 
@@ -938,12 +1025,12 @@ void launch_multidot(const T* V, int k, const T* w, size_t n, double* part, int 
 }
 
 void launch_multifinal(const double* part, int k, int nb, double* H, hipStream_t s) {
-    hipLaunchKernelGGL(k_multifinal, dim3(1), dim3(64), 0, s, part, k, nb, H, 0);
+    hipLaunchKernelGGL(k_multifinal, dim3(1), dim3(kThreads), 0, s, part, k, nb, H, 0);
     check_launch("multifinal");
 }
 
 void launch_normfinal(const double* part, int nb, double* out, hipStream_t s) {
-    hipLaunchKernelGGL(k_multifinal, dim3(1), dim3(64), 0, s, part, 1, nb, out, 1);
+    hipLaunchKernelGGL(k_multifinal, dim3(1), dim3(kThreads), 0, s, part, 1, nb, out, 1);
     check_launch("normfinal");
 }
 
@@ -977,7 +1064,7 @@ void launch_combine(const T* V, int k, const double* y, T* w, size_t n, hipStrea
     template void launch_apply<T>(const OpDev<T>&, int, const T*, T*, const T*, T*, T*, T, T, double*, hipStream_t); \
     template void launch_restrict<T>(const XferDev<T>&, int, const T*, T*, hipStream_t);                             \
     template void launch_prolong_add<T>(const XferDev<T>&, int, const T*, T*, hipStream_t);                          \
-    template void launch_tsolve<T>(int, const int*, const TFacDev<T>*, T*, hipStream_t);                            \
+    template void launch_tsolve<T>(int, const int*, const TFacDev<T>*, const T*, T*, T*, hipStream_t);                            \
     template void launch_fill<T>(T*, T, size_t, hipStream_t);                                                        \
     template void launch_copy<T>(const T*, T*, size_t, hipStream_t);                                                 \
     template void launch_axpby<T>(T, const T*, T, T*, size_t, hipStream_t);                                          \

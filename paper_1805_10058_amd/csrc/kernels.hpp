@@ -41,6 +41,7 @@ struct TFacDev {
     const T* l;     // l[i*bw + k-1] = L(i, i-k)
     const T* dinv;  // 1 / D(i)
     int m, bw;
+    int warm;       // rows a chunk's recurrence starts early (see recurrence_warmup)
 };
 
 enum ApplyMode : int {
@@ -65,8 +66,9 @@ void launch_restrict(const XferDev<T>& X, int ncomp, const T* rf, T* rc, hipStre
 template <typename T>
 void launch_prolong_add(const XferDev<T>& X, int ncomp, const T* ec, T* xf, hipStream_t s);
 
+// z = T^{-1} v, T = I_d (x) T_1 (x) ... (x) T_d; v may equal z; tmp: n scratch.
 template <typename T>
-void launch_tsolve(int dim, const int* m, const TFacDev<T>* fac, T* z, hipStream_t s);
+void launch_tsolve(int dim, const int* m, const TFacDev<T>* fac, const T* v, T* tmp, T* z, hipStream_t s);
 
 // ---- vector kernels ---------------------------------------------------------
 template <typename TA, typename TB>

@@ -313,6 +313,32 @@ TFactor toeplitz_factor(int m, int p) {
     return F;
 }
 
+int recurrence_warmup(const TFactor& F, double tol) {
+    const int bw = F.bw, m = F.m;
+    if (bw == 0) return 0;
+    const int r = m / 2;  // interior row: coefficients of the asymptotic recurrence
+    std::vector<double> c(bw, 0.0);
+    for (int k = 1; k <= bw; ++k)
+        if (r - k >= 0) c[k - 1] = F.l[size_t(r) * bw + (k - 1)];
+    int worst = 0;
+    for (int j = 0; j < bw; ++j) {
+        std::vector<double> win(bw, 0.0);
+        win[j] = 1.0;
+        int steps = 0;
+        for (; steps < m; ++steps) {
+            double mx = 0.0;
+            for (double v : win) mx = std::max(mx, std::fabs(v));
+            if (mx < tol) break;
+            double y = 0.0;
+            for (int k = 1; k <= bw; ++k) y -= c[k - 1] * win[k - 1];
+            for (int k = bw - 1; k >= 1; --k) win[k] = win[k - 1];
+            win[0] = y;
+        }
+        worst = std::max(worst, steps);
+    }
+    return std::min(m, worst + bw + 2);
+}
+
 std::vector<double> dense_operator(int d, const int* m, const Band* M, const Band* A, const Band* S,
                                    double alpha, double beta) {
     size_t G = 1;

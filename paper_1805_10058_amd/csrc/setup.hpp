@@ -63,6 +63,12 @@ struct TFactor {
     Band T;  // the matrix itself (for export)
 };
 TFactor toeplitz_factor(int m, int p);
+// Number of steps after which the homogeneous part of the factor's line
+// recurrence (forward L y = v, or backward L^T z = w) has decayed below
+// `tol` relative to its start, measured on the interior coefficients; m if
+// it does not within m steps.  A line solve that starts this many rows
+// early from a zero state agrees with the exact solve to `tol`.
+int recurrence_warmup(const TFactor& F, double tol);
 
 // Dense coarse system matrix (N x N, row-major) of the curl-div block form,
 // built from the 1D matrices of each axis (block (c,c): beta D_c + alpha

@@ -10,7 +10,9 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <chrono>
 #include <cmath>
+#include <deque>
 #include <cstring>
 #include <functional>
 #include <memory>
@@ -111,6 +113,7 @@ struct VWork {
     T* w = nullptr;
     T* z = nullptr;
     T* io_in = nullptr;   // precision-converted input (mixed mode)
+    T* tmp = nullptr;     // scratch of the T-solve
     double* H = nullptr;  // (s+1) x s column-major
     double* y = nullptr;
     double* part = nullptr;  // multidot partials
@@ -119,6 +122,14 @@ struct VWork {
 };
 
 }  // namespace
+
+struct SolveState {
+    const double* b = nullptr;
+    double* x = nullptr;
+    double r0 = 0.0, rel = 1.0;
+    int k = 0, status = CD_NOT_CONVERGED;
+    bool done = true;
+};
 
 struct cd_solver {
     cd_problem prob{};
@@ -153,11 +164,15 @@ struct cd_solver {
         int cls;
         double bytes;
     };
+    SolveState state;
+    hipEvent_t iter_event = nullptr;
+
     bool prof = false;
     std::vector<ProfRec> prof_pending;
     std::vector<std::pair<hipEvent_t, hipEvent_t>> prof_pool;
     std::vector<cd_kernel_stats> prof_stats;  // index 2*level + fp32
     ~cd_solver() {
+        if (iter_event) (void)hipEventDestroy(iter_event);
         for (auto& r : prof_pending) { (void)hipEventDestroy(r.a); (void)hipEventDestroy(r.b); }
         for (auto& e : prof_pool) { (void)hipEventDestroy(e.first); (void)hipEventDestroy(e.second); }
     }
@@ -191,8 +206,8 @@ void validate(const cd_problem* pr, const cd_options* op) {
         throw CdError(CD_EINVAL, "coarse_max_dofs must be in 1..8192");
     // the operator kernels keep a plane chunk with a +-p row halo in LDS
     const int mlast = pr->n[pr->dim - 1] + pr->degree - 2;
-    const size_t lds = (pr->dim == 3) ? 8 * (256 + 2 * size_t(pr->degree) * mlast + 2 * pr->degree + 3 * (256 + 2 * pr->degree))
-                                      : 8 * (2 * (256 + 2 * size_t(pr->degree) * mlast + 2 * pr->degree) + 6 * (256 + 2 * pr->degree));
+    const size_t lds = (pr->dim == 3) ? 8 * (3 * (256 + 2 * size_t(pr->degree) * mlast) + 9 * 256)
+                                      : 8 * (2 * (256 + 2 * size_t(pr->degree) * mlast) + 6 * 256);
     if (lds > 160 * 1024) throw CdError(CD_EINVAL, "grid too large along the last axis for the operator kernel");
 }
 
@@ -309,6 +324,9 @@ cd::TFacDev<T> make_tfac(cd_solver* s, const cd::TFactor& F, hipStream_t st) {
     t.bw = F.bw;
     t.l = s->arena.upload(convert<T>(F.l), st);
     t.dinv = s->arena.upload(convert<T>(F.dinv), st);
+    // start each chunk's recurrence early enough to forget the zero start state
+    // far below the rounding level of T
+    t.warm = cd::recurrence_warmup(F, sizeof(T) == 8 ? 1e-18 : 1e-9);
     return t;
 }
 
@@ -333,6 +351,7 @@ std::unique_ptr<VWork<T>> make_work(cd_solver* s, DevArena& ar) {
     w->w = ar.alloc<T>(s->N);
     w->z = ar.alloc<T>(s->N);
     w->io_in = ar.alloc<T>(s->N);
+    w->tmp = ar.alloc<T>(s->N);
     w->H = ar.alloc<double>(size_t(ks + 1) * ks);
     w->y = ar.alloc<double>(ks + 1);
     w->nb = cd::reduce_blocks(s->N);
@@ -439,8 +458,7 @@ void gmres_post(cd_solver* s, VWork<T>& W, const T* b, T* x) {
     cd::launch_finalize(W.part, nb, W.scal, st);
     cd::launch_normalize<T>(W.part, nb, W.w, V, N, st);
     for (int j = 0; j < ks; ++j) {
-        cd::launch_copy<T>(V + size_t(j) * N, W.z, N, st);
-        cd::launch_tsolve<T>(s->d, s->lv[0].m, tfacs<T>(s), W.z, st);
+        cd::launch_tsolve<T>(s->d, s->lv[0].m, tfacs<T>(s), V + size_t(j) * N, W.tmp, W.z, st);
         apply_op<T>(s, 0, kApplyY, W.z, W.w, nullptr, nullptr, nullptr, T(0), T(0), nullptr);
         cd::launch_multidot<T>(V, j + 1, W.w, N, W.part, nb, st);
         cd::launch_multifinal(W.part, j + 1, nb, W.H + size_t(j) * ld, st);
@@ -451,7 +469,7 @@ void gmres_post(cd_solver* s, VWork<T>& W, const T* b, T* x) {
     }
     cd::launch_hessenberg_ls(W.H, ld, ks, W.scal, W.y, st);
     cd::launch_combine<T>(V, ks, W.y, W.w, N, st);
-    cd::launch_tsolve<T>(s->d, s->lv[0].m, tfacs<T>(s), W.w, st);
+    cd::launch_tsolve<T>(s->d, s->lv[0].m, tfacs<T>(s), W.w, W.tmp, W.w, st);
     cd::launch_axpby<T>(T(1), W.w, T(1), x, N, st);
 }
 
@@ -617,10 +635,19 @@ void create(cd_solver* s, const cd_problem* pr, const cd_options* op, void* stre
     hip_check(hipStreamSynchronize(st), "sync");
 }
 
-void solve(cd_solver* s, const double* b, double* x, cd_result* res) {
+// ---- the outer flexible CG as a resumable state machine ---------------------------
+// begin: x = 0, r = b, ||r_0|| (one synchronisation); iterate: enqueue one
+// outer iteration (preconditioner, direction, A d, updates) and an
+// asynchronous read of (r.r, d.q) into pinned memory followed by an event;
+// check: after the event completed, apply the stopping rule ||r_k||/||r_0|| <
+// rtol of Sec. 6.2 and the breakdown test; finish: FP64 true residual.
+void solve_begin(cd_solver* s, const double* b, double* x) {
     hipStream_t st = s->stream;
     const size_t N = s->N;
-    cd_result out{};
+    SolveState& S = s->state;
+    S = SolveState{};
+    S.b = b;
+    S.x = x;
     cd::launch_fill<double>(x, 0.0, N, st);
     cd::launch_copy<double>(b, s->r, N, st);
     cd::launch_dot_partial<double, double>(s->r, s->r, N, s->prr, st);
@@ -629,55 +656,80 @@ void solve(cd_solver* s, const double* b, double* x, cd_result* res) {
     hip_check(hipStreamSynchronize(st), "sync");
     const double rr0 = s->host_scal[0];
     if (!std::isfinite(rr0)) throw CdError(CD_EINVAL, "right-hand side is not finite");
-    if (rr0 == 0.0) {
-        out.status = CD_OK;
-        if (res) *res = out;
-        return;
+    S.r0 = std::sqrt(rr0);
+    S.rel = 1.0;
+    S.status = (rr0 == 0.0) ? CD_OK : CD_NOT_CONVERGED;
+    S.done = (rr0 == 0.0);
+    if (!s->iter_event) hip_check(hipEventCreateWithFlags(&s->iter_event, hipEventDisableTiming), "hipEventCreate");
+}
+
+void solve_iterate(cd_solver* s) {
+    hipStream_t st = s->stream;
+    const size_t N = s->N;
+    SolveState& S = s->state;
+    if (s->opt.method == CD_METHOD_CG) {
+        cd::launch_copy<double>(s->r, s->z, N, st);
+    } else {
+        precondition(s, s->r, s->z);
     }
-    const double r0 = std::sqrt(rr0);
-    const cd::OpDev<double>& op = s->ld64[0].op;
-    int status = CD_NOT_CONVERGED;
-    int k = 0;
-    double rel = 1.0;
-    while (k < s->opt.max_iter) {
-        if (s->opt.method == CD_METHOD_CG) {
-            cd::launch_copy<double>(s->r, s->z, N, st);
-        } else {
-            precondition(s, s->r, s->z);
-        }
-        if (k > 0) cd::launch_dot_partial<double, double>(s->z, s->q, N, s->pzq, st);
-        cd::launch_fcg_direction(k == 0, s->z, s->pzq, s->nbr, s->scal + 1, s->dd, s->r, s->pdr, N, st);
-        apply_op<double>(s, 0, kApplyYDot, s->dd, s->q, nullptr, nullptr, nullptr, 0.0, 0.0, s->pdq);
-        cd::launch_fcg_update(s->pdr, s->nbr, s->pdq, s->nba, s->scal + 1, x, s->r, s->dd, s->q, s->prr, N, st);
-        cd::launch_finalize(s->prr, s->nbr, s->scal, st);
-        hip_check(hipMemcpyAsync(s->host_scal, s->scal, 2 * sizeof(double), hipMemcpyDeviceToHost, st), "read");
+    if (S.k > 0) cd::launch_dot_partial<double, double>(s->z, s->q, N, s->pzq, st);
+    cd::launch_fcg_direction(S.k == 0, s->z, s->pzq, s->nbr, s->scal + 1, s->dd, s->r, s->pdr, N, st);
+    apply_op<double>(s, 0, kApplyYDot, s->dd, s->q, nullptr, nullptr, nullptr, 0.0, 0.0, s->pdq);
+    cd::launch_fcg_update(s->pdr, s->nbr, s->pdq, s->nba, s->scal + 1, S.x, s->r, s->dd, s->q, s->prr, N, st);
+    cd::launch_finalize(s->prr, s->nbr, s->scal, st);
+    hip_check(hipMemcpyAsync(s->host_scal, s->scal, 2 * sizeof(double), hipMemcpyDeviceToHost, st), "read");
+    hip_check(hipEventRecord(s->iter_event, st), "hipEventRecord");
+}
+
+// Call after s->iter_event completed; returns true when the solve has ended.
+bool solve_check(cd_solver* s) {
+    SolveState& S = s->state;
+    if (s->prof) prof_flush(s);
+    ++S.k;
+    const double rr = s->host_scal[0], dq = s->host_scal[1];
+    S.rel = std::sqrt(rr) / S.r0;
+    if (!std::isfinite(rr) || !std::isfinite(dq) || !(dq > 0.0)) {
+        S.status = CD_EBREAKDOWN;
+        S.done = true;
+    } else if (S.rel < s->opt.rtol) {
+        S.status = CD_OK;
+        S.done = true;
+    } else if (S.k >= s->opt.max_iter) {
+        S.status = CD_NOT_CONVERGED;
+        S.done = true;
+    }
+    return S.done;
+}
+
+cd_result solve_finish(cd_solver* s) {
+    hipStream_t st = s->stream;
+    const size_t N = s->N;
+    SolveState& S = s->state;
+    cd_result out{};
+    out.status = S.status;
+    out.iterations = S.k;
+    out.rel_residual = (S.r0 > 0.0) ? S.rel : 0.0;
+    if (S.r0 > 0.0) {
+        cd::launch_apply<double>(s->ld64[0].op, kApplyRes, S.x, s->z, S.b, nullptr, nullptr, 0.0, 0.0, nullptr, st);
+        cd::launch_dot_partial<double, double>(s->z, s->z, N, s->prr, st);
+        cd::launch_finalize(s->prr, s->nbr, s->scal + 2, st);
+        hip_check(hipMemcpyAsync(s->host_scal + 2, s->scal + 2, sizeof(double), hipMemcpyDeviceToHost, st), "read");
         hip_check(hipStreamSynchronize(st), "sync");
-        if (s->prof) prof_flush(s);
-        ++k;
-        const double rr = s->host_scal[0], dq = s->host_scal[1];
-        if (!std::isfinite(rr) || !std::isfinite(dq) || !(dq > 0.0)) {
-            status = CD_EBREAKDOWN;
-            rel = std::sqrt(rr) / r0;
-            break;
-        }
-        rel = std::sqrt(rr) / r0;
-        if (rel < s->opt.rtol) {
-            status = CD_OK;
-            break;
-        }
+        out.true_rel_residual = std::sqrt(s->host_scal[2]) / S.r0;
     }
-    // true residual in FP64
-    cd::launch_apply<double>(op, kApplyRes, x, s->z, b, nullptr, nullptr, 0.0, 0.0, nullptr, st);
-    cd::launch_dot_partial<double, double>(s->z, s->z, N, s->prr, st);
-    cd::launch_finalize(s->prr, s->nbr, s->scal + 2, st);
-    hip_check(hipMemcpyAsync(s->host_scal + 2, s->scal + 2, sizeof(double), hipMemcpyDeviceToHost, st), "read");
-    hip_check(hipStreamSynchronize(st), "sync");
-    out.status = status;
-    out.iterations = k;
-    out.rel_residual = rel;
-    out.true_rel_residual = std::sqrt(s->host_scal[2]) / r0;
+    return out;
+}
+
+void solve(cd_solver* s, const double* b, double* x, cd_result* res) {
+    solve_begin(s, b, x);
+    while (!s->state.done) {
+        solve_iterate(s);
+        hip_check(hipEventSynchronize(s->iter_event), "hipEventSynchronize");
+        solve_check(s);
+    }
+    const cd_result out = solve_finish(s);
     if (res) *res = out;
-    if (status == CD_EBREAKDOWN) throw CdError(CD_EBREAKDOWN, "Krylov breakdown (d^T A d <= 0 or non-finite)");
+    if (out.status == CD_EBREAKDOWN) throw CdError(CD_EBREAKDOWN, "Krylov breakdown (d^T A d <= 0 or non-finite)");
 }
 
 }  // namespace
@@ -909,8 +961,8 @@ int cd_prolong_add(cd_solver* s, int level, const double* ec, double* xf) {
 int cd_tsolve(cd_solver* s, const double* v, double* z) {
     return run([&] {
         need(s);
-        if (v != z) cd::launch_copy<double>(v, z, s->N, s->stream);
-        cd::launch_tsolve<double>(s->d, s->lv[0].m, s->tfd64, z, s->stream);
+        // the outer vector q is free outside a solve and serves as scratch
+        cd::launch_tsolve<double>(s->d, s->lv[0].m, s->tfd64, v, s->q, z, s->stream);
         hip_check(hipStreamSynchronize(s->stream), "sync");
     });
 }
@@ -954,6 +1006,178 @@ int cd_profile_read(const cd_solver* s, int level, int fp32, cd_kernel_stats* ou
         *out = (k < s->prof_stats.size()) ? s->prof_stats[k] : cd_kernel_stats{0, 0.0, 0.0};
     });
 }
+
+// =============================== serving loop ===============================
+struct cd_server {
+    cd_server_options opt{};
+    std::vector<hipStream_t> streams;
+    struct Req {
+        uint64_t ticket;
+        cd_problem prob;
+        cd_options opt;
+        const double* b;
+        double* x;
+        size_t fp;
+        double t_submit, t_admit;
+        cd_solver* solver;
+    };
+    std::deque<Req> queue;
+    std::vector<Req> active;
+    std::deque<cd_completion> done;
+    size_t used = 0;
+    uint64_t next_ticket = 1;
+    uint64_t admitted = 0;
+    std::chrono::steady_clock::time_point t0;
+    double now() const { return std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count(); }
+    ~cd_server() {
+        for (auto& r : active) cd_solver_destroy(r.solver);
+        for (hipStream_t st : streams) (void)hipStreamDestroy(st);
+    }
+};
+
+namespace {
+void server_complete(cd_server* srv, cd_server::Req& r, const cd_result& res) {
+    cd_completion c{};
+    c.ticket = r.ticket;
+    c.result = res;
+    c.t_submit = r.t_submit;
+    c.t_admit = r.t_admit;
+    c.t_done = srv->now();
+    c.footprint_bytes = r.fp;
+    srv->done.push_back(c);
+}
+}  // namespace
+
+void cd_server_default_options(cd_server_options* o) {
+    if (!o) return;
+    o->hbm_budget_bytes = 0;
+    o->max_active = 64;
+    o->num_streams = 4;
+}
+
+int cd_server_create(const cd_server_options* opt, cd_server** out) {
+    if (!out) {
+        g_last_error = "null output pointer";
+        return CD_EINVAL;
+    }
+    *out = nullptr;
+    cd_server* srv = new (std::nothrow) cd_server();
+    if (!srv) return CD_ENOMEM;
+    const int rc = run([&] {
+        cd_server_options o;
+        cd_server_default_options(&o);
+        if (opt) o = *opt;
+        if (o.max_active <= 0) o.max_active = 64;
+        if (o.num_streams <= 0) o.num_streams = 4;
+        if (o.num_streams > 16) throw CdError(CD_EINVAL, "num_streams must be <= 16");
+        if (o.hbm_budget_bytes == 0) {
+            size_t fr = 0, tot = 0;
+            hip_check(hipMemGetInfo(&fr, &tot), "hipMemGetInfo");
+            o.hbm_budget_bytes = size_t(0.8 * double(fr));
+        }
+        srv->opt = o;
+        for (int i = 0; i < o.num_streams; ++i) {
+            hipStream_t st = nullptr;
+            hip_check(hipStreamCreateWithFlags(&st, hipStreamNonBlocking), "hipStreamCreate");
+            srv->streams.push_back(st);
+        }
+        srv->t0 = std::chrono::steady_clock::now();
+    });
+    if (rc != CD_OK) {
+        delete srv;
+        return rc;
+    }
+    *out = srv;
+    return CD_OK;
+}
+
+int cd_server_submit(cd_server* srv, const cd_problem* prob, const cd_options* opt, const double* b, double* x,
+                     uint64_t* ticket) {
+    return run([&] {
+        if (!srv) throw CdError(CD_EINVAL, "null server");
+        if (!b || !x) throw CdError(CD_EINVAL, "null vector");
+        validate(prob, opt);
+        const size_t fp = cd_footprint_bytes(prob, opt);
+        if (fp == 0 || fp > srv->opt.hbm_budget_bytes) throw CdError(CD_ENOMEM, "request larger than the server's HBM budget");
+        cd_server::Req r{};
+        r.ticket = srv->next_ticket++;
+        r.prob = *prob;
+        r.opt = *opt;
+        r.b = b;
+        r.x = x;
+        r.fp = fp;
+        r.t_submit = srv->now();
+        r.solver = nullptr;
+        srv->queue.push_back(r);
+        if (ticket) *ticket = r.ticket;
+    });
+}
+
+int cd_server_step(cd_server* srv, int* n_active, int* n_queued) {
+    return run([&] {
+        if (!srv) throw CdError(CD_EINVAL, "null server");
+        // admission: FIFO, by footprint and slot count
+        while (!srv->queue.empty() && int(srv->active.size()) < srv->opt.max_active &&
+               srv->used + srv->queue.front().fp <= srv->opt.hbm_budget_bytes) {
+            cd_server::Req r = srv->queue.front();
+            srv->queue.pop_front();
+            r.t_admit = srv->now();
+            hipStream_t st = srv->streams[srv->admitted++ % srv->streams.size()];
+            cd_solver* h = nullptr;
+            const int rc = cd_solver_create(&r.prob, &r.opt, st, &h);
+            if (rc != CD_OK) {
+                cd_result res{};
+                res.status = rc;
+                server_complete(srv, r, res);
+                continue;
+            }
+            r.solver = h;
+            const int rb = run([&] { solve_begin(h, r.b, r.x); });
+            if (rb != CD_OK || h->state.done) {
+                cd_result res{};
+                res.status = (rb != CD_OK) ? rb : h->state.status;
+                server_complete(srv, r, res);
+                cd_solver_destroy(h);
+                continue;
+            }
+            srv->used += r.fp;
+            srv->active.push_back(r);
+        }
+        // one outer iteration of every active solve, all enqueued before any wait
+        for (auto& r : srv->active) solve_iterate(r.solver);
+        std::vector<cd_server::Req> keep;
+        keep.reserve(srv->active.size());
+        for (auto& r : srv->active) {
+            hip_check(hipEventSynchronize(r.solver->iter_event), "hipEventSynchronize");
+            if (solve_check(r.solver)) {
+                const cd_result res = solve_finish(r.solver);
+                server_complete(srv, r, res);
+                cd_solver_destroy(r.solver);
+                srv->used -= r.fp;
+            } else {
+                keep.push_back(r);
+            }
+        }
+        srv->active.swap(keep);
+        if (n_active) *n_active = int(srv->active.size());
+        if (n_queued) *n_queued = int(srv->queue.size());
+    });
+}
+
+int cd_server_poll(cd_server* srv, cd_completion* out, int max, int* n_out) {
+    return run([&] {
+        if (!srv) throw CdError(CD_EINVAL, "null server");
+        int n = 0;
+        while (n < max && !srv->done.empty()) {
+            if (out) out[n] = srv->done.front();
+            srv->done.pop_front();
+            ++n;
+        }
+        if (n_out) *n_out = n;
+    });
+}
+
+void cd_server_destroy(cd_server* srv) { delete srv; }
 
 const char* cd_status_string(int st) {
     switch (st) {
