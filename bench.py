@@ -64,6 +64,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-c4", action="store_true", help="skip the 3D p=3 n=128 operator-apply measurement")
     ap.add_argument("--only-c4", action="store_true", help="run only the 3D p=3 n=128 operator-apply measurement")
+    ap.add_argument("--serve", type=int, default=16, help="requests of the serving stream to run (0: skip)")
+    ap.add_argument("--serve-max-iter", type=int, default=4000)
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: this build has no multi-GPU path (see DESIGN.md, sharding)",
@@ -181,10 +183,67 @@ def main():
         out["operator_apply_c4"] = c4_apply(capi, torch, st)
         log(f"3D p=3 n=128 operator apply: {out['operator_apply_c4']}")
 
+    if args.serve > 0:
+        out["serving"] = serve_bench(capi, torch, st, args.serve, args.serve_max_iter, log)
+        log(f"serving: {out['serving']}")
+
     if not args.no_cpu_baseline:
         log("timing the oracle on the host")
         out["cpu_baseline"] = cpu_baseline(cfg, its)
     print(json.dumps(out), flush=True)
+
+
+def serve_bench(capi, torch, st, count, max_iter, log):
+    """The serving workload: `count` seeded requests of the stream (2D/3D,
+    p in {2,3,4}, n log-uniform, beta log-uniform in [1e-6, 1]) submitted at
+    once to the mixed-precision server; then the same requests solved one
+    after another by the plain FP64 single-solve path.  Both include solver
+    setup; right-hand sides are resident in HBM before timing starts."""
+    import curldiv_inputs as ci
+
+    reqs = ci.serving_stream(count, seed=7)
+    data = []
+    for r in reqs:
+        prob = capi.problem(r["dim"], r["p"], r["n"], r["alpha"], r["beta"])
+        b = torch.as_tensor(ci.rhs(r["dim"], r["p"], r["n"], r["seed"])).cuda()
+        data.append((prob, b, torch.zeros_like(b), torch.zeros_like(b)))
+    torch.cuda.synchronize()
+    srv = capi.Server(max_active=32)
+    t0 = time.perf_counter()
+    ticket = {}
+    for i, (prob, b, x, _) in enumerate(data):
+        opt = capi.options(precision=capi.CD_MIXED_FP32, rtol=1e-8, max_iter=max_iter)
+        ticket[srv.submit(prob, opt, b.data_ptr(), x.data_ptr())] = i
+    done = {}
+    while True:
+        a, q = srv.step()
+        for c in srv.poll():
+            done[ticket[c.ticket]] = c
+        if a == 0 and q == 0:
+            break
+    T = time.perf_counter() - t0
+    srv.close()
+    lat = [c.t_done - c.t_submit for c in done.values()]
+    ok = sum(1 for c in done.values() if c.result.status == capi.CD_OK)
+    its = [c.result.iterations for c in done.values()]
+    log(f"server done in {T:.2f}s; converged {ok}/{count}")
+    t1 = time.perf_counter()
+    ok64, lat64 = 0, []
+    for prob, b, _, x in data:
+        ts = time.perf_counter()
+        s = capi.Solver(prob, capi.options(rtol=1e-8, max_iter=max_iter), st)
+        r = s.solve(b.data_ptr(), x.data_ptr())
+        s.close()
+        lat64.append(time.perf_counter() - ts)
+        ok64 += int(r.status == capi.CD_OK)
+    T64 = time.perf_counter() - t1
+    return {"requests": count, "mode": "burst (all submitted at t=0), mixed FP32/FP64, max 32 in flight",
+            "solves_per_s": count / T, "converged": ok, "p50_ms": 1e3 * percentile(lat, 50),
+            "p99_ms": 1e3 * percentile(lat, 99), "iterations_min_max": [min(its), max(its)],
+            "max_iter": max_iter,
+            "fp64_sequential": {"solves_per_s": count / T64, "converged": ok64,
+                                "p50_ms": 1e3 * percentile(lat64, 50), "p99_ms": 1e3 * percentile(lat64, 99)},
+            "speedup_vs_fp64_sequential": T64 / T}
 
 
 def c4_apply(capi, torch, st, reps=20):

@@ -89,11 +89,13 @@ typedef struct {
     double cheb_ratio;    /* smoothing interval [hi/ratio, hi]               */
     int power_iters;      /* power steps for the smoother's eigenvalue bound */
     int krylov_steps;     /* finest post-smoothing GMRES steps; < 0 means p  */
+    int graphs;           /* 1: replay outer iterations from a captured HIP graph
+                             (identical arithmetic); 0: launch every kernel eagerly */
 } cd_options;
 
 /* Fill *opt with the defaults: P_MIM, knot insertion, FP64, rtol 1e-8,
  * max_iter 10000, coarse_max_dofs 1000, cheb_degree 3, cheb_ratio 30,
- * power_iters 10, krylov_steps = p. */
+ * power_iters 10, krylov_steps = p, graphs 1. */
 void cd_default_options(cd_options* opt);
 
 typedef struct {

@@ -14,7 +14,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(HERE, "libcurldiv.so")
-SOURCES = ["csrc/setup.cpp", "csrc/kernels.hip", "csrc/solver.hip"]
+SOURCES = ["csrc/setup.cpp", "csrc/kernels.hip", "csrc/coarse.hip", "csrc/solver.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [

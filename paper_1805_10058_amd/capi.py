@@ -39,7 +39,7 @@ class cd_options(ctypes.Structure):
     _fields_ = [("method", ctypes.c_int), ("transfer", ctypes.c_int), ("precision", ctypes.c_int),
                 ("rtol", ctypes.c_double), ("max_iter", ctypes.c_int), ("coarse_max_dofs", ctypes.c_int),
                 ("cheb_degree", ctypes.c_int), ("cheb_ratio", ctypes.c_double), ("power_iters", ctypes.c_int),
-                ("krylov_steps", ctypes.c_int)]
+                ("krylov_steps", ctypes.c_int), ("graphs", ctypes.c_int)]
 
 
 class cd_kernel_stats(ctypes.Structure):

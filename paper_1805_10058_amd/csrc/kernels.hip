@@ -4,6 +4,8 @@
 // Every reduction accumulates in FP64 and combines partial sums in a fixed
 // order, so results are bitwise reproducible run to run.
 #include <algorithm>
+#include <map>
+#include <mutex>
 #include <stdexcept>
 #include <string>
 
@@ -375,6 +377,25 @@ size_t apply_lds_bytes(const OpDev<T>& op) {
     return sizeof(T) * (2 * size_t(kThreads + 2 * hb * op.m[1]) + 6 * size_t(kThreads));
 }
 
+// Raise a kernel's dynamic-LDS limit (default 64 KiB) to what a launch needs,
+// once per kernel and size.  The first launch of every kernel with a given
+// problem happens in setup or in the first, uncaptured outer iteration, so
+// this never runs inside a stream capture.
+void allow_lds(const void* kern, size_t lds) {
+    if (lds <= 64 * 1024) return;
+    static std::mutex mu;
+    static std::map<const void*, size_t> done;
+    std::lock_guard<std::mutex> g(mu);
+    auto it = done.find(kern);
+    if (it != done.end() && it->second >= lds) return;
+    const hipError_t e = hipFuncSetAttribute(kern, hipFuncAttributeMaxDynamicSharedMemorySize, int(lds));
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        throw std::runtime_error(std::string("hipFuncSetAttribute: ") + hipGetErrorString(e));
+    }
+    done[kern] = lds;
+}
+
 template <typename T, int HB, int MODE>
 void apply_dispatch(const OpDev<T>& op, const T* x, T* y, const T* b, T* u, T* xout, T c1, T c2, double* part,
                     hipStream_t s) {
@@ -386,14 +407,14 @@ void apply_dispatch(const OpDev<T>& op, const T* x, T* y, const T* b, T* u, T* x
         const int nchunk = (PL + tpb - 1) / tpb;
         const int nx1 = (op.m[0] + kX1Chunk - 1) / kX1Chunk;
         auto kern = k_apply3d<T, HB, MODE>;
-        if (lds > 64 * 1024) hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, int(lds));
+        allow_lds(reinterpret_cast<const void*>(kern), lds);
         hipLaunchKernelGGL(kern, dim3(nchunk * nx1), dim3(kThreads), lds, s, op, x, y, b, u, xout, c1, c2, part,
                            nchunk, kX1Chunk);
     } else {
         const int G = op.m[0] * op.m[1];
         const int tpb = kThreads - 2 * HB;
         auto kern = k_apply2d<T, HB, MODE>;
-        if (lds > 64 * 1024) hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, int(lds));
+        allow_lds(reinterpret_cast<const void*>(kern), lds);
         hipLaunchKernelGGL(kern, dim3((G + tpb - 1) / tpb), dim3(kThreads), lds, s, op, x, y, b, u, xout, c1, c2,
                            part);
     }
@@ -416,6 +437,8 @@ void apply_mode(const OpDev<T>& op, int mode, const T* x, T* y, const T* b, T* u
 // Grid transfers: Kronecker products of 1D prolongators, one thread per
 // output entry (coarse entry for the restriction P^T r, fine entry for x += P e).
 // ------------------------------------------------------------------------------
+constexpr int kMaxWin = 8;  // widest prolongator window (p + 2 for p <= 6)
+
 template <typename T>
 __global__ __launch_bounds__(kThreads) void k_restrict(XferDev<T> X, int ncomp, const T* __restrict__ rf,
                                                        T* __restrict__ rc) {
@@ -432,22 +455,25 @@ __global__ __launch_bounds__(kThreads) void k_restrict(XferDev<T> X, int ncomp, 
     rem /= a2.mc;
     const int J1 = int(rem % a1.mc);
     const int J0 = int(rem / a1.mc);
-    double acc = 0.0;
+    T p2[kMaxWin];
+#pragma unroll
+    for (int k2 = 0; k2 < kMaxWin; ++k2) p2[k2] = (k2 < a2.wr) ? a2.vt[J2 * a2.wr + k2] : T(0);
+    T acc = T(0);
     for (int k0 = 0; k0 < a0.wr; ++k0) {
         const T p0 = a0.vt[J0 * a0.wr + k0];
-        if (p0 == T(0)) continue;
         const int i0 = a0.r0[J0] + k0;
         for (int k1 = 0; k1 < a1.wr; ++k1) {
             const T p1 = a1.vt[J1 * a1.wr + k1];
-            if (p1 == T(0)) continue;
             const int i1 = a1.r0[J1] + k1;
             const T* row = rf + size_t(c) * Gf + (size_t(i0) * a1.mf + i1) * a2.mf + a2.r0[J2];
             T s2 = T(0);
-            for (int k2 = 0; k2 < a2.wr; ++k2) s2 += a2.vt[J2 * a2.wr + k2] * row[k2];
-            acc += double(p0 * p1 * s2);
+#pragma unroll
+            for (int k2 = 0; k2 < kMaxWin; ++k2)
+                if (k2 < a2.wr) s2 += p2[k2] * row[k2];
+            acc += p0 * p1 * s2;
         }
     }
-    rc[id] = T(acc);
+    rc[id] = acc;
 }
 
 template <typename T>
@@ -466,18 +492,21 @@ __global__ __launch_bounds__(kThreads) void k_prolong_add(XferDev<T> X, int ncom
     rem /= a2.mf;
     const int i1 = int(rem % a1.mf);
     const int i0 = int(rem / a1.mf);
+    T p2[kMaxWin];
+#pragma unroll
+    for (int k2 = 0; k2 < kMaxWin; ++k2) p2[k2] = (k2 < a2.w) ? a2.v[i2 * a2.w + k2] : T(0);
     T acc = T(0);
     for (int k0 = 0; k0 < a0.w; ++k0) {
         const T p0 = a0.v[i0 * a0.w + k0];
-        if (p0 == T(0)) continue;
         const int J0 = a0.c0[i0] + k0;
         for (int k1 = 0; k1 < a1.w; ++k1) {
             const T p1 = a1.v[i1 * a1.w + k1];
-            if (p1 == T(0)) continue;
             const int J1 = a1.c0[i1] + k1;
             const T* row = ec + size_t(c) * Gc + (size_t(J0) * a1.mc + J1) * a2.mc + a2.c0[i2];
             T s2 = T(0);
-            for (int k2 = 0; k2 < a2.w; ++k2) s2 += a2.v[i2 * a2.w + k2] * row[k2];
+#pragma unroll
+            for (int k2 = 0; k2 < kMaxWin; ++k2)
+                if (k2 < a2.w) s2 += p2[k2] * row[k2];
             acc += p0 * p1 * s2;
         }
     }
@@ -496,102 +525,121 @@ __global__ __launch_bounds__(kThreads) void k_prolong_add(XferDev<T> X, int ncom
 // ------------------------------------------------------------------------------
 struct LineGeom {
     size_t G, lines_per_comp;
-    int ma, axis, m1, m2, nchunk, chunk;
+    int ma, axis, m1, m2, nchunk, chunk, ncomp;
 };
 
-__device__ inline void line_base(const LineGeom& g, size_t item, int& c, int& ch, size_t& base, size_t& stride) {
-    const size_t line = item % g.lines_per_comp;
-    const size_t rest = item / g.lines_per_comp;
-    ch = int(rest % g.nchunk);
-    c = int(rest / g.nchunk);
-    if (g.axis == 0) {
-        base = line;
-        stride = size_t(g.m1) * g.m2;
-    } else if (g.axis == 1) {
-        base = (line / g.m2) * size_t(g.m1) * g.m2 + line % g.m2;
-        stride = g.m2;
-    } else {
-        base = line * g.m2;
-        stride = 1;
-    }
-    base += size_t(c) * g.G;
-}
+constexpr int kLineThreads = 64;  // one wave per block in the line solves
+constexpr int kLoadGroup = 16;    // staging loads issued together per lane
 
-constexpr int kRowBatch = 8;  // rows whose loads are issued together in the line recurrences
-
+// One chunk of one grid line per lane; the 64 lanes of a block take 64
+// consecutive lines of the same chunk (the line index is padded to a
+// multiple of 64), so they share the row span [r0-warm, r1+warm).  The block
+// stages the factor rows of the span in LDS once, each lane stages its line's
+// values (loads issued in groups before any store), runs the forward
+// recurrence over the whole span (storing D^{-1} y back into LDS), then the
+// backward recurrence from the top of the span down to r0, and writes rows
+// [r0, r1).  LDS layout [row][lane] keeps a wave's accesses conflict free.
+// Out of place: in != out.
 template <typename T, int BW>
-__global__ __launch_bounds__(kThreads) void k_tsolve_fwd(const T* __restrict__ in, T* __restrict__ out, size_t items,
-                                                         LineGeom g, const T* __restrict__ L,
-                                                         const T* __restrict__ dinv, int warm) {
-    const size_t item = size_t(blockIdx.x) * kThreads + threadIdx.x;
-    if (item >= items) return;
-    int c, ch;
-    size_t base, stride;
-    line_base(g, item, c, ch, base, stride);
+__global__ __launch_bounds__(kLineThreads) void k_tsolve_line(const T* __restrict__ in, T* __restrict__ out,
+                                                              LineGeom g, size_t lines_padded,
+                                                              const T* __restrict__ L,
+                                                              const T* __restrict__ dinv, int warm) {
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    T* sp = reinterpret_cast<T*>(smem_raw);
+    const int lane = threadIdx.x;
+    const size_t first = size_t(blockIdx.x) * kLineThreads;  // block-uniform
+    const size_t grp = first / lines_padded;                  // (component, chunk) of the block
+    const size_t line = first % lines_padded + lane;
+    const int ch = int(grp % g.nchunk);
+    const int c = int(grp / g.nchunk);
     const int r0 = ch * g.chunk, r1 = min(g.ma, r0 + g.chunk);
-    const int rs = max(0, r0 - warm);
+    const int rs = max(0, r0 - warm), re = min(g.ma, r1 + warm);
+    const int span = re - rs;
+    T* cf = sp + size_t(span) * kLineThreads;  // [span][BW] factor rows
+    T* dv = cf + size_t(span) * BW;            // [span] 1 / D
+    for (int e = lane; e < span * BW; e += kLineThreads) cf[e] = L[size_t(rs) * BW + e];
+    for (int e = lane; e < span; e += kLineThreads) dv[e] = dinv[rs + e];
+    const bool active = line < g.lines_per_comp;
+    size_t base = 0, stride = 0;
+    if (active) {
+        if (g.axis == 0) {
+            base = line;
+            stride = size_t(g.m1) * g.m2;
+        } else if (g.axis == 1) {
+            base = (line / g.m2) * size_t(g.m1) * g.m2 + line % g.m2;
+            stride = g.m2;
+        } else {
+            base = line * g.m2;
+            stride = 1;
+        }
+        base += size_t(c) * g.G;
+        for (int r = 0; r < span; r += kLoadGroup) {
+            T v[kLoadGroup];
+#pragma unroll
+            for (int q = 0; q < kLoadGroup; ++q) v[q] = (r + q < span) ? in[base + size_t(rs + r + q) * stride] : T(0);
+#pragma unroll
+            for (int q = 0; q < kLoadGroup; ++q)
+                if (r + q < span) sp[(r + q) * kLineThreads + lane] = v[q];
+        }
+    }
+    __syncthreads();
+    if (!active) return;
+    // recurrences in groups of kRowGroup rows: the group's LDS reads are issued
+    // together, then the dependent FMA chain runs on registers
+    constexpr int G = 8;
     T win[BW];
 #pragma unroll
     for (int k = 0; k < BW; ++k) win[k] = T(0);
-    for (int rb = rs; rb < r1; rb += kRowBatch) {
-        T vin[kRowBatch], lc[kRowBatch][BW], dv[kRowBatch];
+    for (int rb = 0; rb < span; rb += G) {
+        T v[G], cq[G][BW], dq[G];
 #pragma unroll
-        for (int q = 0; q < kRowBatch; ++q) {
-            const int r = min(rb + q, r1 - 1);  // clamped: rows past r1 are loaded but not used
-            vin[q] = in[base + size_t(r) * stride];
-            dv[q] = dinv[r];
+        for (int q = 0; q < G; ++q) {
+            const int r = min(rb + q, span - 1);
+            v[q] = sp[r * kLineThreads + lane];
+            dq[q] = dv[r];
 #pragma unroll
-            for (int k = 0; k < BW; ++k) lc[q][k] = L[r * BW + k];
+            for (int k = 0; k < BW; ++k) cq[q][k] = cf[r * BW + k];
         }
 #pragma unroll
-        for (int q = 0; q < kRowBatch; ++q) {
-            const int r = rb + q;
-            if (r < r1) {
-                T v = vin[q];
+        for (int q = 0; q < G; ++q) {
+            T x = v[q];
 #pragma unroll
-                for (int k = 1; k <= BW; ++k) v -= lc[q][k - 1] * win[k - 1];
+            for (int k = 1; k <= BW; ++k) x -= cq[q][k - 1] * win[k - 1];
+            if (rb + q < span) {
 #pragma unroll
                 for (int k = BW - 1; k >= 1; --k) win[k] = win[k - 1];
-                win[0] = v;
-                if (r >= r0) out[base + size_t(r) * stride] = v * dv[q];
+                win[0] = x;
             }
+            v[q] = x * dq[q];
         }
+#pragma unroll
+        for (int q = 0; q < G; ++q)
+            if (rb + q < span) sp[(rb + q) * kLineThreads + lane] = v[q];
     }
-}
-
-template <typename T, int BW>
-__global__ __launch_bounds__(kThreads) void k_tsolve_bwd(const T* __restrict__ in, T* __restrict__ out, size_t items,
-                                                         LineGeom g, const T* __restrict__ L, int warm) {
-    const size_t item = size_t(blockIdx.x) * kThreads + threadIdx.x;
-    if (item >= items) return;
-    int c, ch;
-    size_t base, stride;
-    line_base(g, item, c, ch, base, stride);
-    const int r0 = ch * g.chunk, r1 = min(g.ma, r0 + g.chunk);
-    const int re = min(g.ma, r1 + warm);
-    T win[BW];
 #pragma unroll
     for (int k = 0; k < BW; ++k) win[k] = T(0);
-    for (int rb = re - 1; rb >= r0; rb -= kRowBatch) {
-        T vin[kRowBatch], lc[kRowBatch][BW];
+    const int rlo = r0 - rs;
+    for (int rb = span - 1; rb >= rlo; rb -= G) {
+        T v[G], cq[G][BW];
 #pragma unroll
-        for (int q = 0; q < kRowBatch; ++q) {
-            const int r = max(rb - q, r0);  // clamped: rows below r0 are loaded but not used
-            vin[q] = in[base + size_t(r) * stride];
+        for (int q = 0; q < G; ++q) {
+            const int r = max(rb - q, rlo);
+            v[q] = sp[r * kLineThreads + lane];
 #pragma unroll
-            for (int k = 1; k <= BW; ++k) lc[q][k - 1] = (r + k < g.ma) ? L[(r + k) * BW + k - 1] : T(0);
+            for (int k = 1; k <= BW; ++k) cq[q][k - 1] = (r + k < span) ? cf[(r + k) * BW + k - 1] : T(0);
         }
 #pragma unroll
-        for (int q = 0; q < kRowBatch; ++q) {
+        for (int q = 0; q < G; ++q) {
             const int r = rb - q;
-            if (r >= r0) {
-                T v = vin[q];
+            if (r >= rlo) {
+                T x = v[q];
 #pragma unroll
-                for (int k = 1; k <= BW; ++k) v -= lc[q][k - 1] * win[k - 1];
+                for (int k = 1; k <= BW; ++k) x -= cq[q][k - 1] * win[k - 1];
 #pragma unroll
                 for (int k = BW - 1; k >= 1; --k) win[k] = win[k - 1];
-                win[0] = v;
-                if (r < r1) out[base + size_t(r) * stride] = v;
+                win[0] = x;
+                if (rs + r < r1) out[base + size_t(rs + r) * stride] = x;
             }
         }
     }
@@ -691,11 +739,11 @@ __global__ __launch_bounds__(kThreads) void k_cheb_first(OpDev<T> op, const T* _
 
 // z = Kinv r, one block per row, FP64 accumulation
 template <typename T>
-__global__ __launch_bounds__(kThreads) void k_coarse_gemv(const double* __restrict__ Kinv, int N,
+__global__ __launch_bounds__(kThreads) void k_coarse_gemv(const double* __restrict__ Kinv, int N, int ld,
                                                           const T* __restrict__ r, T* __restrict__ z) {
     const int row = blockIdx.x;
     double s = 0.0;
-    for (int j = threadIdx.x; j < N; j += kThreads) s += Kinv[size_t(row) * N + j] * double(r[j]);
+    for (int j = threadIdx.x; j < N; j += kThreads) s += Kinv[size_t(row) * ld + j] * double(r[j]);
     s = block_sum(s);
     if (threadIdx.x == 0) z[row] = T(s);
 }
@@ -843,7 +891,7 @@ int grid_for(size_t n) {
 // ================================ launch wrappers =================================
 
 int reduce_blocks(size_t n) {
-    const size_t nb = (n + size_t(kThreads) * 8 - 1) / (size_t(kThreads) * 8);
+    const size_t nb = (n + size_t(kThreads) * 2 - 1) / (size_t(kThreads) * 2);
     return int(std::max<size_t>(1, std::min<size_t>(nb, 1024)));
 }
 
@@ -886,22 +934,28 @@ void launch_prolong_add(const XferDev<T>& X, int ncomp, const T* ec, T* xf, hipS
 }
 
 template <typename T, int BW>
-void tsolve_axis(const T* v, T* tmp, T* z, const LineGeom& g, const TFacDev<T>& F, size_t items, hipStream_t s) {
-    const dim3 grid((items + kThreads - 1) / kThreads);
-    hipLaunchKernelGGL((k_tsolve_fwd<T, BW>), grid, dim3(kThreads), 0, s, v, tmp, items, g, F.l, F.dinv, F.warm);
-    hipLaunchKernelGGL((k_tsolve_bwd<T, BW>), grid, dim3(kThreads), 0, s, tmp, z, items, g, F.l, F.warm);
+void tsolve_axis(const T* v, T* z, const LineGeom& g, const TFacDev<T>& F, size_t lines_padded, size_t lds,
+                 hipStream_t s) {
+    const size_t items = lines_padded * g.nchunk * size_t(g.ncomp);
+    const dim3 grid(items / kLineThreads);
+    auto kern = k_tsolve_line<T, BW>;
+    allow_lds(reinterpret_cast<const void*>(kern), lds);
+    hipLaunchKernelGGL(kern, grid, dim3(kLineThreads), lds, s, v, z, g, lines_padded, F.l, F.dinv, F.warm);
 }
 
 template <typename T>
 void launch_tsolve(int dim, const int* m, const TFacDev<T>* fac, const T* v, T* tmp, T* z, hipStream_t s) {
+    if (v == z || v == tmp || tmp == z) throw std::runtime_error("tsolve needs three distinct buffers");
     const int m0 = m[0], m1 = m[1], m2 = (dim == 3) ? m[2] : 1;
     const size_t G = size_t(m0) * m1 * m2;
     if (fac[0].bw == 0) {  // p = 1: T is the identity
-        if (v != z) launch_copy<T>(v, z, size_t(dim) * G, s);
+        launch_copy<T>(v, z, size_t(dim) * G, s);
         return;
     }
     const T* src = v;
     for (int a = 0; a < dim; ++a) {
+        // alternate destinations so that the last pass lands in z
+        T* dst = ((dim - 1 - a) % 2 == 0) ? z : tmp;
         const TFacDev<T>& F = fac[a];
         LineGeom g;
         g.G = G;
@@ -911,22 +965,27 @@ void launch_tsolve(int dim, const int* m, const TFacDev<T>* fac, const T* v, T* 
         g.m2 = m2;
         g.lines_per_comp = G / F.m;
         const size_t lines = size_t(dim) * g.lines_per_comp;
-        // enough independent chunks to fill the device, chunks no shorter than 16 rows
+        // enough independent chunks to fill the device; chunks of at least 16 rows,
+        // and a staged span (chunk + 2 warm rows per lane) that fits in LDS
         const size_t want = (size_t(1) << 17) / std::max<size_t>(lines, 1) + 1;
         g.nchunk = int(std::max<size_t>(1, std::min<size_t>(want, size_t((F.m + 15) / 16))));
         g.chunk = (F.m + g.nchunk - 1) / g.nchunk;
         g.nchunk = (F.m + g.chunk - 1) / g.chunk;
-        const size_t items = lines * g.nchunk;
+        const int span = std::min(F.m, g.chunk + 2 * F.warm);
+        const size_t lds = size_t(span) * (kLineThreads + F.bw + 1) * sizeof(T);
+        if (lds > 160 * 1024) throw std::runtime_error("T-solve span does not fit in LDS");
+        g.ncomp = dim;
+        const size_t lp = (g.lines_per_comp + kLineThreads - 1) / kLineThreads * kLineThreads;
         switch (F.bw) {
-            case 1: tsolve_axis<T, 1>(src, tmp, z, g, F, items, s); break;
-            case 2: tsolve_axis<T, 2>(src, tmp, z, g, F, items, s); break;
-            case 3: tsolve_axis<T, 3>(src, tmp, z, g, F, items, s); break;
-            case 4: tsolve_axis<T, 4>(src, tmp, z, g, F, items, s); break;
-            case 5: tsolve_axis<T, 5>(src, tmp, z, g, F, items, s); break;
+            case 1: tsolve_axis<T, 1>(src, dst, g, F, lp, lds, s); break;
+            case 2: tsolve_axis<T, 2>(src, dst, g, F, lp, lds, s); break;
+            case 3: tsolve_axis<T, 3>(src, dst, g, F, lp, lds, s); break;
+            case 4: tsolve_axis<T, 4>(src, dst, g, F, lp, lds, s); break;
+            case 5: tsolve_axis<T, 5>(src, dst, g, F, lp, lds, s); break;
             default: throw std::runtime_error("degree out of range (1..6)");
         }
         check_launch("tsolve");
-        src = z;
+        src = dst;
     }
 }
 
@@ -998,8 +1057,8 @@ void launch_cheb_first(const OpDev<T>& op, const T* b, T* u, T* x, T inv_theta, 
 }
 
 template <typename T>
-void launch_coarse_gemv(const double* Kinv, int N, const T* r, T* z, hipStream_t s) {
-    hipLaunchKernelGGL(k_coarse_gemv<T>, dim3(N), dim3(kThreads), 0, s, Kinv, N, r, z);
+void launch_coarse_gemv(const double* Kinv, int N, int ld, const T* r, T* z, hipStream_t s) {
+    hipLaunchKernelGGL(k_coarse_gemv<T>, dim3(N), dim3(kThreads), 0, s, Kinv, N, ld, r, z);
     check_launch("coarse_gemv");
 }
 
@@ -1072,7 +1131,7 @@ void launch_combine(const T* V, int k, const double* y, T* w, size_t n, hipStrea
     template void launch_diag_scale<T>(const OpDev<T>&, bool, const T*, T*, hipStream_t);                            \
     template void launch_diag_dot<T>(const OpDev<T>&, const T*, double*, hipStream_t);                               \
     template void launch_cheb_first<T>(const OpDev<T>&, const T*, T*, T*, T, hipStream_t);                           \
-    template void launch_coarse_gemv<T>(const double*, int, const T*, T*, hipStream_t);                              \
+    template void launch_coarse_gemv<T>(const double*, int, int, const T*, T*, hipStream_t);                              \
     template void launch_multidot<T>(const T*, int, const T*, size_t, double*, int, hipStream_t);                    \
     template void launch_multiaxpy<T>(const T*, int, const double*, T*, size_t, hipStream_t);                        \
     template void launch_scale_by<T>(const double*, const T*, T*, size_t, hipStream_t);                              \

@@ -98,8 +98,9 @@ template <typename T>
 void launch_cheb_first(const OpDev<T>& op, const T* b, T* u, T* x, T inv_theta, hipStream_t s);
 
 // ---- coarse level -------------------------------------------------------------
+// z = Kinv r, Kinv N x N inside an ld x ld row-major array
 template <typename T>
-void launch_coarse_gemv(const double* Kinv, int N, const T* r, T* z, hipStream_t s);
+void launch_coarse_gemv(const double* Kinv, int N, int ld, const T* r, T* z, hipStream_t s);
 
 // ---- flexible CG (FP64) ---------------------------------------------------------
 // d = z - (sum pzq / *dq_prev) d   (first = true: d = z); pdr[block] = d.r

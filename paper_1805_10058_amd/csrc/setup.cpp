@@ -391,39 +391,4 @@ std::vector<double> dense_operator(int d, const int* m, const Band* M, const Ban
     return K;
 }
 
-bool spd_inverse(std::vector<double>& K, int N) {
-    // Cholesky K = L L^T (lower triangle, in place)
-    for (int j = 0; j < N; ++j) {
-        double s = K[size_t(j) * N + j];
-        for (int k = 0; k < j; ++k) s -= K[size_t(j) * N + k] * K[size_t(j) * N + k];
-        if (!(s > 0.0)) return false;
-        const double ljj = std::sqrt(s);
-        K[size_t(j) * N + j] = ljj;
-        for (int i = j + 1; i < N; ++i) {
-            double t = K[size_t(i) * N + j];
-            for (int k = 0; k < j; ++k) t -= K[size_t(i) * N + k] * K[size_t(j) * N + k];
-            K[size_t(i) * N + j] = t / ljj;
-        }
-    }
-    // W = L^{-1} (lower triangular), row-major
-    std::vector<double> W(size_t(N) * N, 0.0);
-    for (int i = 0; i < N; ++i) {
-        W[size_t(i) * N + i] = 1.0 / K[size_t(i) * N + i];
-        for (int j = 0; j < i; ++j) {
-            double s = 0.0;
-            for (int k = j; k < i; ++k) s += K[size_t(i) * N + k] * W[size_t(k) * N + j];
-            W[size_t(i) * N + j] = -s / K[size_t(i) * N + i];
-        }
-    }
-    // K^{-1} = W^T W
-    for (int i = 0; i < N; ++i)
-        for (int j = 0; j <= i; ++j) {
-            double s = 0.0;
-            for (int k = i; k < N; ++k) s += W[size_t(k) * N + i] * W[size_t(k) * N + j];
-            K[size_t(i) * N + j] = s;
-            K[size_t(j) * N + i] = s;
-        }
-    return true;
-}
-
 }  // namespace cd

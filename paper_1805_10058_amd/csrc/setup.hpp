@@ -75,8 +75,5 @@ int recurrence_warmup(const TFactor& F, double tol);
 // sum_{e!=c} D_e; block (c,e): (alpha-beta) A on axes c,e and M elsewhere).
 std::vector<double> dense_operator(int d, const int* m, const Band* M, const Band* A, const Band* S,
                                    double alpha, double beta);
-// In-place Cholesky-based inverse of an SPD matrix (row-major, N x N).
-// Returns false if the matrix is not numerically SPD.
-bool spd_inverse(std::vector<double>& K, int N);
 
 }  // namespace cd

@@ -21,6 +21,7 @@
 #include <vector>
 
 #include "../../include/curldiv.h"
+#include "coarse.hpp"
 #include "kernels.hpp"
 #include "setup.hpp"
 
@@ -134,7 +135,9 @@ struct SolveState {
 struct cd_solver {
     cd_problem prob{};
     cd_options opt{};
-    hipStream_t stream = nullptr;
+    hipStream_t stream = nullptr;  // all work of the handle
+    bool own_stream = false;       // created here because the caller passed the null stream
+    hipEvent_t entry_event = nullptr;
     int d = 0, p = 0, ksteps = 0;
     size_t N = 0;
     std::vector<LevelHost> lv;
@@ -146,7 +149,8 @@ struct cd_solver {
     std::vector<LevelDev<float>> ld32;
     cd::TFacDev<double> tfd64[3]{};
     cd::TFacDev<float> tfd32[3]{};
-    double* Kinv = nullptr;
+    double* Kinv = nullptr;  // inverse of the coarsest operator, leading dimension ldK
+    int ldK = 0;
 
     std::unique_ptr<VWork<double>> w64;
     std::unique_ptr<VWork<float>> w32;
@@ -166,6 +170,8 @@ struct cd_solver {
     };
     SolveState state;
     hipEvent_t iter_event = nullptr;
+    double* xw = nullptr;                 // iterate of the outer iteration (copied to the caller's x)
+    hipGraphExec_t iter_graph = nullptr;  // captured outer iteration k >= 1
 
     bool prof = false;
     std::vector<ProfRec> prof_pending;
@@ -173,6 +179,8 @@ struct cd_solver {
     std::vector<cd_kernel_stats> prof_stats;  // index 2*level + fp32
     ~cd_solver() {
         if (iter_event) (void)hipEventDestroy(iter_event);
+        if (entry_event) (void)hipEventDestroy(entry_event);
+        if (iter_graph) (void)hipGraphExecDestroy(iter_graph);
         for (auto& r : prof_pending) { (void)hipEventDestroy(r.a); (void)hipEventDestroy(r.b); }
         for (auto& e : prof_pool) { (void)hipEventDestroy(e.first); (void)hipEventDestroy(e.second); }
     }
@@ -202,6 +210,7 @@ void validate(const cd_problem* pr, const cd_options* op) {
     if (!(op->cheb_ratio > 1.0)) throw CdError(CD_EINVAL, "cheb_ratio must be > 1");
     if (op->power_iters < 1) throw CdError(CD_EINVAL, "power_iters must be >= 1");
     if (op->krylov_steps > 7) throw CdError(CD_EINVAL, "krylov_steps must be <= 7");
+    if (op->graphs != 0 && op->graphs != 1) throw CdError(CD_EINVAL, "graphs must be 0 or 1");
     if (op->coarse_max_dofs < 1 || op->coarse_max_dofs > 8192)
         throw CdError(CD_EINVAL, "coarse_max_dofs must be in 1..8192");
     // the operator kernels keep a plane chunk with a +-p row halo in LDS
@@ -248,6 +257,7 @@ void build_host(cd_solver* s) {
         for (int l = 0; l < 3; ++l) C.m[l] = 1;
         for (int l = 0; l < d; ++l) {
             F.P[l] = (s->opt.transfer == CD_XFER_KNOT) ? cd::knot_insertion(nl[l], p) : cd::paper_prolong(F.m[l]);
+            if (F.P[l].w > 8 || F.P[l].wr > 8) throw CdError(CD_EINVAL, "prolongator window wider than 8");
             C.M[l] = cd::galerkin(F.M[l], F.P[l]);
             C.A[l] = cd::galerkin(F.A[l], F.P[l]);
             C.S[l] = cd::galerkin(F.S[l], F.P[l]);
@@ -469,8 +479,8 @@ void gmres_post(cd_solver* s, VWork<T>& W, const T* b, T* x) {
     }
     cd::launch_hessenberg_ls(W.H, ld, ks, W.scal, W.y, st);
     cd::launch_combine<T>(V, ks, W.y, W.w, N, st);
-    cd::launch_tsolve<T>(s->d, s->lv[0].m, tfacs<T>(s), W.w, W.tmp, W.w, st);
-    cd::launch_axpby<T>(T(1), W.w, T(1), x, N, st);
+    cd::launch_tsolve<T>(s->d, s->lv[0].m, tfacs<T>(s), W.w, W.tmp, W.z, st);
+    cd::launch_axpby<T>(T(1), W.z, T(1), x, N, st);
 }
 
 // One V-cycle on level l for A_l x = W.lv[l].b; result in W.lv[l].xcur.
@@ -480,7 +490,7 @@ void vcycle(cd_solver* s, VWork<T>& W, int l) {
     auto& Wl = W.lv[l];
     hipStream_t st = s->stream;
     if (l == L - 1) {
-        cd::launch_coarse_gemv<T>(s->Kinv, s->Nc, Wl.b, Wl.xa, st);
+        cd::launch_coarse_gemv<T>(s->Kinv, s->Nc, s->ldK, Wl.b, Wl.xa, st);
         Wl.xcur = Wl.xa;
         return;
     }
@@ -571,12 +581,27 @@ void estimate_bounds(cd_solver* s) {
     }
 }
 
+// Work given the legacy null stream goes to a stream owned by the handle
+// (stream capture is not permitted on the null stream); every entry point
+// first orders it after the work already queued on the null stream.
+void enter(cd_solver* s) {
+    if (!s->own_stream) return;
+    hip_check(hipEventRecord(s->entry_event, nullptr), "hipEventRecord");
+    hip_check(hipStreamWaitEvent(s->stream, s->entry_event, 0), "hipStreamWaitEvent");
+}
+
 void create(cd_solver* s, const cd_problem* pr, const cd_options* op, void* stream) {
     validate(pr, op);
     s->prob = *pr;
     s->opt = *op;
     if (s->prob.dim == 2) s->prob.n[2] = 1;
     s->stream = static_cast<hipStream_t>(stream);
+    if (!s->stream) {
+        hip_check(hipStreamCreateWithFlags(&s->stream, hipStreamNonBlocking), "hipStreamCreate");
+        s->own_stream = true;
+        hip_check(hipEventCreateWithFlags(&s->entry_event, hipEventDisableTiming), "hipEventCreate");
+        enter(s);
+    }
     s->d = pr->dim;
     s->p = pr->degree;
     s->ksteps = (op->krylov_steps < 0) ? pr->degree : op->krylov_steps;
@@ -600,17 +625,29 @@ void create(cd_solver* s, const cd_problem* pr, const cd_options* op, void* stre
         s->tfd64[l] = make_tfac<double>(s, s->tf[l], st);
         s->tfd32[l] = make_tfac<float>(s, s->tf[l], st);
     }
-    // coarse level: dense operator and its inverse (FP64)
+    // coarse level: dense operator (host), Cholesky factorization and inverse
+    // on the GPU (FP64 MFMA); the factor workspace is released after setup
     {
         const LevelHost& C = s->lv.back();
-        std::vector<double> K = cd::dense_operator(s->d, C.m, C.M, C.A, C.S, s->prob.alpha, s->prob.beta);
-        if (!cd::spd_inverse(K, s->Nc)) throw CdError(CD_EINVAL, "coarse operator is not positive definite");
-        s->Kinv = s->arena.upload(K, st);
+        const std::vector<double> K = cd::dense_operator(s->d, C.m, C.M, C.A, C.S, s->prob.alpha, s->prob.beta);
+        const int ld = cd::coarse_padded(s->Nc);
+        s->ldK = ld;
+        s->Kinv = s->arena.alloc<double>(size_t(ld) * ld);
+        DevArena tmp;
+        double* Kd = tmp.upload(K, st);
+        double* fac = tmp.alloc<double>(size_t(ld) * ld);
+        int* flag = tmp.alloc<int>(1);
+        hip_check(hipMemsetAsync(flag, 0, sizeof(int), st), "hipMemsetAsync");
+        cd::coarse_inverse(Kd, s->Nc, fac, s->Kinv, flag, st);
+        int hflag = 0;
+        hip_check(hipMemcpyAsync(&hflag, flag, sizeof(int), hipMemcpyDeviceToHost, st), "read");
         hip_check(hipStreamSynchronize(st), "sync");
+        if (hflag) throw CdError(CD_EINVAL, "coarse operator is not positive definite");
     }
     // outer vectors
     const size_t N = s->N;
     s->r = s->arena.alloc<double>(N);
+    s->xw = s->arena.alloc<double>(N);
     s->z = s->arena.alloc<double>(N);
     s->dd = s->arena.alloc<double>(N);
     s->q = s->arena.alloc<double>(N);
@@ -648,7 +685,7 @@ void solve_begin(cd_solver* s, const double* b, double* x) {
     S = SolveState{};
     S.b = b;
     S.x = x;
-    cd::launch_fill<double>(x, 0.0, N, st);
+    cd::launch_fill<double>(s->xw, 0.0, N, st);
     cd::launch_copy<double>(b, s->r, N, st);
     cd::launch_dot_partial<double, double>(s->r, s->r, N, s->prr, st);
     cd::launch_finalize(s->prr, s->nbr, s->scal, st);
@@ -663,21 +700,50 @@ void solve_begin(cd_solver* s, const double* b, double* x) {
     if (!s->iter_event) hip_check(hipEventCreateWithFlags(&s->iter_event, hipEventDisableTiming), "hipEventCreate");
 }
 
-void solve_iterate(cd_solver* s) {
+void enqueue_iteration(cd_solver* s, bool first) {
     hipStream_t st = s->stream;
     const size_t N = s->N;
-    SolveState& S = s->state;
     if (s->opt.method == CD_METHOD_CG) {
         cd::launch_copy<double>(s->r, s->z, N, st);
     } else {
         precondition(s, s->r, s->z);
     }
-    if (S.k > 0) cd::launch_dot_partial<double, double>(s->z, s->q, N, s->pzq, st);
-    cd::launch_fcg_direction(S.k == 0, s->z, s->pzq, s->nbr, s->scal + 1, s->dd, s->r, s->pdr, N, st);
+    if (!first) cd::launch_dot_partial<double, double>(s->z, s->q, N, s->pzq, st);
+    cd::launch_fcg_direction(first, s->z, s->pzq, s->nbr, s->scal + 1, s->dd, s->r, s->pdr, N, st);
     apply_op<double>(s, 0, kApplyYDot, s->dd, s->q, nullptr, nullptr, nullptr, 0.0, 0.0, s->pdq);
-    cd::launch_fcg_update(s->pdr, s->nbr, s->pdq, s->nba, s->scal + 1, S.x, s->r, s->dd, s->q, s->prr, N, st);
+    cd::launch_fcg_update(s->pdr, s->nbr, s->pdq, s->nba, s->scal + 1, s->xw, s->r, s->dd, s->q, s->prr, N, st);
     cd::launch_finalize(s->prr, s->nbr, s->scal, st);
     hip_check(hipMemcpyAsync(s->host_scal, s->scal, 2 * sizeof(double), hipMemcpyDeviceToHost, st), "read");
+}
+
+// Enqueue one outer iteration.  Every iteration after the first reads and
+// writes the same solver-owned buffers with the same coefficients, so it is
+// captured once into a HIP graph and replayed (no memset nodes: buffers are
+// cleared by kernels).  With live timing enabled iterations run eagerly.
+void solve_iterate(cd_solver* s) {
+    hipStream_t st = s->stream;
+    SolveState& S = s->state;
+    const bool first = (S.k == 0);
+    if (first || !s->opt.graphs || s->prof) {
+        enqueue_iteration(s, first);
+    } else {
+        if (!s->iter_graph) {
+            hipGraph_t g = nullptr;
+            hip_check(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal), "hipStreamBeginCapture");
+            try {
+                enqueue_iteration(s, false);
+            } catch (...) {
+                (void)hipStreamEndCapture(st, &g);
+                if (g) (void)hipGraphDestroy(g);
+                throw;
+            }
+            hip_check(hipStreamEndCapture(st, &g), "hipStreamEndCapture");
+            const hipError_t e = hipGraphInstantiate(&s->iter_graph, g, nullptr, nullptr, 0);
+            (void)hipGraphDestroy(g);
+            hip_check(e, "hipGraphInstantiate");
+        }
+        hip_check(hipGraphLaunch(s->iter_graph, st), "hipGraphLaunch");
+    }
     hip_check(hipEventRecord(s->iter_event, st), "hipEventRecord");
 }
 
@@ -709,6 +775,7 @@ cd_result solve_finish(cd_solver* s) {
     out.status = S.status;
     out.iterations = S.k;
     out.rel_residual = (S.r0 > 0.0) ? S.rel : 0.0;
+    cd::launch_copy<double>(s->xw, S.x, N, st);
     if (S.r0 > 0.0) {
         cd::launch_apply<double>(s->ld64[0].op, kApplyRes, S.x, s->z, S.b, nullptr, nullptr, 0.0, 0.0, nullptr, st);
         cd::launch_dot_partial<double, double>(s->z, s->z, N, s->prr, st);
@@ -776,6 +843,7 @@ void cd_default_options(cd_options* o) {
     o->cheb_ratio = 30.0;
     o->power_iters = 10;
     o->krylov_steps = -1;
+    o->graphs = 1;
 }
 
 size_t cd_num_dofs(const cd_problem* pr) {
@@ -812,7 +880,7 @@ size_t cd_footprint_bytes(const cd_problem* pr, const cd_options* op) {
         vw += N * (size_t(std::max(tmp.ksteps, 1)) + 4);
         total = 4 * N * 8                                   // outer r, z, d, q
                 + (op->method == CD_METHOD_PMIM ? vw * es : 0)  // V-cycle workspace
-                + size_t(tmp.Nc) * tmp.Nc * 8                // coarse inverse
+                + size_t(cd::coarse_padded(tmp.Nc)) * cd::coarse_padded(tmp.Nc) * 8  // coarse inverse
                 + (1 << 20);                                 // 1D tables and partial sums
     });
     return rc == CD_OK ? total : 0;
@@ -839,7 +907,10 @@ void cd_solver_destroy(cd_solver* s) {
     if (!s) return;
     (void)hipStreamSynchronize(s->stream);
     if (s->host_scal) (void)hipHostFree(s->host_scal);
+    const bool own = s->own_stream;
+    hipStream_t st = s->stream;
     delete s;
+    if (own) (void)hipStreamDestroy(st);
 }
 
 int cd_solve(cd_solver* s, const double* b, double* x, cd_result* res) {
@@ -847,6 +918,7 @@ int cd_solve(cd_solver* s, const double* b, double* x, cd_result* res) {
     int st = CD_OK;
     const int rc = run([&] {
         need(s);
+        enter(s);
         if (!b || !x) throw CdError(CD_EINVAL, "null vector");
         cd_result r{};
         solve(s, b, x, &r);
@@ -909,6 +981,7 @@ int cd_get_lambda(const cd_solver* s, int level, double* lam) {
 int cd_apply(cd_solver* s, int level, const double* x, double* y) {
     return run([&] {
         need_level(s, level);
+        enter(s);
         apply_op<double>(s, level, kApplyY, x, y, nullptr, nullptr, nullptr, 0.0, 0.0, nullptr);
         hip_check(hipStreamSynchronize(s->stream), "sync");
         if (s->prof) prof_flush(s);
@@ -918,6 +991,7 @@ int cd_apply(cd_solver* s, int level, const double* x, double* y) {
 int cd_apply_f32(cd_solver* s, int level, const float* x, float* y) {
     return run([&] {
         need_level(s, level);
+        enter(s);
         apply_op<float>(s, level, kApplyY, x, y, nullptr, nullptr, nullptr, 0.f, 0.f, nullptr);
         hip_check(hipStreamSynchronize(s->stream), "sync");
         if (s->prof) prof_flush(s);
@@ -927,6 +1001,7 @@ int cd_apply_f32(cd_solver* s, int level, const float* x, float* y) {
 int cd_smooth(cd_solver* s, int level, const double* b, const double* x_in, double* x_out) {
     return run([&] {
         need_level(s, level);
+        enter(s);
         if (level == int(s->lv.size()) - 1) throw CdError(CD_EINVAL, "coarsest level has no smoother");
         if (s->opt.method != CD_METHOD_PMIM) throw CdError(CD_EINVAL, "no smoother for plain CG");
         VWork<double>& W = work64(s);
@@ -943,6 +1018,7 @@ int cd_smooth(cd_solver* s, int level, const double* b, const double* x_in, doub
 int cd_restrict(cd_solver* s, int level, const double* rf, double* rc) {
     return run([&] {
         need_level(s, level);
+        enter(s);
         if (level == int(s->lv.size()) - 1) throw CdError(CD_EINVAL, "coarsest level");
         cd::launch_restrict<double>(s->ld64[level].xf, s->d, rf, rc, s->stream);
         hip_check(hipStreamSynchronize(s->stream), "sync");
@@ -952,6 +1028,7 @@ int cd_restrict(cd_solver* s, int level, const double* rf, double* rc) {
 int cd_prolong_add(cd_solver* s, int level, const double* ec, double* xf) {
     return run([&] {
         need_level(s, level);
+        enter(s);
         if (level == int(s->lv.size()) - 1) throw CdError(CD_EINVAL, "coarsest level");
         cd::launch_prolong_add<double>(s->ld64[level].xf, s->d, ec, xf, s->stream);
         hip_check(hipStreamSynchronize(s->stream), "sync");
@@ -961,8 +1038,14 @@ int cd_prolong_add(cd_solver* s, int level, const double* ec, double* xf) {
 int cd_tsolve(cd_solver* s, const double* v, double* z) {
     return run([&] {
         need(s);
-        // the outer vector q is free outside a solve and serves as scratch
-        cd::launch_tsolve<double>(s->d, s->lv[0].m, s->tfd64, v, s->q, z, s->stream);
+        enter(s);
+        // the outer vectors q and z are free outside a solve and serve as scratch
+        const double* src = v;
+        if (v == z) {
+            cd::launch_copy<double>(v, s->z, s->N, s->stream);
+            src = s->z;
+        }
+        cd::launch_tsolve<double>(s->d, s->lv[0].m, s->tfd64, src, s->q, z, s->stream);
         hip_check(hipStreamSynchronize(s->stream), "sync");
     });
 }
@@ -970,7 +1053,8 @@ int cd_tsolve(cd_solver* s, const double* v, double* z) {
 int cd_coarse_solve(cd_solver* s, const double* r, double* z) {
     return run([&] {
         need(s);
-        cd::launch_coarse_gemv<double>(s->Kinv, s->Nc, r, z, s->stream);
+        enter(s);
+        cd::launch_coarse_gemv<double>(s->Kinv, s->Nc, s->ldK, r, z, s->stream);
         hip_check(hipStreamSynchronize(s->stream), "sync");
     });
 }
@@ -978,9 +1062,10 @@ int cd_coarse_solve(cd_solver* s, const double* r, double* z) {
 int cd_precondition(cd_solver* s, const double* r, double* z) {
     return run([&] {
         need(s);
+        enter(s);
         if (s->opt.method != CD_METHOD_PMIM) throw CdError(CD_EINVAL, "plain CG has no preconditioner");
         if (s->lv.size() == 1) {
-            cd::launch_coarse_gemv<double>(s->Kinv, s->Nc, r, z, s->stream);
+            cd::launch_coarse_gemv<double>(s->Kinv, s->Nc, s->ldK, r, z, s->stream);
         } else {
             precondition(s, r, z);
         }
@@ -991,6 +1076,7 @@ int cd_precondition(cd_solver* s, const double* r, double* z) {
 int cd_profile_enable(cd_solver* s, int on) {
     return run([&] {
         need(s);
+        enter(s);
         hip_check(hipStreamSynchronize(s->stream), "sync");
         prof_flush(s);
         s->prof = (on != 0);
@@ -1132,11 +1218,14 @@ int cd_server_step(cd_server* srv, int* n_active, int* n_queued) {
                 continue;
             }
             r.solver = h;
-            const int rb = run([&] { solve_begin(h, r.b, r.x); });
+            cd_result res0{};
+            const int rb = run([&] {
+                solve_begin(h, r.b, r.x);
+                if (h->state.done) res0 = solve_finish(h);  // zero right-hand side: x = 0
+            });
             if (rb != CD_OK || h->state.done) {
-                cd_result res{};
-                res.status = (rb != CD_OK) ? rb : h->state.status;
-                server_complete(srv, r, res);
+                if (rb != CD_OK) res0.status = rb;
+                server_complete(srv, r, res0);
                 cd_solver_destroy(h);
                 continue;
             }
