@@ -114,10 +114,15 @@ def main():
     def log(msg):
         print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
+    # live timing on from the warm-up on, so that the timed region replays
+    # graphs that were captured (with their timing event nodes) before it
+    for s in mixed.values():
+        s.profile_enable(True)
     for k in range(args.warmup):
         step(k, mixed, [], its, [])
         log(f"warmup step {k} done, iterations {its}")
-    for s in mixed.values():
+    for s in mixed.values():  # restart the counters
+        s.profile_enable(False)
         s.profile_enable(True)
     torch.cuda.synchronize()
     t0 = time.perf_counter()

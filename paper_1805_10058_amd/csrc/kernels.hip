@@ -271,74 +271,92 @@ __global__ __launch_bounds__(kThreads) void k_apply3d(OpDev<T> op, const T* __re
 }
 
 // ------------------------------------------------------------------------------
-// 2D operator apply: block owns TPB = kThreads - 2HB consecutive points of the
-// flattened (x1, x2) grid.  (A) axis-1 contractions (stride m2) S1, M1, A1 of
-// both components at the kThreads stage positions; (B) axis-2 contraction at
-// the point:
+// 2D operator apply on tiles of kT1 x kT2 output points (x1 rows, x2 columns;
+// x2 contiguous).  The block issues the loads of its input tile (both
+// components, +-HB halo on both axes, zero outside the grid) before storing
+// any of them to LDS, then
+//   (A) contracts axis 1: S1 x, M1 x, A1 x of both components at the kT1
+//       output rows and all kT2 + 2HB tile columns;
+//   (B) contracts axis 2 at the output point:
 //   y1 = beta M2(S1 x1) + alpha S2(M1 x1) + (alpha-beta) A2(A1 x2)
 //   y2 = alpha M2(S1 x2) + beta S2(M1 x2) + (alpha-beta) A2(A1 x1)
+// 12 band contractions per point.
 // ------------------------------------------------------------------------------
+constexpr int kT1 = 8, kT2 = 32;  // 2D output tile: kT1 * kT2 = kThreads points
+
 template <typename T, int HB, int MODE>
 __global__ __launch_bounds__(kThreads) void k_apply2d(OpDev<T> op, const T* __restrict__ x, T* __restrict__ y,
                                                       const T* __restrict__ b, T* __restrict__ u,
                                                       T* __restrict__ xout, T c1, T c2, double* __restrict__ part) {
     constexpr int R = 2 * HB + 1;
-    constexpr int TPB = kThreads - 2 * HB;
-    extern __shared__ __align__(16) unsigned char smem_raw[];
+    constexpr int E1 = kT1 + 2 * HB, E2 = kT2 + 2 * HB;  // input tile rows, columns
+    constexpr int NIN = E1 * E2;                         // input tile size per component
+    constexpr int NLD = (2 * NIN + kThreads - 1) / kThreads;
+    constexpr int NA = kT1 * E2;                         // stage-A positions
+    __shared__ T xs[2 * NIN];
+    __shared__ T st[6 * NA];  // S1x1 M1x1 A1x1 S1x2 M1x2 A1x2, each [kT1][E2]
     const int m1 = op.m[0], m2 = op.m[1];
     const int G = m1 * m2;
-    const int XSN = kThreads + 2 * HB * m2;
-    T* xs = reinterpret_cast<T*>(smem_raw);  // [2][XSN]
-    T* st = xs + 2 * XSN;                    // [6][kThreads]: S1x1 M1x1 A1x1 S1x2 M1x2 A1x2
-    const int s = blockIdx.x * TPB;
+    const int nt2 = (m2 + kT2 - 1) / kT2;
+    const int o1 = (blockIdx.x / nt2) * kT1, o2 = (blockIdx.x % nt2) * kT2;
     const int tid = threadIdx.x;
-    const int base = s - HB - HB * m2;
-    for (int q = tid; q < XSN; q += kThreads) {
-        const int ff = base + q;
-        const bool in = ff >= 0 && ff < G;
-        xs[q] = in ? x[ff] : T(0);
-        xs[XSN + q] = in ? x[G + ff] : T(0);
-    }
-    __syncthreads();
     {
-        const int ffa = s - HB + tid;
-        T v[6] = {T(0), T(0), T(0), T(0), T(0), T(0)};
-        if (ffa >= 0 && ffa < G) {
-            const int r1 = ffa / m2;
+        T v[NLD];
 #pragma unroll
-            for (int k = 0; k < R; ++k) {
-                const T cS = op.band[0][2][k * m1 + r1];
-                const T cM = op.band[0][0][k * m1 + r1];
-                const T cA = op.band[0][1][k * m1 + r1];
-                const T x1 = xs[tid + k * m2], x2 = xs[XSN + tid + k * m2];
-                v[0] += cS * x1;
-                v[1] += cM * x1;
-                v[2] += cA * x1;
-                v[3] += cS * x2;
-                v[4] += cM * x2;
-                v[5] += cA * x2;
-            }
+        for (int q = 0; q < NLD; ++q) {
+            const int e = min(tid + q * kThreads, 2 * NIN - 1);
+            const int c = e / NIN, r = (e % NIN) / E2, cc = e % E2;
+            const int g1 = o1 - HB + r, g2 = o2 - HB + cc;
+            const bool in = g1 >= 0 && g1 < m1 && g2 >= 0 && g2 < m2;
+            const T val = x[size_t(c) * G + size_t(in ? g1 : 0) * m2 + (in ? g2 : 0)];
+            v[q] = in ? val : T(0);
         }
 #pragma unroll
-        for (int w = 0; w < 6; ++w) st[w * kThreads + tid] = v[w];
+        for (int q = 0; q < NLD; ++q) {
+            const int e = tid + q * kThreads;
+            if (e < 2 * NIN) xs[e] = v[q];
+        }
+    }
+    __syncthreads();
+    for (int p = tid; p < NA; p += kThreads) {
+        const int i = p / E2, j = p % E2;
+        const int r1 = min(o1 + i, m1 - 1);  // rows past the grid produce unused values
+        T v[6] = {T(0), T(0), T(0), T(0), T(0), T(0)};
+#pragma unroll
+        for (int k = 0; k < R; ++k) {
+            const T cS = op.band[0][2][k * m1 + r1];
+            const T cM = op.band[0][0][k * m1 + r1];
+            const T cA = op.band[0][1][k * m1 + r1];
+            const T x1 = xs[(i + k) * E2 + j], x2 = xs[NIN + (i + k) * E2 + j];
+            v[0] += cS * x1;
+            v[1] += cM * x1;
+            v[2] += cA * x1;
+            v[3] += cS * x2;
+            v[4] += cM * x2;
+            v[5] += cA * x2;
+        }
+#pragma unroll
+        for (int w = 0; w < 6; ++w) st[w * NA + p] = v[w];
     }
     __syncthreads();
     double dot = 0.0;
-    const int f = s + tid;
-    if (tid < TPB && f < G) {
-        const int i2 = f % m2, i1 = f / m2;
+    const int i = tid / kT2, j = tid % kT2;
+    const int i1 = o1 + i, i2 = o2 + j;
+    if (i1 < m1 && i2 < m2) {
+        const int f = i1 * m2 + i2;
         T mS1 = T(0), sM1 = T(0), aA2 = T(0), mS2 = T(0), sM2 = T(0), aA1 = T(0);
+        const int q0 = i * E2 + j;
 #pragma unroll
         for (int k = 0; k < R; ++k) {
             const T cM = op.band[1][0][k * m2 + i2];
             const T cA = op.band[1][1][k * m2 + i2];
             const T cS = op.band[1][2][k * m2 + i2];
-            mS1 += cM * st[0 * kThreads + tid + k];
-            sM1 += cS * st[1 * kThreads + tid + k];
-            aA1 += cA * st[2 * kThreads + tid + k];
-            mS2 += cM * st[3 * kThreads + tid + k];
-            sM2 += cS * st[4 * kThreads + tid + k];
-            aA2 += cA * st[5 * kThreads + tid + k];
+            mS1 += cM * st[0 * NA + q0 + k];
+            sM1 += cS * st[1 * NA + q0 + k];
+            aA1 += cA * st[2 * NA + q0 + k];
+            mS2 += cM * st[3 * NA + q0 + k];
+            sM2 += cS * st[4 * NA + q0 + k];
+            aA2 += cA * st[5 * NA + q0 + k];
         }
         const T al = op.alpha, be = op.beta, ab = op.alpha - op.beta;
         const T kx[2] = {be * mS1 + al * sM1 + ab * aA2, al * mS2 + be * sM2 + ab * aA1};
@@ -374,7 +392,7 @@ template <typename T>
 size_t apply_lds_bytes(const OpDev<T>& op) {
     const int hb = op.hb;
     if (op.dim == 3) return sizeof(T) * (3 * size_t(kThreads + 2 * hb * op.m[2]) + 9 * size_t(kThreads));
-    return sizeof(T) * (2 * size_t(kThreads + 2 * hb * op.m[1]) + 6 * size_t(kThreads));
+    return 0;  // 2D: static LDS tiles
 }
 
 // Raise a kernel's dynamic-LDS limit (default 64 KiB) to what a launch needs,
@@ -411,12 +429,10 @@ void apply_dispatch(const OpDev<T>& op, const T* x, T* y, const T* b, T* u, T* x
         hipLaunchKernelGGL(kern, dim3(nchunk * nx1), dim3(kThreads), lds, s, op, x, y, b, u, xout, c1, c2, part,
                            nchunk, kX1Chunk);
     } else {
-        const int G = op.m[0] * op.m[1];
-        const int tpb = kThreads - 2 * HB;
-        auto kern = k_apply2d<T, HB, MODE>;
-        allow_lds(reinterpret_cast<const void*>(kern), lds);
-        hipLaunchKernelGGL(kern, dim3((G + tpb - 1) / tpb), dim3(kThreads), lds, s, op, x, y, b, u, xout, c1, c2,
-                           part);
+        static_assert(kT1 * kT2 == kThreads, "2D tile must match the block size");
+        const int tiles = ((op.m[0] + kT1 - 1) / kT1) * ((op.m[1] + kT2 - 1) / kT2);
+        hipLaunchKernelGGL((k_apply2d<T, HB, MODE>), dim3(tiles), dim3(kThreads), 0, s, op, x, y, b, u, xout, c1,
+                           c2, part);
     }
     check_launch("apply");
 }
@@ -513,6 +529,78 @@ __global__ __launch_bounds__(kThreads) void k_prolong_add(XferDev<T> X, int ncom
     xf[id] += acc;
 }
 
+// The same transfers with every window width a compile-time constant, so all
+// loads of a thread are independent and issue together (2D: the third axis
+// has width 1).  Windows are stored clamped inside the matrix, so the fixed
+// widths never read outside the vectors.
+template <typename T, int W0, int W1, int W2>
+__global__ __launch_bounds__(kThreads) void k_restrict_w(XferDev<T> X, int ncomp, const T* __restrict__ rf,
+                                                         T* __restrict__ rc) {
+    const XferAxisDev<T>& a0 = X.ax[0];
+    const XferAxisDev<T>& a1 = X.ax[1];
+    const XferAxisDev<T>& a2 = X.ax[2];
+    const size_t Gc = size_t(a0.mc) * a1.mc * a2.mc;
+    const size_t Gf = size_t(a0.mf) * a1.mf * a2.mf;
+    const size_t id = size_t(blockIdx.x) * kThreads + threadIdx.x;
+    if (id >= Gc * ncomp) return;
+    const int c = int(id / Gc);
+    size_t rem = id % Gc;
+    const int J2 = int(rem % a2.mc);
+    rem /= a2.mc;
+    const int J1 = int(rem % a1.mc);
+    const int J0 = int(rem / a1.mc);
+    const T* base = rf + size_t(c) * Gf + (size_t(a0.r0[J0]) * a1.mf + a1.r0[J1]) * a2.mf + a2.r0[J2];
+    T acc = T(0);
+#pragma unroll
+    for (int k0 = 0; k0 < W0; ++k0) {
+        const T p0 = a0.vt[J0 * W0 + k0];
+#pragma unroll
+        for (int k1 = 0; k1 < W1; ++k1) {
+            const T p1 = a1.vt[J1 * W1 + k1];
+            const T* row = base + (size_t(k0) * a1.mf + k1) * a2.mf;
+            T s2 = T(0);
+#pragma unroll
+            for (int k2 = 0; k2 < W2; ++k2) s2 += a2.vt[J2 * W2 + k2] * row[k2];
+            acc += p0 * p1 * s2;
+        }
+    }
+    rc[id] = acc;
+}
+
+template <typename T, int W0, int W1, int W2>
+__global__ __launch_bounds__(kThreads) void k_prolong_add_w(XferDev<T> X, int ncomp, const T* __restrict__ ec,
+                                                            T* __restrict__ xf) {
+    const XferAxisDev<T>& a0 = X.ax[0];
+    const XferAxisDev<T>& a1 = X.ax[1];
+    const XferAxisDev<T>& a2 = X.ax[2];
+    const size_t Gc = size_t(a0.mc) * a1.mc * a2.mc;
+    const size_t Gf = size_t(a0.mf) * a1.mf * a2.mf;
+    const size_t id = size_t(blockIdx.x) * kThreads + threadIdx.x;
+    if (id >= Gf * ncomp) return;
+    const int c = int(id / Gf);
+    size_t rem = id % Gf;
+    const int i2 = int(rem % a2.mf);
+    rem /= a2.mf;
+    const int i1 = int(rem % a1.mf);
+    const int i0 = int(rem / a1.mf);
+    const T* base = ec + size_t(c) * Gc + (size_t(a0.c0[i0]) * a1.mc + a1.c0[i1]) * a2.mc + a2.c0[i2];
+    T acc = T(0);
+#pragma unroll
+    for (int k0 = 0; k0 < W0; ++k0) {
+        const T p0 = a0.v[i0 * W0 + k0];
+#pragma unroll
+        for (int k1 = 0; k1 < W1; ++k1) {
+            const T p1 = a1.v[i1 * W1 + k1];
+            const T* row = base + (size_t(k0) * a1.mc + k1) * a2.mc;
+            T s2 = T(0);
+#pragma unroll
+            for (int k2 = 0; k2 < W2; ++k2) s2 += a2.v[i2 * W2 + k2] * row[k2];
+            acc += p0 * p1 * s2;
+        }
+    }
+    xf[id] += acc;
+}
+
 // ------------------------------------------------------------------------------
 // T^{-1}: banded LDL^T solves along every grid line of one axis, in two
 // out-of-place passes (forward L y = v with y scaled by D^{-1}, then backward
@@ -529,16 +617,24 @@ struct LineGeom {
 };
 
 constexpr int kLineThreads = 64;  // one wave per block in the line solves
-constexpr int kLoadGroup = 16;    // staging loads issued together per lane
+constexpr int kRowGroup = 16;     // rows per group: staging loads and recurrence LDS reads
+
+// Rows of the staged span, padded to a whole number of row groups.
+__host__ __device__ inline int padded_span(int span) { return (span + kRowGroup - 1) / kRowGroup * kRowGroup; }
 
 // One chunk of one grid line per lane; the 64 lanes of a block take 64
 // consecutive lines of the same chunk (the line index is padded to a
-// multiple of 64), so they share the row span [r0-warm, r1+warm).  The block
-// stages the factor rows of the span in LDS once, each lane stages its line's
-// values (loads issued in groups before any store), runs the forward
-// recurrence over the whole span (storing D^{-1} y back into LDS), then the
-// backward recurrence from the top of the span down to r0, and writes rows
-// [r0, r1).  LDS layout [row][lane] keeps a wave's accesses conflict free.
+// multiple of 64), so they share the row span [rs, re) = [r0-warm, r1+warm)
+// clipped to the line.  LDS holds the lanes' values [row][lane] (conflict
+// free), the factor rows of the span and 1/D, all padded to whole groups of
+// 16 rows with zero factor entries, so no loop below branches per row:
+//  1. staging: every lane issues the loads of two row groups (clamped to the
+//     last row of the span) before it stores them, factor rows likewise;
+//  2. forward L y = v over the padded span (padded rows carry 1/D = 0 and
+//     store 0), keeping D^{-1} y in LDS;
+//  3. backward L^T z = D^{-1} y from the top of the padded span down to the
+//     chunk (zero padded rows keep the recurrence state at zero);
+//  4. the chunk's rows [r0, r1) are written out.
 // Out of place: in != out.
 template <typename T, int BW>
 __global__ __launch_bounds__(kLineThreads) void k_tsolve_line(const T* __restrict__ in, T* __restrict__ out,
@@ -556,93 +652,109 @@ __global__ __launch_bounds__(kLineThreads) void k_tsolve_line(const T* __restric
     const int r0 = ch * g.chunk, r1 = min(g.ma, r0 + g.chunk);
     const int rs = max(0, r0 - warm), re = min(g.ma, r1 + warm);
     const int span = re - rs;
-    T* cf = sp + size_t(span) * kLineThreads;  // [span][BW] factor rows
-    T* dv = cf + size_t(span) * BW;            // [span] 1 / D
-    for (int e = lane; e < span * BW; e += kLineThreads) cf[e] = L[size_t(rs) * BW + e];
-    for (int e = lane; e < span; e += kLineThreads) dv[e] = dinv[rs + e];
+    const int spanP = padded_span(span);
+    T* cf = sp + size_t(spanP) * kLineThreads;  // [spanP + BW][BW] factor rows, zero past the span
+    T* dv = cf + size_t(spanP + BW) * BW;       // [spanP] 1 / D, zero past the span
     const bool active = line < g.lines_per_comp;
     size_t base = 0, stride = 0;
-    if (active) {
-        if (g.axis == 0) {
-            base = line;
-            stride = size_t(g.m1) * g.m2;
-        } else if (g.axis == 1) {
-            base = (line / g.m2) * size_t(g.m1) * g.m2 + line % g.m2;
-            stride = g.m2;
-        } else {
-            base = line * g.m2;
-            stride = 1;
+    if (g.axis == 0) {
+        base = line;
+        stride = size_t(g.m1) * g.m2;
+    } else if (g.axis == 1) {
+        base = (line / g.m2) * size_t(g.m1) * g.m2 + line % g.m2;
+        stride = g.m2;
+    } else {
+        base = line * g.m2;
+        stride = 1;
+    }
+    base += size_t(c) * g.G;
+    // 1. staging
+    {
+        const int ncf = span * BW, ncfP = (spanP + BW) * BW;
+        const T* Ls = L + size_t(rs) * BW;
+        for (int e0 = 0; e0 < ncfP; e0 += 4 * kLineThreads) {
+            T t[4];
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const int e = e0 + q * kLineThreads + lane;
+                const T val = Ls[min(e, ncf - 1)];
+                t[q] = (e < ncf) ? val : T(0);
+            }
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const int e = e0 + q * kLineThreads + lane;
+                if (e < ncfP) cf[e] = t[q];
+            }
         }
-        base += size_t(c) * g.G;
-        for (int r = 0; r < span; r += kLoadGroup) {
-            T v[kLoadGroup];
+        for (int e = lane; e < spanP; e += kLineThreads) {
+            const T val = dinv[rs + min(e, span - 1)];
+            dv[e] = (e < span) ? val : T(0);
+        }
+    }
+    if (active) {
+        const T* src = in + base;
+        const int last = re - 1;
+        for (int rb = 0; rb < spanP; rb += 2 * kRowGroup) {
+            T v[2 * kRowGroup];
 #pragma unroll
-            for (int q = 0; q < kLoadGroup; ++q) v[q] = (r + q < span) ? in[base + size_t(rs + r + q) * stride] : T(0);
+            for (int q = 0; q < 2 * kRowGroup; ++q) v[q] = src[size_t(min(rs + rb + q, last)) * stride];
 #pragma unroll
-            for (int q = 0; q < kLoadGroup; ++q)
-                if (r + q < span) sp[(r + q) * kLineThreads + lane] = v[q];
+            for (int q = 0; q < kRowGroup; ++q) sp[(rb + q) * kLineThreads + lane] = v[q];
+            if (rb + kRowGroup < spanP) {
+#pragma unroll
+                for (int q = 0; q < kRowGroup; ++q) sp[(rb + kRowGroup + q) * kLineThreads + lane] = v[kRowGroup + q];
+            }
         }
     }
     __syncthreads();
     if (!active) return;
-    // recurrences in groups of kRowGroup rows: the group's LDS reads are issued
-    // together, then the dependent FMA chain runs on registers
-    constexpr int G = 8;
+    // 2. forward recurrence
     T win[BW];
 #pragma unroll
     for (int k = 0; k < BW; ++k) win[k] = T(0);
-    for (int rb = 0; rb < span; rb += G) {
-        T v[G], cq[G][BW], dq[G];
+    for (int rb = 0; rb < spanP; rb += kRowGroup) {
+        T v[kRowGroup];
 #pragma unroll
-        for (int q = 0; q < G; ++q) {
-            const int r = min(rb + q, span - 1);
-            v[q] = sp[r * kLineThreads + lane];
-            dq[q] = dv[r];
+        for (int q = 0; q < kRowGroup; ++q) v[q] = sp[(rb + q) * kLineThreads + lane];
 #pragma unroll
-            for (int k = 0; k < BW; ++k) cq[q][k] = cf[r * BW + k];
-        }
-#pragma unroll
-        for (int q = 0; q < G; ++q) {
+        for (int q = 0; q < kRowGroup; ++q) {
             T x = v[q];
 #pragma unroll
-            for (int k = 1; k <= BW; ++k) x -= cq[q][k - 1] * win[k - 1];
-            if (rb + q < span) {
+            for (int k = 1; k <= BW; ++k) x -= cf[(rb + q) * BW + k - 1] * win[k - 1];
 #pragma unroll
-                for (int k = BW - 1; k >= 1; --k) win[k] = win[k - 1];
-                win[0] = x;
-            }
-            v[q] = x * dq[q];
+            for (int k = BW - 1; k >= 1; --k) win[k] = win[k - 1];
+            win[0] = x;
+            v[q] = x * dv[rb + q];
         }
 #pragma unroll
-        for (int q = 0; q < G; ++q)
-            if (rb + q < span) sp[(rb + q) * kLineThreads + lane] = v[q];
+        for (int q = 0; q < kRowGroup; ++q) sp[(rb + q) * kLineThreads + lane] = v[q];
     }
+    // 3. backward recurrence, rows spanP-1 down to the chunk start (rows below
+    //    it, clamped to row 0, only rewrite LDS rows that are not output)
+    const int rlo = r0 - rs;
 #pragma unroll
     for (int k = 0; k < BW; ++k) win[k] = T(0);
-    const int rlo = r0 - rs;
-    for (int rb = span - 1; rb >= rlo; rb -= G) {
-        T v[G], cq[G][BW];
+    for (int rb = spanP - 1; rb >= rlo; rb -= kRowGroup) {
+        T v[kRowGroup];
 #pragma unroll
-        for (int q = 0; q < G; ++q) {
-            const int r = max(rb - q, rlo);
-            v[q] = sp[r * kLineThreads + lane];
+        for (int q = 0; q < kRowGroup; ++q) v[q] = sp[max(rb - q, 0) * kLineThreads + lane];
 #pragma unroll
-            for (int k = 1; k <= BW; ++k) cq[q][k - 1] = (r + k < span) ? cf[(r + k) * BW + k - 1] : T(0);
+        for (int q = 0; q < kRowGroup; ++q) {
+            const int r = max(rb - q, 0);
+            T x = v[q];
+#pragma unroll
+            for (int k = 1; k <= BW; ++k) x -= cf[(r + k) * BW + k - 1] * win[k - 1];
+#pragma unroll
+            for (int k = BW - 1; k >= 1; --k) win[k] = win[k - 1];
+            win[0] = x;
+            v[q] = x;
         }
 #pragma unroll
-        for (int q = 0; q < G; ++q) {
-            const int r = rb - q;
-            if (r >= rlo) {
-                T x = v[q];
-#pragma unroll
-                for (int k = 1; k <= BW; ++k) x -= cq[q][k - 1] * win[k - 1];
-#pragma unroll
-                for (int k = BW - 1; k >= 1; --k) win[k] = win[k - 1];
-                win[0] = x;
-                if (rs + r < r1) out[base + size_t(rs + r) * stride] = x;
-            }
-        }
+        for (int q = 0; q < kRowGroup; ++q) sp[max(rb - q, 0) * kLineThreads + lane] = v[q];
     }
+    // 4. output rows [r0, r1)
+    T* dst = out + base;
+    for (int r = r0; r < r1; ++r) dst[size_t(r) * stride] = sp[(r - rs) * kLineThreads + lane];
 }
 
 // ------------------------------------------------------------------------------
@@ -902,7 +1014,7 @@ int apply_blocks(const OpDev<T>& op) {
         const int PL = op.m[1] * op.m[2];
         return ((PL + tpb - 1) / tpb) * ((op.m[0] + kX1Chunk - 1) / kX1Chunk);
     }
-    return (op.m[0] * op.m[1] + tpb - 1) / tpb;
+    return ((op.m[0] + kT1 - 1) / kT1) * ((op.m[1] + kT2 - 1) / kT2);
 }
 
 template <typename T>
@@ -919,17 +1031,60 @@ void launch_apply(const OpDev<T>& op, int mode, const T* x, T* y, const T* b, T*
     }
 }
 
+// Fixed-width kernel when every real axis has the same window width w
+// (2D: <w, w, 1>, 3D: <w, w, w>); the generic kernel otherwise.
+template <typename T, bool Restrict, int W>
+bool launch_xfer_w(const XferDev<T>& X, int ncomp, const T* in, T* out, size_t n, hipStream_t s) {
+    const dim3 grid((n + kThreads - 1) / kThreads);
+    if (X.dim == 2) {
+        if (Restrict)
+            hipLaunchKernelGGL((k_restrict_w<T, W, W, 1>), grid, dim3(kThreads), 0, s, X, ncomp, in, out);
+        else
+            hipLaunchKernelGGL((k_prolong_add_w<T, W, W, 1>), grid, dim3(kThreads), 0, s, X, ncomp, in, out);
+    } else {
+        if (Restrict)
+            hipLaunchKernelGGL((k_restrict_w<T, W, W, W>), grid, dim3(kThreads), 0, s, X, ncomp, in, out);
+        else
+            hipLaunchKernelGGL((k_prolong_add_w<T, W, W, W>), grid, dim3(kThreads), 0, s, X, ncomp, in, out);
+    }
+    return true;
+}
+
+template <typename T, bool Restrict>
+bool launch_xfer_fixed(const XferDev<T>& X, int ncomp, const T* in, T* out, size_t n, hipStream_t s) {
+    auto width = [&](int a) { return Restrict ? X.ax[a].wr : X.ax[a].w; };
+    const int w = width(0);
+    for (int a = 1; a < X.dim; ++a)
+        if (width(a) != w) return false;
+    for (int a = X.dim; a < 3; ++a)
+        if (width(a) != 1) return false;
+    switch (w) {
+        case 2: return launch_xfer_w<T, Restrict, 2>(X, ncomp, in, out, n, s);
+        case 3: return launch_xfer_w<T, Restrict, 3>(X, ncomp, in, out, n, s);
+        case 4: return launch_xfer_w<T, Restrict, 4>(X, ncomp, in, out, n, s);
+        case 5: return launch_xfer_w<T, Restrict, 5>(X, ncomp, in, out, n, s);
+        case 6: return launch_xfer_w<T, Restrict, 6>(X, ncomp, in, out, n, s);
+        case 7: return launch_xfer_w<T, Restrict, 7>(X, ncomp, in, out, n, s);
+        case 8: return launch_xfer_w<T, Restrict, 8>(X, ncomp, in, out, n, s);
+        default: return false;
+    }
+}
+
 template <typename T>
 void launch_restrict(const XferDev<T>& X, int ncomp, const T* rf, T* rc, hipStream_t s) {
     const size_t n = size_t(ncomp) * X.ax[0].mc * X.ax[1].mc * X.ax[2].mc;
-    hipLaunchKernelGGL(k_restrict<T>, dim3((n + kThreads - 1) / kThreads), dim3(kThreads), 0, s, X, ncomp, rf, rc);
+    if (!launch_xfer_fixed<T, true>(X, ncomp, rf, rc, n, s))
+        hipLaunchKernelGGL(k_restrict<T>, dim3((n + kThreads - 1) / kThreads), dim3(kThreads), 0, s, X, ncomp, rf,
+                           rc);
     check_launch("restrict");
 }
 
 template <typename T>
 void launch_prolong_add(const XferDev<T>& X, int ncomp, const T* ec, T* xf, hipStream_t s) {
     const size_t n = size_t(ncomp) * X.ax[0].mf * X.ax[1].mf * X.ax[2].mf;
-    hipLaunchKernelGGL(k_prolong_add<T>, dim3((n + kThreads - 1) / kThreads), dim3(kThreads), 0, s, X, ncomp, ec, xf);
+    if (!launch_xfer_fixed<T, false>(X, ncomp, ec, xf, n, s))
+        hipLaunchKernelGGL(k_prolong_add<T>, dim3((n + kThreads - 1) / kThreads), dim3(kThreads), 0, s, X, ncomp,
+                           ec, xf);
     check_launch("prolong");
 }
 
@@ -965,14 +1120,17 @@ void launch_tsolve(int dim, const int* m, const TFacDev<T>* fac, const T* v, T* 
         g.m2 = m2;
         g.lines_per_comp = G / F.m;
         const size_t lines = size_t(dim) * g.lines_per_comp;
-        // enough independent chunks to fill the device; chunks of at least 16 rows,
-        // and a staged span (chunk + 2 warm rows per lane) that fits in LDS
+        // enough independent chunks to fill the device; a chunk is then grown
+        // to fill the padding of its staged span (chunk + 2 warm rows,
+        // rounded up to whole row groups), which costs nothing extra
         const size_t want = (size_t(1) << 17) / std::max<size_t>(lines, 1) + 1;
-        g.nchunk = int(std::max<size_t>(1, std::min<size_t>(want, size_t((F.m + 15) / 16))));
-        g.chunk = (F.m + g.nchunk - 1) / g.nchunk;
+        const int nc0 = int(std::max<size_t>(1, std::min<size_t>(want, size_t((F.m + 15) / 16))));
+        int chunk = (F.m + nc0 - 1) / nc0;
+        if (chunk < F.m) chunk = std::max(chunk, padded_span(chunk + 2 * F.warm) - 2 * F.warm);
+        g.chunk = std::min(chunk, F.m);
         g.nchunk = (F.m + g.chunk - 1) / g.chunk;
-        const int span = std::min(F.m, g.chunk + 2 * F.warm);
-        const size_t lds = size_t(span) * (kLineThreads + F.bw + 1) * sizeof(T);
+        const int spanP = padded_span(std::min(F.m, g.chunk + 2 * F.warm));
+        const size_t lds = (size_t(spanP) * (kLineThreads + F.bw + 1) + size_t(F.bw) * F.bw) * sizeof(T);
         if (lds > 160 * 1024) throw std::runtime_error("T-solve span does not fit in LDS");
         g.ncomp = dim;
         const size_t lp = (g.lines_per_comp + kLineThreads - 1) / kLineThreads * kLineThreads;

@@ -40,6 +40,7 @@ struct CdError : std::runtime_error {
 
 void hip_check(hipError_t e, const char* what) {
     if (e != hipSuccess) {
+        (void)hipGetLastError();  // do not leave the error for the caller's next HIP call
         if (e == hipErrorOutOfMemory) throw CdError(CD_ENOMEM, std::string(what) + ": out of device memory");
         throw CdError(CD_EHIP, std::string(what) + ": " + hipGetErrorString(e));
     }
@@ -172,6 +173,11 @@ struct cd_solver {
     hipEvent_t iter_event = nullptr;
     double* xw = nullptr;                 // iterate of the outer iteration (copied to the caller's x)
     hipGraphExec_t iter_graph = nullptr;  // captured outer iteration k >= 1
+    // the same iteration captured with live timing: the apply events are
+    // external event nodes of this graph, read back after every replay
+    hipGraphExec_t iter_graph_prof = nullptr;
+    std::vector<ProfRec> prof_graph;
+    bool capturing = false, graph_prof_ran = false;
 
     bool prof = false;
     std::vector<ProfRec> prof_pending;
@@ -181,6 +187,8 @@ struct cd_solver {
         if (iter_event) (void)hipEventDestroy(iter_event);
         if (entry_event) (void)hipEventDestroy(entry_event);
         if (iter_graph) (void)hipGraphExecDestroy(iter_graph);
+        if (iter_graph_prof) (void)hipGraphExecDestroy(iter_graph_prof);
+        for (auto& r : prof_graph) { (void)hipEventDestroy(r.a); (void)hipEventDestroy(r.b); }
         for (auto& r : prof_pending) { (void)hipEventDestroy(r.a); (void)hipEventDestroy(r.b); }
         for (auto& e : prof_pool) { (void)hipEventDestroy(e.first); (void)hipEventDestroy(e.second); }
     }
@@ -383,6 +391,35 @@ const cd::TFacDev<double>* tfacs<double>(cd_solver* s) { return s->tfd64; }
 template <>
 const cd::TFacDev<float>* tfacs<float>(cd_solver* s) { return s->tfd32; }
 
+void prof_add(cd_solver* s, const cd_solver::ProfRec& r) {
+    float ms = 0.f;
+    hip_check(hipEventElapsedTime(&ms, r.a, r.b), "hipEventElapsedTime");
+    cd_kernel_stats& st = s->prof_stats[r.cls];
+    st.launches += 1;
+    st.total_ms += ms;
+    st.bytes += r.bytes;
+}
+
+// Record a timing event on the solver stream.  Inside a stream capture the
+// event becomes an event-record node of the captured graph, appended to the
+// capture's current dependency set, so every replay records it.
+void record_timing_event(cd_solver* s, hipEvent_t ev) {
+    if (!s->capturing) {
+        hip_check(hipEventRecord(ev, s->stream), "hipEventRecord");
+        return;
+    }
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    hipGraph_t g = nullptr;
+    const hipGraphNode_t* deps = nullptr;
+    size_t nd = 0;
+    hip_check(hipStreamGetCaptureInfo_v2(s->stream, &cs, nullptr, &g, &deps, &nd), "hipStreamGetCaptureInfo_v2");
+    if (cs != hipStreamCaptureStatusActive || !g) throw CdError(CD_EHIP, "timing event outside an active capture");
+    hipGraphNode_t node = nullptr;
+    hip_check(hipGraphAddEventRecordNode(&node, g, deps, nd, ev), "hipGraphAddEventRecordNode");
+    hip_check(hipStreamUpdateCaptureDependencies(s->stream, &node, 1, hipStreamSetCaptureDependencies),
+              "hipStreamUpdateCaptureDependencies");
+}
+
 // ---- operator apply with optional live timing ---------------------------------------
 template <typename T>
 void apply_op(cd_solver* s, int level, int mode, const T* x, T* y, const T* b, T* u, T* xout, T c1, T c2,
@@ -402,25 +439,29 @@ void apply_op(cd_solver* s, int level, int mode, const T* x, T* y, const T* b, T
     }
     const double nvec = (mode == kApplyRes) ? 3.0 : (mode == kApplyCheb) ? 5.0 : 2.0;
     const int cls = 2 * level + (sizeof(T) == 4 ? 1 : 0);
-    hip_check(hipEventRecord(ev.first, s->stream), "hipEventRecord");
+    record_timing_event(s, ev.first);
     cd::launch_apply<T>(op, mode, x, y, b, u, xout, c1, c2, part, s->stream);
-    hip_check(hipEventRecord(ev.second, s->stream), "hipEventRecord");
-    s->prof_pending.push_back({ev.first, ev.second, cls, nvec * double(s->lv[level].N) * sizeof(T)});
+    record_timing_event(s, ev.second);
+    const cd_solver::ProfRec rec{ev.first, ev.second, cls, nvec * double(s->lv[level].N) * sizeof(T)};
+    if (s->capturing)
+        s->prof_graph.push_back(rec);
+    else
+        s->prof_pending.push_back(rec);
 }
+
 
 // Fold finished event pairs into the totals (call after a stream sync).
 void prof_flush(cd_solver* s) {
     if (s->prof_stats.size() < 2 * s->lv.size()) s->prof_stats.resize(2 * s->lv.size(), cd_kernel_stats{0, 0.0, 0.0});
     for (auto& r : s->prof_pending) {
-        float ms = 0.f;
-        hip_check(hipEventElapsedTime(&ms, r.a, r.b), "hipEventElapsedTime");
-        cd_kernel_stats& st = s->prof_stats[r.cls];
-        st.launches += 1;
-        st.total_ms += ms;
-        st.bytes += r.bytes;
+        prof_add(s, r);
         s->prof_pool.push_back({r.a, r.b});
     }
     s->prof_pending.clear();
+    if (s->graph_prof_ran) {  // events of the last replay of the timed graph
+        for (auto& r : s->prof_graph) prof_add(s, r);
+        s->graph_prof_ran = false;
+    }
 }
 
 // ---- V-cycle pieces ------------------------------------------------------------
@@ -719,30 +760,38 @@ void enqueue_iteration(cd_solver* s, bool first) {
 // Enqueue one outer iteration.  Every iteration after the first reads and
 // writes the same solver-owned buffers with the same coefficients, so it is
 // captured once into a HIP graph and replayed (no memset nodes: buffers are
-// cleared by kernels).  With live timing enabled iterations run eagerly.
+// cleared by kernels).  With live timing enabled a second graph is captured
+// whose operator applies are bracketed by external event-record nodes.
+constexpr bool kGraphTiming = true;
+
 void solve_iterate(cd_solver* s) {
     hipStream_t st = s->stream;
     SolveState& S = s->state;
     const bool first = (S.k == 0);
-    if (first || !s->opt.graphs || s->prof) {
+    if (first || !s->opt.graphs || (s->prof && !kGraphTiming)) {
         enqueue_iteration(s, first);
     } else {
-        if (!s->iter_graph) {
+        hipGraphExec_t& exec = s->prof ? s->iter_graph_prof : s->iter_graph;
+        if (!exec) {
             hipGraph_t g = nullptr;
             hip_check(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal), "hipStreamBeginCapture");
+            s->capturing = s->prof;
             try {
                 enqueue_iteration(s, false);
             } catch (...) {
+                s->capturing = false;
                 (void)hipStreamEndCapture(st, &g);
                 if (g) (void)hipGraphDestroy(g);
                 throw;
             }
+            s->capturing = false;
             hip_check(hipStreamEndCapture(st, &g), "hipStreamEndCapture");
-            const hipError_t e = hipGraphInstantiate(&s->iter_graph, g, nullptr, nullptr, 0);
+            const hipError_t e = hipGraphInstantiate(&exec, g, nullptr, nullptr, 0);
             (void)hipGraphDestroy(g);
             hip_check(e, "hipGraphInstantiate");
         }
-        hip_check(hipGraphLaunch(s->iter_graph, st), "hipGraphLaunch");
+        hip_check(hipGraphLaunch(exec, st), "hipGraphLaunch");
+        if (s->prof) s->graph_prof_ran = true;
     }
     hip_check(hipEventRecord(s->iter_event, st), "hipEventRecord");
 }
