@@ -17,6 +17,7 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+PROF_PERIOD = 8  # outer iterations per timed one in the timed region
 
 
 def percentile(v, q):
@@ -66,6 +67,8 @@ def main():
     ap.add_argument("--only-c4", action="store_true", help="run only the 3D p=3 n=128 operator-apply measurement")
     ap.add_argument("--serve", type=int, default=16, help="requests of the serving stream to run (0: skip)")
     ap.add_argument("--serve-max-iter", type=int, default=4000)
+    ap.add_argument("--copy-cal", action="store_true",
+                    help="also run a plain 256 MiB device copy 5 times (calibrates HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: this build has no multi-GPU path (see DESIGN.md, sharding)",
@@ -80,6 +83,8 @@ def main():
 
     torch.cuda.set_device(0)
     st = torch.cuda.current_stream().cuda_stream
+    if args.copy_cal:
+        copy_calibration(torch)
     if args.only_c4:
         print(json.dumps({"operator_apply_c4": c4_apply(capi, torch, st)}), flush=True)
         return
@@ -115,15 +120,16 @@ def main():
         print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
     # live timing on from the warm-up on, so that the timed region replays
-    # graphs that were captured (with their timing event nodes) before it
+    # graphs that were captured (with their timing event nodes) before it;
+    # every PROF_PERIOD-th outer iteration carries the timing events
     for s in mixed.values():
-        s.profile_enable(True)
+        s.profile_enable(True, PROF_PERIOD)
     for k in range(args.warmup):
         step(k, mixed, [], its, [])
         log(f"warmup step {k} done, iterations {its}")
     for s in mixed.values():  # restart the counters
         s.profile_enable(False)
-        s.profile_enable(True)
+        s.profile_enable(True, PROF_PERIOD)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for k in range(args.warmup, nsteps):
@@ -249,6 +255,17 @@ def serve_bench(capi, torch, st, count, max_iter, log):
             "fp64_sequential": {"solves_per_s": count / T64, "converged": ok64,
                                 "p50_ms": 1e3 * percentile(lat64, 50), "p99_ms": 1e3 * percentile(lat64, 99)},
             "speedup_vs_fp64_sequential": T64 / T}
+
+
+def copy_calibration(torch, mib=256, reps=5):
+    """A plain device-to-device copy of known size: its FETCH_SIZE and
+    WRITE_SIZE counters per dispatch calibrate those of the solver kernels."""
+    a = torch.empty(mib << 18, dtype=torch.float32, device="cuda").fill_(1.0)
+    b = torch.empty_like(a)
+    for _ in range(reps):
+        torch.mul(a, 1.0, out=b)  # an elementwise kernel of its own name: reads and writes mib MiB
+    torch.cuda.synchronize()
+    print(f"[bench] copy calibration: {reps} copies of {mib} MiB", file=sys.stderr, flush=True)
 
 
 def c4_apply(capi, torch, st, reps=20):

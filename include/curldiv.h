@@ -162,9 +162,12 @@ int cd_coarse_solve(cd_solver* s, const double* r_dev, double* z_dev);
 int cd_precondition(cd_solver* s, const double* r_dev, double* z_dev);
 
 /* ---- live kernel timing ------------------------------------------------- */
-/* When enabled, every operator-apply launch of the handle is bracketed by a
- * pair of HIP events on the handle's stream; the elapsed times are folded
- * into per-(level, precision) totals at the next synchronisation point.
+/* When enabled, the operator-apply launches of the handle are bracketed by
+ * pairs of HIP events on the handle's stream (event-record nodes when the
+ * outer iteration is replayed from a HIP graph); the elapsed times are
+ * folded into per-(level, precision) totals at the next synchronisation
+ * point.  Hooks (cd_apply, cd_precondition, ...) are always timed; during
+ * cd_solve every `on`-th outer iteration is (on = 1: all of them).
  * `bytes` accumulates the algorithmic traffic of those launches: the vectors
  * each launch must read and write once (2 N s for y = A x, 3 N s for the
  * residual, 5 N s for a Chebyshev step; s = 8 or 4 bytes). */
@@ -173,7 +176,8 @@ typedef struct {
     double total_ms;
     double bytes;
 } cd_kernel_stats;
-/* Enable (on != 0) or disable timing; enabling resets the totals. */
+/* Enable (on > 0, the sampling period of outer iterations) or disable
+ * (on <= 0) timing; enabling resets the totals. */
 int cd_profile_enable(cd_solver* s, int on);
 /* Totals of level `level` applies in FP64 (fp32 = 0) or FP32 (fp32 = 1). */
 int cd_profile_read(const cd_solver* s, int level, int fp32, cd_kernel_stats* out);

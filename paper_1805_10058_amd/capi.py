@@ -230,8 +230,10 @@ class Solver:
     def coarse_solve(self, r_ptr, z_ptr):
         check(lib().cd_coarse_solve(self._h, ctypes.c_void_p(r_ptr), ctypes.c_void_p(z_ptr)))
 
-    def profile_enable(self, on=True):
-        check(lib().cd_profile_enable(self._h, 1 if on else 0))
+    def profile_enable(self, on=True, period=1):
+        """Live timing of operator applies; during solves every `period`-th
+        outer iteration is timed."""
+        check(lib().cd_profile_enable(self._h, max(int(period), 1) if on else 0))
 
     def profile_read(self, level, fp32):
         st = cd_kernel_stats()

@@ -178,6 +178,9 @@ struct cd_solver {
     hipGraphExec_t iter_graph_prof = nullptr;
     std::vector<ProfRec> prof_graph;
     bool capturing = false, graph_prof_ran = false;
+    int prof_period = 1;        // time every prof_period-th outer iteration
+    long long prof_iter = 0;    // outer iterations run while timing was on
+    bool prof_sample = true;    // the current iteration is timed
 
     bool prof = false;
     std::vector<ProfRec> prof_pending;
@@ -425,7 +428,7 @@ template <typename T>
 void apply_op(cd_solver* s, int level, int mode, const T* x, T* y, const T* b, T* u, T* xout, T c1, T c2,
               double* part) {
     const cd::OpDev<T>& op = devlevels<T>(s)[level].op;
-    if (!s->prof) {
+    if (!s->prof || !s->prof_sample) {
         cd::launch_apply<T>(op, mode, x, y, b, u, xout, c1, c2, part, s->stream);
         return;
     }
@@ -762,20 +765,20 @@ void enqueue_iteration(cd_solver* s, bool first) {
 // captured once into a HIP graph and replayed (no memset nodes: buffers are
 // cleared by kernels).  With live timing enabled a second graph is captured
 // whose operator applies are bracketed by external event-record nodes.
-constexpr bool kGraphTiming = true;
-
 void solve_iterate(cd_solver* s) {
     hipStream_t st = s->stream;
     SolveState& S = s->state;
     const bool first = (S.k == 0);
-    if (first || !s->opt.graphs || (s->prof && !kGraphTiming)) {
+    const bool timed = s->prof && (s->prof_iter++ % s->prof_period == 0);
+    s->prof_sample = timed;
+    if (first || !s->opt.graphs) {
         enqueue_iteration(s, first);
     } else {
-        hipGraphExec_t& exec = s->prof ? s->iter_graph_prof : s->iter_graph;
+        hipGraphExec_t& exec = timed ? s->iter_graph_prof : s->iter_graph;
         if (!exec) {
             hipGraph_t g = nullptr;
             hip_check(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal), "hipStreamBeginCapture");
-            s->capturing = s->prof;
+            s->capturing = timed;
             try {
                 enqueue_iteration(s, false);
             } catch (...) {
@@ -791,8 +794,9 @@ void solve_iterate(cd_solver* s) {
             hip_check(e, "hipGraphInstantiate");
         }
         hip_check(hipGraphLaunch(exec, st), "hipGraphLaunch");
-        if (s->prof) s->graph_prof_ran = true;
+        if (timed) s->graph_prof_ran = true;
     }
+    s->prof_sample = true;
     hip_check(hipEventRecord(s->iter_event, st), "hipEventRecord");
 }
 
@@ -1128,7 +1132,9 @@ int cd_profile_enable(cd_solver* s, int on) {
         enter(s);
         hip_check(hipStreamSynchronize(s->stream), "sync");
         prof_flush(s);
-        s->prof = (on != 0);
+        s->prof = (on > 0);
+        s->prof_period = std::max(on, 1);
+        s->prof_iter = 0;
         if (s->prof) s->prof_stats.assign(2 * s->lv.size(), cd_kernel_stats{0, 0.0, 0.0});
     });
 }
