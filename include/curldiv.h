@@ -170,7 +170,8 @@ int cd_precondition(cd_solver* s, const double* r_dev, double* z_dev);
  * cd_solve every `on`-th outer iteration is (on = 1: all of them).
  * `bytes` accumulates the algorithmic traffic of those launches: the vectors
  * each launch must read and write once (2 N s for y = A x, 3 N s for the
- * residual, 5 N s for a Chebyshev step; s = 8 or 4 bytes). */
+ * residual, 5 N s for a Chebyshev step, (2 + k) N s for y = A x fused with
+ * k Krylov-basis dot products; s = 8 or 4 bytes). */
 typedef struct {
     long long launches;
     double total_ms;

@@ -75,108 +75,219 @@ __device__ inline T diag_entry(const OpDev<T>& op, int c, int i0, int i1, int i2
            (c == 2 ? op.beta : op.alpha) * t2;
 }
 
+// 3D output tile: k3T2 rows (x2) of k3T3(HB) = 32 - 2HB columns (x3), so that
+// the stage-A positions (k3T2 rows of 32 tile columns) are exactly one per thread.
+constexpr int k3T2 = 8, k3E3 = 32;
+__host__ __device__ constexpr int k3T3(int hb) { return k3E3 - 2 * hb; }
+constexpr int kXcds = 8;
+
+// Launch geometry of the 3D operator kernel: tiles of the (x2, x3) plane times
+// ranges of x1 planes, about two resident blocks per compute unit.
+struct Apply3dGeom {
+    int nt2, nt3, c1len, nblocks;
+};
+
+Apply3dGeom apply3d_geom(const int* m, int hb) {
+    constexpr int kTargetBlocks = 512;
+    Apply3dGeom g;
+    g.nt2 = (m[1] + k3T2 - 1) / k3T2;
+    g.nt3 = (m[2] + k3T3(hb) - 1) / k3T3(hb);
+    const int planar = g.nt2 * g.nt3;
+    const int nx1 = std::max(1, std::min(m[0], kTargetBlocks / planar));
+    g.c1len = (m[0] + nx1 - 1) / nx1;
+    g.nblocks = planar * ((m[0] + g.c1len - 1) / g.c1len);
+    return g;
+}
+
+// Partial dot products an operator kernel accumulates per thread.
+template <int MODE>
+constexpr int apply_ndots() {
+    return MODE == kApplyYMulti ? kMaxBasis : 1;
+}
+
+// Epilogue of the operator kernels at one output entry idx (component c,
+// grid point (i1, i2, i3)) with kx = (A x)[idx]; ntot = vector length.
+template <typename T, int MODE>
+__device__ inline void apply_epilogue(const OpDev<T>& op, int c, size_t idx, T kx, int i1, int i2, int i3,
+                                      const T* __restrict__ x, T* __restrict__ y, const T* __restrict__ b,
+                                      T* __restrict__ u, T* __restrict__ xout, T c1, T c2, int nv, size_t ntot,
+                                      double* dots) {
+    if (MODE == kApplyY) {
+        y[idx] = kx;
+    } else if (MODE == kApplyRes) {
+        y[idx] = b[idx] - kx;
+    } else if (MODE == kApplyResDot) {
+        const T r = b[idx] - kx;
+        y[idx] = r;
+        dots[0] += double(r) * double(r);
+    } else if (MODE == kApplyYMulti) {
+        y[idx] = kx;
+#pragma unroll
+        for (int i = 0; i < kMaxBasis; ++i)
+            if (i < nv) dots[i] += double(b[size_t(i) * ntot + idx]) * double(kx);
+    } else if (MODE == kApplyCheb) {
+        const T r = b[idx] - kx;
+        const T dg = diag_entry(op, c, i1, i2, i3);
+        const T uprev = (c1 != T(0)) ? u[idx] : T(0);  // u is not read on a first step
+        const T un = c1 * uprev + c2 * r / dg;
+        u[idx] = un;
+        xout[idx] = x[idx] + un;
+    } else {
+        y[idx] = kx;
+        dots[0] += double(x[idx]) * double(kx);
+    }
+}
+
+// Block sums of the per-thread partial dots: part[i * gridDim.x + block].
+template <int MODE>
+__device__ inline void apply_write_dots(const double* dots, int nv, double* __restrict__ part) {
+    if (MODE == kApplyYDot || MODE == kApplyResDot) {
+        const double tot = block_sum(dots[0]);
+        if (threadIdx.x == 0) part[blockIdx.x] = tot;
+    } else if (MODE == kApplyYMulti) {
+#pragma unroll
+        for (int i = 0; i < kMaxBasis; ++i) {
+            if (i < nv) {  // block-uniform
+                const double tot = block_sum(dots[i]);
+                if (threadIdx.x == 0) part[size_t(i) * gridDim.x + blockIdx.x] = tot;
+            }
+        }
+    }
+}
+
 // ------------------------------------------------------------------------------
 // 3D operator apply.
 //
-// Block (chunk, x1-range): the block owns TPB = kThreads - 2HB consecutive
-// points f = s + tid of the flattened (x2, x3) plane and output planes x1 in
-// [o0, o1).  Every thread keeps the same in-plane position for the whole
-// march, so the band coefficients of its axis-2 row and axis-3 row are loaded
-// into registers once.  For every input plane j in [o0-HB, o1+HB):
-//   load    the three components' plane chunk with a +-HB row halo into LDS;
-//   (A)     contract axis 2 (stride m3): M2 x, A2 x, S2 x of all components at
-//           the kThreads stage positions s-HB .. s+TPB+HB-1;
-//   (B)     contract axis 3 (contiguous) at f and combine the raw products
-//           with alpha, beta, alpha-beta into W[c][{S,M,A}], the inputs of the
-//           axis-1 contraction of output component c;
-//   (C)     scatter W into a ring of 2HB+1 per-plane accumulators in
-//           registers: acc(i) += X1(i, j) W for i in [j-HB, j+HB] (X1 entries
-//           are block-uniform scalars).
+// A block owns an output tile of k3T2 x (32 - 2HB) columns of the (x2, x3)
+// plane (one per thread; the other threads only help with loads and stage A)
+// and the output planes x1 in [o0, o1); it marches over the
+// input planes j in [o0-HB, o1+HB).  For every input plane:
+//   (A) contract axis 2 (stride m3): M2 x, A2 x, S2 x of the three components
+//       at the tile rows and all k3T3 + 2HB tile columns (LDS tile of the
+//       plane with a +-HB halo on both in-plane axes);
+//   (B) contract axis 3 at the thread's column and combine the raw products
+//       with alpha, beta, alpha-beta into W[c][{S,M,A}], the inputs of the
+//       axis-1 contraction of output component c;
+//   (C) scatter W into a ring of 2HB+1 per-plane accumulators in registers:
+//       acc(i) += X1(i, j) W for i in [j-HB, j+HB].
 // After plane j the accumulator of output plane j-HB is complete and goes
-// through the epilogue.  33 band contractions per point.
+// through the epilogue.  The loads of plane j+2 are issued while plane j is
+// computed (registers), and stored to LDS once stage A of plane j+1 is done.
+// 33 band contractions per point.
+//
+// Tiles are numbered with x2 fastest, then x3, then the x1 range, and block b
+// takes tile (b mod 8) * ceil-share + b / 8: consecutive blocks land on
+// different XCDs, so this keeps spatially adjacent tiles, whose halos overlap,
+// on the same XCD and its L2.
 // ------------------------------------------------------------------------------
+
 template <typename T, int HB, int MODE>
 __global__ __launch_bounds__(kThreads) void k_apply3d(OpDev<T> op, const T* __restrict__ x, T* __restrict__ y,
                                                       const T* __restrict__ b, T* __restrict__ u,
                                                       T* __restrict__ xout, T c1, T c2, double* __restrict__ part,
-                                                      int nchunk, int c1len) {
+                                                      int nv, Apply3dGeom g) {
     constexpr int R = 2 * HB + 1;
-    constexpr int TPB = kThreads - 2 * HB;
-    extern __shared__ __align__(16) unsigned char smem_raw[];
+    constexpr int T3 = k3T3(HB);
+    constexpr int E2 = k3T2 + 2 * HB, E3 = k3E3;
+    constexpr int NIN = E2 * E3;  // input tile per component and plane
+    constexpr int NLD = (3 * NIN + kThreads - 1) / kThreads;
+    constexpr int NA = k3T2 * E3;  // stage-A positions
+    constexpr int NPA = (NA + kThreads - 1) / kThreads;
+    static_assert(NA == kThreads, "one stage-A position per thread");
+    __shared__ T xs[3 * NIN];
+    __shared__ T st[9 * NA];          // M2x A2x S2x of components 0, 1, 2, each [k3T2][E3]
+    __shared__ T ca[3 * R * k3T2];    // axis-2 band rows of the tile: [w][k][row]
     const int m1 = op.m[0], m2 = op.m[1], m3 = op.m[2];
-    const int PL = m2 * m3;
-    const size_t G = size_t(m1) * PL;
-    const int XSN = kThreads + 2 * HB * m3;
-    T* xs = reinterpret_cast<T*>(smem_raw);  // [3][XSN]
-    T* st = xs + 3 * XSN;                    // [9][kThreads]: M2x A2x S2x of components 0,1,2
-    const int chunk = blockIdx.x % nchunk;
-    const int xc = blockIdx.x / nchunk;
-    const int s = chunk * TPB;
-    const int o0 = xc * c1len;
-    const int o1 = min(o0 + c1len, m1);
+    const size_t PL = size_t(m2) * m3, G = size_t(m1) * PL;
+    const int xcd = int(blockIdx.x % kXcds), slot = int(blockIdx.x / kXcds);
+    const int per = g.nblocks / kXcds, rem = g.nblocks % kXcds;
+    const int tile = xcd * per + min(xcd, rem) + slot;
+    const int o2 = (tile % g.nt2) * k3T2;
+    const int o3 = ((tile / g.nt2) % g.nt3) * T3;
+    const int o0 = (tile / (g.nt2 * g.nt3)) * g.c1len;
+    const int o1 = min(o0 + g.c1len, m1);
     const int tid = threadIdx.x;
-    const int base = s - HB - HB * m3;  // flat index of xs[0]
-
-    // stage-A position of this thread and its axis-2 band row
-    const int ffa = s - HB + tid;
-    const bool ina = (ffa >= 0 && ffa < PL);
-    const int r2 = ina ? ffa / m3 : 0;
-    T ca[3][R];
-#pragma unroll
-    for (int w = 0; w < 3; ++w)
-#pragma unroll
-        for (int k = 0; k < R; ++k) ca[w][k] = ina ? op.band[1][w][k * m2 + r2] : T(0);
-    // output point of this thread and its axis-3 band row
-    const int f = s + tid;
-    const bool active = (tid < TPB) && (f < PL);
-    const int i3 = active ? f % m3 : 0;
-    const int i2 = active ? f / m3 : 0;
+    for (int e = tid; e < 3 * R * k3T2; e += kThreads) {
+        const int i = e % k3T2, k = (e / k3T2) % R, w = e / (k3T2 * R);
+        ca[e] = op.band[1][w][k * m2 + min(o2 + i, m2 - 1)];  // rows past the grid feed unused outputs
+    }
+    // output column of this thread and its axis-3 band row
+    const int ty = tid / E3, tx = tid % E3;
+    const int i2 = o2 + ty, i3 = o3 + tx;
+    const bool active = (tx < T3) && (i2 < m2) && (i3 < m3);
     T cb[3][R];
 #pragma unroll
     for (int w = 0; w < 3; ++w)
 #pragma unroll
         for (int k = 0; k < R; ++k) cb[w][k] = active ? op.band[2][w][k * m3 + i3] : T(0);
-
     T acc[3][R];
 #pragma unroll
     for (int c = 0; c < 3; ++c)
 #pragma unroll
         for (int r = 0; r < R; ++r) acc[c][r] = T(0);
-    double dot = 0.0;
+    double dots[apply_ndots<MODE>()];
+#pragma unroll
+    for (int i = 0; i < apply_ndots<MODE>(); ++i) dots[i] = 0.0;
     const T al = op.alpha, be = op.beta, ab = op.alpha - op.beta;
 
+    T v[NLD];
+    auto load_plane = [&](int j) {
+#pragma unroll
+        for (int q = 0; q < NLD; ++q) {
+            const int e = min(tid + q * kThreads, 3 * NIN - 1);
+            const int c = e / NIN, rr = e % NIN;
+            const int g2 = o2 - HB + rr / E3, g3 = o3 - HB + rr % E3;
+            const bool in = j >= 0 && j < m1 && g2 >= 0 && g2 < m2 && g3 >= 0 && g3 < m3;
+            const T val = x[size_t(c) * G + (in ? size_t(j) * PL + size_t(g2) * m3 + g3 : 0)];
+            v[q] = in ? val : T(0);
+        }
+    };
+    auto store_plane = [&]() {
+#pragma unroll
+        for (int q = 0; q < NLD; ++q) {
+            const int e = tid + q * kThreads;
+            if (e < 3 * NIN) xs[e] = v[q];
+        }
+    };
     const int TI = (o1 - o0) + 2 * HB;
+    load_plane(o0 - HB);
+    store_plane();
+    if (TI > 1) load_plane(o0 - HB + 1);
+    __syncthreads();
     for (int t0 = 0; t0 < TI; t0 += R) {
 #pragma unroll
         for (int uu = 0; uu < R; ++uu) {
             const int t = t0 + uu;
-            if (t < TI) {
+            if (t < TI) {  // block-uniform
                 const int j = o0 - HB + t;
-                if (j >= 0 && j < m1) {
-                    const T* xp = x + size_t(j) * PL;
-                    for (int q = tid; q < XSN; q += kThreads) {
-                        const int ff = base + q;
-                        const bool in = (ff >= 0 && ff < PL);
-                        xs[q] = in ? xp[ff] : T(0);
-                        xs[XSN + q] = in ? xp[G + ff] : T(0);
-                        xs[2 * XSN + q] = in ? xp[2 * G + ff] : T(0);
-                    }
-                    __syncthreads();
+                const bool live = (j >= 0 && j < m1);  // planes outside the grid are zero
+                if (live) {
 #pragma unroll
-                    for (int c = 0; c < 3; ++c) {
-                        T aM = T(0), aA = T(0), aS = T(0);
+                    for (int pa = 0; pa < NPA; ++pa) {
+                        const int p = tid + pa * kThreads;
+                        if (p < NA) {
+                            const int i = p / E3, qc = p % E3;
 #pragma unroll
-                        for (int k = 0; k < R; ++k) {
-                            const T xv = xs[c * XSN + tid + k * m3];
-                            aM += ca[0][k] * xv;
-                            aA += ca[1][k] * xv;
-                            aS += ca[2][k] * xv;
+                            for (int c = 0; c < 3; ++c) {
+                                T aM = T(0), aA = T(0), aS = T(0);
+#pragma unroll
+                                for (int k = 0; k < R; ++k) {
+                                    const T xv = xs[c * NIN + (i + k) * E3 + qc];
+                                    aM += ca[(0 * R + k) * k3T2 + i] * xv;
+                                    aA += ca[(1 * R + k) * k3T2 + i] * xv;
+                                    aS += ca[(2 * R + k) * k3T2 + i] * xv;
+                                }
+                                st[(3 * c + 0) * NA + p] = aM;
+                                st[(3 * c + 1) * NA + p] = aA;
+                                st[(3 * c + 2) * NA + p] = aS;
+                            }
                         }
-                        st[(3 * c + 0) * kThreads + tid] = aM;
-                        st[(3 * c + 1) * kThreads + tid] = aA;
-                        st[(3 * c + 2) * kThreads + tid] = aS;
                     }
-                    __syncthreads();
+                }
+                __syncthreads();  // stage A done: xs free, st complete
+                if (t + 1 < TI) store_plane();
+                if (t + 2 < TI) load_plane(j + 2);
+                if (live) {
                     T W[3][3];
 #pragma unroll
                     for (int c = 0; c < 3; ++c)
@@ -185,14 +296,15 @@ __global__ __launch_bounds__(kThreads) void k_apply3d(OpDev<T> op, const T* __re
                     if (active) {
                         // raw products per input component c: M3(M2x), S3(M2x), A3(M2x), M3(S2x), M3(A2x), A3(A2x)
                         T mm[3], sm[3], am[3], ms[3], ma[3], aa[3];
+                        const int q0 = ty * E3 + tx;
 #pragma unroll
                         for (int c = 0; c < 3; ++c) {
                             mm[c] = sm[c] = am[c] = ms[c] = ma[c] = aa[c] = T(0);
 #pragma unroll
                             for (int k = 0; k < R; ++k) {
-                                const T vM = st[(3 * c + 0) * kThreads + tid + k];
-                                const T vA = st[(3 * c + 1) * kThreads + tid + k];
-                                const T vS = st[(3 * c + 2) * kThreads + tid + k];
+                                const T vM = st[(3 * c + 0) * NA + q0 + k];
+                                const T vA = st[(3 * c + 1) * NA + q0 + k];
+                                const T vS = st[(3 * c + 2) * NA + q0 + k];
                                 mm[c] += cb[0][k] * vM;
                                 sm[c] += cb[2][k] * vM;
                                 if (c != 1) am[c] += cb[1][k] * vM;
@@ -219,55 +331,39 @@ __global__ __launch_bounds__(kThreads) void k_apply3d(OpDev<T> op, const T* __re
                             const T cS = op.band[0][2][kk * m1 + i];
                             const T cM = op.band[0][0][kk * m1 + i];
                             const T cA = op.band[0][1][kk * m1 + i];
-                            const int slot = (uu + k + 1) % R;
+                            const int sl = (uu + k + 1) % R;
 #pragma unroll
                             for (int c = 0; c < 3; ++c)
 #pragma unroll
                                 for (int r = 0; r < R; ++r)
-                                    if (r == slot) acc[c][r] += cS * W[c][0] + cM * W[c][1] + cA * W[c][2];
+                                    if (r == sl) acc[c][r] += cS * W[c][0] + cM * W[c][1] + cA * W[c][2];
                         }
                     }
-                    __syncthreads();  // xs / st are overwritten by the next plane
                 }
                 const int io = j - HB;
                 if (io >= o0 && io < o1) {
-                    const int slot = (uu + 1) % R;
+                    const int sl = (uu + 1) % R;
 #pragma unroll
                     for (int c = 0; c < 3; ++c) {
                         T kx = T(0);
 #pragma unroll
                         for (int r = 0; r < R; ++r)
-                            if (r == slot) {
+                            if (r == sl) {
                                 kx = acc[c][r];
                                 acc[c][r] = T(0);
                             }
                         if (active) {
-                            const size_t idx = size_t(c) * G + size_t(io) * PL + f;
-                            if (MODE == kApplyY) {
-                                y[idx] = kx;
-                            } else if (MODE == kApplyRes) {
-                                y[idx] = b[idx] - kx;
-                            } else if (MODE == kApplyCheb) {
-                                const T r = b[idx] - kx;
-                                const T dg = diag_entry(op, c, io, i2, i3);
-                                const T uprev = (c1 != T(0)) ? u[idx] : T(0);  // u is not read on a first step
-                                const T un = c1 * uprev + c2 * r / dg;
-                                u[idx] = un;
-                                xout[idx] = x[idx] + un;
-                            } else {
-                                y[idx] = kx;
-                                dot += double(x[idx]) * double(kx);
-                            }
+                            const size_t idx = size_t(c) * G + size_t(io) * PL + size_t(i2) * m3 + i3;
+                            apply_epilogue<T, MODE>(op, c, idx, kx, io, i2, i3, x, y, b, u, xout, c1, c2, nv, 3 * G,
+                                                    dots);
                         }
                     }
                 }
+                __syncthreads();  // stage B done: st free; plane t+1 complete in xs
             }
         }
     }
-    if (MODE == kApplyYDot) {
-        const double tot = block_sum(dot);
-        if (threadIdx.x == 0) part[blockIdx.x] = tot;
-    }
+    apply_write_dots<MODE>(dots, nv, part);
 }
 
 // ------------------------------------------------------------------------------
@@ -287,7 +383,8 @@ constexpr int kT1 = 8, kT2 = 32;  // 2D output tile: kT1 * kT2 = kThreads points
 template <typename T, int HB, int MODE>
 __global__ __launch_bounds__(kThreads) void k_apply2d(OpDev<T> op, const T* __restrict__ x, T* __restrict__ y,
                                                       const T* __restrict__ b, T* __restrict__ u,
-                                                      T* __restrict__ xout, T c1, T c2, double* __restrict__ part) {
+                                                      T* __restrict__ xout, T c1, T c2, double* __restrict__ part,
+                                                      int nv) {
     constexpr int R = 2 * HB + 1;
     constexpr int E1 = kT1 + 2 * HB, E2 = kT2 + 2 * HB;  // input tile rows, columns
     constexpr int NIN = E1 * E2;                         // input tile size per component
@@ -339,7 +436,9 @@ __global__ __launch_bounds__(kThreads) void k_apply2d(OpDev<T> op, const T* __re
         for (int w = 0; w < 6; ++w) st[w * NA + p] = v[w];
     }
     __syncthreads();
-    double dot = 0.0;
+    double dots[apply_ndots<MODE>()];
+#pragma unroll
+    for (int q = 0; q < apply_ndots<MODE>(); ++q) dots[q] = 0.0;
     const int i = tid / kT2, j = tid % kT2;
     const int i1 = o1 + i, i2 = o2 + j;
     if (i1 < m1 && i2 < m2) {
@@ -361,38 +460,11 @@ __global__ __launch_bounds__(kThreads) void k_apply2d(OpDev<T> op, const T* __re
         const T al = op.alpha, be = op.beta, ab = op.alpha - op.beta;
         const T kx[2] = {be * mS1 + al * sM1 + ab * aA2, al * mS2 + be * sM2 + ab * aA1};
 #pragma unroll
-        for (int c = 0; c < 2; ++c) {
-            const size_t idx = size_t(c) * G + f;
-            if (MODE == kApplyY) {
-                y[idx] = kx[c];
-            } else if (MODE == kApplyRes) {
-                y[idx] = b[idx] - kx[c];
-            } else if (MODE == kApplyCheb) {
-                const T r = b[idx] - kx[c];
-                const T dg = diag_entry(op, c, i1, i2, 0);
-                const T uprev = (c1 != T(0)) ? u[idx] : T(0);  // u is not read on a first step
-                const T un = c1 * uprev + c2 * r / dg;
-                u[idx] = un;
-                xout[idx] = x[idx] + un;
-            } else {
-                y[idx] = kx[c];
-                dot += double(x[idx]) * double(kx[c]);
-            }
-        }
+        for (int c = 0; c < 2; ++c)
+            apply_epilogue<T, MODE>(op, c, size_t(c) * G + f, kx[c], i1, i2, 0, x, y, b, u, xout, c1, c2, nv,
+                                    size_t(2) * G, dots);
     }
-    if (MODE == kApplyYDot) {
-        const double tot = block_sum(dot);
-        if (threadIdx.x == 0) part[blockIdx.x] = tot;
-    }
-}
-
-constexpr int kX1Chunk = 16;
-
-template <typename T>
-size_t apply_lds_bytes(const OpDev<T>& op) {
-    const int hb = op.hb;
-    if (op.dim == 3) return sizeof(T) * (3 * size_t(kThreads + 2 * hb * op.m[2]) + 9 * size_t(kThreads));
-    return 0;  // 2D: static LDS tiles
+    apply_write_dots<MODE>(dots, nv, part);
 }
 
 // Raise a kernel's dynamic-LDS limit (default 64 KiB) to what a launch needs,
@@ -416,35 +488,30 @@ void allow_lds(const void* kern, size_t lds) {
 
 template <typename T, int HB, int MODE>
 void apply_dispatch(const OpDev<T>& op, const T* x, T* y, const T* b, T* u, T* xout, T c1, T c2, double* part,
-                    hipStream_t s) {
-    const size_t lds = apply_lds_bytes(op);
-    if (lds > 160 * 1024) throw std::runtime_error("grid too large for the operator kernel's LDS tile");
+                    int nv, hipStream_t s) {
     if (op.dim == 3) {
-        const int PL = op.m[1] * op.m[2];
-        const int tpb = kThreads - 2 * HB;
-        const int nchunk = (PL + tpb - 1) / tpb;
-        const int nx1 = (op.m[0] + kX1Chunk - 1) / kX1Chunk;
-        auto kern = k_apply3d<T, HB, MODE>;
-        allow_lds(reinterpret_cast<const void*>(kern), lds);
-        hipLaunchKernelGGL(kern, dim3(nchunk * nx1), dim3(kThreads), lds, s, op, x, y, b, u, xout, c1, c2, part,
-                           nchunk, kX1Chunk);
+        const Apply3dGeom g = apply3d_geom(op.m, HB);
+        hipLaunchKernelGGL((k_apply3d<T, HB, MODE>), dim3(g.nblocks), dim3(kThreads), 0, s, op, x, y, b, u, xout,
+                           c1, c2, part, nv, g);
     } else {
         static_assert(kT1 * kT2 == kThreads, "2D tile must match the block size");
         const int tiles = ((op.m[0] + kT1 - 1) / kT1) * ((op.m[1] + kT2 - 1) / kT2);
         hipLaunchKernelGGL((k_apply2d<T, HB, MODE>), dim3(tiles), dim3(kThreads), 0, s, op, x, y, b, u, xout, c1,
-                           c2, part);
+                           c2, part, nv);
     }
     check_launch("apply");
 }
 
 template <typename T, int HB>
 void apply_mode(const OpDev<T>& op, int mode, const T* x, T* y, const T* b, T* u, T* xout, T c1, T c2, double* part,
-                hipStream_t s) {
+                int nv, hipStream_t s) {
     switch (mode) {
-        case kApplyY: apply_dispatch<T, HB, kApplyY>(op, x, y, b, u, xout, c1, c2, part, s); break;
-        case kApplyRes: apply_dispatch<T, HB, kApplyRes>(op, x, y, b, u, xout, c1, c2, part, s); break;
-        case kApplyCheb: apply_dispatch<T, HB, kApplyCheb>(op, x, y, b, u, xout, c1, c2, part, s); break;
-        case kApplyYDot: apply_dispatch<T, HB, kApplyYDot>(op, x, y, b, u, xout, c1, c2, part, s); break;
+        case kApplyY: apply_dispatch<T, HB, kApplyY>(op, x, y, b, u, xout, c1, c2, part, nv, s); break;
+        case kApplyRes: apply_dispatch<T, HB, kApplyRes>(op, x, y, b, u, xout, c1, c2, part, nv, s); break;
+        case kApplyCheb: apply_dispatch<T, HB, kApplyCheb>(op, x, y, b, u, xout, c1, c2, part, nv, s); break;
+        case kApplyYDot: apply_dispatch<T, HB, kApplyYDot>(op, x, y, b, u, xout, c1, c2, part, nv, s); break;
+        case kApplyResDot: apply_dispatch<T, HB, kApplyResDot>(op, x, y, b, u, xout, c1, c2, part, nv, s); break;
+        case kApplyYMulti: apply_dispatch<T, HB, kApplyYMulti>(op, x, y, b, u, xout, c1, c2, part, nv, s); break;
         default: throw std::runtime_error("bad apply mode");
     }
 }
@@ -634,9 +701,9 @@ __host__ __device__ inline int padded_span(int span) { return (span + kRowGroup 
 //     store 0), keeping D^{-1} y in LDS;
 //  3. backward L^T z = D^{-1} y from the top of the padded span down to the
 //     chunk (zero padded rows keep the recurrence state at zero);
-//  4. the chunk's rows [r0, r1) are written out.
+//  4. the chunk's rows [r0, r1) are written out (ACC: added to out).
 // Out of place: in != out.
-template <typename T, int BW>
+template <typename T, int BW, bool ACC>
 __global__ __launch_bounds__(kLineThreads) void k_tsolve_line(const T* __restrict__ in, T* __restrict__ out,
                                                               LineGeom g, size_t lines_padded,
                                                               const T* __restrict__ L,
@@ -754,7 +821,13 @@ __global__ __launch_bounds__(kLineThreads) void k_tsolve_line(const T* __restric
     }
     // 4. output rows [r0, r1)
     T* dst = out + base;
-    for (int r = r0; r < r1; ++r) dst[size_t(r) * stride] = sp[(r - rs) * kLineThreads + lane];
+    for (int r = r0; r < r1; ++r) {
+        const T val = sp[(r - rs) * kLineThreads + lane];
+        if (ACC)
+            dst[size_t(r) * stride] += val;
+        else
+            dst[size_t(r) * stride] = val;
+    }
 }
 
 // ------------------------------------------------------------------------------
@@ -904,58 +977,14 @@ __global__ __launch_bounds__(kThreads) void k_fcg_update(const double* __restric
 }
 
 // ---- GMRES helpers -----------------------------------------------------------------
-constexpr int kMaxBasis = 8;
 
-template <typename T>
-__global__ __launch_bounds__(kThreads) void k_multidot(const T* __restrict__ V, int k, const T* __restrict__ w,
-                                                       size_t n, double* __restrict__ part, int nb) {
-    double s[kMaxBasis];
-#pragma unroll
-    for (int j = 0; j < kMaxBasis; ++j) s[j] = 0.0;
-    for (size_t i = size_t(blockIdx.x) * kThreads + threadIdx.x; i < n; i += size_t(gridDim.x) * kThreads) {
-        const double wv = double(w[i]);
-#pragma unroll
-        for (int j = 0; j < kMaxBasis; ++j)
-            if (j < k) s[j] += double(V[size_t(j) * n + i]) * wv;
-    }
-    for (int j = 0; j < k; ++j) {
-        const double t = block_sum(s[j]);
-        if (threadIdx.x == 0) part[size_t(j) * nb + blockIdx.x] = t;
-    }
-}
-
-// H[j] = sum of the nb partials of dot j, j < k; one block, partials read in
-// parallel and combined in a fixed order.
-__global__ __launch_bounds__(kThreads) void k_multifinal(const double* __restrict__ part, int k, int nb,
-                                                         double* __restrict__ H, int take_sqrt) {
-    for (int j = 0; j < k; ++j) {
-        const double s = sum_partials(part + size_t(j) * nb, nb);
-        if (threadIdx.x == 0) H[j] = take_sqrt ? sqrt(s) : s;
-    }
-}
-
-template <typename T>
-__global__ __launch_bounds__(kThreads) void k_multiaxpy(const T* __restrict__ V, int k, const double* __restrict__ h,
-                                                        T* __restrict__ w, size_t n) {
-    for (size_t i = size_t(blockIdx.x) * kThreads + threadIdx.x; i < n; i += size_t(gridDim.x) * kThreads) {
-        T acc = w[i];
-        for (int j = 0; j < k; ++j) acc -= T(h[j]) * V[size_t(j) * n + i];
-        w[i] = acc;
-    }
-}
-
-template <typename T>
-__global__ __launch_bounds__(kThreads) void k_scale_by(const double* __restrict__ h, const T* __restrict__ w,
-                                                       T* __restrict__ v, size_t n) {
-    const double hv = h[0];
-    const T sc = (hv != 0.0) ? T(1.0 / hv) : T(0);
-    for (size_t i = size_t(blockIdx.x) * kThreads + threadIdx.x; i < n; i += size_t(gridDim.x) * kThreads)
-        v[i] = w[i] * sc;
-}
-
-__global__ void k_hessenberg_ls(const double* __restrict__ H, int ld, int k, const double* __restrict__ beta0sq,
-                                double* __restrict__ y) {
+__global__ __launch_bounds__(kThreads) void k_hessenberg_ls(double* __restrict__ H, int ld, int k,
+                                                            const double* __restrict__ beta0sq,
+                                                            double* __restrict__ y,
+                                                            const double* __restrict__ plast, int nlast) {
+    const double last = sqrt(sum_partials(plast, nlast));  // H(k, k-1)
     if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    H[size_t(k - 1) * ld + k] = last;
     double R[kMaxBasis + 1][kMaxBasis];
     double g[kMaxBasis + 1];
     for (int i = 0; i <= k; ++i) {
@@ -981,6 +1010,51 @@ __global__ void k_hessenberg_ls(const double* __restrict__ H, int ld, int k, con
         for (int col = i + 1; col < k; ++col) s -= R[i][col] * y[col];
         y[i] = (fabs(R[i][i]) > 0.0) ? s / R[i][i] : 0.0;
     }
+}
+
+// Classical Gram-Schmidt step in one pass: every block sums the partials of
+// the k dots itself (same order in every block), then w -= sum_i h_i V_i and
+// the block's partial sum of w.w.
+template <typename T>
+__global__ __launch_bounds__(kThreads) void k_gs_update(const double* __restrict__ pdot, int k, int nbp,
+                                                        double* __restrict__ Hcol, const T* __restrict__ V,
+                                                        T* __restrict__ w, size_t n, double* __restrict__ pnorm) {
+    __shared__ double hs[kMaxBasis];
+    for (int i = 0; i < k; ++i) {
+        const double t = sum_partials(pdot + size_t(i) * nbp, nbp);
+        if (threadIdx.x == 0) hs[i] = t;
+    }
+    __syncthreads();
+    if (blockIdx.x == 0 && threadIdx.x < k) Hcol[threadIdx.x] = hs[threadIdx.x];
+    T h[kMaxBasis];
+#pragma unroll
+    for (int i = 0; i < kMaxBasis; ++i) h[i] = (i < k) ? T(hs[i]) : T(0);
+    double acc = 0.0;
+    for (size_t e = size_t(blockIdx.x) * kThreads + threadIdx.x; e < n; e += size_t(gridDim.x) * kThreads) {
+        T a = w[e];
+#pragma unroll
+        for (int i = 0; i < kMaxBasis; ++i)
+            if (i < k) a -= h[i] * V[size_t(i) * n + e];
+        w[e] = a;
+        acc += double(a) * double(a);
+    }
+    const double tot = block_sum(acc);
+    if (threadIdx.x == 0) pnorm[blockIdx.x] = tot;
+}
+
+// ss = sum of the partials (every block); block 0 stores ss or sqrt(ss);
+// v = w / sqrt(ss) when v is given.
+template <typename T>
+__global__ __launch_bounds__(kThreads) void k_normscale(const double* __restrict__ pnorm, int np,
+                                                        double* __restrict__ out, int square,
+                                                        const T* __restrict__ w, T* __restrict__ v, size_t n) {
+    const double ss = sum_partials(pnorm, np);
+    const double nrm = sqrt(ss);
+    if (blockIdx.x == 0 && threadIdx.x == 0) *out = square ? ss : nrm;
+    if (v == nullptr) return;
+    const T sc = (nrm != 0.0) ? T(1.0 / nrm) : T(0);
+    for (size_t e = size_t(blockIdx.x) * kThreads + threadIdx.x; e < n; e += size_t(gridDim.x) * kThreads)
+        v[e] = w[e] * sc;
 }
 
 template <typename T>
@@ -1009,24 +1083,21 @@ int reduce_blocks(size_t n) {
 
 template <typename T>
 int apply_blocks(const OpDev<T>& op) {
-    const int tpb = kThreads - 2 * op.hb;
-    if (op.dim == 3) {
-        const int PL = op.m[1] * op.m[2];
-        return ((PL + tpb - 1) / tpb) * ((op.m[0] + kX1Chunk - 1) / kX1Chunk);
-    }
+    if (op.dim == 3) return apply3d_geom(op.m, op.hb).nblocks;
     return ((op.m[0] + kT1 - 1) / kT1) * ((op.m[1] + kT2 - 1) / kT2);
 }
 
 template <typename T>
 void launch_apply(const OpDev<T>& op, int mode, const T* x, T* y, const T* b, T* u, T* xout, T c1, T c2, double* part,
-                  hipStream_t s) {
+                  hipStream_t s, int nv) {
+    if (mode == kApplyYMulti && (nv < 1 || nv > kMaxBasis)) throw std::runtime_error("bad number of dot vectors");
     switch (op.hb) {
-        case 1: apply_mode<T, 1>(op, mode, x, y, b, u, xout, c1, c2, part, s); break;
-        case 2: apply_mode<T, 2>(op, mode, x, y, b, u, xout, c1, c2, part, s); break;
-        case 3: apply_mode<T, 3>(op, mode, x, y, b, u, xout, c1, c2, part, s); break;
-        case 4: apply_mode<T, 4>(op, mode, x, y, b, u, xout, c1, c2, part, s); break;
-        case 5: apply_mode<T, 5>(op, mode, x, y, b, u, xout, c1, c2, part, s); break;
-        case 6: apply_mode<T, 6>(op, mode, x, y, b, u, xout, c1, c2, part, s); break;
+        case 1: apply_mode<T, 1>(op, mode, x, y, b, u, xout, c1, c2, part, nv, s); break;
+        case 2: apply_mode<T, 2>(op, mode, x, y, b, u, xout, c1, c2, part, nv, s); break;
+        case 3: apply_mode<T, 3>(op, mode, x, y, b, u, xout, c1, c2, part, nv, s); break;
+        case 4: apply_mode<T, 4>(op, mode, x, y, b, u, xout, c1, c2, part, nv, s); break;
+        case 5: apply_mode<T, 5>(op, mode, x, y, b, u, xout, c1, c2, part, nv, s); break;
+        case 6: apply_mode<T, 6>(op, mode, x, y, b, u, xout, c1, c2, part, nv, s); break;
         default: throw std::runtime_error("degree out of range (1..6)");
     }
 }
@@ -1089,28 +1160,34 @@ void launch_prolong_add(const XferDev<T>& X, int ncomp, const T* ec, T* xf, hipS
 }
 
 template <typename T, int BW>
-void tsolve_axis(const T* v, T* z, const LineGeom& g, const TFacDev<T>& F, size_t lines_padded, size_t lds,
+void tsolve_axis(const T* v, T* z, bool acc, const LineGeom& g, const TFacDev<T>& F, size_t lines_padded, size_t lds,
                  hipStream_t s) {
     const size_t items = lines_padded * g.nchunk * size_t(g.ncomp);
     const dim3 grid(items / kLineThreads);
-    auto kern = k_tsolve_line<T, BW>;
+    auto kern = acc ? k_tsolve_line<T, BW, true> : k_tsolve_line<T, BW, false>;
     allow_lds(reinterpret_cast<const void*>(kern), lds);
     hipLaunchKernelGGL(kern, grid, dim3(kLineThreads), lds, s, v, z, g, lines_padded, F.l, F.dinv, F.warm);
 }
 
 template <typename T>
-void launch_tsolve(int dim, const int* m, const TFacDev<T>* fac, const T* v, T* tmp, T* z, hipStream_t s) {
+void launch_tsolve(int dim, const int* m, const TFacDev<T>* fac, const T* v, T* tmp, T* z, hipStream_t s, T* acc) {
     if (v == z || v == tmp || tmp == z) throw std::runtime_error("tsolve needs three distinct buffers");
+    if (acc && (acc == v || acc == tmp || acc == z)) throw std::runtime_error("tsolve accumulator aliases a buffer");
     const int m0 = m[0], m1 = m[1], m2 = (dim == 3) ? m[2] : 1;
     const size_t G = size_t(m0) * m1 * m2;
     if (fac[0].bw == 0) {  // p = 1: T is the identity
-        launch_copy<T>(v, z, size_t(dim) * G, s);
+        if (acc)
+            launch_axpby<T>(T(1), v, T(1), acc, size_t(dim) * G, s);
+        else
+            launch_copy<T>(v, z, size_t(dim) * G, s);
         return;
     }
     const T* src = v;
     for (int a = 0; a < dim; ++a) {
         // alternate destinations so that the last pass lands in z
         T* dst = ((dim - 1 - a) % 2 == 0) ? z : tmp;
+        const bool last_acc = acc && (a == dim - 1);
+        if (last_acc) dst = acc;
         const TFacDev<T>& F = fac[a];
         LineGeom g;
         g.G = G;
@@ -1135,11 +1212,11 @@ void launch_tsolve(int dim, const int* m, const TFacDev<T>* fac, const T* v, T* 
         g.ncomp = dim;
         const size_t lp = (g.lines_per_comp + kLineThreads - 1) / kLineThreads * kLineThreads;
         switch (F.bw) {
-            case 1: tsolve_axis<T, 1>(src, dst, g, F, lp, lds, s); break;
-            case 2: tsolve_axis<T, 2>(src, dst, g, F, lp, lds, s); break;
-            case 3: tsolve_axis<T, 3>(src, dst, g, F, lp, lds, s); break;
-            case 4: tsolve_axis<T, 4>(src, dst, g, F, lp, lds, s); break;
-            case 5: tsolve_axis<T, 5>(src, dst, g, F, lp, lds, s); break;
+            case 1: tsolve_axis<T, 1>(src, dst, last_acc, g, F, lp, lds, s); break;
+            case 2: tsolve_axis<T, 2>(src, dst, last_acc, g, F, lp, lds, s); break;
+            case 3: tsolve_axis<T, 3>(src, dst, last_acc, g, F, lp, lds, s); break;
+            case 4: tsolve_axis<T, 4>(src, dst, last_acc, g, F, lp, lds, s); break;
+            case 5: tsolve_axis<T, 5>(src, dst, last_acc, g, F, lp, lds, s); break;
             default: throw std::runtime_error("degree out of range (1..6)");
         }
         check_launch("tsolve");
@@ -1234,39 +1311,33 @@ void launch_fcg_update(const double* pdr, int npdr, const double* pdq, int npdq,
     check_launch("fcg_update");
 }
 
-template <typename T>
-void launch_multidot(const T* V, int k, const T* w, size_t n, double* part, int nb, hipStream_t s) {
-    if (k > kMaxBasis) throw std::runtime_error("too many Krylov vectors");
-    hipLaunchKernelGGL(k_multidot<T>, dim3(nb), dim3(kThreads), 0, s, V, k, w, n, part, nb);
-    check_launch("multidot");
-}
 
-void launch_multifinal(const double* part, int k, int nb, double* H, hipStream_t s) {
-    hipLaunchKernelGGL(k_multifinal, dim3(1), dim3(kThreads), 0, s, part, k, nb, H, 0);
-    check_launch("multifinal");
-}
 
-void launch_normfinal(const double* part, int nb, double* out, hipStream_t s) {
-    hipLaunchKernelGGL(k_multifinal, dim3(1), dim3(kThreads), 0, s, part, 1, nb, out, 1);
-    check_launch("normfinal");
-}
 
-template <typename T>
-void launch_multiaxpy(const T* V, int k, const double* h, T* w, size_t n, hipStream_t s) {
-    hipLaunchKernelGGL(k_multiaxpy<T>, dim3(grid_for(n)), dim3(kThreads), 0, s, V, k, h, w, n);
-    check_launch("multiaxpy");
-}
 
-template <typename T>
-void launch_scale_by(const double* h, const T* w, T* v, size_t n, hipStream_t s) {
-    hipLaunchKernelGGL(k_scale_by<T>, dim3(grid_for(n)), dim3(kThreads), 0, s, h, w, v, n);
-    check_launch("scale_by");
-}
 
-void launch_hessenberg_ls(const double* H, int ld, int k, const double* beta0sq, double* y, hipStream_t s) {
-    if (k > kMaxBasis) throw std::runtime_error("too many Krylov vectors");
-    hipLaunchKernelGGL(k_hessenberg_ls, dim3(1), dim3(64), 0, s, H, ld, k, beta0sq, y);
+void launch_hessenberg_ls(double* H, int ld, int k, const double* beta0sq, double* y, const double* plast,
+                          int nlast, hipStream_t s) {
+    if (k < 1 || k > kMaxBasis) throw std::runtime_error("bad number of Krylov vectors");
+    hipLaunchKernelGGL(k_hessenberg_ls, dim3(1), dim3(kThreads), 0, s, H, ld, k, beta0sq, y, plast, nlast);
     check_launch("hessenberg_ls");
+}
+
+template <typename T>
+void launch_gs_update(const double* pdot, int k, int nbp, double* Hcol, const T* V, T* w, size_t n, double* pnorm,
+                      hipStream_t s) {
+    if (k < 1 || k > kMaxBasis) throw std::runtime_error("bad number of Krylov vectors");
+    hipLaunchKernelGGL(k_gs_update<T>, dim3(reduce_blocks(n)), dim3(kThreads), 0, s, pdot, k, nbp, Hcol, V, w, n,
+                       pnorm);
+    check_launch("gs_update");
+}
+
+template <typename T>
+void launch_normscale(const double* pnorm, int np, double* out, bool square, const T* w, T* v, size_t n,
+                      hipStream_t s) {
+    const int grid = (v == nullptr) ? 1 : grid_for(n);
+    hipLaunchKernelGGL(k_normscale<T>, dim3(grid), dim3(kThreads), 0, s, pnorm, np, out, square ? 1 : 0, w, v, n);
+    check_launch("normscale");
 }
 
 template <typename T>
@@ -1278,10 +1349,11 @@ void launch_combine(const T* V, int k, const double* y, T* w, size_t n, hipStrea
 // ---- explicit instantiations ----
 #define CD_INST(T)                                                                                                   \
     template int apply_blocks<T>(const OpDev<T>&);                                                                   \
-    template void launch_apply<T>(const OpDev<T>&, int, const T*, T*, const T*, T*, T*, T, T, double*, hipStream_t); \
+    template void launch_apply<T>(const OpDev<T>&, int, const T*, T*, const T*, T*, T*, T, T, double*, hipStream_t,  \
+                                  int);                                                                              \
     template void launch_restrict<T>(const XferDev<T>&, int, const T*, T*, hipStream_t);                             \
     template void launch_prolong_add<T>(const XferDev<T>&, int, const T*, T*, hipStream_t);                          \
-    template void launch_tsolve<T>(int, const int*, const TFacDev<T>*, const T*, T*, T*, hipStream_t);                            \
+    template void launch_tsolve<T>(int, const int*, const TFacDev<T>*, const T*, T*, T*, hipStream_t, T*);                            \
     template void launch_fill<T>(T*, T, size_t, hipStream_t);                                                        \
     template void launch_copy<T>(const T*, T*, size_t, hipStream_t);                                                 \
     template void launch_axpby<T>(T, const T*, T, T*, size_t, hipStream_t);                                          \
@@ -1290,10 +1362,9 @@ void launch_combine(const T* V, int k, const double* y, T* w, size_t n, hipStrea
     template void launch_diag_dot<T>(const OpDev<T>&, const T*, double*, hipStream_t);                               \
     template void launch_cheb_first<T>(const OpDev<T>&, const T*, T*, T*, T, hipStream_t);                           \
     template void launch_coarse_gemv<T>(const double*, int, int, const T*, T*, hipStream_t);                              \
-    template void launch_multidot<T>(const T*, int, const T*, size_t, double*, int, hipStream_t);                    \
-    template void launch_multiaxpy<T>(const T*, int, const double*, T*, size_t, hipStream_t);                        \
-    template void launch_scale_by<T>(const double*, const T*, T*, size_t, hipStream_t);                              \
-    template void launch_combine<T>(const T*, int, const double*, T*, size_t, hipStream_t);
+    template void launch_combine<T>(const T*, int, const double*, T*, size_t, hipStream_t);                          \
+    template void launch_gs_update<T>(const double*, int, int, double*, const T*, T*, size_t, double*, hipStream_t); \
+    template void launch_normscale<T>(const double*, int, double*, bool, const T*, T*, size_t, hipStream_t);
 
 CD_INST(double)
 CD_INST(float)

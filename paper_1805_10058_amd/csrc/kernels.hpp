@@ -49,26 +49,33 @@ enum ApplyMode : int {
     kApplyRes = 1,   // y = b - A x
     kApplyCheb = 2,  // u = c1 u + c2 D^{-1}(b - A x); xout = x + u
     kApplyYDot = 3,  // y = A x; part[block] = sum x.y (FP64)
+    kApplyResDot = 4,  // y = b - A x; part[block] = sum y.y (FP64)
+    kApplyYMulti = 5,  // y = A x; part[i*nblocks + block] = sum V_i.y, i < nv, V_i = b + i*n (FP64)
 };
+
+constexpr int kMaxBasis = 8;  // most Krylov vectors of the GMRES post-smoother
 
 // Partial-sum count used by every reduction of a vector of length n.
 int reduce_blocks(size_t n);
-// Number of partial sums written by the apply kernel in kApplyYDot mode.
+// Number of blocks of the apply kernel: partial sums per dot in the dot modes.
 template <typename T>
 int apply_blocks(const OpDev<T>& op);
 
 template <typename T>
 void launch_apply(const OpDev<T>& op, int mode, const T* x, T* y, const T* b, T* u, T* xout, T c1, T c2,
-                  double* part, hipStream_t s);
+                  double* part, hipStream_t s, int nv = 0);
 
 template <typename T>
 void launch_restrict(const XferDev<T>& X, int ncomp, const T* rf, T* rc, hipStream_t s);
 template <typename T>
 void launch_prolong_add(const XferDev<T>& X, int ncomp, const T* ec, T* xf, hipStream_t s);
 
-// z = T^{-1} v, T = I_d (x) T_1 (x) ... (x) T_d; v may equal z; tmp: n scratch.
+// z = T^{-1} v, T = I_d (x) T_1 (x) ... (x) T_d; v, tmp, z distinct, tmp: n
+// scratch.  With acc != nullptr the result is added to acc instead
+// (acc += T^{-1} v) and z is used as scratch.
 template <typename T>
-void launch_tsolve(int dim, const int* m, const TFacDev<T>* fac, const T* v, T* tmp, T* z, hipStream_t s);
+void launch_tsolve(int dim, const int* m, const TFacDev<T>* fac, const T* v, T* tmp, T* z, hipStream_t s,
+                   T* acc = nullptr);
 
 // ---- vector kernels ---------------------------------------------------------
 template <typename TA, typename TB>
@@ -112,20 +119,23 @@ void launch_fcg_update(const double* pdr, int npdr, const double* pdq, int npdq,
                        hipStream_t s);
 
 // ---- GMRES helpers (vectors of type T, scalars FP64) ----------------------------
-// part[(j)*nb + block] = V_j . w for j < k  (V: k vectors of length n, stride n)
+// Classical Gram-Schmidt step: h_i = sum of the nbp partials pdot[i*nbp ..]
+// (i < k; stored in Hcol by block 0), w -= sum_i h_i V_i, pnorm[block] =
+// partial sums of w.w (reduce_blocks(n) of them).
 template <typename T>
-void launch_multidot(const T* V, int k, const T* w, size_t n, double* part, int nb, hipStream_t s);
-// H[j] = sum_b part[j*nb + b], j < k (one small kernel)
-void launch_multifinal(const double* part, int k, int nb, double* H, hipStream_t s);
-// w -= sum_j h[j] V_j
+void launch_gs_update(const double* pdot, int k, int nbp, double* Hcol, const T* V, T* w, size_t n, double* pnorm,
+                      hipStream_t s);
+// ss = sum of the np partials; *out = square ? ss : sqrt(ss) (block 0);
+// v = w / sqrt(ss) (zero if ss == 0) unless v == nullptr.
 template <typename T>
-void launch_multiaxpy(const T* V, int k, const double* h, T* w, size_t n, hipStream_t s);
-// v = w / h (h device scalar, zero-guarded)
-template <typename T>
-void launch_scale_by(const double* h, const T* w, T* v, size_t n, hipStream_t s);
+void launch_normscale(const double* pnorm, int np, double* out, bool square, const T* w, T* v, size_t n,
+                      hipStream_t s);
 // Least squares min || beta0 e1 - H y || for the (k+1) x k Hessenberg H
-// (column-major, leading dimension ld) by Givens rotations; y[0..k)
-void launch_hessenberg_ls(const double* H, int ld, int k, const double* beta0, double* y, hipStream_t s);
+// (column-major, leading dimension ld) by Givens rotations; y[0..k).  The
+// subdiagonal entry H(k, k-1) is sqrt of the sum of the nlast partials plast
+// (stored into H as well).
+void launch_hessenberg_ls(double* H, int ld, int k, const double* beta0sq, double* y, const double* plast,
+                          int nlast, hipStream_t s);
 // w = sum_j y[j] V_j
 template <typename T>
 void launch_combine(const T* V, int k, const double* y, T* w, size_t n, hipStream_t s);

@@ -25,10 +25,6 @@
 #include "kernels.hpp"
 #include "setup.hpp"
 
-namespace cd {
-void launch_normfinal(const double* part, int nb, double* out, hipStream_t s);
-}
-
 namespace {
 
 thread_local std::string g_last_error;
@@ -118,9 +114,11 @@ struct VWork {
     T* tmp = nullptr;     // scratch of the T-solve
     double* H = nullptr;  // (s+1) x s column-major
     double* y = nullptr;
-    double* part = nullptr;  // multidot partials
-    double* scal = nullptr;  // [0] beta0^2
-    int nb = 0;
+    double* pdot = nullptr;   // partial dot products of the apply kernel: ks x nba
+    double* pnorm = nullptr;  // partial sums of squares: max(nba, nb)
+    double* scal = nullptr;   // [0] beta0^2
+    int nb = 0;               // reduce_blocks(N)
+    int nba = 0;              // blocks of the level-0 apply kernel
 };
 
 }  // namespace
@@ -352,6 +350,13 @@ cd::TFacDev<T> make_tfac(cd_solver* s, const cd::TFactor& F, hipStream_t st) {
 }
 
 template <typename T>
+const std::vector<LevelDev<T>>& devlevels(cd_solver* s);
+template <>
+const std::vector<LevelDev<double>>& devlevels<double>(cd_solver* s) { return s->ld64; }
+template <>
+const std::vector<LevelDev<float>>& devlevels<float>(cd_solver* s) { return s->ld32; }
+
+template <typename T>
 std::unique_ptr<VWork<T>> make_work(cd_solver* s, DevArena& ar) {
     auto w = std::make_unique<VWork<T>>();
     const int L = int(s->lv.size());
@@ -376,17 +381,13 @@ std::unique_ptr<VWork<T>> make_work(cd_solver* s, DevArena& ar) {
     w->H = ar.alloc<double>(size_t(ks + 1) * ks);
     w->y = ar.alloc<double>(ks + 1);
     w->nb = cd::reduce_blocks(s->N);
-    w->part = ar.alloc<double>(size_t(w->nb) * (ks + 2));
+    w->nba = cd::apply_blocks<T>(devlevels<T>(s)[0].op);
+    w->pdot = ar.alloc<double>(size_t(w->nba) * ks);
+    w->pnorm = ar.alloc<double>(size_t(std::max(w->nba, w->nb)));
     w->scal = ar.alloc<double>(4);
     return w;
 }
 
-template <typename T>
-const std::vector<LevelDev<T>>& devlevels(cd_solver* s);
-template <>
-const std::vector<LevelDev<double>>& devlevels<double>(cd_solver* s) { return s->ld64; }
-template <>
-const std::vector<LevelDev<float>>& devlevels<float>(cd_solver* s) { return s->ld32; }
 template <typename T>
 const cd::TFacDev<T>* tfacs(cd_solver* s);
 template <>
@@ -426,10 +427,10 @@ void record_timing_event(cd_solver* s, hipEvent_t ev) {
 // ---- operator apply with optional live timing ---------------------------------------
 template <typename T>
 void apply_op(cd_solver* s, int level, int mode, const T* x, T* y, const T* b, T* u, T* xout, T c1, T c2,
-              double* part) {
+              double* part, int nv = 0) {
     const cd::OpDev<T>& op = devlevels<T>(s)[level].op;
     if (!s->prof || !s->prof_sample) {
-        cd::launch_apply<T>(op, mode, x, y, b, u, xout, c1, c2, part, s->stream);
+        cd::launch_apply<T>(op, mode, x, y, b, u, xout, c1, c2, part, s->stream, nv);
         return;
     }
     std::pair<hipEvent_t, hipEvent_t> ev;
@@ -440,10 +441,13 @@ void apply_op(cd_solver* s, int level, int mode, const T* x, T* y, const T* b, T
         ev = s->prof_pool.back();
         s->prof_pool.pop_back();
     }
-    const double nvec = (mode == kApplyRes) ? 3.0 : (mode == kApplyCheb) ? 5.0 : 2.0;
+    const double nvec = (mode == kApplyRes || mode == cd::kApplyResDot) ? 3.0
+                        : (mode == kApplyCheb)                         ? 5.0
+                        : (mode == cd::kApplyYMulti)                   ? 2.0 + nv
+                                                                       : 2.0;
     const int cls = 2 * level + (sizeof(T) == 4 ? 1 : 0);
     record_timing_event(s, ev.first);
-    cd::launch_apply<T>(op, mode, x, y, b, u, xout, c1, c2, part, s->stream);
+    cd::launch_apply<T>(op, mode, x, y, b, u, xout, c1, c2, part, s->stream, nv);
     record_timing_event(s, ev.second);
     const cd_solver::ProfRec rec{ev.first, ev.second, cls, nvec * double(s->lv[level].N) * sizeof(T)};
     if (s->capturing)
@@ -502,29 +506,29 @@ T* chebyshev(cd_solver* s, int l, const T* b, T* x, T* other, T* u, bool from_ze
 // (Sec. 6.1 post-smoother), classical Gram-Schmidt; x += T^{-1} V y.
 template <typename T>
 void gmres_post(cd_solver* s, VWork<T>& W, const T* b, T* x) {
-    const cd::OpDev<T>& op = devlevels<T>(s)[0].op;
     const size_t N = s->N;
-    const int ks = s->ksteps, ld = ks + 1, nb = W.nb;
+    const int ks = s->ksteps, ld = ks + 1, nb = W.nb, nba = W.nba;
     hipStream_t st = s->stream;
     T* V = W.V;
-    apply_op<T>(s, 0, kApplyRes, x, W.w, b, nullptr, nullptr, T(0), T(0), nullptr);
-    cd::launch_dot_partial<T, T>(W.w, W.w, N, W.part, st);
-    cd::launch_finalize(W.part, nb, W.scal, st);
-    cd::launch_normalize<T>(W.part, nb, W.w, V, N, st);
+    const int d = s->d;
+    const int* m0 = s->lv[0].m;
+    // r = b - A x and its norm: V_0 = r / ||r||, beta0^2 kept for the least squares
+    apply_op<T>(s, 0, cd::kApplyResDot, x, W.w, b, nullptr, nullptr, T(0), T(0), W.pnorm);
+    cd::launch_normscale<T>(W.pnorm, nba, W.scal, true, W.w, V, N, st);
     for (int j = 0; j < ks; ++j) {
-        cd::launch_tsolve<T>(s->d, s->lv[0].m, tfacs<T>(s), V + size_t(j) * N, W.tmp, W.z, st);
-        apply_op<T>(s, 0, kApplyY, W.z, W.w, nullptr, nullptr, nullptr, T(0), T(0), nullptr);
-        cd::launch_multidot<T>(V, j + 1, W.w, N, W.part, nb, st);
-        cd::launch_multifinal(W.part, j + 1, nb, W.H + size_t(j) * ld, st);
-        cd::launch_multiaxpy<T>(V, j + 1, W.H + size_t(j) * ld, W.w, N, st);
-        cd::launch_dot_partial<T, T>(W.w, W.w, N, W.part, st);
-        cd::launch_normfinal(W.part, nb, W.H + size_t(j) * ld + (j + 1), st);
-        cd::launch_scale_by<T>(W.H + size_t(j) * ld + (j + 1), W.w, V + size_t(j + 1) * N, N, st);
+        double* Hcol = W.H + size_t(j) * ld;
+        cd::launch_tsolve<T>(d, m0, tfacs<T>(s), V + size_t(j) * N, W.tmp, W.z, st);
+        // w = A T^{-1} V_j together with the dots V_i . w, i <= j
+        apply_op<T>(s, 0, cd::kApplyYMulti, W.z, W.w, V, nullptr, nullptr, T(0), T(0), W.pdot, j + 1);
+        // H(0..j, j) = those dots; w -= sum_i H(i, j) V_i; partial sums of w.w
+        cd::launch_gs_update<T>(W.pdot, j + 1, nba, Hcol, V, W.w, N, W.pnorm, st);
+        // H(j+1, j) = ||w||, V_{j+1} = w / ||w|| (the last norm is taken by the least squares)
+        if (j + 1 < ks) cd::launch_normscale<T>(W.pnorm, nb, Hcol + (j + 1), false, W.w, V + size_t(j + 1) * N, N, st);
     }
-    cd::launch_hessenberg_ls(W.H, ld, ks, W.scal, W.y, st);
+    cd::launch_hessenberg_ls(W.H, ld, ks, W.scal, W.y, W.pnorm, nb, st);
     cd::launch_combine<T>(V, ks, W.y, W.w, N, st);
-    cd::launch_tsolve<T>(s->d, s->lv[0].m, tfacs<T>(s), W.w, W.tmp, W.z, st);
-    cd::launch_axpby<T>(T(1), W.z, T(1), x, N, st);
+    // x += T^{-1} (V y)
+    cd::launch_tsolve<T>(d, m0, tfacs<T>(s), W.w, W.tmp, W.z, st, x);
 }
 
 // One V-cycle on level l for A_l x = W.lv[l].b; result in W.lv[l].xcur.
