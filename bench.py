@@ -140,17 +140,33 @@ def main():
     T = t1 - t0
     nsolves = args.steps * len(betas)
 
-    # live kernel timing (HIP events on the solver stream) of the dominant kernel:
-    # the level-0 operator apply of the FP32 V-cycle
+    # live kernel timing (stamps written by the kernels themselves, sampled
+    # outer iterations of the timed region) of the FP32 V-cycle operator apply
+    # (k_apply2d<float, 3, *> on every level), the kernel that takes the most
+    # GPU time in the timed solves, and of the FP32 T-solve passes
+    nlev = {beta: mixed[beta].num_levels() for beta in betas}
     tot_ms = tot_b = 0.0
     launches = 0
-    for s in mixed.values():
-        stt = s.profile_read(0, True)
-        tot_ms += stt.total_ms
-        tot_b += stt.bytes
-        launches += stt.launches
+    per_level = {}
+    ts_ms = ts_b = 0.0
+    ts_n = 0
+    for beta, s in mixed.items():
+        for lvl in range(nlev[beta]):
+            stt = s.profile_read(lvl, True)
+            tot_ms += stt.total_ms
+            tot_b += stt.bytes
+            launches += stt.launches
+            pl = per_level.setdefault(lvl, [0, 0.0, 0.0])
+            pl[0] += stt.launches
+            pl[1] += stt.total_ms
+            pl[2] += stt.bytes
+        tst = s.profile_read_tsolve(True)
+        ts_ms += tst.total_ms
+        ts_b += tst.bytes
+        ts_n += tst.launches
         s.profile_enable(False)
     ach = (tot_b / (tot_ms * 1e-3)) / 1e9 if tot_ms > 0 else 0.0
+    ts_gbs = (ts_b / (ts_ms * 1e-3)) / 1e9 if ts_ms > 0 else 0.0
 
     # plain FP64 single-solve path on the same inputs (comparison, not the headline)
     lat64, its64, tres64 = [], {}, []
@@ -186,8 +202,14 @@ def main():
                       "max_true_rel_residual": max(tres64)},
         "roofline": {"bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": ach / HBM_PEAK_GBS, "traffic": None,
-                     "kernel": "level-0 FP32 operator apply (k_apply2d<float,3,*>) inside the timed solves",
-                     "launches": launches, "avg_us": 1e3 * tot_ms / max(launches, 1)},
+                     "kernel": "FP32 V-cycle operator apply k_apply2d<float,3,*>, all levels, inside the timed solves "
+                               f"(every {PROF_PERIOD}th outer iteration timed)",
+                     "launches": launches, "avg_us": 1e3 * tot_ms / max(launches, 1),
+                     "per_level": {str(l): {"launches": v[0], "avg_us": 1e3 * v[1] / max(v[0], 1),
+                                            "GB_s": (v[2] / (v[1] * 1e-3)) / 1e9 if v[1] > 0 else 0.0}
+                                   for l, v in sorted(per_level.items())}},
+        "tsolve": {"kernel": "FP32 T-solve axis passes k_tsolve_line<float,2,*>", "launches": ts_n,
+                   "avg_us": 1e3 * ts_ms / max(ts_n, 1), "GB_s": ts_gbs, "hbm_frac": ts_gbs / HBM_PEAK_GBS},
     }
 
     if not args.no_c4:

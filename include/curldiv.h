@@ -162,16 +162,19 @@ int cd_coarse_solve(cd_solver* s, const double* r_dev, double* z_dev);
 int cd_precondition(cd_solver* s, const double* r_dev, double* z_dev);
 
 /* ---- live kernel timing ------------------------------------------------- */
-/* When enabled, the operator-apply launches of the handle are bracketed by
- * pairs of HIP events on the handle's stream (event-record nodes when the
- * outer iteration is replayed from a HIP graph); the elapsed times are
- * folded into per-(level, precision) totals at the next synchronisation
- * point.  Hooks (cd_apply, cd_precondition, ...) are always timed; during
- * cd_solve every `on`-th outer iteration is (on = 1: all of them).
- * `bytes` accumulates the algorithmic traffic of those launches: the vectors
- * each launch must read and write once (2 N s for y = A x, 3 N s for the
- * residual, 5 N s for a Chebyshev step, (2 + k) N s for y = A x fused with
- * k Krylov-basis dot products; s = 8 or 4 bytes). */
+/* When enabled, the operator-apply kernels and the T-solve line kernels of
+ * the handle time themselves: each launch writes the wall-clock time of its
+ * earliest block start and latest block end (after its stores) into a
+ * device slot; slots are cleared before and copied to pinned host memory
+ * after each timed outer iteration (inside the replayed HIP graph as well),
+ * and folded into per-(kernel, level, precision) totals at the next
+ * synchronisation point.  Hooks (cd_apply, cd_tsolve, cd_precondition, ...)
+ * are always timed; during cd_solve every `on`-th outer iteration is (on = 1:
+ * all of them).  `bytes` accumulates the algorithmic traffic of those
+ * launches: the vectors each launch must read and write once (2 N s for
+ * y = A x, 3 N s for the residual, 5 N s for a Chebyshev step, (2 + k) N s
+ * for y = A x fused with k Krylov-basis dot products, 2 N s per T-solve axis
+ * pass and 3 N s for the accumulating last pass; s = 8 or 4 bytes). */
 typedef struct {
     long long launches;
     double total_ms;
@@ -182,6 +185,9 @@ typedef struct {
 int cd_profile_enable(cd_solver* s, int on);
 /* Totals of level `level` applies in FP64 (fp32 = 0) or FP32 (fp32 = 1). */
 int cd_profile_read(const cd_solver* s, int level, int fp32, cd_kernel_stats* out);
+/* Totals of the finest-level T-solve axis passes (Sec. 6.1 preconditioner
+ * T of the Krylov post-smoother), one launch per axis pass. */
+int cd_profile_read_tsolve(const cd_solver* s, int fp32, cd_kernel_stats* out);
 
 /* ---- serving: continuous batching of independent solves ----------------- */
 /* A server keeps a FIFO of submitted solves and a set of active ones.  Each

@@ -85,6 +85,7 @@ SIGNATURES = {
     "cd_precondition": (_I, [_P, _P, _P]),
     "cd_profile_enable": (_I, [_P, _I]),
     "cd_profile_read": (_I, [_P, _I, _I, ctypes.POINTER(cd_kernel_stats)]),
+    "cd_profile_read_tsolve": (_I, [_P, _I, ctypes.POINTER(cd_kernel_stats)]),
     "cd_server_default_options": (None, [ctypes.POINTER(cd_server_options)]),
     "cd_server_create": (_I, [ctypes.POINTER(cd_server_options), ctypes.POINTER(_P)]),
     "cd_server_submit": (_I, [_P, ctypes.POINTER(cd_problem), ctypes.POINTER(cd_options), _P, _P,
@@ -238,6 +239,11 @@ class Solver:
     def profile_read(self, level, fp32):
         st = cd_kernel_stats()
         check(lib().cd_profile_read(self._h, level, 1 if fp32 else 0, ctypes.byref(st)))
+        return st
+
+    def profile_read_tsolve(self, fp32=False):
+        st = cd_kernel_stats()
+        check(lib().cd_profile_read_tsolve(self._h, 1 if fp32 else 0, ctypes.byref(st)))
         return st
 
     def precondition(self, r_ptr, z_ptr):

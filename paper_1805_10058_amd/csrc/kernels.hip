@@ -53,6 +53,24 @@ __device__ inline double sum_partials(const double* part, int np) {
     return block_sum(v);
 }
 
+// Kernel-side timing on the constant-rate wall clock.  A timing slot is
+// kStampWords words: [0] = start of block 0 (the first block dispatched),
+// [1 + b % kStampEnds] = latest end of the blocks b mapped there, taken after
+// the block's memory operations completed.  The end words start at zero
+// (k_stamp_reduce clears them after use).  stamp == nullptr: no timing.
+// stamp_end must be reached by every thread of the block.
+__device__ inline void stamp_begin(unsigned long long* stamp) {
+    if (stamp != nullptr && blockIdx.x == 0 && threadIdx.x == 0) stamp[0] = (unsigned long long)wall_clock64();
+}
+
+__device__ inline void stamp_end(unsigned long long* stamp) {
+    if (stamp != nullptr) {
+        __builtin_amdgcn_s_waitcnt(0);  // this wave's loads and stores are done
+        __syncthreads();
+        if (threadIdx.x == 0) atomicMax(stamp + 1 + blockIdx.x % kStampEnds, (unsigned long long)wall_clock64());
+    }
+}
+
 template <typename T>
 __device__ inline T band_at(const OpDev<T>& op, int axis, int which, int k, int i) {
     return op.band[axis][which][k * op.m[axis] + i];
@@ -185,7 +203,8 @@ template <typename T, int HB, int MODE>
 __global__ __launch_bounds__(kThreads) void k_apply3d(OpDev<T> op, const T* __restrict__ x, T* __restrict__ y,
                                                       const T* __restrict__ b, T* __restrict__ u,
                                                       T* __restrict__ xout, T c1, T c2, double* __restrict__ part,
-                                                      int nv, Apply3dGeom g) {
+                                                      int nv, Apply3dGeom g, unsigned long long* stamp) {
+    stamp_begin(stamp);
     constexpr int R = 2 * HB + 1;
     constexpr int T3 = k3T3(HB);
     constexpr int E2 = k3T2 + 2 * HB, E3 = k3E3;
@@ -364,6 +383,7 @@ __global__ __launch_bounds__(kThreads) void k_apply3d(OpDev<T> op, const T* __re
         }
     }
     apply_write_dots<MODE>(dots, nv, part);
+    stamp_end(stamp);
 }
 
 // ------------------------------------------------------------------------------
@@ -384,7 +404,8 @@ template <typename T, int HB, int MODE>
 __global__ __launch_bounds__(kThreads) void k_apply2d(OpDev<T> op, const T* __restrict__ x, T* __restrict__ y,
                                                       const T* __restrict__ b, T* __restrict__ u,
                                                       T* __restrict__ xout, T c1, T c2, double* __restrict__ part,
-                                                      int nv) {
+                                                      int nv, unsigned long long* stamp) {
+    stamp_begin(stamp);
     constexpr int R = 2 * HB + 1;
     constexpr int E1 = kT1 + 2 * HB, E2 = kT2 + 2 * HB;  // input tile rows, columns
     constexpr int NIN = E1 * E2;                         // input tile size per component
@@ -465,6 +486,7 @@ __global__ __launch_bounds__(kThreads) void k_apply2d(OpDev<T> op, const T* __re
                                     size_t(2) * G, dots);
     }
     apply_write_dots<MODE>(dots, nv, part);
+    stamp_end(stamp);
 }
 
 // Raise a kernel's dynamic-LDS limit (default 64 KiB) to what a launch needs,
@@ -488,30 +510,30 @@ void allow_lds(const void* kern, size_t lds) {
 
 template <typename T, int HB, int MODE>
 void apply_dispatch(const OpDev<T>& op, const T* x, T* y, const T* b, T* u, T* xout, T c1, T c2, double* part,
-                    int nv, hipStream_t s) {
+                    int nv, unsigned long long* stamp, hipStream_t s) {
     if (op.dim == 3) {
         const Apply3dGeom g = apply3d_geom(op.m, HB);
         hipLaunchKernelGGL((k_apply3d<T, HB, MODE>), dim3(g.nblocks), dim3(kThreads), 0, s, op, x, y, b, u, xout,
-                           c1, c2, part, nv, g);
+                           c1, c2, part, nv, g, stamp);
     } else {
         static_assert(kT1 * kT2 == kThreads, "2D tile must match the block size");
         const int tiles = ((op.m[0] + kT1 - 1) / kT1) * ((op.m[1] + kT2 - 1) / kT2);
         hipLaunchKernelGGL((k_apply2d<T, HB, MODE>), dim3(tiles), dim3(kThreads), 0, s, op, x, y, b, u, xout, c1,
-                           c2, part, nv);
+                           c2, part, nv, stamp);
     }
     check_launch("apply");
 }
 
 template <typename T, int HB>
 void apply_mode(const OpDev<T>& op, int mode, const T* x, T* y, const T* b, T* u, T* xout, T c1, T c2, double* part,
-                int nv, hipStream_t s) {
+                int nv, unsigned long long* stamp, hipStream_t s) {
     switch (mode) {
-        case kApplyY: apply_dispatch<T, HB, kApplyY>(op, x, y, b, u, xout, c1, c2, part, nv, s); break;
-        case kApplyRes: apply_dispatch<T, HB, kApplyRes>(op, x, y, b, u, xout, c1, c2, part, nv, s); break;
-        case kApplyCheb: apply_dispatch<T, HB, kApplyCheb>(op, x, y, b, u, xout, c1, c2, part, nv, s); break;
-        case kApplyYDot: apply_dispatch<T, HB, kApplyYDot>(op, x, y, b, u, xout, c1, c2, part, nv, s); break;
-        case kApplyResDot: apply_dispatch<T, HB, kApplyResDot>(op, x, y, b, u, xout, c1, c2, part, nv, s); break;
-        case kApplyYMulti: apply_dispatch<T, HB, kApplyYMulti>(op, x, y, b, u, xout, c1, c2, part, nv, s); break;
+        case kApplyY: apply_dispatch<T, HB, kApplyY>(op, x, y, b, u, xout, c1, c2, part, nv, stamp, s); break;
+        case kApplyRes: apply_dispatch<T, HB, kApplyRes>(op, x, y, b, u, xout, c1, c2, part, nv, stamp, s); break;
+        case kApplyCheb: apply_dispatch<T, HB, kApplyCheb>(op, x, y, b, u, xout, c1, c2, part, nv, stamp, s); break;
+        case kApplyYDot: apply_dispatch<T, HB, kApplyYDot>(op, x, y, b, u, xout, c1, c2, part, nv, stamp, s); break;
+        case kApplyResDot: apply_dispatch<T, HB, kApplyResDot>(op, x, y, b, u, xout, c1, c2, part, nv, stamp, s); break;
+        case kApplyYMulti: apply_dispatch<T, HB, kApplyYMulti>(op, x, y, b, u, xout, c1, c2, part, nv, stamp, s); break;
         default: throw std::runtime_error("bad apply mode");
     }
 }
@@ -707,7 +729,9 @@ template <typename T, int BW, bool ACC>
 __global__ __launch_bounds__(kLineThreads) void k_tsolve_line(const T* __restrict__ in, T* __restrict__ out,
                                                               LineGeom g, size_t lines_padded,
                                                               const T* __restrict__ L,
-                                                              const T* __restrict__ dinv, int warm) {
+                                                              const T* __restrict__ dinv, int warm,
+                                                              unsigned long long* stamp) {
+    stamp_begin(stamp);
     extern __shared__ __align__(16) unsigned char smem_raw[];
     T* sp = reinterpret_cast<T*>(smem_raw);
     const int lane = threadIdx.x;
@@ -774,60 +798,62 @@ __global__ __launch_bounds__(kLineThreads) void k_tsolve_line(const T* __restric
         }
     }
     __syncthreads();
-    if (!active) return;
-    // 2. forward recurrence
-    T win[BW];
-#pragma unroll
-    for (int k = 0; k < BW; ++k) win[k] = T(0);
-    for (int rb = 0; rb < spanP; rb += kRowGroup) {
-        T v[kRowGroup];
-#pragma unroll
-        for (int q = 0; q < kRowGroup; ++q) v[q] = sp[(rb + q) * kLineThreads + lane];
-#pragma unroll
-        for (int q = 0; q < kRowGroup; ++q) {
-            T x = v[q];
-#pragma unroll
-            for (int k = 1; k <= BW; ++k) x -= cf[(rb + q) * BW + k - 1] * win[k - 1];
-#pragma unroll
-            for (int k = BW - 1; k >= 1; --k) win[k] = win[k - 1];
-            win[0] = x;
-            v[q] = x * dv[rb + q];
+    if (active) {
+        // 2. forward recurrence
+        T win[BW];
+    #pragma unroll
+        for (int k = 0; k < BW; ++k) win[k] = T(0);
+        for (int rb = 0; rb < spanP; rb += kRowGroup) {
+            T v[kRowGroup];
+    #pragma unroll
+            for (int q = 0; q < kRowGroup; ++q) v[q] = sp[(rb + q) * kLineThreads + lane];
+    #pragma unroll
+            for (int q = 0; q < kRowGroup; ++q) {
+                T x = v[q];
+    #pragma unroll
+                for (int k = 1; k <= BW; ++k) x -= cf[(rb + q) * BW + k - 1] * win[k - 1];
+    #pragma unroll
+                for (int k = BW - 1; k >= 1; --k) win[k] = win[k - 1];
+                win[0] = x;
+                v[q] = x * dv[rb + q];
+            }
+    #pragma unroll
+            for (int q = 0; q < kRowGroup; ++q) sp[(rb + q) * kLineThreads + lane] = v[q];
         }
-#pragma unroll
-        for (int q = 0; q < kRowGroup; ++q) sp[(rb + q) * kLineThreads + lane] = v[q];
-    }
-    // 3. backward recurrence, rows spanP-1 down to the chunk start (rows below
-    //    it, clamped to row 0, only rewrite LDS rows that are not output)
-    const int rlo = r0 - rs;
-#pragma unroll
-    for (int k = 0; k < BW; ++k) win[k] = T(0);
-    for (int rb = spanP - 1; rb >= rlo; rb -= kRowGroup) {
-        T v[kRowGroup];
-#pragma unroll
-        for (int q = 0; q < kRowGroup; ++q) v[q] = sp[max(rb - q, 0) * kLineThreads + lane];
-#pragma unroll
-        for (int q = 0; q < kRowGroup; ++q) {
-            const int r = max(rb - q, 0);
-            T x = v[q];
-#pragma unroll
-            for (int k = 1; k <= BW; ++k) x -= cf[(r + k) * BW + k - 1] * win[k - 1];
-#pragma unroll
-            for (int k = BW - 1; k >= 1; --k) win[k] = win[k - 1];
-            win[0] = x;
-            v[q] = x;
+        // 3. backward recurrence, rows spanP-1 down to the chunk start (rows below
+        //    it, clamped to row 0, only rewrite LDS rows that are not output)
+        const int rlo = r0 - rs;
+    #pragma unroll
+        for (int k = 0; k < BW; ++k) win[k] = T(0);
+        for (int rb = spanP - 1; rb >= rlo; rb -= kRowGroup) {
+            T v[kRowGroup];
+    #pragma unroll
+            for (int q = 0; q < kRowGroup; ++q) v[q] = sp[max(rb - q, 0) * kLineThreads + lane];
+    #pragma unroll
+            for (int q = 0; q < kRowGroup; ++q) {
+                const int r = max(rb - q, 0);
+                T x = v[q];
+    #pragma unroll
+                for (int k = 1; k <= BW; ++k) x -= cf[(r + k) * BW + k - 1] * win[k - 1];
+    #pragma unroll
+                for (int k = BW - 1; k >= 1; --k) win[k] = win[k - 1];
+                win[0] = x;
+                v[q] = x;
+            }
+    #pragma unroll
+            for (int q = 0; q < kRowGroup; ++q) sp[max(rb - q, 0) * kLineThreads + lane] = v[q];
         }
-#pragma unroll
-        for (int q = 0; q < kRowGroup; ++q) sp[max(rb - q, 0) * kLineThreads + lane] = v[q];
+        // 4. output rows [r0, r1)
+        T* dst = out + base;
+        for (int r = r0; r < r1; ++r) {
+            const T val = sp[(r - rs) * kLineThreads + lane];
+            if (ACC)
+                dst[size_t(r) * stride] += val;
+            else
+                dst[size_t(r) * stride] = val;
+        }
     }
-    // 4. output rows [r0, r1)
-    T* dst = out + base;
-    for (int r = r0; r < r1; ++r) {
-        const T val = sp[(r - rs) * kLineThreads + lane];
-        if (ACC)
-            dst[size_t(r) * stride] += val;
-        else
-            dst[size_t(r) * stride] = val;
-    }
+    stamp_end(stamp);
 }
 
 // ------------------------------------------------------------------------------
@@ -1067,6 +1093,32 @@ __global__ __launch_bounds__(kThreads) void k_combine(const T* __restrict__ V, i
     }
 }
 
+// pairs[2 s] = start, pairs[2 s + 1] = latest end of slot s (one block per
+// slot); the slot's words are cleared for its next use (start to max: a slot
+// no kernel wrote reads as (max, 0)).
+__global__ __launch_bounds__(kThreads) void k_stamp_reduce(unsigned long long* __restrict__ st, int slot0,
+                                                           unsigned long long* __restrict__ pairs) {
+    __shared__ unsigned long long red[kThreads];
+    const int sl = slot0 + blockIdx.x;
+    unsigned long long* p = st + size_t(sl) * kStampWords;
+    unsigned long long mx = 0;
+    for (int i = threadIdx.x; i < kStampEnds; i += kThreads) {
+        mx = max(mx, p[1 + i]);
+        p[1 + i] = 0;
+    }
+    red[threadIdx.x] = mx;
+    __syncthreads();
+    for (int off = kThreads / 2; off > 0; off >>= 1) {
+        if (threadIdx.x < off) red[threadIdx.x] = max(red[threadIdx.x], red[threadIdx.x + off]);
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        pairs[2 * sl] = p[0];
+        pairs[2 * sl + 1] = red[0];
+        p[0] = ~0ull;
+    }
+}
+
 int grid_for(size_t n) {
     const size_t nb = (n + kThreads - 1) / kThreads;
     return int(std::max<size_t>(1, std::min<size_t>(nb, 8192)));
@@ -1089,15 +1141,16 @@ int apply_blocks(const OpDev<T>& op) {
 
 template <typename T>
 void launch_apply(const OpDev<T>& op, int mode, const T* x, T* y, const T* b, T* u, T* xout, T c1, T c2, double* part,
-                  hipStream_t s, int nv) {
+                  hipStream_t s, int nv,
+                  unsigned long long* stamp) {
     if (mode == kApplyYMulti && (nv < 1 || nv > kMaxBasis)) throw std::runtime_error("bad number of dot vectors");
     switch (op.hb) {
-        case 1: apply_mode<T, 1>(op, mode, x, y, b, u, xout, c1, c2, part, nv, s); break;
-        case 2: apply_mode<T, 2>(op, mode, x, y, b, u, xout, c1, c2, part, nv, s); break;
-        case 3: apply_mode<T, 3>(op, mode, x, y, b, u, xout, c1, c2, part, nv, s); break;
-        case 4: apply_mode<T, 4>(op, mode, x, y, b, u, xout, c1, c2, part, nv, s); break;
-        case 5: apply_mode<T, 5>(op, mode, x, y, b, u, xout, c1, c2, part, nv, s); break;
-        case 6: apply_mode<T, 6>(op, mode, x, y, b, u, xout, c1, c2, part, nv, s); break;
+        case 1: apply_mode<T, 1>(op, mode, x, y, b, u, xout, c1, c2, part, nv, stamp, s); break;
+        case 2: apply_mode<T, 2>(op, mode, x, y, b, u, xout, c1, c2, part, nv, stamp, s); break;
+        case 3: apply_mode<T, 3>(op, mode, x, y, b, u, xout, c1, c2, part, nv, stamp, s); break;
+        case 4: apply_mode<T, 4>(op, mode, x, y, b, u, xout, c1, c2, part, nv, stamp, s); break;
+        case 5: apply_mode<T, 5>(op, mode, x, y, b, u, xout, c1, c2, part, nv, stamp, s); break;
+        case 6: apply_mode<T, 6>(op, mode, x, y, b, u, xout, c1, c2, part, nv, stamp, s); break;
         default: throw std::runtime_error("degree out of range (1..6)");
     }
 }
@@ -1161,16 +1214,17 @@ void launch_prolong_add(const XferDev<T>& X, int ncomp, const T* ec, T* xf, hipS
 
 template <typename T, int BW>
 void tsolve_axis(const T* v, T* z, bool acc, const LineGeom& g, const TFacDev<T>& F, size_t lines_padded, size_t lds,
-                 hipStream_t s) {
+                 unsigned long long* stamp, hipStream_t s) {
     const size_t items = lines_padded * g.nchunk * size_t(g.ncomp);
     const dim3 grid(items / kLineThreads);
     auto kern = acc ? k_tsolve_line<T, BW, true> : k_tsolve_line<T, BW, false>;
     allow_lds(reinterpret_cast<const void*>(kern), lds);
-    hipLaunchKernelGGL(kern, grid, dim3(kLineThreads), lds, s, v, z, g, lines_padded, F.l, F.dinv, F.warm);
+    hipLaunchKernelGGL(kern, grid, dim3(kLineThreads), lds, s, v, z, g, lines_padded, F.l, F.dinv, F.warm, stamp);
 }
 
 template <typename T>
-void launch_tsolve(int dim, const int* m, const TFacDev<T>* fac, const T* v, T* tmp, T* z, hipStream_t s, T* acc) {
+void launch_tsolve(int dim, const int* m, const TFacDev<T>* fac, const T* v, T* tmp, T* z, hipStream_t s, T* acc,
+                   unsigned long long* stamps) {
     if (v == z || v == tmp || tmp == z) throw std::runtime_error("tsolve needs three distinct buffers");
     if (acc && (acc == v || acc == tmp || acc == z)) throw std::runtime_error("tsolve accumulator aliases a buffer");
     const int m0 = m[0], m1 = m[1], m2 = (dim == 3) ? m[2] : 1;
@@ -1188,6 +1242,7 @@ void launch_tsolve(int dim, const int* m, const TFacDev<T>* fac, const T* v, T* 
         T* dst = ((dim - 1 - a) % 2 == 0) ? z : tmp;
         const bool last_acc = acc && (a == dim - 1);
         if (last_acc) dst = acc;
+        unsigned long long* st = stamps ? stamps + size_t(a) * kStampWords : nullptr;
         const TFacDev<T>& F = fac[a];
         LineGeom g;
         g.G = G;
@@ -1212,11 +1267,11 @@ void launch_tsolve(int dim, const int* m, const TFacDev<T>* fac, const T* v, T* 
         g.ncomp = dim;
         const size_t lp = (g.lines_per_comp + kLineThreads - 1) / kLineThreads * kLineThreads;
         switch (F.bw) {
-            case 1: tsolve_axis<T, 1>(src, dst, last_acc, g, F, lp, lds, s); break;
-            case 2: tsolve_axis<T, 2>(src, dst, last_acc, g, F, lp, lds, s); break;
-            case 3: tsolve_axis<T, 3>(src, dst, last_acc, g, F, lp, lds, s); break;
-            case 4: tsolve_axis<T, 4>(src, dst, last_acc, g, F, lp, lds, s); break;
-            case 5: tsolve_axis<T, 5>(src, dst, last_acc, g, F, lp, lds, s); break;
+            case 1: tsolve_axis<T, 1>(src, dst, last_acc, g, F, lp, lds, st, s); break;
+            case 2: tsolve_axis<T, 2>(src, dst, last_acc, g, F, lp, lds, st, s); break;
+            case 3: tsolve_axis<T, 3>(src, dst, last_acc, g, F, lp, lds, st, s); break;
+            case 4: tsolve_axis<T, 4>(src, dst, last_acc, g, F, lp, lds, st, s); break;
+            case 5: tsolve_axis<T, 5>(src, dst, last_acc, g, F, lp, lds, st, s); break;
             default: throw std::runtime_error("degree out of range (1..6)");
         }
         check_launch("tsolve");
@@ -1316,6 +1371,12 @@ void launch_fcg_update(const double* pdr, int npdr, const double* pdq, int npdq,
 
 
 
+void launch_stamp_reduce(unsigned long long* st, int slot0, int nslots, unsigned long long* pairs, hipStream_t s) {
+    if (nslots <= 0) return;
+    hipLaunchKernelGGL(k_stamp_reduce, dim3(nslots), dim3(kThreads), 0, s, st, slot0, pairs);
+    check_launch("stamp_reduce");
+}
+
 void launch_hessenberg_ls(double* H, int ld, int k, const double* beta0sq, double* y, const double* plast,
                           int nlast, hipStream_t s) {
     if (k < 1 || k > kMaxBasis) throw std::runtime_error("bad number of Krylov vectors");
@@ -1350,10 +1411,11 @@ void launch_combine(const T* V, int k, const double* y, T* w, size_t n, hipStrea
 #define CD_INST(T)                                                                                                   \
     template int apply_blocks<T>(const OpDev<T>&);                                                                   \
     template void launch_apply<T>(const OpDev<T>&, int, const T*, T*, const T*, T*, T*, T, T, double*, hipStream_t,  \
-                                  int);                                                                              \
+                                  int, unsigned long long*);                                                         \
     template void launch_restrict<T>(const XferDev<T>&, int, const T*, T*, hipStream_t);                             \
     template void launch_prolong_add<T>(const XferDev<T>&, int, const T*, T*, hipStream_t);                          \
-    template void launch_tsolve<T>(int, const int*, const TFacDev<T>*, const T*, T*, T*, hipStream_t, T*);                            \
+    template void launch_tsolve<T>(int, const int*, const TFacDev<T>*, const T*, T*, T*, hipStream_t, T*,            \
+                                   unsigned long long*);                            \
     template void launch_fill<T>(T*, T, size_t, hipStream_t);                                                        \
     template void launch_copy<T>(const T*, T*, size_t, hipStream_t);                                                 \
     template void launch_axpby<T>(T, const T*, T, T*, size_t, hipStream_t);                                          \

@@ -61,9 +61,17 @@ int reduce_blocks(size_t n);
 template <typename T>
 int apply_blocks(const OpDev<T>& op);
 
+// Kernel-side timing: a slot of kStampWords words per timed launch (see
+// stamp_begin / stamp_end in kernels.hip).
+constexpr int kStampEnds = 2048;
+constexpr int kStampWords = 1 + kStampEnds;
+// stamp: nullptr, or the timing slot of this launch.
 template <typename T>
 void launch_apply(const OpDev<T>& op, int mode, const T* x, T* y, const T* b, T* u, T* xout, T c1, T c2,
-                  double* part, hipStream_t s, int nv = 0);
+                  double* part, hipStream_t s, int nv = 0, unsigned long long* stamp = nullptr);
+// pairs[2 i], pairs[2 i + 1] = start and end of slots i in [slot0, slot0 +
+// nslots); clears those slots for reuse.
+void launch_stamp_reduce(unsigned long long* st, int slot0, int nslots, unsigned long long* pairs, hipStream_t s);
 
 template <typename T>
 void launch_restrict(const XferDev<T>& X, int ncomp, const T* rf, T* rc, hipStream_t s);
@@ -72,10 +80,11 @@ void launch_prolong_add(const XferDev<T>& X, int ncomp, const T* ec, T* xf, hipS
 
 // z = T^{-1} v, T = I_d (x) T_1 (x) ... (x) T_d; v, tmp, z distinct, tmp: n
 // scratch.  With acc != nullptr the result is added to acc instead
-// (acc += T^{-1} v) and z is used as scratch.
+// (acc += T^{-1} v) and z is used as scratch.  stamps: nullptr or dim
+// consecutive timing slots, one per axis pass.
 template <typename T>
 void launch_tsolve(int dim, const int* m, const TFacDev<T>* fac, const T* v, T* tmp, T* z, hipStream_t s,
-                   T* acc = nullptr);
+                   T* acc = nullptr, unsigned long long* stamps = nullptr);
 
 // ---- vector kernels ---------------------------------------------------------
 template <typename TA, typename TB>

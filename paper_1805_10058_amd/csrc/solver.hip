@@ -161,18 +161,29 @@ struct cd_solver {
     double* host_scal = nullptr;  // pinned: [0] r.r, [1] d.q
     int nbr = 0, nba = 0;
 
-    // live timing of operator applies (cd_profile_enable)
+    // live kernel timing (cd_profile_enable): every timed launch gets a slot,
+    // a pair of wall-clock stamps the kernel itself writes (earliest block
+    // start, latest block end).  A timed unit (one outer iteration, or one
+    // hook call) clears its slots first and copies them to pinned host memory
+    // last; the captured timed iteration uses slots [0, kGraphSlots) and does
+    // both inside the graph.
     struct ProfRec {
-        hipEvent_t a, b;
-        int cls;
+        int slot;
+        int cls;  // kind * 2L + 2 level + fp32; kind 0 = operator apply, 1 = T-solve pass
         double bytes;
     };
+    static constexpr int kGraphSlots = 128, kStampSlots = 512, kUnitSlots = 128;
+    unsigned long long* stamps = nullptr;       // device, kStampSlots slots of cd::kStampWords words
+    unsigned long long* pairs = nullptr;        // device, 2 kStampSlots: (start, end) per slot
+    unsigned long long* stamps_host = nullptr;  // pinned copy of pairs
+    double wall_khz = 0.0;                      // wall-clock rate
+    bool unit_open = false;
+    int unit_base = 0, unit_next = 0, eager_next = kGraphSlots;
     SolveState state;
     hipEvent_t iter_event = nullptr;
     double* xw = nullptr;                 // iterate of the outer iteration (copied to the caller's x)
     hipGraphExec_t iter_graph = nullptr;  // captured outer iteration k >= 1
-    // the same iteration captured with live timing: the apply events are
-    // external event nodes of this graph, read back after every replay
+    // the same iteration captured with live timing (stamp slots [0, kGraphSlots))
     hipGraphExec_t iter_graph_prof = nullptr;
     std::vector<ProfRec> prof_graph;
     bool capturing = false, graph_prof_ran = false;
@@ -182,16 +193,15 @@ struct cd_solver {
 
     bool prof = false;
     std::vector<ProfRec> prof_pending;
-    std::vector<std::pair<hipEvent_t, hipEvent_t>> prof_pool;
-    std::vector<cd_kernel_stats> prof_stats;  // index 2*level + fp32
+    std::vector<cd_kernel_stats> prof_stats;  // index cls
     ~cd_solver() {
         if (iter_event) (void)hipEventDestroy(iter_event);
         if (entry_event) (void)hipEventDestroy(entry_event);
         if (iter_graph) (void)hipGraphExecDestroy(iter_graph);
         if (iter_graph_prof) (void)hipGraphExecDestroy(iter_graph_prof);
-        for (auto& r : prof_graph) { (void)hipEventDestroy(r.a); (void)hipEventDestroy(r.b); }
-        for (auto& r : prof_pending) { (void)hipEventDestroy(r.a); (void)hipEventDestroy(r.b); }
-        for (auto& e : prof_pool) { (void)hipEventDestroy(e.first); (void)hipEventDestroy(e.second); }
+        if (stamps) (void)hipFree(stamps);
+        if (pairs) (void)hipFree(pairs);
+        if (stamps_host) (void)hipHostFree(stamps_host);
     }
 };
 
@@ -395,80 +405,115 @@ const cd::TFacDev<double>* tfacs<double>(cd_solver* s) { return s->tfd64; }
 template <>
 const cd::TFacDev<float>* tfacs<float>(cd_solver* s) { return s->tfd32; }
 
-void prof_add(cd_solver* s, const cd_solver::ProfRec& r) {
-    float ms = 0.f;
-    hip_check(hipEventElapsedTime(&ms, r.a, r.b), "hipEventElapsedTime");
-    cd_kernel_stats& st = s->prof_stats[r.cls];
-    st.launches += 1;
-    st.total_ms += ms;
-    st.bytes += r.bytes;
+// ---- live kernel timing ----------------------------------------------------------------
+int prof_class(const cd_solver* s, int kind, int level, bool fp32) {
+    return kind * 2 * int(s->lv.size()) + 2 * level + (fp32 ? 1 : 0);
 }
 
-// Record a timing event on the solver stream.  Inside a stream capture the
-// event becomes an event-record node of the captured graph, appended to the
-// capture's current dependency set, so every replay records it.
-void record_timing_event(cd_solver* s, hipEvent_t ev) {
-    if (!s->capturing) {
-        hip_check(hipEventRecord(ev, s->stream), "hipEventRecord");
-        return;
+// Fold the stamps of the records into the totals (host copies complete).
+void prof_add(cd_solver* s, const std::vector<cd_solver::ProfRec>& recs) {
+    for (const auto& r : recs) {
+        const unsigned long long t0 = s->stamps_host[2 * r.slot], t1 = s->stamps_host[2 * r.slot + 1];
+        if (t0 == ~0ull || t1 == 0 || t1 < t0) continue;  // slot not written (no kernel ran)
+        cd_kernel_stats& st = s->prof_stats[r.cls];
+        st.launches += 1;
+        st.total_ms += double(t1 - t0) / s->wall_khz;
+        st.bytes += r.bytes;
     }
-    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
-    hipGraph_t g = nullptr;
-    const hipGraphNode_t* deps = nullptr;
-    size_t nd = 0;
-    hip_check(hipStreamGetCaptureInfo_v2(s->stream, &cs, nullptr, &g, &deps, &nd), "hipStreamGetCaptureInfo_v2");
-    if (cs != hipStreamCaptureStatusActive || !g) throw CdError(CD_EHIP, "timing event outside an active capture");
-    hipGraphNode_t node = nullptr;
-    hip_check(hipGraphAddEventRecordNode(&node, g, deps, nd, ev), "hipGraphAddEventRecordNode");
-    hip_check(hipStreamUpdateCaptureDependencies(s->stream, &node, 1, hipStreamSetCaptureDependencies),
-              "hipStreamUpdateCaptureDependencies");
 }
 
-// ---- operator apply with optional live timing ---------------------------------------
+// Call after a stream sync.
+void prof_flush(cd_solver* s) {
+    if (s->prof_stats.size() < 4 * s->lv.size()) s->prof_stats.resize(4 * s->lv.size(), cd_kernel_stats{0, 0.0, 0.0});
+    prof_add(s, s->prof_pending);
+    s->prof_pending.clear();
+    s->eager_next = cd_solver::kGraphSlots;
+    if (s->graph_prof_ran) {  // stamps of the last replay of the timed graph
+        prof_add(s, s->prof_graph);
+        s->graph_prof_ran = false;
+    }
+}
+
+void prof_unit_begin(cd_solver* s) {
+    if (s->capturing) {
+        s->unit_base = 0;
+        s->prof_graph.clear();
+    } else {
+        if (s->eager_next + cd_solver::kUnitSlots > cd_solver::kStampSlots) {
+            hip_check(hipStreamSynchronize(s->stream), "sync");
+            prof_flush(s);
+        }
+        s->unit_base = s->eager_next;
+    }
+    s->unit_next = s->unit_base;
+    s->unit_open = true;
+}
+
+// n consecutive slots of class cls, bytes each.
+unsigned long long* prof_slots(cd_solver* s, int n, int cls, double bytes) {
+    if (s->unit_next + n > s->unit_base + cd_solver::kUnitSlots)
+        throw CdError(CD_EHIP, "too many timed launches in one outer iteration");
+    unsigned long long* p = s->stamps + size_t(s->unit_next) * cd::kStampWords;
+    for (int i = 0; i < n; ++i) {
+        const cd_solver::ProfRec rec{s->unit_next + i, cls, bytes};
+        (s->capturing ? s->prof_graph : s->prof_pending).push_back(rec);
+    }
+    s->unit_next += n;
+    return p;
+}
+
+void prof_unit_end(cd_solver* s) {
+    const int n = s->unit_next - s->unit_base;
+    if (n > 0) {
+        cd::launch_stamp_reduce(s->stamps, s->unit_base, n, s->pairs, s->stream);
+        hip_check(hipMemcpyAsync(s->stamps_host + 2 * s->unit_base, s->pairs + 2 * s->unit_base,
+                                 size_t(2 * n) * sizeof(unsigned long long), hipMemcpyDeviceToHost, s->stream),
+                  "read stamps");
+    }
+    if (!s->capturing) s->eager_next = s->unit_next;
+    s->unit_open = false;
+}
+
+bool timing(const cd_solver* s) { return s->prof && s->prof_sample; }
+
+// ---- operator apply and T-solve with optional live timing ------------------------------
 template <typename T>
 void apply_op(cd_solver* s, int level, int mode, const T* x, T* y, const T* b, T* u, T* xout, T c1, T c2,
               double* part, int nv = 0) {
     const cd::OpDev<T>& op = devlevels<T>(s)[level].op;
-    if (!s->prof || !s->prof_sample) {
+    if (!timing(s)) {
         cd::launch_apply<T>(op, mode, x, y, b, u, xout, c1, c2, part, s->stream, nv);
         return;
     }
-    std::pair<hipEvent_t, hipEvent_t> ev;
-    if (s->prof_pool.empty()) {
-        hip_check(hipEventCreate(&ev.first), "hipEventCreate");
-        hip_check(hipEventCreate(&ev.second), "hipEventCreate");
-    } else {
-        ev = s->prof_pool.back();
-        s->prof_pool.pop_back();
-    }
+    const bool own = !s->unit_open;
+    if (own) prof_unit_begin(s);
     const double nvec = (mode == kApplyRes || mode == cd::kApplyResDot) ? 3.0
                         : (mode == kApplyCheb)                         ? 5.0
                         : (mode == cd::kApplyYMulti)                   ? 2.0 + nv
                                                                        : 2.0;
-    const int cls = 2 * level + (sizeof(T) == 4 ? 1 : 0);
-    record_timing_event(s, ev.first);
-    cd::launch_apply<T>(op, mode, x, y, b, u, xout, c1, c2, part, s->stream, nv);
-    record_timing_event(s, ev.second);
-    const cd_solver::ProfRec rec{ev.first, ev.second, cls, nvec * double(s->lv[level].N) * sizeof(T)};
-    if (s->capturing)
-        s->prof_graph.push_back(rec);
-    else
-        s->prof_pending.push_back(rec);
+    unsigned long long* st = prof_slots(s, 1, prof_class(s, 0, level, sizeof(T) == 4),
+                                        nvec * double(s->lv[level].N) * sizeof(T));
+    cd::launch_apply<T>(op, mode, x, y, b, u, xout, c1, c2, part, s->stream, nv, st);
+    if (own) prof_unit_end(s);
 }
 
-
-// Fold finished event pairs into the totals (call after a stream sync).
-void prof_flush(cd_solver* s) {
-    if (s->prof_stats.size() < 2 * s->lv.size()) s->prof_stats.resize(2 * s->lv.size(), cd_kernel_stats{0, 0.0, 0.0});
-    for (auto& r : s->prof_pending) {
-        prof_add(s, r);
-        s->prof_pool.push_back({r.a, r.b});
+// z = T^{-1} v (acc == nullptr) or acc += T^{-1} v on the finest level.
+template <typename T>
+void tsolve_op(cd_solver* s, const T* v, T* tmp, T* z, T* acc = nullptr) {
+    const int d = s->d;
+    if (!timing(s) || s->tf[0].bw == 0) {
+        cd::launch_tsolve<T>(d, s->lv[0].m, tfacs<T>(s), v, tmp, z, s->stream, acc);
+        return;
     }
-    s->prof_pending.clear();
-    if (s->graph_prof_ran) {  // events of the last replay of the timed graph
-        for (auto& r : s->prof_graph) prof_add(s, r);
-        s->graph_prof_ran = false;
-    }
+    const bool own = !s->unit_open;
+    if (own) prof_unit_begin(s);
+    const int cls = prof_class(s, 1, 0, sizeof(T) == 4);
+    const double pass = 2.0 * double(s->N) * sizeof(T);  // read the input, write the output
+    unsigned long long* st = prof_slots(s, d - 1, cls, pass);
+    unsigned long long* last = prof_slots(s, 1, cls, acc ? pass + double(s->N) * sizeof(T) : pass);
+    if (d == 1) st = last;
+    cd::launch_tsolve<T>(d, s->lv[0].m, tfacs<T>(s), v, tmp, z, s->stream, acc, st);
+    if (own) prof_unit_end(s);
 }
 
 // ---- V-cycle pieces ------------------------------------------------------------
@@ -510,14 +555,12 @@ void gmres_post(cd_solver* s, VWork<T>& W, const T* b, T* x) {
     const int ks = s->ksteps, ld = ks + 1, nb = W.nb, nba = W.nba;
     hipStream_t st = s->stream;
     T* V = W.V;
-    const int d = s->d;
-    const int* m0 = s->lv[0].m;
     // r = b - A x and its norm: V_0 = r / ||r||, beta0^2 kept for the least squares
     apply_op<T>(s, 0, cd::kApplyResDot, x, W.w, b, nullptr, nullptr, T(0), T(0), W.pnorm);
     cd::launch_normscale<T>(W.pnorm, nba, W.scal, true, W.w, V, N, st);
     for (int j = 0; j < ks; ++j) {
         double* Hcol = W.H + size_t(j) * ld;
-        cd::launch_tsolve<T>(d, m0, tfacs<T>(s), V + size_t(j) * N, W.tmp, W.z, st);
+        tsolve_op<T>(s, V + size_t(j) * N, W.tmp, W.z);
         // w = A T^{-1} V_j together with the dots V_i . w, i <= j
         apply_op<T>(s, 0, cd::kApplyYMulti, W.z, W.w, V, nullptr, nullptr, T(0), T(0), W.pdot, j + 1);
         // H(0..j, j) = those dots; w -= sum_i H(i, j) V_i; partial sums of w.w
@@ -528,7 +571,7 @@ void gmres_post(cd_solver* s, VWork<T>& W, const T* b, T* x) {
     cd::launch_hessenberg_ls(W.H, ld, ks, W.scal, W.y, W.pnorm, nb, st);
     cd::launch_combine<T>(V, ks, W.y, W.w, N, st);
     // x += T^{-1} (V y)
-    cd::launch_tsolve<T>(d, m0, tfacs<T>(s), W.w, W.tmp, W.z, st, x);
+    tsolve_op<T>(s, W.w, W.tmp, W.z, x);
 }
 
 // One V-cycle on level l for A_l x = W.lv[l].b; result in W.lv[l].xcur.
@@ -775,8 +818,13 @@ void solve_iterate(cd_solver* s) {
     const bool first = (S.k == 0);
     const bool timed = s->prof && (s->prof_iter++ % s->prof_period == 0);
     s->prof_sample = timed;
+    auto enqueue = [&](bool f) {
+        if (timed) prof_unit_begin(s);
+        enqueue_iteration(s, f);
+        if (timed) prof_unit_end(s);
+    };
     if (first || !s->opt.graphs) {
-        enqueue_iteration(s, first);
+        enqueue(first);
     } else {
         hipGraphExec_t& exec = timed ? s->iter_graph_prof : s->iter_graph;
         if (!exec) {
@@ -784,9 +832,10 @@ void solve_iterate(cd_solver* s) {
             hip_check(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal), "hipStreamBeginCapture");
             s->capturing = timed;
             try {
-                enqueue_iteration(s, false);
+                enqueue(false);
             } catch (...) {
                 s->capturing = false;
+                s->unit_open = false;
                 (void)hipStreamEndCapture(st, &g);
                 if (g) (void)hipGraphDestroy(g);
                 throw;
@@ -1102,8 +1151,9 @@ int cd_tsolve(cd_solver* s, const double* v, double* z) {
             cd::launch_copy<double>(v, s->z, s->N, s->stream);
             src = s->z;
         }
-        cd::launch_tsolve<double>(s->d, s->lv[0].m, s->tfd64, src, s->q, z, s->stream);
+        tsolve_op<double>(s, src, s->q, z);
         hip_check(hipStreamSynchronize(s->stream), "sync");
+        if (s->prof) prof_flush(s);
     });
 }
 
@@ -1135,11 +1185,25 @@ int cd_profile_enable(cd_solver* s, int on) {
         need(s);
         enter(s);
         hip_check(hipStreamSynchronize(s->stream), "sync");
-        prof_flush(s);
+        if (s->stamps) prof_flush(s);
+        if (on > 0 && !s->stamps) {
+            int dev = 0, khz = 0;
+            hip_check(hipGetDevice(&dev), "hipGetDevice");
+            hip_check(hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, dev), "wall clock rate");
+            if (khz <= 0) throw CdError(CD_EHIP, "device reports no wall-clock rate");
+            s->wall_khz = double(khz);
+            const size_t words = size_t(cd_solver::kStampSlots) * cd::kStampWords;
+            const size_t pbytes = size_t(2 * cd_solver::kStampSlots) * sizeof(unsigned long long);
+            hip_check(hipMalloc(&s->stamps, words * sizeof(unsigned long long)), "hipMalloc stamps");
+            hip_check(hipMemsetAsync(s->stamps, 0, words * sizeof(unsigned long long), s->stream), "clear stamps");
+            hip_check(hipMalloc(&s->pairs, pbytes), "hipMalloc stamps");
+            hip_check(hipHostMalloc(&s->stamps_host, pbytes, hipHostMallocDefault), "hipHostMalloc stamps");
+            hip_check(hipStreamSynchronize(s->stream), "sync");
+        }
         s->prof = (on > 0);
         s->prof_period = std::max(on, 1);
         s->prof_iter = 0;
-        if (s->prof) s->prof_stats.assign(2 * s->lv.size(), cd_kernel_stats{0, 0.0, 0.0});
+        if (s->prof) s->prof_stats.assign(4 * s->lv.size(), cd_kernel_stats{0, 0.0, 0.0});
     });
 }
 
@@ -1147,7 +1211,16 @@ int cd_profile_read(const cd_solver* s, int level, int fp32, cd_kernel_stats* ou
     return run([&] {
         need_level(s, level);
         if (!out) throw CdError(CD_EINVAL, "null output");
-        const size_t k = size_t(2 * level + (fp32 ? 1 : 0));
+        const size_t k = size_t(prof_class(s, 0, level, fp32 != 0));
+        *out = (k < s->prof_stats.size()) ? s->prof_stats[k] : cd_kernel_stats{0, 0.0, 0.0};
+    });
+}
+
+int cd_profile_read_tsolve(const cd_solver* s, int fp32, cd_kernel_stats* out) {
+    return run([&] {
+        need(s);
+        if (!out) throw CdError(CD_EINVAL, "null output");
+        const size_t k = size_t(prof_class(s, 1, 0, fp32 != 0));
         *out = (k < s->prof_stats.size()) ? s->prof_stats[k] : cd_kernel_stats{0, 0.0, 0.0};
     });
 }

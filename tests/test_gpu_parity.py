@@ -279,3 +279,35 @@ def test_graph_replay_equals_eager(case, precision):
         re = s_e.solve(bd.data_ptr(), xe.data_ptr())
         assert rg.iterations == re.iterations and rg.iterations >= 3
         np.testing.assert_array_equal(host(xg), host(xe))
+
+
+@pytest.mark.gpu
+@pytest.mark.parametrize("graphs", [1, 0])
+def test_live_timing_counts_and_leaves_results_unchanged(graphs):
+    # kernel-side timing of the applies and T-solve passes: results are bitwise
+    # those of an untimed solve, every timed launch is counted once, and the
+    # algorithmic bytes follow the launch kinds (2D p=3: 2 T-solve passes per
+    # solve of T, 4 of them per outer iteration with 3 Krylov steps)
+    case = CASES[2]
+    d, p, n, beta, _, cmax = case
+    opt = capi.options(coarse_max_dofs=cmax, precision=capi.CD_MIXED_FP32, rtol=1e-9, graphs=graphs)
+    s_t = capi.Solver(capi.problem(d, p, n, 1.0, beta), opt, stream())
+    s_u = capi.Solver(capi.problem(d, p, n, 1.0, beta), opt, stream())
+    b = np.random.default_rng(5).uniform(-1, 1, capi.num_dofs(s_t.prob))
+    bd, xt, xu = dev(b), empty(b.size), empty(b.size)
+    s_t.profile_enable(True, 1)
+    rt = s_t.solve(bd.data_ptr(), xt.data_ptr())
+    ru = s_u.solve(bd.data_ptr(), xu.data_ptr())
+    assert rt.iterations == ru.iterations
+    np.testing.assert_array_equal(host(xt), host(xu))
+    ts = s_t.profile_read_tsolve(True)
+    assert ts.launches == rt.iterations * (p + 1) * d
+    assert ts.total_ms > 0
+    a0 = s_t.profile_read(0, True)
+    assert a0.launches >= rt.iterations * (p + 2) and a0.total_ms > 0 and a0.bytes > 0
+    # sampled: every 2nd outer iteration
+    s_t.profile_enable(True, 2)
+    rt2 = s_t.solve(bd.data_ptr(), xt.data_ptr())
+    ts2 = s_t.profile_read_tsolve(True)
+    assert ts2.launches == ((rt2.iterations + 1) // 2) * (p + 1) * d
+    s_t.profile_enable(False)
