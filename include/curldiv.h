@@ -174,7 +174,7 @@ int cd_precondition(cd_solver* s, const double* r_dev, double* z_dev);
  * launches: the vectors each launch must read and write once (2 N s for
  * y = A x, 3 N s for the residual, 5 N s for a Chebyshev step, (2 + k) N s
  * for y = A x fused with k Krylov-basis dot products, 2 N s per T-solve axis
- * pass and 3 N s for the accumulating last pass; s = 8 or 4 bytes). */
+ * pass; s = 8 or 4 bytes). */
 typedef struct {
     long long launches;
     double total_ms;

@@ -622,9 +622,12 @@ __global__ __launch_bounds__(kThreads) void k_prolong_add(XferDev<T> X, int ncom
 // loads of a thread are independent and issue together (2D: the third axis
 // has width 1).  Windows are stored clamped inside the matrix, so the fixed
 // widths never read outside the vectors.
-template <typename T, int W0, int W1, int W2>
+// CHEB: also the first Chebyshev step of the coarse level from zero,
+// u = x = inv_theta D_c^{-1} rc, with D_c the diagonal of the coarse operator.
+template <typename T, int W0, int W1, int W2, bool CHEB>
 __global__ __launch_bounds__(kThreads) void k_restrict_w(XferDev<T> X, int ncomp, const T* __restrict__ rf,
-                                                         T* __restrict__ rc) {
+                                                         T* __restrict__ rc, OpDev<T> opc, T inv_theta,
+                                                         T* __restrict__ u, T* __restrict__ xo) {
     const XferAxisDev<T>& a0 = X.ax[0];
     const XferAxisDev<T>& a1 = X.ax[1];
     const XferAxisDev<T>& a2 = X.ax[2];
@@ -654,6 +657,11 @@ __global__ __launch_bounds__(kThreads) void k_restrict_w(XferDev<T> X, int ncomp
         }
     }
     rc[id] = acc;
+    if (CHEB) {
+        const T v = inv_theta * acc / diag_entry(opc, c, J0, J1, J2);
+        u[id] = v;
+        xo[id] = v;
+    }
 }
 
 template <typename T, int W0, int W1, int W2>
@@ -723,9 +731,9 @@ __host__ __device__ inline int padded_span(int span) { return (span + kRowGroup 
 //     store 0), keeping D^{-1} y in LDS;
 //  3. backward L^T z = D^{-1} y from the top of the padded span down to the
 //     chunk (zero padded rows keep the recurrence state at zero);
-//  4. the chunk's rows [r0, r1) are written out (ACC: added to out).
+//  4. the chunk's rows [r0, r1) are written out.
 // Out of place: in != out.
-template <typename T, int BW, bool ACC>
+template <typename T, int BW>
 __global__ __launch_bounds__(kLineThreads) void k_tsolve_line(const T* __restrict__ in, T* __restrict__ out,
                                                               LineGeom g, size_t lines_padded,
                                                               const T* __restrict__ L,
@@ -845,13 +853,7 @@ __global__ __launch_bounds__(kLineThreads) void k_tsolve_line(const T* __restric
         }
         // 4. output rows [r0, r1)
         T* dst = out + base;
-        for (int r = r0; r < r1; ++r) {
-            const T val = sp[(r - rs) * kLineThreads + lane];
-            if (ACC)
-                dst[size_t(r) * stride] += val;
-            else
-                dst[size_t(r) * stride] = val;
-        }
+        for (int r = r0; r < r1; ++r) dst[size_t(r) * stride] = sp[(r - rs) * kLineThreads + lane];
     }
     stamp_end(stamp);
 }
@@ -946,6 +948,36 @@ __global__ __launch_bounds__(kThreads) void k_cheb_first(OpDev<T> op, const T* _
         u[id] = v;
         x[id] = v;
     }
+}
+
+// y = x (converted) and the first Chebyshev step from zero on y.
+template <typename TO, typename TI>
+__global__ __launch_bounds__(kThreads) void k_cast_cheb(const TI* __restrict__ x, TO* __restrict__ y, size_t n,
+                                                        OpDev<TO> op, TO inv_theta, TO* __restrict__ u,
+                                                        TO* __restrict__ xo) {
+    for (size_t id = size_t(blockIdx.x) * kThreads + threadIdx.x; id < n; id += size_t(gridDim.x) * kThreads) {
+        const TO b = TO(x[id]);
+        y[id] = b;
+        int c, i0, i1, i2;
+        unflatten(op, id, c, i0, i1, i2);
+        const TO v = inv_theta * b / diag_entry(op, c, i0, i1, i2);
+        u[id] = v;
+        xo[id] = v;
+    }
+}
+
+// y = x (converted) and part[block] = partial sums of y . q (FP64).
+template <typename TO, typename TI>
+__global__ __launch_bounds__(kThreads) void k_cast_dot(const TI* __restrict__ x, TO* __restrict__ y, size_t n,
+                                                       const double* __restrict__ q, double* __restrict__ part) {
+    double acc = 0.0;
+    for (size_t i = size_t(blockIdx.x) * kThreads + threadIdx.x; i < n; i += size_t(gridDim.x) * kThreads) {
+        const TO v = TO(x[i]);
+        y[i] = v;
+        acc += double(v) * q[i];
+    }
+    const double tot = block_sum(acc);
+    if (threadIdx.x == 0) part[blockIdx.x] = tot;
 }
 
 // z = Kinv r, one block per row, FP64 accumulation
@@ -1084,12 +1116,12 @@ __global__ __launch_bounds__(kThreads) void k_normscale(const double* __restrict
 }
 
 template <typename T>
-__global__ __launch_bounds__(kThreads) void k_combine(const T* __restrict__ V, int k, const double* __restrict__ y,
-                                                      T* __restrict__ w, size_t n) {
+__global__ __launch_bounds__(kThreads) void k_combine_add(const T* __restrict__ V, int k,
+                                                          const double* __restrict__ y, T* __restrict__ w, size_t n) {
     for (size_t i = size_t(blockIdx.x) * kThreads + threadIdx.x; i < n; i += size_t(gridDim.x) * kThreads) {
         T acc = T(0);
         for (int j = 0; j < k; ++j) acc += T(y[j]) * V[size_t(j) * n + i];
-        w[i] = acc;
+        w[i] += acc;
     }
 }
 
@@ -1158,16 +1190,27 @@ void launch_apply(const OpDev<T>& op, int mode, const T* x, T* y, const T* b, T*
 // Fixed-width kernel when every real axis has the same window width w
 // (2D: <w, w, 1>, 3D: <w, w, w>); the generic kernel otherwise.
 template <typename T, bool Restrict, int W>
-bool launch_xfer_w(const XferDev<T>& X, int ncomp, const T* in, T* out, size_t n, hipStream_t s) {
+bool launch_xfer_w(const XferDev<T>& X, int ncomp, const T* in, T* out, size_t n, const ChebFirst<T>* cf,
+                   hipStream_t s) {
     const dim3 grid((n + kThreads - 1) / kThreads);
+    const ChebFirst<T> c0{};
+    const ChebFirst<T>& c = cf ? *cf : c0;
     if (X.dim == 2) {
-        if (Restrict)
-            hipLaunchKernelGGL((k_restrict_w<T, W, W, 1>), grid, dim3(kThreads), 0, s, X, ncomp, in, out);
+        if (Restrict && cf)
+            hipLaunchKernelGGL((k_restrict_w<T, W, W, 1, true>), grid, dim3(kThreads), 0, s, X, ncomp, in, out, c.op,
+                               c.inv_theta, c.u, c.x);
+        else if (Restrict)
+            hipLaunchKernelGGL((k_restrict_w<T, W, W, 1, false>), grid, dim3(kThreads), 0, s, X, ncomp, in, out, c.op,
+                               c.inv_theta, c.u, c.x);
         else
             hipLaunchKernelGGL((k_prolong_add_w<T, W, W, 1>), grid, dim3(kThreads), 0, s, X, ncomp, in, out);
     } else {
-        if (Restrict)
-            hipLaunchKernelGGL((k_restrict_w<T, W, W, W>), grid, dim3(kThreads), 0, s, X, ncomp, in, out);
+        if (Restrict && cf)
+            hipLaunchKernelGGL((k_restrict_w<T, W, W, W, true>), grid, dim3(kThreads), 0, s, X, ncomp, in, out, c.op,
+                               c.inv_theta, c.u, c.x);
+        else if (Restrict)
+            hipLaunchKernelGGL((k_restrict_w<T, W, W, W, false>), grid, dim3(kThreads), 0, s, X, ncomp, in, out, c.op,
+                               c.inv_theta, c.u, c.x);
         else
             hipLaunchKernelGGL((k_prolong_add_w<T, W, W, W>), grid, dim3(kThreads), 0, s, X, ncomp, in, out);
     }
@@ -1175,7 +1218,8 @@ bool launch_xfer_w(const XferDev<T>& X, int ncomp, const T* in, T* out, size_t n
 }
 
 template <typename T, bool Restrict>
-bool launch_xfer_fixed(const XferDev<T>& X, int ncomp, const T* in, T* out, size_t n, hipStream_t s) {
+bool launch_xfer_fixed(const XferDev<T>& X, int ncomp, const T* in, T* out, size_t n, const ChebFirst<T>* cf,
+                       hipStream_t s) {
     auto width = [&](int a) { return Restrict ? X.ax[a].wr : X.ax[a].w; };
     const int w = width(0);
     for (int a = 1; a < X.dim; ++a)
@@ -1183,65 +1227,61 @@ bool launch_xfer_fixed(const XferDev<T>& X, int ncomp, const T* in, T* out, size
     for (int a = X.dim; a < 3; ++a)
         if (width(a) != 1) return false;
     switch (w) {
-        case 2: return launch_xfer_w<T, Restrict, 2>(X, ncomp, in, out, n, s);
-        case 3: return launch_xfer_w<T, Restrict, 3>(X, ncomp, in, out, n, s);
-        case 4: return launch_xfer_w<T, Restrict, 4>(X, ncomp, in, out, n, s);
-        case 5: return launch_xfer_w<T, Restrict, 5>(X, ncomp, in, out, n, s);
-        case 6: return launch_xfer_w<T, Restrict, 6>(X, ncomp, in, out, n, s);
-        case 7: return launch_xfer_w<T, Restrict, 7>(X, ncomp, in, out, n, s);
-        case 8: return launch_xfer_w<T, Restrict, 8>(X, ncomp, in, out, n, s);
+        case 2: return launch_xfer_w<T, Restrict, 2>(X, ncomp, in, out, n, cf, s);
+        case 3: return launch_xfer_w<T, Restrict, 3>(X, ncomp, in, out, n, cf, s);
+        case 4: return launch_xfer_w<T, Restrict, 4>(X, ncomp, in, out, n, cf, s);
+        case 5: return launch_xfer_w<T, Restrict, 5>(X, ncomp, in, out, n, cf, s);
+        case 6: return launch_xfer_w<T, Restrict, 6>(X, ncomp, in, out, n, cf, s);
+        case 7: return launch_xfer_w<T, Restrict, 7>(X, ncomp, in, out, n, cf, s);
+        case 8: return launch_xfer_w<T, Restrict, 8>(X, ncomp, in, out, n, cf, s);
         default: return false;
     }
 }
 
 template <typename T>
-void launch_restrict(const XferDev<T>& X, int ncomp, const T* rf, T* rc, hipStream_t s) {
+void launch_restrict(const XferDev<T>& X, int ncomp, const T* rf, T* rc, hipStream_t s, const ChebFirst<T>* cf) {
     const size_t n = size_t(ncomp) * X.ax[0].mc * X.ax[1].mc * X.ax[2].mc;
-    if (!launch_xfer_fixed<T, true>(X, ncomp, rf, rc, n, s))
+    if (!launch_xfer_fixed<T, true>(X, ncomp, rf, rc, n, cf, s)) {
         hipLaunchKernelGGL(k_restrict<T>, dim3((n + kThreads - 1) / kThreads), dim3(kThreads), 0, s, X, ncomp, rf,
                            rc);
+        if (cf) launch_cheb_first<T>(cf->op, rc, cf->u, cf->x, cf->inv_theta, s);
+    }
     check_launch("restrict");
 }
 
 template <typename T>
 void launch_prolong_add(const XferDev<T>& X, int ncomp, const T* ec, T* xf, hipStream_t s) {
     const size_t n = size_t(ncomp) * X.ax[0].mf * X.ax[1].mf * X.ax[2].mf;
-    if (!launch_xfer_fixed<T, false>(X, ncomp, ec, xf, n, s))
+    if (!launch_xfer_fixed<T, false>(X, ncomp, ec, xf, n, nullptr, s))
         hipLaunchKernelGGL(k_prolong_add<T>, dim3((n + kThreads - 1) / kThreads), dim3(kThreads), 0, s, X, ncomp,
                            ec, xf);
     check_launch("prolong");
 }
 
 template <typename T, int BW>
-void tsolve_axis(const T* v, T* z, bool acc, const LineGeom& g, const TFacDev<T>& F, size_t lines_padded, size_t lds,
+void tsolve_axis(const T* v, T* z, const LineGeom& g, const TFacDev<T>& F, size_t lines_padded, size_t lds,
                  unsigned long long* stamp, hipStream_t s) {
     const size_t items = lines_padded * g.nchunk * size_t(g.ncomp);
     const dim3 grid(items / kLineThreads);
-    auto kern = acc ? k_tsolve_line<T, BW, true> : k_tsolve_line<T, BW, false>;
+    auto kern = k_tsolve_line<T, BW>;
     allow_lds(reinterpret_cast<const void*>(kern), lds);
     hipLaunchKernelGGL(kern, grid, dim3(kLineThreads), lds, s, v, z, g, lines_padded, F.l, F.dinv, F.warm, stamp);
 }
 
 template <typename T>
-void launch_tsolve(int dim, const int* m, const TFacDev<T>* fac, const T* v, T* tmp, T* z, hipStream_t s, T* acc,
+void launch_tsolve(int dim, const int* m, const TFacDev<T>* fac, const T* v, T* tmp, T* z, hipStream_t s,
                    unsigned long long* stamps) {
     if (v == z || v == tmp || tmp == z) throw std::runtime_error("tsolve needs three distinct buffers");
-    if (acc && (acc == v || acc == tmp || acc == z)) throw std::runtime_error("tsolve accumulator aliases a buffer");
     const int m0 = m[0], m1 = m[1], m2 = (dim == 3) ? m[2] : 1;
     const size_t G = size_t(m0) * m1 * m2;
     if (fac[0].bw == 0) {  // p = 1: T is the identity
-        if (acc)
-            launch_axpby<T>(T(1), v, T(1), acc, size_t(dim) * G, s);
-        else
-            launch_copy<T>(v, z, size_t(dim) * G, s);
+        launch_copy<T>(v, z, size_t(dim) * G, s);
         return;
     }
     const T* src = v;
     for (int a = 0; a < dim; ++a) {
         // alternate destinations so that the last pass lands in z
         T* dst = ((dim - 1 - a) % 2 == 0) ? z : tmp;
-        const bool last_acc = acc && (a == dim - 1);
-        if (last_acc) dst = acc;
         unsigned long long* st = stamps ? stamps + size_t(a) * kStampWords : nullptr;
         const TFacDev<T>& F = fac[a];
         LineGeom g;
@@ -1267,11 +1307,11 @@ void launch_tsolve(int dim, const int* m, const TFacDev<T>* fac, const T* v, T* 
         g.ncomp = dim;
         const size_t lp = (g.lines_per_comp + kLineThreads - 1) / kLineThreads * kLineThreads;
         switch (F.bw) {
-            case 1: tsolve_axis<T, 1>(src, dst, last_acc, g, F, lp, lds, st, s); break;
-            case 2: tsolve_axis<T, 2>(src, dst, last_acc, g, F, lp, lds, st, s); break;
-            case 3: tsolve_axis<T, 3>(src, dst, last_acc, g, F, lp, lds, st, s); break;
-            case 4: tsolve_axis<T, 4>(src, dst, last_acc, g, F, lp, lds, st, s); break;
-            case 5: tsolve_axis<T, 5>(src, dst, last_acc, g, F, lp, lds, st, s); break;
+            case 1: tsolve_axis<T, 1>(src, dst, g, F, lp, lds, st, s); break;
+            case 2: tsolve_axis<T, 2>(src, dst, g, F, lp, lds, st, s); break;
+            case 3: tsolve_axis<T, 3>(src, dst, g, F, lp, lds, st, s); break;
+            case 4: tsolve_axis<T, 4>(src, dst, g, F, lp, lds, st, s); break;
+            case 5: tsolve_axis<T, 5>(src, dst, g, F, lp, lds, st, s); break;
             default: throw std::runtime_error("degree out of range (1..6)");
         }
         check_launch("tsolve");
@@ -1288,6 +1328,19 @@ void launch_dot_partial(const TA* a, const TB* b, size_t n, double* part, hipStr
 void launch_finalize(const double* part, int np, double* out, hipStream_t s) {
     hipLaunchKernelGGL(k_finalize, dim3(1), dim3(kThreads), 0, s, part, np, out);
     check_launch("finalize");
+}
+
+template <typename TO, typename TI>
+void launch_cast_cheb(const TI* x, TO* y, size_t n, const ChebFirst<TO>& cf, hipStream_t s) {
+    hipLaunchKernelGGL((k_cast_cheb<TO, TI>), dim3(grid_for(n)), dim3(kThreads), 0, s, x, y, n, cf.op, cf.inv_theta,
+                       cf.u, cf.x);
+    check_launch("cast_cheb");
+}
+
+template <typename TO, typename TI>
+void launch_cast_dot(const TI* x, TO* y, size_t n, const double* q, double* part, hipStream_t s) {
+    hipLaunchKernelGGL((k_cast_dot<TO, TI>), dim3(reduce_blocks(n)), dim3(kThreads), 0, s, x, y, n, q, part);
+    check_launch("cast_dot");
 }
 
 template <typename TO, typename TI>
@@ -1402,9 +1455,9 @@ void launch_normscale(const double* pnorm, int np, double* out, bool square, con
 }
 
 template <typename T>
-void launch_combine(const T* V, int k, const double* y, T* w, size_t n, hipStream_t s) {
-    hipLaunchKernelGGL(k_combine<T>, dim3(grid_for(n)), dim3(kThreads), 0, s, V, k, y, w, n);
-    check_launch("combine");
+void launch_combine_add(const T* V, int k, const double* y, T* w, size_t n, hipStream_t s) {
+    hipLaunchKernelGGL(k_combine_add<T>, dim3(grid_for(n)), dim3(kThreads), 0, s, V, k, y, w, n);
+    check_launch("combine_add");
 }
 
 // ---- explicit instantiations ----
@@ -1412,9 +1465,9 @@ void launch_combine(const T* V, int k, const double* y, T* w, size_t n, hipStrea
     template int apply_blocks<T>(const OpDev<T>&);                                                                   \
     template void launch_apply<T>(const OpDev<T>&, int, const T*, T*, const T*, T*, T*, T, T, double*, hipStream_t,  \
                                   int, unsigned long long*);                                                         \
-    template void launch_restrict<T>(const XferDev<T>&, int, const T*, T*, hipStream_t);                             \
+    template void launch_restrict<T>(const XferDev<T>&, int, const T*, T*, hipStream_t, const ChebFirst<T>*);        \
     template void launch_prolong_add<T>(const XferDev<T>&, int, const T*, T*, hipStream_t);                          \
-    template void launch_tsolve<T>(int, const int*, const TFacDev<T>*, const T*, T*, T*, hipStream_t, T*,            \
+    template void launch_tsolve<T>(int, const int*, const TFacDev<T>*, const T*, T*, T*, hipStream_t,                \
                                    unsigned long long*);                            \
     template void launch_fill<T>(T*, T, size_t, hipStream_t);                                                        \
     template void launch_copy<T>(const T*, T*, size_t, hipStream_t);                                                 \
@@ -1424,7 +1477,7 @@ void launch_combine(const T* V, int k, const double* y, T* w, size_t n, hipStrea
     template void launch_diag_dot<T>(const OpDev<T>&, const T*, double*, hipStream_t);                               \
     template void launch_cheb_first<T>(const OpDev<T>&, const T*, T*, T*, T, hipStream_t);                           \
     template void launch_coarse_gemv<T>(const double*, int, int, const T*, T*, hipStream_t);                              \
-    template void launch_combine<T>(const T*, int, const double*, T*, size_t, hipStream_t);                          \
+    template void launch_combine_add<T>(const T*, int, const double*, T*, size_t, hipStream_t);                          \
     template void launch_gs_update<T>(const double*, int, int, double*, const T*, T*, size_t, double*, hipStream_t); \
     template void launch_normscale<T>(const double*, int, double*, bool, const T*, T*, size_t, hipStream_t);
 
@@ -1435,5 +1488,10 @@ template void launch_dot_partial<double, double>(const double*, const double*, s
 template void launch_dot_partial<float, float>(const float*, const float*, size_t, double*, hipStream_t);
 template void launch_cast<float, double>(const double*, float*, size_t, hipStream_t);
 template void launch_cast<double, float>(const float*, double*, size_t, hipStream_t);
+template void launch_cast_cheb<float, double>(const double*, float*, size_t, const ChebFirst<float>&, hipStream_t);
+template void launch_cast_cheb<double, double>(const double*, double*, size_t, const ChebFirst<double>&,
+                                               hipStream_t);
+template void launch_cast_dot<double, float>(const float*, double*, size_t, const double*, double*, hipStream_t);
+template void launch_cast_dot<double, double>(const double*, double*, size_t, const double*, double*, hipStream_t);
 
 }  // namespace cd

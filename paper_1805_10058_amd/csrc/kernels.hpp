@@ -73,18 +73,27 @@ void launch_apply(const OpDev<T>& op, int mode, const T* x, T* y, const T* b, T*
 // nslots); clears those slots for reuse.
 void launch_stamp_reduce(unsigned long long* st, int slot0, int nslots, unsigned long long* pairs, hipStream_t s);
 
+// First Chebyshev step from zero on a level: u = x = inv_theta D^{-1} b.
 template <typename T>
-void launch_restrict(const XferDev<T>& X, int ncomp, const T* rf, T* rc, hipStream_t s);
+struct ChebFirst {
+    OpDev<T> op;
+    T inv_theta;
+    T* u;
+    T* x;
+};
+
+// rc = P^T rf; with cf also the first Chebyshev step of the coarse level on rc.
+template <typename T>
+void launch_restrict(const XferDev<T>& X, int ncomp, const T* rf, T* rc, hipStream_t s,
+                     const ChebFirst<T>* cf = nullptr);
 template <typename T>
 void launch_prolong_add(const XferDev<T>& X, int ncomp, const T* ec, T* xf, hipStream_t s);
 
 // z = T^{-1} v, T = I_d (x) T_1 (x) ... (x) T_d; v, tmp, z distinct, tmp: n
-// scratch.  With acc != nullptr the result is added to acc instead
-// (acc += T^{-1} v) and z is used as scratch.  stamps: nullptr or dim
-// consecutive timing slots, one per axis pass.
+// scratch.  stamps: nullptr or dim consecutive timing slots, one per axis pass.
 template <typename T>
 void launch_tsolve(int dim, const int* m, const TFacDev<T>* fac, const T* v, T* tmp, T* z, hipStream_t s,
-                   T* acc = nullptr, unsigned long long* stamps = nullptr);
+                   unsigned long long* stamps = nullptr);
 
 // ---- vector kernels ---------------------------------------------------------
 template <typename TA, typename TB>
@@ -93,6 +102,12 @@ void launch_dot_partial(const TA* a, const TB* b, size_t n, double* part, hipStr
 void launch_finalize(const double* part, int np, double* out, hipStream_t s);
 template <typename TO, typename TI>
 void launch_cast(const TI* x, TO* y, size_t n, hipStream_t s);
+// y = x converted, then the first Chebyshev step on y (cf.op is y's level)
+template <typename TO, typename TI>
+void launch_cast_cheb(const TI* x, TO* y, size_t n, const ChebFirst<TO>& cf, hipStream_t s);
+// y = x converted; part[block] = partial sums of y . q, reduce_blocks(n) of them
+template <typename TO, typename TI>
+void launch_cast_dot(const TI* x, TO* y, size_t n, const double* q, double* part, hipStream_t s);
 template <typename T>
 void launch_fill(T* x, T v, size_t n, hipStream_t s);
 template <typename T>
@@ -145,8 +160,8 @@ void launch_normscale(const double* pnorm, int np, double* out, bool square, con
 // (stored into H as well).
 void launch_hessenberg_ls(double* H, int ld, int k, const double* beta0sq, double* y, const double* plast,
                           int nlast, hipStream_t s);
-// w = sum_j y[j] V_j
+// w += sum_j y[j] V_j
 template <typename T>
-void launch_combine(const T* V, int k, const double* y, T* w, size_t n, hipStream_t s);
+void launch_combine_add(const T* V, int k, const double* y, T* w, size_t n, hipStream_t s);
 
 }  // namespace cd

@@ -108,6 +108,7 @@ struct VWork {
     };
     std::vector<L> lv;
     T* V = nullptr;  // finest GMRES basis, (s+1) x N
+    T* Z = nullptr;  // T^{-1} V_j, s x N
     T* w = nullptr;
     T* z = nullptr;
     T* io_in = nullptr;   // precision-converted input (mixed mode)
@@ -384,6 +385,7 @@ std::unique_ptr<VWork<T>> make_work(cd_solver* s, DevArena& ar) {
     }
     const int ks = std::max(s->ksteps, 1);
     w->V = ar.alloc<T>(size_t(ks + 1) * s->N);
+    w->Z = ar.alloc<T>(size_t(ks) * s->N);
     w->w = ar.alloc<T>(s->N);
     w->z = ar.alloc<T>(s->N);
     w->io_in = ar.alloc<T>(s->N);
@@ -497,22 +499,19 @@ void apply_op(cd_solver* s, int level, int mode, const T* x, T* y, const T* b, T
     if (own) prof_unit_end(s);
 }
 
-// z = T^{-1} v (acc == nullptr) or acc += T^{-1} v on the finest level.
+// z = T^{-1} v on the finest level.
 template <typename T>
-void tsolve_op(cd_solver* s, const T* v, T* tmp, T* z, T* acc = nullptr) {
+void tsolve_op(cd_solver* s, const T* v, T* tmp, T* z) {
     const int d = s->d;
     if (!timing(s) || s->tf[0].bw == 0) {
-        cd::launch_tsolve<T>(d, s->lv[0].m, tfacs<T>(s), v, tmp, z, s->stream, acc);
+        cd::launch_tsolve<T>(d, s->lv[0].m, tfacs<T>(s), v, tmp, z, s->stream);
         return;
     }
     const bool own = !s->unit_open;
     if (own) prof_unit_begin(s);
-    const int cls = prof_class(s, 1, 0, sizeof(T) == 4);
-    const double pass = 2.0 * double(s->N) * sizeof(T);  // read the input, write the output
-    unsigned long long* st = prof_slots(s, d - 1, cls, pass);
-    unsigned long long* last = prof_slots(s, 1, cls, acc ? pass + double(s->N) * sizeof(T) : pass);
-    if (d == 1) st = last;
-    cd::launch_tsolve<T>(d, s->lv[0].m, tfacs<T>(s), v, tmp, z, s->stream, acc, st);
+    // one pass per axis, each reads its input and writes its output once
+    unsigned long long* st = prof_slots(s, d, prof_class(s, 1, 0, sizeof(T) == 4), 2.0 * double(s->N) * sizeof(T));
+    cd::launch_tsolve<T>(d, s->lv[0].m, tfacs<T>(s), v, tmp, z, s->stream, st);
     if (own) prof_unit_end(s);
 }
 
@@ -523,7 +522,7 @@ void tsolve_op(cd_solver* s, const T* v, T* tmp, T* z, T* acc = nullptr) {
 // (first step without an operator apply), else from *x; the result pointer
 // is returned (one of the level's two iterate buffers).
 template <typename T>
-T* chebyshev(cd_solver* s, int l, const T* b, T* x, T* other, T* u, bool from_zero) {
+T* chebyshev(cd_solver* s, int l, const T* b, T* x, T* other, T* u, bool from_zero, bool first_done = false) {
     const LevelHost& L = s->lv[l];
     const cd::OpDev<T>& op = devlevels<T>(s)[l].op;
     const double theta = 0.5 * (L.hi + L.lo), delta = 0.5 * (L.hi - L.lo);
@@ -533,7 +532,8 @@ T* chebyshev(cd_solver* s, int l, const T* b, T* x, T* other, T* u, bool from_ze
     T* cur = x;
     T* nxt = other;
     if (from_zero) {
-        cd::launch_cheb_first<T>(op, b, u, cur, T(1.0 / theta), s->stream);
+        // first_done: the producer of b already wrote x = u = D^{-1} b / theta
+        if (!first_done) cd::launch_cheb_first<T>(op, b, u, cur, T(1.0 / theta), s->stream);
     } else {
         apply_op<T>(s, l, kApplyCheb, cur, nullptr, b, u, nxt, T(0), T(1.0 / theta), nullptr);
         std::swap(cur, nxt);
@@ -545,6 +545,14 @@ T* chebyshev(cd_solver* s, int l, const T* b, T* x, T* other, T* u, bool from_ze
         rho = rn;
     }
     return cur;
+}
+
+// The first Chebyshev step from zero on level l, to be fused into the kernel
+// that produces the level's right-hand side; result in the level's xa and u.
+template <typename T>
+cd::ChebFirst<T> cheb_first_of(cd_solver* s, VWork<T>& W, int l) {
+    const LevelHost& L = s->lv[l];
+    return cd::ChebFirst<T>{devlevels<T>(s)[l].op, T(1.0 / (0.5 * (L.hi + L.lo))), W.lv[l].u, W.lv[l].xa};
 }
 
 // p steps of GMRES on A_0 e = b - A_0 x from e = 0, right preconditioner T
@@ -560,23 +568,24 @@ void gmres_post(cd_solver* s, VWork<T>& W, const T* b, T* x) {
     cd::launch_normscale<T>(W.pnorm, nba, W.scal, true, W.w, V, N, st);
     for (int j = 0; j < ks; ++j) {
         double* Hcol = W.H + size_t(j) * ld;
-        tsolve_op<T>(s, V + size_t(j) * N, W.tmp, W.z);
+        T* Zj = W.Z + size_t(j) * N;
+        tsolve_op<T>(s, V + size_t(j) * N, W.tmp, Zj);
         // w = A T^{-1} V_j together with the dots V_i . w, i <= j
-        apply_op<T>(s, 0, cd::kApplyYMulti, W.z, W.w, V, nullptr, nullptr, T(0), T(0), W.pdot, j + 1);
+        apply_op<T>(s, 0, cd::kApplyYMulti, Zj, W.w, V, nullptr, nullptr, T(0), T(0), W.pdot, j + 1);
         // H(0..j, j) = those dots; w -= sum_i H(i, j) V_i; partial sums of w.w
         cd::launch_gs_update<T>(W.pdot, j + 1, nba, Hcol, V, W.w, N, W.pnorm, st);
         // H(j+1, j) = ||w||, V_{j+1} = w / ||w|| (the last norm is taken by the least squares)
         if (j + 1 < ks) cd::launch_normscale<T>(W.pnorm, nb, Hcol + (j + 1), false, W.w, V + size_t(j + 1) * N, N, st);
     }
     cd::launch_hessenberg_ls(W.H, ld, ks, W.scal, W.y, W.pnorm, nb, st);
-    cd::launch_combine<T>(V, ks, W.y, W.w, N, st);
-    // x += T^{-1} (V y)
-    tsolve_op<T>(s, W.w, W.tmp, W.z, x);
+    // x += T^{-1} (V y) = sum_j y_j T^{-1} V_j  (T is linear)
+    cd::launch_combine_add<T>(W.Z, ks, W.y, x, N, st);
 }
 
 // One V-cycle on level l for A_l x = W.lv[l].b; result in W.lv[l].xcur.
+// first_done: the first pre-smoothing step was fused into the producer of b.
 template <typename T>
-void vcycle(cd_solver* s, VWork<T>& W, int l) {
+void vcycle(cd_solver* s, VWork<T>& W, int l, bool first_done = false) {
     const int L = int(s->lv.size());
     auto& Wl = W.lv[l];
     hipStream_t st = s->stream;
@@ -586,11 +595,13 @@ void vcycle(cd_solver* s, VWork<T>& W, int l) {
         return;
     }
     const auto& D = devlevels<T>(s)[l];
-    T* x = chebyshev<T>(s, l, Wl.b, Wl.xa, Wl.xb, Wl.u, true);
+    T* x = chebyshev<T>(s, l, Wl.b, Wl.xa, Wl.xb, Wl.u, true, first_done);
     T* other = (x == Wl.xa) ? Wl.xb : Wl.xa;
     apply_op<T>(s, l, kApplyRes, x, Wl.r, Wl.b, nullptr, nullptr, T(0), T(0), nullptr);
-    cd::launch_restrict<T>(D.xf, s->d, Wl.r, W.lv[l + 1].b, st);
-    vcycle<T>(s, W, l + 1);
+    const bool fuse = (l + 1 < L - 1);  // the next level smooths (it is not the coarsest)
+    const cd::ChebFirst<T> cf = fuse ? cheb_first_of<T>(s, W, l + 1) : cd::ChebFirst<T>{};
+    cd::launch_restrict<T>(D.xf, s->d, Wl.r, W.lv[l + 1].b, st, fuse ? &cf : nullptr);
+    vcycle<T>(s, W, l + 1, fuse);
     cd::launch_prolong_add<T>(D.xf, s->d, W.lv[l + 1].xcur, x, st);
     if (l == 0 && s->ksteps > 0) {
         gmres_post<T>(s, W, Wl.b, x);
@@ -609,18 +620,32 @@ VWork<double>& work64(cd_solver* s) {
 }
 
 // z = V(r) in the handle's precision; r, z FP64 device vectors.
-void precondition(cd_solver* s, const double* r, double* z) {
+// With q != nullptr also part[block] = partial sums of z . q (reduce_blocks(N)).
+void precondition(cd_solver* s, const double* r, double* z, const double* q = nullptr, double* part = nullptr) {
     hipStream_t st = s->stream;
+    const bool fuse = s->lv.size() > 1;  // level 0 smooths: its first step is fused into the input conversion
     if (s->opt.precision == CD_FP64) {
         VWork<double>& W = work64(s);
-        cd::launch_copy<double>(r, W.lv[0].b, s->N, st);
-        vcycle<double>(s, W, 0);
-        cd::launch_copy<double>(W.lv[0].xcur, z, s->N, st);
+        if (fuse)
+            cd::launch_cast_cheb<double, double>(r, W.lv[0].b, s->N, cheb_first_of<double>(s, W, 0), st);
+        else
+            cd::launch_copy<double>(r, W.lv[0].b, s->N, st);
+        vcycle<double>(s, W, 0, fuse);
+        if (q)
+            cd::launch_cast_dot<double, double>(W.lv[0].xcur, z, s->N, q, part, st);
+        else
+            cd::launch_copy<double>(W.lv[0].xcur, z, s->N, st);
     } else {
         VWork<float>& W = *s->w32;
-        cd::launch_cast<float, double>(r, W.lv[0].b, s->N, st);
-        vcycle<float>(s, W, 0);
-        cd::launch_cast<double, float>(W.lv[0].xcur, z, s->N, st);
+        if (fuse)
+            cd::launch_cast_cheb<float, double>(r, W.lv[0].b, s->N, cheb_first_of<float>(s, W, 0), st);
+        else
+            cd::launch_cast<float, double>(r, W.lv[0].b, s->N, st);
+        vcycle<float>(s, W, 0, fuse);
+        if (q)
+            cd::launch_cast_dot<double, float>(W.lv[0].xcur, z, s->N, q, part, st);
+        else
+            cd::launch_cast<double, float>(W.lv[0].xcur, z, s->N, st);
     }
 }
 
@@ -794,12 +819,15 @@ void solve_begin(cd_solver* s, const double* b, double* x) {
 void enqueue_iteration(cd_solver* s, bool first) {
     hipStream_t st = s->stream;
     const size_t N = s->N;
+    // z = B r, with the partial sums of z . q for the direction update fused in
     if (s->opt.method == CD_METHOD_CG) {
-        cd::launch_copy<double>(s->r, s->z, N, st);
+        if (first)
+            cd::launch_copy<double>(s->r, s->z, N, st);
+        else
+            cd::launch_cast_dot<double, double>(s->r, s->z, N, s->q, s->pzq, st);
     } else {
-        precondition(s, s->r, s->z);
+        precondition(s, s->r, s->z, first ? nullptr : s->q, s->pzq);
     }
-    if (!first) cd::launch_dot_partial<double, double>(s->z, s->q, N, s->pzq, st);
     cd::launch_fcg_direction(first, s->z, s->pzq, s->nbr, s->scal + 1, s->dd, s->r, s->pdr, N, st);
     apply_op<double>(s, 0, kApplyYDot, s->dd, s->q, nullptr, nullptr, nullptr, 0.0, 0.0, s->pdq);
     cd::launch_fcg_update(s->pdr, s->nbr, s->pdq, s->nba, s->scal + 1, s->xw, s->r, s->dd, s->q, s->prr, N, st);
