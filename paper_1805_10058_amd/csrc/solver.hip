@@ -1011,8 +1011,9 @@ size_t cd_footprint_bytes(const cd_problem* pr, const cd_options* op) {
         const size_t es = (op->precision == CD_FP64) ? 8 : 4;
         size_t vw = 0;
         for (size_t l = 0; l < tmp.lv.size(); ++l) vw += tmp.lv[l].N * ((l + 1 < tmp.lv.size()) ? 5 : 2);
-        vw += N * (size_t(std::max(tmp.ksteps, 1)) + 4);
-        total = 4 * N * 8                                   // outer r, z, d, q
+        const size_t ks = size_t(std::max(tmp.ksteps, 1));
+        vw += N * (2 * ks + 5);                             // V (ks+1), Z (ks), w, z, io_in, tmp
+        total = 5 * N * 8                                   // outer r, z, d, q, iterate
                 + (op->method == CD_METHOD_PMIM ? vw * es : 0)  // V-cycle workspace
                 + size_t(cd::coarse_padded(tmp.Nc)) * cd::coarse_padded(tmp.Nc) * 8  // coarse inverse
                 + (1 << 20);                                 // 1D tables and partial sums
