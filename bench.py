@@ -43,7 +43,7 @@ def cpu_baseline(cfg, its_gpu):
     times = []
     with threadpool_limits(limits=1):
         for beta in betas:
-            meth = method.Method(d, p, n, alpha, beta, coarse_max_dofs=1000)
+            meth = method.Method(d, p, n, alpha, beta, coarse_max_dofs=2500)
             b = ci.rhs(d, p, n, 0, dist)
             cap = 12 if beta < 1e-2 else 10000
             t0 = time.perf_counter()
@@ -65,7 +65,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-c4", action="store_true", help="skip the 3D p=3 n=128 operator-apply measurement")
     ap.add_argument("--only-c4", action="store_true", help="run only the 3D p=3 n=128 operator-apply measurement")
-    ap.add_argument("--serve", type=int, default=16, help="requests of the serving stream to run (0: skip)")
+    ap.add_argument("--serve", type=int, default=32, help="requests of the serving stream to run (0: skip)")
+    ap.add_argument("--serve-rate", type=float, default=8.0, help="Poisson arrival rate of the stream, 1/s (0: burst)")
     ap.add_argument("--serve-max-iter", type=int, default=4000)
     ap.add_argument("--copy-cal", action="store_true",
                     help="also run a plain 256 MiB device copy 5 times (calibrates HBM byte counters)")
@@ -217,7 +218,7 @@ def main():
         log(f"3D p=3 n=128 operator apply: {out['operator_apply_c4']}")
 
     if args.serve > 0:
-        out["serving"] = serve_bench(capi, torch, st, args.serve, args.serve_max_iter, log)
+        out["serving"] = serve_bench(capi, torch, st, args.serve, args.serve_max_iter, log, args.serve_rate)
         log(f"serving: {out['serving']}")
 
     if not args.no_cpu_baseline:
@@ -226,51 +227,62 @@ def main():
     print(json.dumps(out), flush=True)
 
 
-def serve_bench(capi, torch, st, count, max_iter, log):
+def serve_bench(capi, torch, st, count, max_iter, log, rate):
     """The serving workload: `count` seeded requests of the stream (2D/3D,
-    p in {2,3,4}, n log-uniform, beta log-uniform in [1e-6, 1]) submitted at
-    once to the mixed-precision server; then the same requests solved one
-    after another by the plain FP64 single-solve path.  Both include solver
-    setup; right-hand sides are resident in HBM before timing starts."""
+    p in {2,3,4}, n log-uniform, beta log-uniform in [1e-6, 1]) arriving as a
+    Poisson process of `rate` requests per second (0: all at t = 0), served
+    by the continuous-batching mixed-precision server; then the same arrival
+    schedule served one request at a time by the plain FP64 single-solve
+    path.  Latency = completion - arrival; both include solver setup; the
+    right-hand sides are resident in HBM before timing starts."""
     import curldiv_inputs as ci
 
-    reqs = ci.serving_stream(count, seed=7)
+    reqs = ci.serving_stream(count, seed=7, rate=rate if rate > 0 else None)
     data = []
     for r in reqs:
         prob = capi.problem(r["dim"], r["p"], r["n"], r["alpha"], r["beta"])
         b = torch.as_tensor(ci.rhs(r["dim"], r["p"], r["n"], r["seed"])).cuda()
-        data.append((prob, b, torch.zeros_like(b), torch.zeros_like(b)))
+        data.append((prob, b, torch.zeros_like(b), torch.zeros_like(b), r["arrival"]))
     torch.cuda.synchronize()
     srv = capi.Server(max_active=32)
+    opt = capi.options(precision=capi.CD_MIXED_FP32, rtol=1e-8, max_iter=max_iter)
+    ticket, done, arrival_of = {}, {}, {}
+    nxt = 0
     t0 = time.perf_counter()
-    ticket = {}
-    for i, (prob, b, x, _) in enumerate(data):
-        opt = capi.options(precision=capi.CD_MIXED_FP32, rtol=1e-8, max_iter=max_iter)
-        ticket[srv.submit(prob, opt, b.data_ptr(), x.data_ptr())] = i
-    done = {}
-    while True:
+    while len(done) < count:
+        now = time.perf_counter() - t0
+        while nxt < count and data[nxt][4] <= now:
+            prob, b, x, _, arr = data[nxt]
+            tk = srv.submit(prob, opt, b.data_ptr(), x.data_ptr())
+            ticket[tk] = nxt
+            arrival_of[nxt] = arr
+            nxt += 1
         a, q = srv.step()
         for c in srv.poll():
-            done[ticket[c.ticket]] = c
-        if a == 0 and q == 0:
-            break
+            done[ticket[c.ticket]] = (c, time.perf_counter() - t0)
+        if a == 0 and q == 0 and nxt < count:
+            time.sleep(max(0.0, data[nxt][4] - (time.perf_counter() - t0)))
     T = time.perf_counter() - t0
     srv.close()
-    lat = [c.t_done - c.t_submit for c in done.values()]
-    ok = sum(1 for c in done.values() if c.result.status == capi.CD_OK)
-    its = [c.result.iterations for c in done.values()]
+    lat = [t_done - arrival_of[i] for i, (c, t_done) in done.items()]
+    ok = sum(1 for c, _ in done.values() if c.result.status == capi.CD_OK)
+    its = [c.result.iterations for c, _ in done.values()]
     log(f"server done in {T:.2f}s; converged {ok}/{count}")
-    t1 = time.perf_counter()
     ok64, lat64 = 0, []
-    for prob, b, _, x in data:
-        ts = time.perf_counter()
+    t1 = time.perf_counter()
+    for prob, b, _, x, arr in data:
+        wait = arr - (time.perf_counter() - t1)
+        if wait > 0:
+            time.sleep(wait)
         s = capi.Solver(prob, capi.options(rtol=1e-8, max_iter=max_iter), st)
         r = s.solve(b.data_ptr(), x.data_ptr())
         s.close()
-        lat64.append(time.perf_counter() - ts)
+        lat64.append(time.perf_counter() - t1 - arr)
         ok64 += int(r.status == capi.CD_OK)
     T64 = time.perf_counter() - t1
-    return {"requests": count, "mode": "burst (all submitted at t=0), mixed FP32/FP64, max 32 in flight",
+    mode = (f"Poisson arrivals at {rate:g}/s" if rate > 0 else "burst (all arrive at t=0)") + \
+        ", continuous batching, mixed FP32/FP64, max 32 in flight"
+    return {"requests": count, "mode": mode,
             "solves_per_s": count / T, "converged": ok, "p50_ms": 1e3 * percentile(lat, 50),
             "p99_ms": 1e3 * percentile(lat, 99), "iterations_min_max": [min(its), max(its)],
             "max_iter": max_iter,

@@ -100,13 +100,14 @@ __host__ __device__ constexpr int k3T3(int hb) { return k3E3 - 2 * hb; }
 constexpr int kXcds = 8;
 
 // Launch geometry of the 3D operator kernel: tiles of the (x2, x3) plane times
-// ranges of x1 planes, about two resident blocks per compute unit.
+// ranges of x1 planes, about as many blocks as fit on the device at once (two
+// per compute unit in FP64, four in FP32, set by the register footprint).
 struct Apply3dGeom {
     int nt2, nt3, c1len, nblocks;
 };
 
-Apply3dGeom apply3d_geom(const int* m, int hb) {
-    constexpr int kTargetBlocks = 512;
+Apply3dGeom apply3d_geom(const int* m, int hb, size_t elem) {
+    const int kTargetBlocks = elem == 4 ? 1024 : 512;
     Apply3dGeom g;
     g.nt2 = (m[1] + k3T2 - 1) / k3T2;
     g.nt3 = (m[2] + k3T3(hb) - 1) / k3T3(hb);
@@ -178,26 +179,34 @@ __device__ inline void apply_write_dots(const double* dots, int nv, double* __re
 //
 // A block owns an output tile of k3T2 x (32 - 2HB) columns of the (x2, x3)
 // plane (one per thread; the other threads only help with loads and stage A)
-// and the output planes x1 in [o0, o1); it marches over the
-// input planes j in [o0-HB, o1+HB).  For every input plane:
+// and the output planes x1 in [o0, o1); it marches over the input planes
+// t = 0, 1, ... (x1 = o0 - HB + t) up to o1 + HB.  Per input plane:
 //   (A) contract axis 2 (stride m3): M2 x, A2 x, S2 x of the three components
-//       at the tile rows and all k3T3 + 2HB tile columns (LDS tile of the
-//       plane with a +-HB halo on both in-plane axes);
+//       at one position per thread: the tile rows times all 32 tile columns
+//       (LDS tile of the plane with a +-HB halo on both in-plane axes);
 //   (B) contract axis 3 at the thread's column and combine the raw products
 //       with alpha, beta, alpha-beta into W[c][{S,M,A}], the inputs of the
 //       axis-1 contraction of output component c;
 //   (C) scatter W into a ring of 2HB+1 per-plane accumulators in registers:
 //       acc(i) += X1(i, j) W for i in [j-HB, j+HB].
 // After plane j the accumulator of output plane j-HB is complete and goes
-// through the epilogue.  The loads of plane j+2 are issued while plane j is
-// computed (registers), and stored to LDS once stage A of plane j+1 is done.
-// 33 band contractions per point.
+// through the epilogue.  33 band contractions per point.
+//
+// Software pipeline, one barrier per plane: phase t runs stage A of plane
+// t+1 and stage B of plane t (independent work for the scheduler), stores the
+// prefetched plane t+2 into the input buffer plane t has vacated, and issues
+// the loads of plane t+3.  Input tiles and stage-A results are double
+// buffered in LDS.
 //
 // Tiles are numbered with x2 fastest, then x3, then the x1 range, and block b
 // takes tile (b mod 8) * ceil-share + b / 8: consecutive blocks land on
 // different XCDs, so this keeps spatially adjacent tiles, whose halos overlap,
 // on the same XCD and its L2.
 // ------------------------------------------------------------------------------
+template <typename T, int HB>
+constexpr size_t apply3d_lds_words() {
+    return 2 * 3 * size_t(k3T2 + 2 * HB) * k3E3 + 2 * 9 * size_t(k3T2) * k3E3 + 3 * size_t(2 * HB + 1) * k3T2;
+}
 
 template <typename T, int HB, int MODE>
 __global__ __launch_bounds__(kThreads) void k_apply3d(OpDev<T> op, const T* __restrict__ x, T* __restrict__ y,
@@ -211,11 +220,11 @@ __global__ __launch_bounds__(kThreads) void k_apply3d(OpDev<T> op, const T* __re
     constexpr int NIN = E2 * E3;  // input tile per component and plane
     constexpr int NLD = (3 * NIN + kThreads - 1) / kThreads;
     constexpr int NA = k3T2 * E3;  // stage-A positions
-    constexpr int NPA = (NA + kThreads - 1) / kThreads;
     static_assert(NA == kThreads, "one stage-A position per thread");
-    __shared__ T xs[3 * NIN];
-    __shared__ T st[9 * NA];          // M2x A2x S2x of components 0, 1, 2, each [k3T2][E3]
-    __shared__ T ca[3 * R * k3T2];    // axis-2 band rows of the tile: [w][k][row]
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    T* xs = reinterpret_cast<T*>(smem_raw);  // [2][3][E2][E3] input tiles
+    T* st = xs + 2 * 3 * NIN;                // [2][9][k3T2][E3]: M2x A2x S2x of components 0, 1, 2
+    T* ca = st + 2 * 9 * NA;                 // [3][R][k3T2] axis-2 band rows of the tile
     const int m1 = op.m[0], m2 = op.m[1], m3 = op.m[2];
     const size_t PL = size_t(m2) * m3, G = size_t(m1) * PL;
     const int xcd = int(blockIdx.x % kXcds), slot = int(blockIdx.x / kXcds);
@@ -230,6 +239,8 @@ __global__ __launch_bounds__(kThreads) void k_apply3d(OpDev<T> op, const T* __re
         const int i = e % k3T2, k = (e / k3T2) % R, w = e / (k3T2 * R);
         ca[e] = op.band[1][w][k * m2 + min(o2 + i, m2 - 1)];  // rows past the grid feed unused outputs
     }
+    // stage-A position of this thread
+    const int ai = tid / E3, aq = tid % E3;
     // output column of this thread and its axis-3 band row
     const int ty = tid / E3, tx = tid % E3;
     const int i2 = o2 + ty, i3 = o3 + tx;
@@ -248,30 +259,74 @@ __global__ __launch_bounds__(kThreads) void k_apply3d(OpDev<T> op, const T* __re
 #pragma unroll
     for (int i = 0; i < apply_ndots<MODE>(); ++i) dots[i] = 0.0;
     const T al = op.alpha, be = op.beta, ab = op.alpha - op.beta;
+    const T* __restrict__ colM = op.col0[0];
+    const T* __restrict__ colA = op.col0[1];
+    const T* __restrict__ colS = op.col0[2];
 
+    // the thread's loads of the input tile: offsets within a plane of the
+    // component stack (the same for every plane), -1 outside the grid
+    long long loff[NLD];
+#pragma unroll
+    for (int q = 0; q < NLD; ++q) {
+        const int e = min(tid + q * kThreads, 3 * NIN - 1);
+        const int c = e / NIN, rr = e % NIN;
+        const int g2 = o2 - HB + rr / E3, g3 = o3 - HB + rr % E3;
+        const bool in = g2 >= 0 && g2 < m2 && g3 >= 0 && g3 < m3;
+        loff[q] = in ? (long long)(size_t(c) * G + size_t(g2) * m3 + g3) : -1;
+    }
     T v[NLD];
-    auto load_plane = [&](int j) {
+    auto load_plane = [&](int t) {
+        const int j = o0 - HB + t;
+        const bool jin = (j >= 0 && j < m1);  // block-uniform
+        const size_t jo = size_t(jin ? j : 0) * PL;
 #pragma unroll
         for (int q = 0; q < NLD; ++q) {
-            const int e = min(tid + q * kThreads, 3 * NIN - 1);
-            const int c = e / NIN, rr = e % NIN;
-            const int g2 = o2 - HB + rr / E3, g3 = o3 - HB + rr % E3;
-            const bool in = j >= 0 && j < m1 && g2 >= 0 && g2 < m2 && g3 >= 0 && g3 < m3;
-            const T val = x[size_t(c) * G + (in ? size_t(j) * PL + size_t(g2) * m3 + g3 : 0)];
+            const bool in = jin && loff[q] >= 0;
+            const T val = x[in ? jo + size_t(loff[q]) : 0];
             v[q] = in ? val : T(0);
         }
     };
-    auto store_plane = [&]() {
+    auto store_plane = [&](int t) {
+        T* dst = xs + (t & 1) * 3 * NIN;
 #pragma unroll
         for (int q = 0; q < NLD; ++q) {
             const int e = tid + q * kThreads;
-            if (e < 3 * NIN) xs[e] = v[q];
+            if (e < 3 * NIN) dst[e] = v[q];
         }
     };
-    const int TI = (o1 - o0) + 2 * HB;
-    load_plane(o0 - HB);
-    store_plane();
-    if (TI > 1) load_plane(o0 - HB + 1);
+    auto live = [&](int t) {
+        const int j = o0 - HB + t;
+        return j >= 0 && j < m1;
+    };
+    auto stage_a = [&](int t) {
+        const T* src = xs + (t & 1) * 3 * NIN;
+        T* dst = st + (t & 1) * 9 * NA;
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            T aM = T(0), aA = T(0), aS = T(0);
+#pragma unroll
+            for (int k = 0; k < R; ++k) {
+                const T xv = src[c * NIN + (ai + k) * E3 + aq];
+                aM += ca[(0 * R + k) * k3T2 + ai] * xv;
+                aA += ca[(1 * R + k) * k3T2 + ai] * xv;
+                aS += ca[(2 * R + k) * k3T2 + ai] * xv;
+            }
+            dst[(3 * c + 0) * NA + tid] = aM;
+            dst[(3 * c + 1) * NA + tid] = aA;
+            dst[(3 * c + 2) * NA + tid] = aS;
+        }
+    };
+
+    const int TI = (o1 - o0) + 2 * HB;  // input planes of the block
+    load_plane(0);
+    store_plane(0);
+    if (TI > 1) {
+        load_plane(1);
+        store_plane(1);
+    }
+    if (TI > 2) load_plane(2);
+    __syncthreads();
+    if (live(0)) stage_a(0);
     __syncthreads();
     for (int t0 = 0; t0 < TI; t0 += R) {
 #pragma unroll
@@ -279,34 +334,9 @@ __global__ __launch_bounds__(kThreads) void k_apply3d(OpDev<T> op, const T* __re
             const int t = t0 + uu;
             if (t < TI) {  // block-uniform
                 const int j = o0 - HB + t;
-                const bool live = (j >= 0 && j < m1);  // planes outside the grid are zero
-                if (live) {
-#pragma unroll
-                    for (int pa = 0; pa < NPA; ++pa) {
-                        const int p = tid + pa * kThreads;
-                        if (p < NA) {
-                            const int i = p / E3, qc = p % E3;
-#pragma unroll
-                            for (int c = 0; c < 3; ++c) {
-                                T aM = T(0), aA = T(0), aS = T(0);
-#pragma unroll
-                                for (int k = 0; k < R; ++k) {
-                                    const T xv = xs[c * NIN + (i + k) * E3 + qc];
-                                    aM += ca[(0 * R + k) * k3T2 + i] * xv;
-                                    aA += ca[(1 * R + k) * k3T2 + i] * xv;
-                                    aS += ca[(2 * R + k) * k3T2 + i] * xv;
-                                }
-                                st[(3 * c + 0) * NA + p] = aM;
-                                st[(3 * c + 1) * NA + p] = aA;
-                                st[(3 * c + 2) * NA + p] = aS;
-                            }
-                        }
-                    }
-                }
-                __syncthreads();  // stage A done: xs free, st complete
-                if (t + 1 < TI) store_plane();
-                if (t + 2 < TI) load_plane(j + 2);
-                if (live) {
+                if (t + 1 < TI && live(t + 1)) stage_a(t + 1);
+                if (live(t)) {
+                    const T* sb = st + (t & 1) * 9 * NA;
                     T W[3][3];
 #pragma unroll
                     for (int c = 0; c < 3; ++c)
@@ -321,9 +351,9 @@ __global__ __launch_bounds__(kThreads) void k_apply3d(OpDev<T> op, const T* __re
                             mm[c] = sm[c] = am[c] = ms[c] = ma[c] = aa[c] = T(0);
 #pragma unroll
                             for (int k = 0; k < R; ++k) {
-                                const T vM = st[(3 * c + 0) * NA + q0 + k];
-                                const T vA = st[(3 * c + 1) * NA + q0 + k];
-                                const T vS = st[(3 * c + 2) * NA + q0 + k];
+                                const T vM = sb[(3 * c + 0) * NA + q0 + k];
+                                const T vA = sb[(3 * c + 1) * NA + q0 + k];
+                                const T vS = sb[(3 * c + 2) * NA + q0 + k];
                                 mm[c] += cb[0][k] * vM;
                                 sm[c] += cb[2][k] * vM;
                                 if (c != 1) am[c] += cb[1][k] * vM;
@@ -346,10 +376,9 @@ __global__ __launch_bounds__(kThreads) void k_apply3d(OpDev<T> op, const T* __re
                     for (int k = 0; k < R; ++k) {
                         const int i = j - HB + k;
                         if (i >= o0 && i < o1) {
-                            const int kk = 2 * HB - k;  // band column of X1(i, j)
-                            const T cS = op.band[0][2][kk * m1 + i];
-                            const T cM = op.band[0][0][kk * m1 + i];
-                            const T cA = op.band[0][1][kk * m1 + i];
+                            const T cS = colS[j * R + k];  // X1(i, j)
+                            const T cM = colM[j * R + k];
+                            const T cA = colA[j * R + k];
                             const int sl = (uu + k + 1) % R;
 #pragma unroll
                             for (int c = 0; c < 3; ++c)
@@ -378,7 +407,9 @@ __global__ __launch_bounds__(kThreads) void k_apply3d(OpDev<T> op, const T* __re
                         }
                     }
                 }
-                __syncthreads();  // stage B done: st free; plane t+1 complete in xs
+                if (t + 2 < TI) store_plane(t + 2);  // into the buffer plane t vacated
+                if (t + 3 < TI) load_plane(t + 3);
+                __syncthreads();
             }
         }
     }
@@ -512,9 +543,12 @@ template <typename T, int HB, int MODE>
 void apply_dispatch(const OpDev<T>& op, const T* x, T* y, const T* b, T* u, T* xout, T c1, T c2, double* part,
                     int nv, unsigned long long* stamp, hipStream_t s) {
     if (op.dim == 3) {
-        const Apply3dGeom g = apply3d_geom(op.m, HB);
-        hipLaunchKernelGGL((k_apply3d<T, HB, MODE>), dim3(g.nblocks), dim3(kThreads), 0, s, op, x, y, b, u, xout,
-                           c1, c2, part, nv, g, stamp);
+        const Apply3dGeom g = apply3d_geom(op.m, HB, sizeof(T));
+        const size_t lds = apply3d_lds_words<T, HB>() * sizeof(T);
+        auto kern = k_apply3d<T, HB, MODE>;
+        allow_lds(reinterpret_cast<const void*>(kern), lds);
+        hipLaunchKernelGGL(kern, dim3(g.nblocks), dim3(kThreads), lds, s, op, x, y, b, u, xout, c1, c2, part, nv, g,
+                           stamp);
     } else {
         static_assert(kT1 * kT2 == kThreads, "2D tile must match the block size");
         const int tiles = ((op.m[0] + kT1 - 1) / kT1) * ((op.m[1] + kT2 - 1) / kT2);
@@ -716,6 +750,23 @@ struct LineGeom {
 constexpr int kLineThreads = 64;  // one wave per block in the line solves
 constexpr int kRowGroup = 16;     // rows per group: staging loads and recurrence LDS reads
 
+// First element of grid line `line` of component c along axis g.axis, and
+// the stride between its rows.
+__device__ inline size_t base_of(const LineGeom& g, size_t line, int c) {
+    size_t b;
+    if (g.axis == 0)
+        b = line;
+    else if (g.axis == 1)
+        b = (line / g.m2) * size_t(g.m1) * g.m2 + line % g.m2;
+    else
+        b = line * g.m2;
+    return b + size_t(c) * g.G;
+}
+
+__device__ inline size_t stride_of(const LineGeom& g) {
+    return g.axis == 0 ? size_t(g.m1) * g.m2 : (g.axis == 1 ? size_t(g.m2) : size_t(1));
+}
+
 // Rows of the staged span, padded to a whole number of row groups.
 __host__ __device__ inline int padded_span(int span) { return (span + kRowGroup - 1) / kRowGroup * kRowGroup; }
 
@@ -755,19 +806,11 @@ __global__ __launch_bounds__(kLineThreads) void k_tsolve_line(const T* __restric
     T* cf = sp + size_t(spanP) * kLineThreads;  // [spanP + BW][BW] factor rows, zero past the span
     T* dv = cf + size_t(spanP + BW) * BW;       // [spanP] 1 / D, zero past the span
     const bool active = line < g.lines_per_comp;
-    size_t base = 0, stride = 0;
-    if (g.axis == 0) {
-        base = line;
-        stride = size_t(g.m1) * g.m2;
-    } else if (g.axis == 1) {
-        base = (line / g.m2) * size_t(g.m1) * g.m2 + line % g.m2;
-        stride = g.m2;
-    } else {
-        base = line * g.m2;
-        stride = 1;
-    }
-    base += size_t(c) * g.G;
-    // 1. staging
+    const size_t base = base_of(g, min(line, g.lines_per_comp - 1), c);
+    // 1. staging: factor rows first, then the lane's values, two row groups of
+    //    loads issued before they are stored.  Inactive lanes (line padding)
+    //    load a valid line and are not used.
+    const size_t stride = stride_of(g);
     {
         const int ncf = span * BW, ncfP = (spanP + BW) * BW;
         const T* Ls = L + size_t(rs) * BW;
@@ -790,7 +833,7 @@ __global__ __launch_bounds__(kLineThreads) void k_tsolve_line(const T* __restric
             dv[e] = (e < span) ? val : T(0);
         }
     }
-    if (active) {
+    {
         const T* src = in + base;
         const int last = re - 1;
         for (int rb = 0; rb < spanP; rb += 2 * kRowGroup) {
@@ -1167,7 +1210,7 @@ int reduce_blocks(size_t n) {
 
 template <typename T>
 int apply_blocks(const OpDev<T>& op) {
-    if (op.dim == 3) return apply3d_geom(op.m, op.hb).nblocks;
+    if (op.dim == 3) return apply3d_geom(op.m, op.hb, sizeof(T)).nblocks;
     return ((op.m[0] + kT1 - 1) / kT1) * ((op.m[1] + kT2 - 1) / kT2);
 }
 

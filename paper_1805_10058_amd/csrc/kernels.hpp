@@ -13,6 +13,9 @@ namespace cd {
 template <typename T>
 struct OpDev {
     const T* band[3][3];
+    // axis-0 columns, row-window form: col0[w][j * (2hb+1) + k] = X(j - hb + k, j)
+    // (zero outside the matrix), so one plane's coefficients are contiguous
+    const T* col0[3];
     int m[3];   // unknowns per axis (m[2] = 1 in 2D)
     int hb;     // half bandwidth (= p on every level)
     int dim;

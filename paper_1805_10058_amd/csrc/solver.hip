@@ -312,6 +312,19 @@ cd::OpDev<T> make_op(cd_solver* s, const LevelHost& L, hipStream_t st) {
         const cd::Band* mats[3] = {&L.M[l], &L.A[l], &L.S[l]};
         for (int w = 0; w < 3; ++w) op.band[l][w] = s->arena.upload(convert<T>(kmajor(*mats[w])), st);
     }
+    {
+        const cd::Band* mats[3] = {&L.M[0], &L.A[0], &L.S[0]};
+        const int hb = s->p, R = 2 * hb + 1, m0 = L.m[0];
+        for (int w = 0; w < 3; ++w) {
+            std::vector<double> col(size_t(m0) * R, 0.0);
+            for (int j = 0; j < m0; ++j)
+                for (int k = 0; k < R; ++k) {
+                    const int i = j - hb + k;
+                    if (i >= 0 && i < m0) col[size_t(j) * R + k] = mats[w]->get(i, j);
+                }
+            op.col0[w] = s->arena.upload(convert<T>(col), st);
+        }
+    }
     if (s->d == 2) {  // unused third axis: a 1x1 identity band keeps pointers valid
         std::vector<double> id(2 * s->p + 1, 0.0);
         id[s->p] = 1.0;
@@ -354,9 +367,9 @@ cd::TFacDev<T> make_tfac(cd_solver* s, const cd::TFactor& F, hipStream_t st) {
     t.bw = F.bw;
     t.l = s->arena.upload(convert<T>(F.l), st);
     t.dinv = s->arena.upload(convert<T>(F.dinv), st);
-    // start each chunk's recurrence early enough to forget the zero start state
-    // far below the rounding level of T
-    t.warm = cd::recurrence_warmup(F, sizeof(T) == 8 ? 1e-18 : 1e-9);
+    // start each chunk's recurrence early enough that the zero start state has
+    // decayed below the unit roundoff of T
+    t.warm = cd::recurrence_warmup(F, sizeof(T) == 8 ? 0x1p-53 : 0x1p-24);
     return t;
 }
 
@@ -972,7 +985,7 @@ void cd_default_options(cd_options* o) {
     o->precision = CD_FP64;
     o->rtol = 1e-8;
     o->max_iter = 10000;
-    o->coarse_max_dofs = 1000;
+    o->coarse_max_dofs = 2500;
     o->cheb_degree = 3;
     o->cheb_ratio = 30.0;
     o->power_iters = 10;
