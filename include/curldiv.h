@@ -121,14 +121,22 @@ typedef struct cd_solver cd_solver;
 /* Set up the hierarchy on the host in FP64 (1D matrices by Gauss
  * quadrature, transfers, Galerkin coarse 1D matrices, banded LDL^T of
  * T_m(m_{p-1}), dense coarse matrix) and on the device (eigenvalue bounds of
- * the smoother, inverse of the coarse matrix).  `stream` is a hipStream_t
- * (NULL = default stream); all later work of the handle is queued on it. */
+ * the smoother, inverse of the coarse matrix).  `stream` is a hipStream_t;
+ * all later work of the handle is queued on it.  With NULL the handle
+ * creates its own non-blocking stream and orders it after the null stream at
+ * every entry point (outer iterations are replayed from HIP graphs, which
+ * cannot be captured on the null stream). */
 int cd_solver_create(const cd_problem* prob, const cd_options* opt, void* stream, cd_solver** out);
 void cd_solver_destroy(cd_solver* s);
 
 /* Solve A x = b (Sec. 6, the linear system of the problem) from x_0 = 0.
  * b_dev, x_dev: device arrays of cd_num_dofs() doubles.  Blocks until done. */
 int cd_solve(cd_solver* s, const double* b_dev, double* x_dev, cd_result* out);
+
+/* Device bytes the handle holds (its allocations after setup; the setup's
+ * temporary workspace is released before cd_solver_create returns).  The
+ * server admits by cd_footprint_bytes, which is at least this. */
+size_t cd_solver_device_bytes(const cd_solver* s);
 
 /* ---- hooks for parity tests and measurement ----------------------------- */
 int cd_num_levels(const cd_solver* s);

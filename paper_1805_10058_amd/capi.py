@@ -72,6 +72,7 @@ SIGNATURES = {
     "cd_solver_destroy": (None, [_P]),
     "cd_solve": (_I, [_P, _P, _P, ctypes.POINTER(cd_result)]),
     "cd_num_levels": (_I, [_P]),
+    "cd_solver_device_bytes": (ctypes.c_size_t, [_P]),
     "cd_level_shape": (_I, [_P, _I, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_size_t)]),
     "cd_get_matrix": (_I, [_P, _I, _I, ctypes.c_char, ctypes.POINTER(ctypes.c_double)]),
     "cd_get_lambda": (_I, [_P, _I, ctypes.POINTER(ctypes.c_double)]),
@@ -189,6 +190,9 @@ class Solver:
         rc = lib().cd_solve(self._h, ctypes.c_void_p(b_ptr), ctypes.c_void_p(x_ptr), ctypes.byref(res))
         check(rc, allow=(CD_OK, CD_NOT_CONVERGED))
         return res
+
+    def device_bytes(self):
+        return lib().cd_solver_device_bytes(self._h)
 
     def num_levels(self):
         return lib().cd_num_levels(self._h)

@@ -1080,6 +1080,13 @@ int cd_solve(cd_solver* s, const double* b, double* x, cd_result* res) {
     return st;
 }
 
+size_t cd_solver_device_bytes(const cd_solver* s) {
+    if (!s) return 0;
+    size_t b = s->arena.bytes + (s->hook_arena ? s->hook_arena->bytes : 0);
+    if (s->stamps) b += size_t(cd_solver::kStampSlots) * (cd::kStampWords + 2) * sizeof(unsigned long long);
+    return b;
+}
+
 int cd_num_levels(const cd_solver* s) { return s ? int(s->lv.size()) : 0; }
 
 int cd_level_shape(const cd_solver* s, int level, int* m3, size_t* ndofs) {

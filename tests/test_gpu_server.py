@@ -90,3 +90,21 @@ def test_request_larger_than_budget_is_refused():
         srv.submit(capi.problem(3, 3, 32, 1.0, -1.0), capi.options(), b.data_ptr(), x.data_ptr())
     assert e.value.code == capi.CD_EINVAL
     srv.close()
+
+
+@pytest.mark.parametrize("case", [(2, 3, 64, capi.CD_MIXED_FP32), (2, 6, 40, capi.CD_FP64),
+                                  (3, 2, 20, capi.CD_FP64), (3, 4, 12, capi.CD_MIXED_FP32)])
+def test_footprint_covers_device_bytes(case):
+    # the server admits by cd_footprint_bytes: it must cover what a solver
+    # really holds (and not overstate it grossly)
+    d, p, n, prec = case
+    prob = capi.problem(d, p, n, 1.0, 0.1)
+    opt = capi.options(precision=prec)
+    fp = capi.footprint_bytes(prob, opt)
+    s = capi.Solver(prob, opt, stream())
+    b = np.random.default_rng(0).uniform(-1, 1, capi.num_dofs(prob))
+    bd, x = dev(b), empty(b.size)
+    s.solve(bd.data_ptr(), x.data_ptr())
+    held = s.device_bytes()
+    assert held <= fp <= 2 * held + (2 << 20)
+    s.close()
