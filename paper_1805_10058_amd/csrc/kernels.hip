@@ -121,7 +121,7 @@ Apply3dGeom apply3d_geom(const int* m, int hb, size_t elem) {
 // Partial dot products an operator kernel accumulates per thread.
 template <int MODE>
 constexpr int apply_ndots() {
-    return MODE == kApplyYMulti ? kMaxBasis : 1;
+    return MODE == kApplyYMulti ? kMaxBasis + 1 : 1;
 }
 
 // Epilogue of the operator kernels at one output entry idx (component c,
@@ -144,6 +144,7 @@ __device__ inline void apply_epilogue(const OpDev<T>& op, int c, size_t idx, T k
 #pragma unroll
         for (int i = 0; i < kMaxBasis; ++i)
             if (i < nv) dots[i] += double(b[size_t(i) * ntot + idx]) * double(kx);
+        dots[kMaxBasis] += double(kx) * double(kx);
     } else if (MODE == kApplyCheb) {
         const T r = b[idx] - kx;
         const T dg = diag_entry(op, c, i1, i2, i3);
@@ -171,6 +172,8 @@ __device__ inline void apply_write_dots(const double* dots, int nv, double* __re
                 if (threadIdx.x == 0) part[size_t(i) * gridDim.x + blockIdx.x] = tot;
             }
         }
+        const double ww = block_sum(dots[kMaxBasis]);
+        if (threadIdx.x == 0) part[size_t(nv) * gridDim.x + blockIdx.x] = ww;
     }
 }
 
@@ -1079,68 +1082,109 @@ __global__ __launch_bounds__(kThreads) void k_fcg_update(const double* __restric
 
 // ---- GMRES helpers -----------------------------------------------------------------
 
-__global__ __launch_bounds__(kThreads) void k_hessenberg_ls(double* __restrict__ H, int ld, int k,
-                                                            const double* __restrict__ beta0sq,
-                                                            double* __restrict__ y,
-                                                            const double* __restrict__ plast, int nlast) {
-    const double last = sqrt(sum_partials(plast, nlast));  // H(k, k-1)
-    if (threadIdx.x != 0 || blockIdx.x != 0) return;
-    H[size_t(k - 1) * ld + k] = last;
+// Least squares min || beta0 e1 - H y || for the (k+1) x k Hessenberg H
+// (column-major, leading dimension ld) by Givens rotations, one thread.
+__device__ inline void hessenberg_lsq(const double* __restrict__ H, int ld, int k, double beta0, double* y) {
     double R[kMaxBasis + 1][kMaxBasis];
     double g[kMaxBasis + 1];
-    for (int i = 0; i <= k; ++i) {
+#pragma unroll
+    for (int i = 0; i <= kMaxBasis; ++i) {
         g[i] = 0.0;
-        for (int j = 0; j < k; ++j) R[i][j] = H[size_t(j) * ld + i];
+#pragma unroll
+        for (int j = 0; j < kMaxBasis; ++j) R[i][j] = (i <= k && j < k) ? H[size_t(j) * ld + i] : 0.0;
     }
-    g[0] = sqrt(beta0sq[0]);
-    for (int j = 0; j < k; ++j) {
-        const double a = R[j][j], b = R[j + 1][j];
-        const double rr = sqrt(a * a + b * b);
-        const double c = (rr > 0.0) ? a / rr : 1.0, sn = (rr > 0.0) ? b / rr : 0.0;
-        for (int col = j; col < k; ++col) {
-            const double t0 = R[j][col], t1 = R[j + 1][col];
-            R[j][col] = c * t0 + sn * t1;
-            R[j + 1][col] = -sn * t0 + c * t1;
+    g[0] = beta0;
+#pragma unroll
+    for (int j = 0; j < kMaxBasis; ++j) {
+        if (j < k) {
+            const double a = R[j][j], b = R[j + 1][j];
+            const double rr = sqrt(a * a + b * b);
+            const double c = (rr > 0.0) ? a / rr : 1.0, sn = (rr > 0.0) ? b / rr : 0.0;
+#pragma unroll
+            for (int col = 0; col < kMaxBasis; ++col) {
+                if (col >= j) {
+                    const double t0 = R[j][col], t1 = R[j + 1][col];
+                    R[j][col] = c * t0 + sn * t1;
+                    R[j + 1][col] = -sn * t0 + c * t1;
+                }
+            }
+            const double g0 = g[j], g1 = g[j + 1];
+            g[j] = c * g0 + sn * g1;
+            g[j + 1] = -sn * g0 + c * g1;
         }
-        const double g0 = g[j], g1 = g[j + 1];
-        g[j] = c * g0 + sn * g1;
-        g[j + 1] = -sn * g0 + c * g1;
     }
-    for (int i = k - 1; i >= 0; --i) {
-        double s = g[i];
-        for (int col = i + 1; col < k; ++col) s -= R[i][col] * y[col];
-        y[i] = (fabs(R[i][i]) > 0.0) ? s / R[i][i] : 0.0;
+#pragma unroll
+    for (int i = kMaxBasis - 1; i >= 0; --i) {
+        if (i < k) {
+            double sum = g[i];
+#pragma unroll
+            for (int col = 0; col < kMaxBasis; ++col)
+                if (col > i && col < k) sum -= R[i][col] * y[col];
+            y[i] = (fabs(R[i][i]) > 0.0) ? sum / R[i][i] : 0.0;
+        }
     }
 }
 
-// Classical Gram-Schmidt step in one pass: every block sums the partials of
-// the k dots itself (same order in every block), then w -= sum_i h_i V_i and
-// the block's partial sum of w.w.
+// Classical Gram-Schmidt step with the Pythagorean norm, one pass: every
+// block sums the partials of the k dots V_i . w and of w . w (written by the
+// operator kernel, the same order in every block): h_i = V_i . w,
+// ||w'||^2 = w . w - sum h_i^2 for w' = w - sum h_i V_i.  Block 0 stores
+// H(0..k-1, j) = h and H(k, j) = ||w'||; with v given, v = w' / ||w'||
+// (zero if ||w'|| = 0).
 template <typename T>
-__global__ __launch_bounds__(kThreads) void k_gs_update(const double* __restrict__ pdot, int k, int nbp,
-                                                        double* __restrict__ Hcol, const T* __restrict__ V,
-                                                        T* __restrict__ w, size_t n, double* __restrict__ pnorm) {
-    __shared__ double hs[kMaxBasis];
-    for (int i = 0; i < k; ++i) {
+__global__ __launch_bounds__(kThreads) void k_gs_normscale(const double* __restrict__ pdot, int k, int nbp,
+                                                           double* __restrict__ Hcol, const T* __restrict__ V,
+                                                           const T* __restrict__ w, T* __restrict__ v, size_t n) {
+    __shared__ double hs[kMaxBasis + 1];
+    for (int i = 0; i <= k; ++i) {
         const double t = sum_partials(pdot + size_t(i) * nbp, nbp);
         if (threadIdx.x == 0) hs[i] = t;
     }
     __syncthreads();
+    double h2 = 0.0;
+    for (int i = 0; i < k; ++i) h2 += hs[i] * hs[i];
+    const double nrm = sqrt(fmax(hs[k] - h2, 0.0));
     if (blockIdx.x == 0 && threadIdx.x < k) Hcol[threadIdx.x] = hs[threadIdx.x];
+    if (blockIdx.x == 0 && threadIdx.x == 0) Hcol[k] = nrm;
+    if (v == nullptr) return;
     T h[kMaxBasis];
 #pragma unroll
     for (int i = 0; i < kMaxBasis; ++i) h[i] = (i < k) ? T(hs[i]) : T(0);
-    double acc = 0.0;
+    const T sc = (nrm != 0.0) ? T(1.0 / nrm) : T(0);
     for (size_t e = size_t(blockIdx.x) * kThreads + threadIdx.x; e < n; e += size_t(gridDim.x) * kThreads) {
         T a = w[e];
 #pragma unroll
         for (int i = 0; i < kMaxBasis; ++i)
             if (i < k) a -= h[i] * V[size_t(i) * n + e];
-        w[e] = a;
-        acc += double(a) * double(a);
+        v[e] = a * sc;
     }
-    const double tot = block_sum(acc);
-    if (threadIdx.x == 0) pnorm[blockIdx.x] = tot;
+}
+
+// The smoother's update: y = argmin || beta0 e1 - H y || (every block solves
+// the small problem itself), then x += sum_j y_j Z_j.
+template <typename T>
+__global__ __launch_bounds__(kThreads) void k_lsq_combine_add(const double* __restrict__ H, int ld, int k,
+                                                              const double* __restrict__ beta0sq,
+                                                              const T* __restrict__ Z, T* __restrict__ x,
+                                                              size_t n) {
+    __shared__ double ys[kMaxBasis];
+    if (threadIdx.x == 0) {
+        double y[kMaxBasis];
+        hessenberg_lsq(H, ld, k, sqrt(beta0sq[0]), y);
+#pragma unroll
+        for (int i = 0; i < kMaxBasis; ++i) ys[i] = (i < k) ? y[i] : 0.0;
+    }
+    __syncthreads();
+    T yv[kMaxBasis];
+#pragma unroll
+    for (int i = 0; i < kMaxBasis; ++i) yv[i] = T(ys[i]);
+    for (size_t e = size_t(blockIdx.x) * kThreads + threadIdx.x; e < n; e += size_t(gridDim.x) * kThreads) {
+        T acc = T(0);
+#pragma unroll
+        for (int j = 0; j < kMaxBasis; ++j)
+            if (j < k) acc += yv[j] * Z[size_t(j) * n + e];
+        x[e] += acc;
+    }
 }
 
 // ss = sum of the partials (every block); block 0 stores ss or sqrt(ss);
@@ -1156,16 +1200,6 @@ __global__ __launch_bounds__(kThreads) void k_normscale(const double* __restrict
     const T sc = (nrm != 0.0) ? T(1.0 / nrm) : T(0);
     for (size_t e = size_t(blockIdx.x) * kThreads + threadIdx.x; e < n; e += size_t(gridDim.x) * kThreads)
         v[e] = w[e] * sc;
-}
-
-template <typename T>
-__global__ __launch_bounds__(kThreads) void k_combine_add(const T* __restrict__ V, int k,
-                                                          const double* __restrict__ y, T* __restrict__ w, size_t n) {
-    for (size_t i = size_t(blockIdx.x) * kThreads + threadIdx.x; i < n; i += size_t(gridDim.x) * kThreads) {
-        T acc = T(0);
-        for (int j = 0; j < k; ++j) acc += T(y[j]) * V[size_t(j) * n + i];
-        w[i] += acc;
-    }
 }
 
 // pairs[2 s] = start, pairs[2 s + 1] = latest end of slot s (one block per
@@ -1473,21 +1507,7 @@ void launch_stamp_reduce(unsigned long long* st, int slot0, int nslots, unsigned
     check_launch("stamp_reduce");
 }
 
-void launch_hessenberg_ls(double* H, int ld, int k, const double* beta0sq, double* y, const double* plast,
-                          int nlast, hipStream_t s) {
-    if (k < 1 || k > kMaxBasis) throw std::runtime_error("bad number of Krylov vectors");
-    hipLaunchKernelGGL(k_hessenberg_ls, dim3(1), dim3(kThreads), 0, s, H, ld, k, beta0sq, y, plast, nlast);
-    check_launch("hessenberg_ls");
-}
 
-template <typename T>
-void launch_gs_update(const double* pdot, int k, int nbp, double* Hcol, const T* V, T* w, size_t n, double* pnorm,
-                      hipStream_t s) {
-    if (k < 1 || k > kMaxBasis) throw std::runtime_error("bad number of Krylov vectors");
-    hipLaunchKernelGGL(k_gs_update<T>, dim3(reduce_blocks(n)), dim3(kThreads), 0, s, pdot, k, nbp, Hcol, V, w, n,
-                       pnorm);
-    check_launch("gs_update");
-}
 
 template <typename T>
 void launch_normscale(const double* pnorm, int np, double* out, bool square, const T* w, T* v, size_t n,
@@ -1498,9 +1518,20 @@ void launch_normscale(const double* pnorm, int np, double* out, bool square, con
 }
 
 template <typename T>
-void launch_combine_add(const T* V, int k, const double* y, T* w, size_t n, hipStream_t s) {
-    hipLaunchKernelGGL(k_combine_add<T>, dim3(grid_for(n)), dim3(kThreads), 0, s, V, k, y, w, n);
-    check_launch("combine_add");
+void launch_gs_normscale(const double* pdot, int k, int nbp, double* Hcol, const T* V, const T* w, T* v, size_t n,
+                         hipStream_t s) {
+    if (k < 1 || k > kMaxBasis) throw std::runtime_error("bad number of Krylov vectors");
+    const int grid = (v == nullptr) ? 1 : grid_for(n);
+    hipLaunchKernelGGL(k_gs_normscale<T>, dim3(grid), dim3(kThreads), 0, s, pdot, k, nbp, Hcol, V, w, v, n);
+    check_launch("gs_normscale");
+}
+
+template <typename T>
+void launch_lsq_combine_add(const double* H, int ld, int k, const double* beta0sq, const T* Z, T* x, size_t n,
+                            hipStream_t s) {
+    if (k < 1 || k > kMaxBasis) throw std::runtime_error("bad number of Krylov vectors");
+    hipLaunchKernelGGL(k_lsq_combine_add<T>, dim3(grid_for(n)), dim3(kThreads), 0, s, H, ld, k, beta0sq, Z, x, n);
+    check_launch("lsq_combine_add");
 }
 
 // ---- explicit instantiations ----
@@ -1520,8 +1551,10 @@ void launch_combine_add(const T* V, int k, const double* y, T* w, size_t n, hipS
     template void launch_diag_dot<T>(const OpDev<T>&, const T*, double*, hipStream_t);                               \
     template void launch_cheb_first<T>(const OpDev<T>&, const T*, T*, T*, T, hipStream_t);                           \
     template void launch_coarse_gemv<T>(const double*, int, int, const T*, T*, hipStream_t);                              \
-    template void launch_combine_add<T>(const T*, int, const double*, T*, size_t, hipStream_t);                          \
-    template void launch_gs_update<T>(const double*, int, int, double*, const T*, T*, size_t, double*, hipStream_t); \
+    template void launch_gs_normscale<T>(const double*, int, int, double*, const T*, const T*, T*, size_t,            \
+                                         hipStream_t);                                                               \
+    template void launch_lsq_combine_add<T>(const double*, int, int, const double*, const T*, T*, size_t,            \
+                                            hipStream_t);                                                            \
     template void launch_normscale<T>(const double*, int, double*, bool, const T*, T*, size_t, hipStream_t);
 
 CD_INST(double)

@@ -53,7 +53,8 @@ enum ApplyMode : int {
     kApplyCheb = 2,  // u = c1 u + c2 D^{-1}(b - A x); xout = x + u
     kApplyYDot = 3,  // y = A x; part[block] = sum x.y (FP64)
     kApplyResDot = 4,  // y = b - A x; part[block] = sum y.y (FP64)
-    kApplyYMulti = 5,  // y = A x; part[i*nblocks + block] = sum V_i.y, i < nv, V_i = b + i*n (FP64)
+    kApplyYMulti = 5,  // y = A x; part[i*nblocks + block] = sum V_i.y, i < nv, V_i = b + i*n, and
+                       // part[nv*nblocks + block] = sum y.y (FP64)
 };
 
 constexpr int kMaxBasis = 8;  // most Krylov vectors of the GMRES post-smoother
@@ -146,25 +147,23 @@ void launch_fcg_update(const double* pdr, int npdr, const double* pdq, int npdq,
                        hipStream_t s);
 
 // ---- GMRES helpers (vectors of type T, scalars FP64) ----------------------------
-// Classical Gram-Schmidt step: h_i = sum of the nbp partials pdot[i*nbp ..]
-// (i < k; stored in Hcol by block 0), w -= sum_i h_i V_i, pnorm[block] =
-// partial sums of w.w (reduce_blocks(n) of them).
+// Classical Gram-Schmidt step with the Pythagorean norm: h_i = sum of the
+// nbp partials pdot[i*nbp ..] (V_i . w, i < k), ww = those of pdot[k*nbp ..]
+// (w . w); block 0 stores Hcol[0..k) = h and Hcol[k] = sqrt(ww - |h|^2);
+// unless v == nullptr, v = (w - sum_i h_i V_i) / Hcol[k] (zero if that is 0).
 template <typename T>
-void launch_gs_update(const double* pdot, int k, int nbp, double* Hcol, const T* V, T* w, size_t n, double* pnorm,
-                      hipStream_t s);
+void launch_gs_normscale(const double* pdot, int k, int nbp, double* Hcol, const T* V, const T* w, T* v, size_t n,
+                         hipStream_t s);
 // ss = sum of the np partials; *out = square ? ss : sqrt(ss) (block 0);
 // v = w / sqrt(ss) (zero if ss == 0) unless v == nullptr.
 template <typename T>
 void launch_normscale(const double* pnorm, int np, double* out, bool square, const T* w, T* v, size_t n,
                       hipStream_t s);
-// Least squares min || beta0 e1 - H y || for the (k+1) x k Hessenberg H
-// (column-major, leading dimension ld) by Givens rotations; y[0..k).  The
-// subdiagonal entry H(k, k-1) is sqrt of the sum of the nlast partials plast
-// (stored into H as well).
-void launch_hessenberg_ls(double* H, int ld, int k, const double* beta0sq, double* y, const double* plast,
-                          int nlast, hipStream_t s);
-// w += sum_j y[j] V_j
+// x += sum_j y_j Z_j with y = argmin || sqrt(*beta0sq) e1 - H y || for the
+// (k+1) x k Hessenberg H (column-major, leading dimension ld), solved by
+// Givens rotations in every block.
 template <typename T>
-void launch_combine_add(const T* V, int k, const double* y, T* w, size_t n, hipStream_t s);
+void launch_lsq_combine_add(const double* H, int ld, int k, const double* beta0sq, const T* Z, T* x, size_t n,
+                            hipStream_t s);
 
 }  // namespace cd

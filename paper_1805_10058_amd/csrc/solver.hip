@@ -114,7 +114,6 @@ struct VWork {
     T* io_in = nullptr;   // precision-converted input (mixed mode)
     T* tmp = nullptr;     // scratch of the T-solve
     double* H = nullptr;  // (s+1) x s column-major
-    double* y = nullptr;
     double* pdot = nullptr;   // partial dot products of the apply kernel: ks x nba
     double* pnorm = nullptr;  // partial sums of squares: max(nba, nb)
     double* scal = nullptr;   // [0] beta0^2
@@ -404,10 +403,9 @@ std::unique_ptr<VWork<T>> make_work(cd_solver* s, DevArena& ar) {
     w->io_in = ar.alloc<T>(s->N);
     w->tmp = ar.alloc<T>(s->N);
     w->H = ar.alloc<double>(size_t(ks + 1) * ks);
-    w->y = ar.alloc<double>(ks + 1);
     w->nb = cd::reduce_blocks(s->N);
     w->nba = cd::apply_blocks<T>(devlevels<T>(s)[0].op);
-    w->pdot = ar.alloc<double>(size_t(w->nba) * ks);
+    w->pdot = ar.alloc<double>(size_t(w->nba) * (ks + 1));
     w->pnorm = ar.alloc<double>(size_t(std::max(w->nba, w->nb)));
     w->scal = ar.alloc<double>(4);
     return w;
@@ -573,7 +571,7 @@ cd::ChebFirst<T> cheb_first_of(cd_solver* s, VWork<T>& W, int l) {
 template <typename T>
 void gmres_post(cd_solver* s, VWork<T>& W, const T* b, T* x) {
     const size_t N = s->N;
-    const int ks = s->ksteps, ld = ks + 1, nb = W.nb, nba = W.nba;
+    const int ks = s->ksteps, ld = ks + 1, nba = W.nba;
     hipStream_t st = s->stream;
     T* V = W.V;
     // r = b - A x and its norm: V_0 = r / ||r||, beta0^2 kept for the least squares
@@ -583,16 +581,15 @@ void gmres_post(cd_solver* s, VWork<T>& W, const T* b, T* x) {
         double* Hcol = W.H + size_t(j) * ld;
         T* Zj = W.Z + size_t(j) * N;
         tsolve_op<T>(s, V + size_t(j) * N, W.tmp, Zj);
-        // w = A T^{-1} V_j together with the dots V_i . w, i <= j
+        // w = A T^{-1} V_j together with the dots V_i . w (i <= j) and w . w
         apply_op<T>(s, 0, cd::kApplyYMulti, Zj, W.w, V, nullptr, nullptr, T(0), T(0), W.pdot, j + 1);
-        // H(0..j, j) = those dots; w -= sum_i H(i, j) V_i; partial sums of w.w
-        cd::launch_gs_update<T>(W.pdot, j + 1, nba, Hcol, V, W.w, N, W.pnorm, st);
-        // H(j+1, j) = ||w||, V_{j+1} = w / ||w|| (the last norm is taken by the least squares)
-        if (j + 1 < ks) cd::launch_normscale<T>(W.pnorm, nb, Hcol + (j + 1), false, W.w, V + size_t(j + 1) * N, N, st);
+        // H(0..j, j) = V_i . w, H(j+1, j) = ||w - sum_i H(i, j) V_i|| (Pythagoras),
+        // V_{j+1} = that vector normalised (not needed after the last step)
+        cd::launch_gs_normscale<T>(W.pdot, j + 1, nba, Hcol, V, W.w, (j + 1 < ks) ? V + size_t(j + 1) * N : nullptr,
+                                   N, st);
     }
-    cd::launch_hessenberg_ls(W.H, ld, ks, W.scal, W.y, W.pnorm, nb, st);
-    // x += T^{-1} (V y) = sum_j y_j T^{-1} V_j  (T is linear)
-    cd::launch_combine_add<T>(W.Z, ks, W.y, x, N, st);
+    // x += T^{-1} (V y) = sum_j y_j T^{-1} V_j  (T is linear), y from the least squares
+    cd::launch_lsq_combine_add<T>(W.H, ld, ks, W.scal, W.Z, x, N, st);
 }
 
 // One V-cycle on level l for A_l x = W.lv[l].b; result in W.lv[l].xcur.
