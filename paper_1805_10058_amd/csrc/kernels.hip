@@ -124,38 +124,71 @@ constexpr int apply_ndots() {
     return MODE == kApplyYMulti ? kMaxBasis + 1 : 1;
 }
 
-// Epilogue of the operator kernels at one output entry idx (component c,
-// grid point (i1, i2, i3)) with kx = (A x)[idx]; ntot = vector length.
+// Operands the epilogue of an operator kernel reads at one output entry,
+// loaded as early as the kernel knows the entry (the 2D kernel: before its
+// input tile), so their latency hides behind the contractions.
+template <typename T>
+struct EpiIn {
+    T b, u, x;
+    T v[kMaxBasis];
+};
+
 template <typename T, int MODE>
-__device__ inline void apply_epilogue(const OpDev<T>& op, int c, size_t idx, T kx, int i1, int i2, int i3,
-                                      const T* __restrict__ x, T* __restrict__ y, const T* __restrict__ b,
-                                      T* __restrict__ u, T* __restrict__ xout, T c1, T c2, int nv, size_t ntot,
-                                      double* dots) {
+__device__ inline void epilogue_load(EpiIn<T>& e, size_t idx, const T* __restrict__ x, const T* __restrict__ b,
+                                     const T* __restrict__ u, T c1, int nv, size_t ntot) {
+    if (MODE == kApplyRes || MODE == kApplyResDot || MODE == kApplyCheb) e.b = b[idx];
+    if (MODE == kApplyCheb) {
+        e.u = (c1 != T(0)) ? u[idx] : T(0);  // u is not read on a first step
+        e.x = x[idx];
+    }
+    if (MODE == kApplyYDot) e.x = x[idx];
+    if (MODE == kApplyYMulti) {
+#pragma unroll
+        for (int i = 0; i < kMaxBasis; ++i) e.v[i] = (i < nv) ? b[size_t(i) * ntot + idx] : T(0);
+    }
+}
+
+// Epilogue at one output entry idx (component c, grid point (i1, i2, i3))
+// with kx = (A x)[idx] and the entry's operands e.
+template <typename T, int MODE>
+__device__ inline void epilogue_store(const OpDev<T>& op, int c, size_t idx, T kx, int i1, int i2, int i3,
+                                      const EpiIn<T>& e, T* __restrict__ y, T* __restrict__ u,
+                                      T* __restrict__ xout, T c1, T c2, int nv, double* dots) {
     if (MODE == kApplyY) {
         y[idx] = kx;
     } else if (MODE == kApplyRes) {
-        y[idx] = b[idx] - kx;
+        y[idx] = e.b - kx;
     } else if (MODE == kApplyResDot) {
-        const T r = b[idx] - kx;
+        const T r = e.b - kx;
         y[idx] = r;
         dots[0] += double(r) * double(r);
     } else if (MODE == kApplyYMulti) {
         y[idx] = kx;
 #pragma unroll
         for (int i = 0; i < kMaxBasis; ++i)
-            if (i < nv) dots[i] += double(b[size_t(i) * ntot + idx]) * double(kx);
+            if (i < nv) dots[i] += double(e.v[i]) * double(kx);
         dots[kMaxBasis] += double(kx) * double(kx);
     } else if (MODE == kApplyCheb) {
-        const T r = b[idx] - kx;
+        const T r = e.b - kx;
         const T dg = diag_entry(op, c, i1, i2, i3);
-        const T uprev = (c1 != T(0)) ? u[idx] : T(0);  // u is not read on a first step
-        const T un = c1 * uprev + c2 * r / dg;
+        const T un = c1 * e.u + c2 * r / dg;
         u[idx] = un;
-        xout[idx] = x[idx] + un;
+        xout[idx] = e.x + un;
     } else {
         y[idx] = kx;
-        dots[0] += double(x[idx]) * double(kx);
+        dots[0] += double(e.x) * double(kx);
     }
+}
+
+// Both at once (the 3D kernel, whose output entries change plane by plane).
+template <typename T, int MODE>
+__device__ inline void apply_epilogue(const OpDev<T>& op, int c, size_t idx, T kx, int i1, int i2, int i3,
+                                      const T* __restrict__ x, T* __restrict__ y, const T* __restrict__ b,
+                                      T* __restrict__ u, T* __restrict__ xout, T c1, T c2, int nv, size_t ntot,
+                                      double* dots) {
+    EpiIn<T> e;
+    epilogue_load<T, MODE>(e, idx, x, b, u, c1, nv, ntot);
+    epilogue_store<T, MODE>(op, c, idx, kx, i1, i2, i3, e, y, u, xout, c1, c2, nv, dots);
 }
 
 // Block sums of the per-thread partial dots: part[i * gridDim.x + block].
@@ -452,6 +485,17 @@ __global__ __launch_bounds__(kThreads) void k_apply2d(OpDev<T> op, const T* __re
     const int nt2 = (m2 + kT2 - 1) / kT2;
     const int o1 = (blockIdx.x / nt2) * kT1, o2 = (blockIdx.x % nt2) * kT2;
     const int tid = threadIdx.x;
+    // the thread's output point and its epilogue operands, loaded first
+    const int i = tid / kT2, j = tid % kT2;
+    const int i1 = o1 + i, i2 = o2 + j;
+    const bool own = (i1 < m1 && i2 < m2);
+    const int f = own ? i1 * m2 + i2 : 0;
+    EpiIn<T> ep[2];
+    if (own) {
+#pragma unroll
+        for (int c = 0; c < 2; ++c)
+            epilogue_load<T, MODE>(ep[c], size_t(c) * G + f, x, b, u, c1, nv, size_t(2) * G);
+    }
     {
         T v[NLD];
 #pragma unroll
@@ -494,10 +538,7 @@ __global__ __launch_bounds__(kThreads) void k_apply2d(OpDev<T> op, const T* __re
     double dots[apply_ndots<MODE>()];
 #pragma unroll
     for (int q = 0; q < apply_ndots<MODE>(); ++q) dots[q] = 0.0;
-    const int i = tid / kT2, j = tid % kT2;
-    const int i1 = o1 + i, i2 = o2 + j;
-    if (i1 < m1 && i2 < m2) {
-        const int f = i1 * m2 + i2;
+    if (own) {
         T mS1 = T(0), sM1 = T(0), aA2 = T(0), mS2 = T(0), sM2 = T(0), aA1 = T(0);
         const int q0 = i * E2 + j;
 #pragma unroll
@@ -516,8 +557,7 @@ __global__ __launch_bounds__(kThreads) void k_apply2d(OpDev<T> op, const T* __re
         const T kx[2] = {be * mS1 + al * sM1 + ab * aA2, al * mS2 + be * sM2 + ab * aA1};
 #pragma unroll
         for (int c = 0; c < 2; ++c)
-            apply_epilogue<T, MODE>(op, c, size_t(c) * G + f, kx[c], i1, i2, 0, x, y, b, u, xout, c1, c2, nv,
-                                    size_t(2) * G, dots);
+            epilogue_store<T, MODE>(op, c, size_t(c) * G + f, kx[c], i1, i2, 0, ep[c], y, u, xout, c1, c2, nv, dots);
     }
     apply_write_dots<MODE>(dots, nv, part);
     stamp_end(stamp);
