@@ -68,6 +68,9 @@ def main():
     ap.add_argument("--serve", type=int, default=32, help="requests of the serving stream to run (0: skip)")
     ap.add_argument("--serve-rate", type=float, default=8.0, help="Poisson arrival rate of the stream, 1/s (0: burst)")
     ap.add_argument("--serve-max-iter", type=int, default=4000)
+    ap.add_argument("--batched", type=int, default=8,
+                    help="also solve this many right-hand sides of the 2D workload at once through the "
+                         "continuous-batching server (0: skip)")
     ap.add_argument("--copy-cal", action="store_true",
                     help="also run a plain 256 MiB device copy 5 times (calibrates HBM byte counters)")
     args = ap.parse_args()
@@ -213,6 +216,10 @@ def main():
                    "avg_us": 1e3 * ts_ms / max(ts_n, 1), "GB_s": ts_gbs, "hbm_frac": ts_gbs / HBM_PEAK_GBS},
     }
 
+    if args.batched > 0:
+        out["batched"] = c2_batched(capi, torch, cfg, args.batched, log)
+        log(f"batched: {out['batched']}")
+
     if not args.no_c4:
         out["operator_apply_c4"] = c4_apply(capi, torch, st)
         log(f"3D p=3 n=128 operator apply: {out['operator_apply_c4']}")
@@ -225,6 +232,37 @@ def main():
         log("timing the oracle on the host")
         out["cpu_baseline"] = cpu_baseline(cfg, its)
     print(json.dumps(out), flush=True)
+
+
+def c2_batched(capi, torch, cfg, count, log):
+    """`count` right-hand sides of the 2D workload (betas alternating), all
+    submitted at t = 0 to the mixed-precision server: the device's capacity
+    when independent solves overlap, next to the one-at-a-time headline.
+    Solver setup is included."""
+    import curldiv_inputs as ci
+
+    d, p, n, alpha, betas, dist, tol = cfg
+    rhs = [torch.as_tensor(ci.rhs(d, p, n, 5000 + k, dist)).cuda() for k in range(count)]
+    xs = [torch.zeros_like(b) for b in rhs]
+    torch.cuda.synchronize()
+    srv = capi.Server(max_active=count)
+    opt = capi.options(precision=capi.CD_MIXED_FP32, rtol=tol)
+    t0 = time.perf_counter()
+    for k in range(count):
+        srv.submit(capi.problem(d, p, n, alpha, betas[k % len(betas)]), opt, rhs[k].data_ptr(), xs[k].data_ptr())
+    done = []
+    while True:
+        a, q = srv.step()
+        done += srv.poll()
+        if a == 0 and q == 0:
+            break
+    T = time.perf_counter() - t0
+    srv.close()
+    ok = sum(1 for c in done if c.result.status == capi.CD_OK)
+    lat = [c.t_done - c.t_submit for c in done]
+    return {"solves": count, "betas": betas, "solves_per_s": count / T, "converged": ok,
+            "p50_ms": 1e3 * percentile(lat, 50), "p99_ms": 1e3 * percentile(lat, 99),
+            "note": "all submitted at t=0 to the continuous-batching server; includes solver setup"}
 
 
 def serve_bench(capi, torch, st, count, max_iter, log, rate):

@@ -370,6 +370,18 @@ __global__ __launch_bounds__(kThreads) void k_apply3d(OpDev<T> op, const T* __re
             const int t = t0 + uu;
             if (t < TI) {  // block-uniform
                 const int j = o0 - HB + t;
+                const int io = j - HB;  // output plane completed in this phase
+                const bool emit = (io >= o0 && io < o1);
+                // operands of this phase's epilogue, loaded before the contractions
+                // (not for the Krylov-dot mode: its basis rows would cost too many registers)
+                constexpr bool kPre = (MODE != kApplyYMulti);
+                EpiIn<T> ep[3];
+                if (kPre && emit && active) {
+#pragma unroll
+                    for (int c = 0; c < 3; ++c)
+                        epilogue_load<T, MODE>(ep[c], size_t(c) * G + size_t(io) * PL + size_t(i2) * m3 + i3, x, b, u,
+                                               c1, nv, 3 * G);
+                }
                 if (t + 1 < TI && live(t + 1)) stage_a(t + 1);
                 if (live(t)) {
                     const T* sb = st + (t & 1) * 9 * NA;
@@ -424,8 +436,7 @@ __global__ __launch_bounds__(kThreads) void k_apply3d(OpDev<T> op, const T* __re
                         }
                     }
                 }
-                const int io = j - HB;
-                if (io >= o0 && io < o1) {
+                if (emit) {
                     const int sl = (uu + 1) % R;
 #pragma unroll
                     for (int c = 0; c < 3; ++c) {
@@ -438,8 +449,12 @@ __global__ __launch_bounds__(kThreads) void k_apply3d(OpDev<T> op, const T* __re
                             }
                         if (active) {
                             const size_t idx = size_t(c) * G + size_t(io) * PL + size_t(i2) * m3 + i3;
-                            apply_epilogue<T, MODE>(op, c, idx, kx, io, i2, i3, x, y, b, u, xout, c1, c2, nv, 3 * G,
-                                                    dots);
+                            if (kPre)
+                                epilogue_store<T, MODE>(op, c, idx, kx, io, i2, i3, ep[c], y, u, xout, c1, c2, nv,
+                                                        dots);
+                            else
+                                apply_epilogue<T, MODE>(op, c, idx, kx, io, i2, i3, x, y, b, u, xout, c1, c2, nv,
+                                                        3 * G, dots);
                         }
                     }
                 }
