@@ -43,7 +43,7 @@ def cpu_baseline(cfg, its_gpu):
     times = []
     with threadpool_limits(limits=1):
         for beta in betas:
-            meth = method.Method(d, p, n, alpha, beta, coarse_max_dofs=2500)
+            meth = method.Method(d, p, n, alpha, beta, coarse_max_dofs=2500, nu=8)
             b = ci.rhs(d, p, n, 0, dist)
             cap = 12 if beta < 1e-2 else 10000
             t0 = time.perf_counter()

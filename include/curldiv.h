@@ -94,7 +94,7 @@ typedef struct {
 } cd_options;
 
 /* Fill *opt with the defaults: P_MIM, knot insertion, FP64, rtol 1e-8,
- * max_iter 10000, coarse_max_dofs 2500, cheb_degree 3, cheb_ratio 30,
+ * max_iter 10000, coarse_max_dofs 2500, cheb_degree 8, cheb_ratio 30,
  * power_iters 10, krylov_steps = p, graphs 1. */
 void cd_default_options(cd_options* opt);
 

@@ -983,7 +983,7 @@ void cd_default_options(cd_options* o) {
     o->rtol = 1e-8;
     o->max_iter = 10000;
     o->coarse_max_dofs = 2500;
-    o->cheb_degree = 3;
+    o->cheb_degree = 8;
     o->cheb_ratio = 30.0;
     o->power_iters = 10;
     o->krylov_steps = -1;
