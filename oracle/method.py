@@ -16,12 +16,13 @@ with these readings, each also listed with its reason in the design notes:
    coarsened further; that coarsest level is solved exactly.
 2. Smoother.  The paper's Gauss-Seidel sweeps are sequential; this method uses
    Chebyshev smoothing of degree ``nu`` on D^{-1} A_l (D = diag A_l), on the
-   interval [hi/ratio, hi], hi = 1.1 * lambda_est.  lambda_est is the pencil
-   Rayleigh quotient v^T A v / v^T D v after ``power_iters`` steps of the
-   power method on D^{-1} A_l started from v0 = (-1)^{i_1+...+i_d} in every
-   component.  One smoothing application (degree nu) replaces each of the
+   interval [hi/ratio, hi], hi = 1.1 * lambda_est.  lambda_est is the
+   largest Ritz value of ``lanczos_steps`` steps of the Lanczos process on
+   D^{-1} A_l in the D inner product (no reorthogonalisation), started from
+   v0 = (-1)^{i_1+...+i_d} in every component.  One smoothing application (degree nu) replaces each of the
    paper's Gauss-Seidel sweeps: before the coarse correction on every level,
-   and after it on all levels but the finest.
+   and after it on all levels but the finest.  Levels below the finest may
+   use their own degree ``nu_coarse`` (None: the same nu everywhere).
 3. Finest-level post-smoother: ``krylov_steps`` (default p) steps of GMRES on
    the error equation with zero initial guess, right-preconditioned by
    T = I_d (x) T_m(m_{p-1})^{(x) d} (Sec. 6.1), Arnoldi by classical
@@ -61,7 +62,7 @@ class Level:
 
 
 def build_hierarchy(d, p, n, alpha, beta, transfer="knot", coarse_max_dofs=1000,
-                    power_iters=10, nu=3, ratio=30.0):
+                    lanczos_steps=20, nu=3, ratio=30.0, nu_coarse=None):
     """List of Level objects, finest first."""
     mats = mass_adv_stiff(n, p)
     levels = [Level(d, p, n, alpha, beta, mats)]
@@ -84,11 +85,11 @@ def build_hierarchy(d, p, n, alpha, beta, transfer="knot", coarse_max_dofs=1000,
         L.P = P
         cm = tuple(P.T @ X @ P for X in (L.M, L.A, L.S))
         levels.append(Level(d, p, nc, alpha, beta, cm))
-    for L in levels[:-1]:
-        L.lam = power_estimate(L, power_iters)
+    for l, L in enumerate(levels[:-1]):
+        L.lam = lanczos_estimate(L, lanczos_steps)
         L.hi = 1.1 * L.lam
         L.lo = L.hi / ratio
-        L.nu = nu
+        L.nu = nu if l == 0 or nu_coarse is None else nu_coarse
     C = levels[-1]
     C.coarse_factor = sla.cho_factor(C.K.toarray())
     return levels
@@ -101,13 +102,30 @@ def start_vector(d, m):
     return np.tile(v, d)
 
 
-def power_estimate(L, iters):
-    """Pencil Rayleigh quotient after ``iters`` power steps on D^{-1} K."""
+def lanczos_estimate(L, steps):
+    """Largest Ritz value of D^{-1} K on the Krylov space of dimension
+    ``steps`` from the start vector.  D^{-1} K is self-adjoint in the inner
+    product <u, v>_D = u^T D v, so the Lanczos three-term recurrence in that
+    inner product tridiagonalises it: with q_0 = v0 / |v0|_D,
+        alpha_j = q_j^T K q_j,
+        w = D^{-1} K q_j - alpha_j q_j - beta_j q_{j-1},
+        beta_{j+1} = |w|_D,  q_{j+1} = w / beta_{j+1}."""
     v = start_vector(L.d, L.m)
-    for _ in range(iters):
-        w = (L.K @ v) / L.D
-        v = w / np.linalg.norm(w)
-    return (v @ (L.K @ v)) / (v @ (L.D * v))
+    q = v / np.sqrt(v @ (L.D * v))
+    qprev = np.zeros_like(q)
+    alpha, beta = [], [0.0]
+    for _ in range(steps):
+        Kq = L.K @ q
+        a = q @ Kq
+        w = Kq / L.D - a * q - beta[-1] * qprev
+        alpha.append(a)
+        b = np.sqrt(w @ (L.D * w))
+        beta.append(b)
+        if b == 0.0:
+            break
+        qprev, q = q, w / b
+    k = len(alpha)
+    return sla.eigvalsh_tridiagonal(np.array(alpha), np.array(beta[1:k]))[-1]
 
 
 def chebyshev(L, x, b, nu=None):
@@ -169,10 +187,10 @@ class Method:
     of the preconditioner, ``solve`` the outer flexible CG."""
 
     def __init__(self, d, p, n, alpha, beta, transfer="knot", coarse_max_dofs=1000,
-                 nu=3, ratio=30.0, power_iters=10, krylov_steps=None):
+                 nu=3, ratio=30.0, lanczos_steps=20, krylov_steps=None, nu_coarse=None):
         self.d, self.p, self.n = d, p, n
         self.levels = build_hierarchy(d, p, n, alpha, beta, transfer, coarse_max_dofs,
-                                      power_iters, nu, ratio)
+                                      lanczos_steps, nu, ratio, nu_coarse)
         self.krylov_steps = p if krylov_steps is None else krylov_steps
         self.T, self.Tsolve = t_operator(d, p, self.levels[0].m)
         self.K = self.levels[0].K

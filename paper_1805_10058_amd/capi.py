@@ -38,8 +38,8 @@ class cd_problem(ctypes.Structure):
 class cd_options(ctypes.Structure):
     _fields_ = [("method", ctypes.c_int), ("transfer", ctypes.c_int), ("precision", ctypes.c_int),
                 ("rtol", ctypes.c_double), ("max_iter", ctypes.c_int), ("coarse_max_dofs", ctypes.c_int),
-                ("cheb_degree", ctypes.c_int), ("cheb_ratio", ctypes.c_double), ("power_iters", ctypes.c_int),
-                ("krylov_steps", ctypes.c_int), ("graphs", ctypes.c_int)]
+                ("cheb_degree", ctypes.c_int), ("cheb_ratio", ctypes.c_double), ("lanczos_steps", ctypes.c_int),
+                ("krylov_steps", ctypes.c_int), ("graphs", ctypes.c_int), ("cheb_degree_coarse", ctypes.c_int)]
 
 
 class cd_kernel_stats(ctypes.Structure):

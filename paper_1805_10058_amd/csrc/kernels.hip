@@ -1039,6 +1039,21 @@ __global__ __launch_bounds__(kThreads) void k_diag_dot(OpDev<T> op, const T* __r
     if (threadIdx.x == 0) part[blockIdx.x] = s;
 }
 
+// One Lanczos step on D^{-1} A in the D inner product: w holds A q on entry
+// and w = D^{-1} A q - alpha q - beta qp on exit, beta = sqrt(beta2).
+__global__ __launch_bounds__(kThreads) void k_lanczos_step(OpDev<double> op, const double* __restrict__ alpha,
+                                                           const double* __restrict__ beta2,
+                                                           const double* __restrict__ q,
+                                                           const double* __restrict__ qp, double* __restrict__ w,
+                                                           size_t n) {
+    const double a = alpha[0], b = sqrt(beta2[0]);
+    for (size_t id = size_t(blockIdx.x) * kThreads + threadIdx.x; id < n; id += size_t(gridDim.x) * kThreads) {
+        int c, i0, i1, i2;
+        unflatten(op, id, c, i0, i1, i2);
+        w[id] = w[id] / diag_entry(op, c, i0, i1, i2) - a * q[id] - b * qp[id];
+    }
+}
+
 template <typename T>
 __global__ __launch_bounds__(kThreads) void k_cheb_first(OpDev<T> op, const T* __restrict__ b, T* __restrict__ u,
                                                          T* __restrict__ x, T inv_theta, size_t n) {
@@ -1522,6 +1537,13 @@ void launch_diag_dot(const OpDev<T>& op, const T* x, double* part, hipStream_t s
     const size_t n = op_len(op);
     hipLaunchKernelGGL(k_diag_dot<T>, dim3(reduce_blocks(n)), dim3(kThreads), 0, s, op, x, n, part);
     check_launch("diag_dot");
+}
+
+void launch_lanczos_step(const OpDev<double>& op, const double* alpha, const double* beta2, const double* q,
+                         const double* qp, double* w, hipStream_t s) {
+    const size_t n = op_len(op);
+    hipLaunchKernelGGL(k_lanczos_step, dim3(grid_for(n)), dim3(kThreads), 0, s, op, alpha, beta2, q, qp, w, n);
+    check_launch("lanczos_step");
 }
 
 template <typename T>

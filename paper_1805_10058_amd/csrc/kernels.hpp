@@ -128,6 +128,10 @@ void launch_diag_scale(const OpDev<T>& op, bool inv, const T* x, T* y, hipStream
 // part[block] = sum D x^2 (FP64)
 template <typename T>
 void launch_diag_dot(const OpDev<T>& op, const T* x, double* part, hipStream_t s);
+// Lanczos step on D^{-1} A (D inner product): w = D^{-1} w - alpha q - sqrt(beta2) qp,
+// with alpha, beta2 read from device memory
+void launch_lanczos_step(const OpDev<double>& op, const double* alpha, const double* beta2, const double* q,
+                         const double* qp, double* w, hipStream_t s);
 // First Chebyshev step from x = 0: u = D^{-1} b / theta; x = u
 template <typename T>
 void launch_cheb_first(const OpDev<T>& op, const T* b, T* u, T* x, T inv_theta, hipStream_t s);

@@ -225,9 +225,10 @@ void validate(const cd_problem* pr, const cd_options* op) {
     if (op->precision != CD_FP64 && op->precision != CD_MIXED_FP32) throw CdError(CD_EINVAL, "unknown precision");
     if (!(op->rtol > 0.0)) throw CdError(CD_EINVAL, "rtol must be positive");
     if (op->max_iter < 1) throw CdError(CD_EINVAL, "max_iter must be >= 1");
-    if (op->cheb_degree < 1 || op->cheb_degree > 32) throw CdError(CD_EINVAL, "cheb_degree must be in 1..32");
+    if (op->cheb_degree < 1 || op->cheb_degree > 128) throw CdError(CD_EINVAL, "cheb_degree must be in 1..128");
+    if (op->cheb_degree_coarse > 128) throw CdError(CD_EINVAL, "cheb_degree_coarse must be at most 128");
     if (!(op->cheb_ratio > 1.0)) throw CdError(CD_EINVAL, "cheb_ratio must be > 1");
-    if (op->power_iters < 1) throw CdError(CD_EINVAL, "power_iters must be >= 1");
+    if (op->lanczos_steps < 1 || op->lanczos_steps > 200) throw CdError(CD_EINVAL, "lanczos_steps must be in 1..200");
     if (op->krylov_steps > 7) throw CdError(CD_EINVAL, "krylov_steps must be <= 7");
     if (op->graphs != 0 && op->graphs != 1) throw CdError(CD_EINVAL, "graphs must be 0 or 1");
     if (op->coarse_max_dofs < 1 || op->coarse_max_dofs > 8192)
@@ -529,7 +530,8 @@ void tsolve_op(cd_solver* s, const T* v, T* tmp, T* z) {
 // ---- V-cycle pieces ------------------------------------------------------------
 
 // Chebyshev smoothing on level l (Sec. 6.1 smoother reading): cheb_degree
-// steps on D^{-1} A_l, interval [lo, hi].  Starts from zero when x == nullptr
+// steps on D^{-1} A_l on the finest level, cheb_degree_coarse (when set) on
+// the others, interval [lo, hi].  Starts from zero when x == nullptr
 // (first step without an operator apply), else from *x; the result pointer
 // is returned (one of the level's two iterate buffers).
 template <typename T>
@@ -539,7 +541,7 @@ T* chebyshev(cd_solver* s, int l, const T* b, T* x, T* other, T* u, bool from_ze
     const double theta = 0.5 * (L.hi + L.lo), delta = 0.5 * (L.hi - L.lo);
     const double sigma = theta / delta;
     double rho = 1.0 / sigma;
-    const int nu = s->opt.cheb_degree;
+    const int nu = (l > 0 && s->opt.cheb_degree_coarse > 0) ? s->opt.cheb_degree_coarse : s->opt.cheb_degree;
     T* cur = x;
     T* nxt = other;
     if (from_zero) {
@@ -659,17 +661,50 @@ void precondition(cd_solver* s, const double* r, double* z, const double* q = nu
     }
 }
 
-// Smoother eigenvalue bounds: power method on D^{-1} A_l from
-// v0 = (-1)^{i_1+...+i_d}, then the pencil Rayleigh quotient.
+// Largest eigenvalue of the symmetric tridiagonal matrix with diagonal a[0..k)
+// and off-diagonal b[1..k) (b[i] couples rows i-1 and i), by bisection on the
+// Sturm count: the number of negative pivots of T - x I is the number of
+// eigenvalues below x.
+double tridiag_max_eig(const std::vector<double>& a, const std::vector<double>& b) {
+    const int k = int(a.size());
+    auto below = [&](double x) {
+        int cnt = 0;
+        double d = 1.0;
+        for (int i = 0; i < k; ++i) {
+            d = a[i] - x - (i > 0 ? b[i] * b[i] / d : 0.0);
+            if (d == 0.0) d = -1e-300;
+            if (d < 0.0) ++cnt;
+        }
+        return cnt;
+    };
+    double lo = a[0], hi = a[0];
+    for (int i = 0; i < k; ++i) {
+        const double r = (i > 0 ? std::fabs(b[i]) : 0.0) + (i + 1 < k ? std::fabs(b[i + 1]) : 0.0);
+        lo = std::min(lo, a[i] - r);
+        hi = std::max(hi, a[i] + r);
+    }
+    for (int it = 0; it < 200 && hi - lo > 1e-16 * std::fabs(hi); ++it) {
+        const double mid = 0.5 * (lo + hi);
+        if (below(mid) >= k) hi = mid; else lo = mid;
+    }
+    return hi;
+}
+
+// Smoother eigenvalue bounds: lanczos_steps steps of Lanczos on D^{-1} A_l in
+// the D inner product (no reorthogonalisation) from v0 = (-1)^{i_1+...+i_d}
+// in every component; the estimate is the largest Ritz value.  The
+// recurrence coefficients stay on the device until the last step.
 void estimate_bounds(cd_solver* s) {
     hipStream_t st = s->stream;
     const int L = int(s->lv.size());
+    const int ks = s->opt.lanczos_steps;
     DevArena tmp;
-    double* v = tmp.alloc<double>(s->N);
+    double* qa = tmp.alloc<double>(s->N);
+    double* qb = tmp.alloc<double>(s->N);
     double* w = tmp.alloc<double>(s->N);
     const int nbmax = std::max(cd::reduce_blocks(s->N), cd::apply_blocks<double>(s->ld64[0].op));
     double* part = tmp.alloc<double>(nbmax);
-    double* res = tmp.alloc<double>(2);
+    double* coef = tmp.alloc<double>(2 * size_t(ks) + 1);  // alpha[0..ks), beta2[0..ks]
     for (int l = 0; l < L - 1; ++l) {
         LevelHost& H = s->lv[l];
         const cd::OpDev<double>& op = s->ld64[l].op;
@@ -685,23 +720,34 @@ void estimate_bounds(cd_solver* s) {
             const int i0 = int(rem / m1);
             v0[id] = ((i0 + i1 + i2) % 2 == 0) ? 1.0 : -1.0;
         }
-        hip_check(hipMemcpyAsync(v, v0.data(), n * sizeof(double), hipMemcpyHostToDevice, st), "upload v0");
+        hip_check(hipMemcpyAsync(w, v0.data(), n * sizeof(double), hipMemcpyHostToDevice, st), "upload v0");
         const int nbr = cd::reduce_blocks(n);
-        for (int it = 0; it < s->opt.power_iters; ++it) {
-            cd::launch_apply<double>(op, kApplyY, v, w, nullptr, nullptr, nullptr, 0.0, 0.0, nullptr, st);
-            cd::launch_diag_scale<double>(op, true, w, w, st);
-            cd::launch_dot_partial<double, double>(w, w, n, part, st);
-            cd::launch_normalize<double>(part, nbr, w, v, n, st);
+        const int nba = cd::apply_blocks<double>(op);
+        double* alpha = coef;
+        double* beta2 = coef + ks;
+        cd::launch_fill<double>(qa, 0.0, n, st);
+        cd::launch_fill<double>(beta2, 0.0, 1, st);
+        cd::launch_diag_dot<double>(op, w, part, st);
+        cd::launch_normalize<double>(part, nbr, w, qb, n, st);
+        // qa = q_{j-1}, qb = q_j
+        for (int j = 0; j < ks; ++j) {
+            cd::launch_apply<double>(op, kApplyYDot, qb, w, nullptr, nullptr, nullptr, 0.0, 0.0, part, st);
+            cd::launch_finalize(part, nba, alpha + j, st);
+            cd::launch_lanczos_step(op, alpha + j, beta2 + j, qb, qa, w, st);
+            cd::launch_diag_dot<double>(op, w, part, st);
+            cd::launch_finalize(part, nbr, beta2 + j + 1, st);
+            cd::launch_normalize<double>(part, nbr, w, qa, n, st);
+            std::swap(qa, qb);
         }
-        cd::launch_apply<double>(op, kApplyYDot, v, w, nullptr, nullptr, nullptr, 0.0, 0.0, part, st);
-        cd::launch_finalize(part, cd::apply_blocks<double>(op), res, st);
-        cd::launch_diag_dot<double>(op, v, part, st);
-        cd::launch_finalize(part, nbr, res + 1, st);
-        double h[2];
-        hip_check(hipMemcpyAsync(h, res, 2 * sizeof(double), hipMemcpyDeviceToHost, st), "read bounds");
+        std::vector<double> h(2 * size_t(ks) + 1);
+        hip_check(hipMemcpyAsync(h.data(), coef, h.size() * sizeof(double), hipMemcpyDeviceToHost, st),
+                  "read lanczos coefficients");
         hip_check(hipStreamSynchronize(st), "sync");
-        if (!(h[0] > 0.0) || !(h[1] > 0.0)) throw CdError(CD_EINVAL, "operator is not positive definite");
-        H.lam = h[0] / h[1];
+        std::vector<double> a(h.begin(), h.begin() + ks), b(ks, 0.0);
+        for (int j = 1; j < ks; ++j) b[j] = std::sqrt(std::max(h[ks + j], 0.0));
+        if (!(a[0] > 0.0)) throw CdError(CD_EINVAL, "operator is not positive definite");
+        H.lam = tridiag_max_eig(a, b);
+        if (!(H.lam > 0.0) || !std::isfinite(H.lam)) throw CdError(CD_EINVAL, "operator is not positive definite");
         H.hi = 1.1 * H.lam;
         H.lo = H.hi / s->opt.cheb_ratio;
     }
@@ -983,11 +1029,12 @@ void cd_default_options(cd_options* o) {
     o->rtol = 1e-8;
     o->max_iter = 10000;
     o->coarse_max_dofs = 2500;
-    o->cheb_degree = 8;
-    o->cheb_ratio = 30.0;
-    o->power_iters = 10;
+    o->cheb_degree = 48;
+    o->cheb_ratio = 1000.0;
+    o->lanczos_steps = 20;
     o->krylov_steps = -1;
     o->graphs = 1;
+    o->cheb_degree_coarse = 16;
 }
 
 size_t cd_num_dofs(const cd_problem* pr) {

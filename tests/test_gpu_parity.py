@@ -48,8 +48,9 @@ def setup_case(case, precision=capi.CD_FP64, **kw):
         opt = capi.options(transfer=tr, coarse_max_dofs=cmax, precision=precision, **kw)
         s = capi.Solver(capi.problem(d, p, n, 1.0, beta), opt, stream())
         m = method.Method(d, p, n, 1.0, beta, transfer=xfer, coarse_max_dofs=cmax,
-                          nu=opt.cheb_degree, ratio=opt.cheb_ratio, power_iters=opt.power_iters,
-                          krylov_steps=None if opt.krylov_steps < 0 else opt.krylov_steps)
+                          nu=opt.cheb_degree, ratio=opt.cheb_ratio, lanczos_steps=opt.lanczos_steps,
+                          krylov_steps=None if opt.krylov_steps < 0 else opt.krylov_steps,
+                          nu_coarse=opt.cheb_degree_coarse if opt.cheb_degree_coarse > 0 else None)
         _cache[key] = (s, m)
     return _cache[key]
 

@@ -33,13 +33,42 @@ def test_chebyshev_error_polynomial():
         np.testing.assert_allclose(E, Pfull[:, cols], atol=1e-12)
 
 
-def test_power_estimate_is_rayleigh_lower_bound():
+def _power_rayleigh(L, iters):
+    # Rayleigh quotient of the pencil (K, D) at (D^{-1} K)^iters v0
+    v = method.start_vector(L.d, L.m)
+    for _ in range(iters):
+        v = (L.K @ v) / L.D
+        v /= np.linalg.norm(v)
+    return (v @ (L.K @ v)) / (v @ (L.D * v))
+
+
+@pytest.mark.parametrize("d,p,n,beta", [(2, 3, 16, 0.1), (2, 1, 20, 0.3), (3, 2, 6, 0.05)])
+def test_lanczos_estimate_bounded_by_krylov_optimality(d, p, n, beta):
+    # The largest Ritz value maximises the Rayleigh quotient over the Krylov
+    # space K_k(D^{-1} K, v0), which holds the power iterate after k-1 steps:
+    # power estimate <= Ritz value <= largest pencil eigenvalue.
+    meth = method.Method(d, p, n, 1.0, beta, coarse_max_dofs=10**6)
+    L = meth.levels[0]
+    lmax = sla.eigh(L.K.toarray(), np.diag(L.D), eigvals_only=True)[-1]
+    prev = 0.0
+    for k in (1, 2, 5, 10, 20):
+        th = method.lanczos_estimate(L, k)
+        assert th <= lmax * (1 + 1e-12)
+        assert th >= _power_rayleigh(L, k - 1) * (1 - 1e-12), k
+        assert th >= prev * (1 - 1e-12), k
+        prev = th
+    # one step: the Rayleigh quotient of v0 itself
+    v0 = method.start_vector(d, L.m)
+    assert abs(method.lanczos_estimate(L, 1) - (v0 @ (L.K @ v0)) / (v0 @ (L.D * v0))) <= 1e-13 * lmax
+    # a full Krylov space reaches the largest eigenvalue the start vector sees
+    assert method.lanczos_estimate(L, 60) >= 0.999 * lmax
+
+
+def test_lanczos_estimate_on_levels_is_close_to_lambda_max():
     meth = method.Method(2, 3, 16, 1.0, 0.1, coarse_max_dofs=100)
     for L in meth.levels[:-1]:
-        K = L.K.toarray()
-        lmax = sla.eigh(K, np.diag(L.D), eigvals_only=True)[-1]
-        assert L.lam <= lmax * (1 + 1e-12)
-        assert L.lam >= 0.8 * lmax
+        lmax = sla.eigh(L.K.toarray(), np.diag(L.D), eigvals_only=True)[-1]
+        assert 0.95 * lmax <= L.lam <= lmax * (1 + 1e-12)
 
 
 def test_gmres_matches_bruteforce_krylov_minimization():
@@ -73,6 +102,38 @@ def test_single_level_vcycle_is_exact_solve():
     assert len(meth.levels) == 1
     b = _rand(meth.K.shape[0], 4)
     np.testing.assert_allclose(meth.vcycle(b), solvers.solve_direct(meth.K, b), rtol=1e-12, atol=1e-14)
+
+
+def _vcycle_matrix(meth):
+    N = meth.K.shape[0]
+    return np.column_stack([meth.vcycle(e) for e in np.eye(N)])
+
+
+def test_coarse_degree_keeps_vcycle_symmetric_positive_definite():
+    # With Chebyshev post-smoothing everywhere, the same polynomial before and
+    # after each coarse correction makes the V-cycle a symmetric positive
+    # definite operator whatever the per-level degrees are; a coarse degree
+    # applied on one side only breaks the symmetry.  Definiteness also needs
+    # every level's interval to cover its spectrum, hence converged estimates.
+    kw = dict(coarse_max_dofs=40, krylov_steps=0, lanczos_steps=100)
+    m1 = method.Method(2, 2, 16, 1.0, 0.1, nu=4, nu_coarse=2, **kw)
+    m2 = method.Method(2, 2, 16, 1.0, 0.1, nu=4, **kw)
+    assert len(m1.levels) >= 3
+    assert [L.nu for L in m1.levels[:-1]] == [4] + [2] * (len(m1.levels) - 2)
+    B1, B2 = _vcycle_matrix(m1), _vcycle_matrix(m2)
+    assert np.abs(B1 - B1.T).max() <= 1e-12 * np.abs(B1).max()
+    assert np.linalg.eigvalsh(0.5 * (B1 + B1.T)).min() > 0
+    assert np.abs(B1 - B2).max() > 1e-6 * np.abs(B2).max()
+
+
+def test_coarse_degree_unused_with_two_levels():
+    # Two levels: the finest is the only smoothed one, the coarsest is exact.
+    kw = dict(coarse_max_dofs=300)
+    m1 = method.Method(2, 3, 16, 1.0, 0.1, nu=5, nu_coarse=1, **kw)
+    m2 = method.Method(2, 3, 16, 1.0, 0.1, nu=5, **kw)
+    assert len(m1.levels) == 2
+    b = _rand(m1.K.shape[0], 12)
+    np.testing.assert_array_equal(m1.vcycle(b), m2.vcycle(b))
 
 
 @pytest.mark.parametrize("d,p,n,beta", [(2, 2, 16, 1.0), (2, 3, 16, 0.1), (3, 2, 8, 0.1), (3, 3, 4, 0.01)])
