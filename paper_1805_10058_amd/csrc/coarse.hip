@@ -4,8 +4,8 @@
 // parts (trailing updates of the factorization, block updates of the
 // substitutions) run on the FP64 matrix cores: v_mfma_f64_16x16x4f64.
 //
-// The matrix is padded to Np = 32 * ceil(N / 32) with an identity tail, so
-// every tile is a full 32 x 32 block.  Row-major storage, leading dimension Np.
+// The matrix comes padded to Np = 32 * ceil(N / 32) with an identity tail,
+// so every tile is a full 32 x 32 block.  Row-major storage, leading dimension Np.
 #include <hip/hip_runtime.h>
 
 #include <stdexcept>
@@ -181,13 +181,6 @@ __global__ __launch_bounds__(256) void k_gemm_rows(const double* A, double* B, i
     for (int q = 0; q < 4; ++q) C[size_t(4 * q + l / 16) * ld + l % 16] = acc[q];
 }
 
-__global__ __launch_bounds__(256) void k_pad_identity(const double* K, int N, double* A, int ld) {
-    const size_t id = size_t(blockIdx.x) * 256 + threadIdx.x;
-    if (id >= size_t(ld) * ld) return;
-    const int r = int(id / ld), c = int(id % ld);
-    A[id] = (r < N && c < N) ? K[size_t(r) * N + c] : (r == c ? 1.0 : 0.0);
-}
-
 __global__ __launch_bounds__(256) void k_identity(double* B, int ld) {
     const size_t id = size_t(blockIdx.x) * 256 + threadIdx.x;
     if (id >= size_t(ld) * ld) return;
@@ -198,13 +191,11 @@ __global__ __launch_bounds__(256) void k_identity(double* B, int ld) {
 
 int coarse_padded(int N) { return NB * ((N + NB - 1) / NB); }
 
-void coarse_inverse(const double* K, int N, double* A, double* Kinv, int* flag, hipStream_t s) {
+void coarse_inverse(double* A, int N, double* Kinv, int* flag, hipStream_t s) {
     const int ld = coarse_padded(N);
     const int nblk = ld / NB;
     const size_t tot = size_t(ld) * ld;
     const dim3 gfill((tot + 255) / 256);
-    hipLaunchKernelGGL(k_pad_identity, gfill, dim3(256), 0, s, K, N, A, ld);
-    check("coarse pad");
     for (int k = 0; k < nblk; ++k) {
         hipLaunchKernelGGL(k_potrf_tile, dim3(1), dim3(256), 0, s, A, ld, k, flag);
         const int nrem = nblk - 1 - k;

@@ -1039,6 +1039,52 @@ __global__ __launch_bounds__(kThreads) void k_diag_dot(OpDev<T> op, const T* __r
     if (threadIdx.x == 0) part[blockIdx.x] = s;
 }
 
+// Dense form of a level operator, padded to ld x ld with an identity tail.
+// Entry ((c, i), (e, j)) of the block operator: on the diagonal blocks
+// beta * (S on axis c, M elsewhere) + alpha * sum over the other axes f of
+// (S on f, M elsewhere); off the diagonal (alpha - beta) * (A on axes c and
+// e, M elsewhere), each a product of 1D entries X(i_l, j_l).
+__global__ __launch_bounds__(kThreads) void k_dense_operator(OpDev<double> op, double* __restrict__ out, int ld,
+                                                             size_t N) {
+    const size_t G = size_t(op.m[0]) * op.m[1] * op.m[2];
+    const size_t total = size_t(ld) * ld;
+    for (size_t id = size_t(blockIdx.x) * kThreads + threadIdx.x; id < total; id += size_t(gridDim.x) * kThreads) {
+        const size_t row = id / ld, col = id % ld;
+        double v = (row == col) ? 1.0 : 0.0;
+        if (row < N && col < N) {
+            int c, i[3], e, j[3];
+            unflatten(op, row, c, i[0], i[1], i[2]);
+            unflatten(op, col, e, j[0], j[1], j[2]);
+            bool near = true;
+            double Mv[3], Av[3], Sv[3];
+            for (int l = 0; l < op.dim; ++l) {
+                const int k = j[l] - i[l] + op.hb;
+                if (k < 0 || k > 2 * op.hb) {
+                    near = false;
+                    break;
+                }
+                Mv[l] = band_at(op, l, 0, k, i[l]);
+                Av[l] = band_at(op, l, 1, k, i[l]);
+                Sv[l] = band_at(op, l, 2, k, i[l]);
+            }
+            v = 0.0;
+            if (near) {
+                if (c == e) {
+                    for (int f = 0; f < op.dim; ++f) {
+                        double t = (f == c) ? op.beta : op.alpha;
+                        for (int l = 0; l < op.dim; ++l) t *= (l == f) ? Sv[l] : Mv[l];
+                        v += t;
+                    }
+                } else {
+                    v = op.alpha - op.beta;
+                    for (int l = 0; l < op.dim; ++l) v *= (l == c || l == e) ? Av[l] : Mv[l];
+                }
+            }
+        }
+        out[id] = v;
+    }
+}
+
 // One Lanczos step on D^{-1} A in the D inner product: w holds A q on entry
 // and w = D^{-1} A q - alpha q - beta qp on exit, beta = sqrt(beta2).
 __global__ __launch_bounds__(kThreads) void k_lanczos_step(OpDev<double> op, const double* __restrict__ alpha,
@@ -1537,6 +1583,13 @@ void launch_diag_dot(const OpDev<T>& op, const T* x, double* part, hipStream_t s
     const size_t n = op_len(op);
     hipLaunchKernelGGL(k_diag_dot<T>, dim3(reduce_blocks(n)), dim3(kThreads), 0, s, op, x, n, part);
     check_launch("diag_dot");
+}
+
+void launch_dense_operator(const OpDev<double>& op, double* out, int ld, hipStream_t s) {
+    const size_t N = op_len(op);
+    if (size_t(ld) < N) throw std::runtime_error("dense_operator: padded order below the operator's");
+    hipLaunchKernelGGL(k_dense_operator, dim3(grid_for(size_t(ld) * ld)), dim3(kThreads), 0, s, op, out, ld, N);
+    check_launch("dense_operator");
 }
 
 void launch_lanczos_step(const OpDev<double>& op, const double* alpha, const double* beta2, const double* q,

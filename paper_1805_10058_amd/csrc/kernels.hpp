@@ -128,6 +128,9 @@ void launch_diag_scale(const OpDev<T>& op, bool inv, const T* x, T* y, hipStream
 // part[block] = sum D x^2 (FP64)
 template <typename T>
 void launch_diag_dot(const OpDev<T>& op, const T* x, double* part, hipStream_t s);
+// out (ld x ld, row-major) = the level operator as a dense matrix in its
+// leading block, identity in the tail; ld >= the operator's order
+void launch_dense_operator(const OpDev<double>& op, double* out, int ld, hipStream_t s);
 // Lanczos step on D^{-1} A (D inner product): w = D^{-1} w - alpha q - sqrt(beta2) qp,
 // with alpha, beta2 read from device memory
 void launch_lanczos_step(const OpDev<double>& op, const double* alpha, const double* beta2, const double* q,

@@ -339,56 +339,4 @@ int recurrence_warmup(const TFactor& F, double tol) {
     return std::min(m, worst + bw + 2);
 }
 
-std::vector<double> dense_operator(int d, const int* m, const Band* M, const Band* A, const Band* S,
-                                   double alpha, double beta) {
-    size_t G = 1;
-    for (int l = 0; l < d; ++l) G *= size_t(m[l]);
-    const size_t N = size_t(d) * G;
-    std::vector<double> K(N * N, 0.0);
-    auto entry = [&](char w, int l, int i, int j) -> double {
-        const Band& B = (w == 'M') ? M[l] : (w == 'A') ? A[l] : S[l];
-        return B.get(i, j);
-    };
-    std::vector<int> ii(d), jj(d);
-    for (int c = 0; c < d; ++c)
-        for (int e = 0; e < d; ++e) {
-            // terms of block (c, e)
-            std::vector<std::pair<double, std::vector<char>>> terms;
-            if (c == e) {
-                for (int f = 0; f < d; ++f) {
-                    std::vector<char> w(d, 'M');
-                    w[f] = 'S';
-                    terms.push_back({f == c ? beta : alpha, w});
-                }
-            } else {
-                std::vector<char> w(d, 'M');
-                w[c] = 'A';
-                w[e] = 'A';
-                terms.push_back({alpha - beta, w});
-            }
-            for (size_t r = 0; r < G; ++r) {
-                size_t t = r;
-                for (int l = d - 1; l >= 0; --l) { ii[l] = int(t % m[l]); t /= m[l]; }
-                for (size_t q = 0; q < G; ++q) {
-                    size_t u = q;
-                    bool far = false;
-                    for (int l = d - 1; l >= 0; --l) {
-                        jj[l] = int(u % m[l]);
-                        u /= m[l];
-                        if (std::abs(jj[l] - ii[l]) > M[l].hb) far = true;
-                    }
-                    if (far) continue;
-                    double v = 0.0;
-                    for (auto& tm : terms) {
-                        double pr = tm.first;
-                        for (int l = 0; l < d; ++l) pr *= entry(tm.second[l], l, ii[l], jj[l]);
-                        v += pr;
-                    }
-                    K[(c * G + r) * N + (e * G + q)] = v;
-                }
-            }
-        }
-    return K;
-}
-
 }  // namespace cd

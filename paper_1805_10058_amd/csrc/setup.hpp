@@ -70,10 +70,4 @@ TFactor toeplitz_factor(int m, int p);
 // early from a zero state agrees with the exact solve to `tol`.
 int recurrence_warmup(const TFactor& F, double tol);
 
-// Dense coarse system matrix (N x N, row-major) of the curl-div block form,
-// built from the 1D matrices of each axis (block (c,c): beta D_c + alpha
-// sum_{e!=c} D_e; block (c,e): (alpha-beta) A on axes c,e and M elsewhere).
-std::vector<double> dense_operator(int d, const int* m, const Band* M, const Band* A, const Band* S,
-                                   double alpha, double beta);
-
 }  // namespace cd

@@ -797,20 +797,18 @@ void create(cd_solver* s, const cd_problem* pr, const cd_options* op, void* stre
         s->tfd64[l] = make_tfac<double>(s, s->tf[l], st);
         s->tfd32[l] = make_tfac<float>(s, s->tf[l], st);
     }
-    // coarse level: dense operator (host), Cholesky factorization and inverse
+    // coarse level: dense operator, Cholesky factorization and inverse, all
     // on the GPU (FP64 MFMA); the factor workspace is released after setup
     {
-        const LevelHost& C = s->lv.back();
-        const std::vector<double> K = cd::dense_operator(s->d, C.m, C.M, C.A, C.S, s->prob.alpha, s->prob.beta);
         const int ld = cd::coarse_padded(s->Nc);
         s->ldK = ld;
         s->Kinv = s->arena.alloc<double>(size_t(ld) * ld);
         DevArena tmp;
-        double* Kd = tmp.upload(K, st);
         double* fac = tmp.alloc<double>(size_t(ld) * ld);
         int* flag = tmp.alloc<int>(1);
         hip_check(hipMemsetAsync(flag, 0, sizeof(int), st), "hipMemsetAsync");
-        cd::coarse_inverse(Kd, s->Nc, fac, s->Kinv, flag, st);
+        cd::launch_dense_operator(s->ld64.back().op, fac, ld, st);
+        cd::coarse_inverse(fac, s->Nc, s->Kinv, flag, st);
         int hflag = 0;
         hip_check(hipMemcpyAsync(&hflag, flag, sizeof(int), hipMemcpyDeviceToHost, st), "read");
         hip_check(hipStreamSynchronize(st), "sync");
