@@ -498,7 +498,13 @@ __global__ __launch_bounds__(kThreads) void k_apply2d(OpDev<T> op, const T* __re
     const int m1 = op.m[0], m2 = op.m[1];
     const int G = m1 * m2;
     const int nt2 = (m2 + kT2 - 1) / kT2;
-    const int o1 = (blockIdx.x / nt2) * kT1, o2 = (blockIdx.x % nt2) * kT2;
+    // blocks go to the XCDs round robin; each XCD takes a contiguous run of
+    // row-major tiles, so most of a tile's input was written through the same
+    // L2 by the previous launch
+    const int xcd = int(blockIdx.x % kXcds), slot = int(blockIdx.x / kXcds);
+    const int per = int(gridDim.x) / kXcds, rem = int(gridDim.x) % kXcds;
+    const int tile = xcd * per + min(xcd, rem) + slot;
+    const int o1 = (tile / nt2) * kT1, o2 = (tile % nt2) * kT2;
     const int tid = threadIdx.x;
     // the thread's output point and its epilogue operands, loaded first
     const int i = tid / kT2, j = tid % kT2;

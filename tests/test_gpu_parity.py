@@ -166,6 +166,23 @@ def test_vcycle(case):
     assert relerr(host(z), m.vcycle(r)) <= 1e-10
 
 
+@pytest.mark.parametrize("case", [CASES[2], CASES[4], CASES[7]], ids=[IDS[2], IDS[4], IDS[7]])
+def test_vcycle_light_smoothing_one_degree_everywhere(case):
+    # cheb_degree_coarse = 0 keeps the finest level's degree on every level
+    s, m = setup_case(case, cheb_degree=3, cheb_degree_coarse=0, cheb_ratio=30.0)
+    assert all(L.nu == 3 for L in m.levels[:-1])
+    rng = np.random.default_rng(17)
+    for l, L in enumerate(m.levels[:-1]):
+        b, x0 = rng.uniform(-1, 1, L.K.shape[0]), rng.uniform(-1, 1, L.K.shape[0])
+        bd, xd, out = dev(b), dev(x0), empty(L.K.shape[0])
+        s.smooth(l, bd.data_ptr(), xd.data_ptr(), out.data_ptr())
+        assert relerr(host(out), method.chebyshev(L, x0, b)) <= 1e-11, l
+    r = rng.uniform(-1, 1, m.K.shape[0])
+    rd, z = dev(r), empty(m.K.shape[0])
+    s.precondition(rd.data_ptr(), z.data_ptr())
+    assert relerr(host(z), m.vcycle(r)) <= 1e-10
+
+
 @pytest.mark.parametrize("case", CASES, ids=IDS)
 def test_solve_matches_direct(case):
     s, m = setup_case(case, rtol=1e-12)
