@@ -29,6 +29,14 @@ def percentile(v, q):
     return v[lo] + (v[hi] - v[lo]) * (k - lo)
 
 
+# HBM bytes per launch of the FP32 V-cycle applies of the 2D p=3 n=256 mixed
+# solve (all levels, the timed solves' launch mix), from FETCH_SIZE and
+# WRITE_SIZE counter runs scaled by a plain copy kernel's readings (factors
+# 2.000 and 1.000): 581.9 KiB x 2 + 537.0 KiB.  The counters were read with
+# the kernels of this source; a change to k_apply2d voids the figure.
+C2_APPLY_HBM_BYTES_PER_LAUNCH = 1741471
+
+
 def cpu_baseline(cfg, its_gpu):
     """Oracle timed on the host: one full solve at beta = 1 and a bounded
     number of outer iterations at beta = 1e-4, projected to the iteration
@@ -75,6 +83,9 @@ def main():
     ap.add_argument("--batched", type=int, default=8,
                     help="also solve this many right-hand sides of the 2D workload at once through the "
                          "continuous-batching server (0: skip)")
+    ap.add_argument("--pmc-pass", action="store_true",
+                    help="only run 6 eager outer iterations of each mixed 2D workload solve (and --copy-cal): a "
+                         "short program for the HBM byte counters of the V-cycle kernels")
     ap.add_argument("--copy-cal", action="store_true",
                     help="also run a plain 256 MiB device copy 5 times (calibrates HBM byte counters)")
     args = ap.parse_args()
@@ -104,6 +115,20 @@ def main():
     def make(beta, precision):
         opt = capi.options(precision=precision, rtol=tol)
         return capi.Solver(capi.problem(d, p, n, alpha, beta), opt, st)
+
+    if args.pmc_pass:
+        # the same kernels and per-iteration launch mix as the timed solves,
+        # launched eagerly and cut to a few outer iterations
+        b0 = torch.as_tensor(ci.rhs(d, p, n, 0, dist)).cuda()
+        x0 = torch.zeros(N, dtype=torch.float64, device="cuda")
+        for beta in betas:
+            opt = capi.options(precision=capi.CD_MIXED_FP32, rtol=tol, max_iter=6, graphs=0)
+            s = capi.Solver(capi.problem(d, p, n, alpha, beta), opt, st)
+            r = s.solve(b0.data_ptr(), x0.data_ptr())
+            s.close()
+            print(f"[bench] counter pass: beta={beta} iterations={r.iterations}", file=sys.stderr, flush=True)
+        torch.cuda.synchronize()
+        return
 
     mixed = {beta: make(beta, capi.CD_MIXED_FP32) for beta in betas}
     fp64 = {beta: make(beta, capi.CD_FP64) for beta in betas}
@@ -209,10 +234,11 @@ def main():
                       "p99_ms": 1e3 * percentile(lat64, 99), "iterations": {str(b): its64[b] for b in betas},
                       "max_true_rel_residual": max(tres64)},
         "roofline": {"bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": ach / HBM_PEAK_GBS, "traffic": None,
+                     "frac": ach / HBM_PEAK_GBS, "traffic": C2_APPLY_HBM_BYTES_PER_LAUNCH,
                      "kernel": "FP32 V-cycle operator apply k_apply2d<float,3,*>, all levels, inside the timed solves "
                                f"(every {PROF_PERIOD}th outer iteration timed)",
                      "launches": launches, "avg_us": 1e3 * tot_ms / max(launches, 1),
+                     "bytes_per_launch": tot_b / max(launches, 1),
                      "per_level": {str(l): {"launches": v[0], "avg_us": 1e3 * v[1] / max(v[0], 1),
                                             "GB_s": (v[2] / (v[1] * 1e-3)) / 1e9 if v[1] > 0 else 0.0}
                                    for l, v in sorted(per_level.items())}},
