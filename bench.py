@@ -83,6 +83,10 @@ def main():
     ap.add_argument("--batched", type=int, default=8,
                     help="also solve this many right-hand sides of the 2D workload at once through the "
                          "continuous-batching server (0: skip)")
+    ap.add_argument("--only-c4-solve", action="store_true",
+                    help="run only the mixed solve of the 3D p=3 n=128 workload (beta = 1e-6)")
+    ap.add_argument("--c4-max-iter", type=int, default=20000,
+                    help="outer-iteration cap of that solve (a small cap gives a short profiling run)")
     ap.add_argument("--pmc-pass", action="store_true",
                     help="only run 6 eager outer iterations of each mixed 2D workload solve (and --copy-cal): a "
                          "short program for the HBM byte counters of the V-cycle kernels")
@@ -106,6 +110,9 @@ def main():
         copy_calibration(torch)
     if args.only_c4:
         print(json.dumps({"operator_apply_c4": c4_apply(capi, torch, st)}), flush=True)
+        return
+    if args.only_c4_solve:
+        print(json.dumps({"solve_c4": c4_solve(capi, torch, st, args.c4_max_iter)}), flush=True)
         return
     name = "c2_2d_p3_n256"
     cfg = ci.CONFIGS[name]
@@ -253,6 +260,8 @@ def main():
     if not args.no_c4:
         out["operator_apply_c4"] = c4_apply(capi, torch, st)
         log(f"3D p=3 n=128 operator apply: {out['operator_apply_c4']}")
+        out["solve_c4"] = c4_solve(capi, torch, st, args.c4_max_iter)
+        log(f"3D p=3 n=128 solve: {out['solve_c4']}")
 
     if args.serve > 0:
         # Poisson arrivals measure latency under load (throughput is then the
@@ -377,7 +386,7 @@ def copy_calibration(torch, mib=256, reps=5):
 
 def c4_apply(capi, torch, st, reps=20):
     """Operator apply A x at the 3D p=3 n=128 size (6,440,067 unknowns),
-    FP64 and FP32, kernel time from HIP events on the solver stream."""
+    FP64 and FP32, kernel time from the kernels' own wall-clock stamps."""
     d, p, n = 3, 3, 128
     opt = capi.options(method=capi.CD_METHOD_CG)
     s = capi.Solver(capi.problem(d, p, n, 1.0, 1e-6), opt, st)
@@ -398,6 +407,31 @@ def c4_apply(capi, torch, st, reps=20):
                      "TFLOP_s": flops / (stt.total_ms * 1e-3) / 1e12}
     s.close()
     return res
+
+
+def c4_solve(capi, torch, st, max_iter):
+    """One mixed-precision solve of the 3D p=3 n=128 workload (beta = 1e-6,
+    Gaussian right-hand side, rel. residual 1e-8): setup and solve times."""
+    import curldiv_inputs as ci
+
+    d, p, n, alpha, betas, dist, tol = ci.CONFIGS["c4_3d_p3_n128"]
+    N = ci.num_dofs(d, p, n)
+    b = torch.as_tensor(ci.rhs(d, p, n, 0, dist)).cuda()
+    x = torch.zeros(N, dtype=torch.float64, device="cuda")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    s = capi.Solver(capi.problem(d, p, n, alpha, betas[0]),
+                    capi.options(precision=capi.CD_MIXED_FP32, rtol=tol, max_iter=max_iter), st)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    r = s.solve(b.data_ptr(), x.data_ptr())
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    out = {"unknowns": N, "beta": betas[0], "levels": s.num_levels(), "iterations": r.iterations,
+           "status": r.status, "true_rel_residual": r.true_rel_residual, "setup_ms": 1e3 * (t1 - t0),
+           "solve_s": t2 - t1, "ms_per_iteration": 1e3 * (t2 - t1) / max(r.iterations, 1)}
+    s.close()
+    return out
 
 
 if __name__ == "__main__":
