@@ -147,8 +147,8 @@ def test_smoother_and_eigenvalue_bound(case):
     s, m = setup_case(case)
     rng = np.random.default_rng(6)
     for l, L in enumerate(m.levels[:-1]):
-        # both sides compute the bound from the same definition (power method from
-        # the same start vector), independently
+        # both sides compute the bound from the same definition (Lanczos from the
+        # same start vector, largest Ritz value), independently
         assert abs(s.get_lambda(l) - L.lam) <= 1e-10 * L.lam
         b = rng.uniform(-1, 1, L.K.shape[0])
         x0 = rng.uniform(-1, 1, L.K.shape[0])
