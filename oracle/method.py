@@ -19,7 +19,8 @@ with these readings, each also listed with its reason in the design notes:
    interval [hi/ratio, hi], hi = 1.1 * lambda_est.  lambda_est is the
    largest Ritz value of ``lanczos_steps`` steps of the Lanczos process on
    D^{-1} A_l in the D inner product (no reorthogonalisation), started from
-   v0 = (-1)^{i_1+...+i_d} in every component.  One smoothing application (degree nu) replaces each of the
+   v0 = (-1)^{i_1+...+i_d} in every component and restarted from a fixed
+   vector when the recurrence breaks down.  One smoothing application (degree nu) replaces each of the
    paper's Gauss-Seidel sweeps: before the coarse correction on every level,
    and after it on all levels but the finest.  Levels below the finest may
    use their own degree ``nu_coarse`` (None: the same nu everywhere).
@@ -102,6 +103,14 @@ def start_vector(d, m):
     return np.tile(v, d)
 
 
+def restart_vector(n):
+    """r_i = cos(0.7 i + 0.3): a fixed vector with no grid symmetry."""
+    return np.cos(0.7 * np.arange(n) + 0.3)
+
+
+LANCZOS_BREAKDOWN = 1e-10
+
+
 def lanczos_estimate(L, steps):
     """Largest Ritz value of D^{-1} K on the Krylov space of dimension
     ``steps`` from the start vector.  D^{-1} K is self-adjoint in the inner
@@ -109,9 +118,15 @@ def lanczos_estimate(L, steps):
     inner product tridiagonalises it: with q_0 = v0 / |v0|_D,
         alpha_j = q_j^T K q_j,
         w = D^{-1} K q_j - alpha_j q_j - beta_j q_{j-1},
-        beta_{j+1} = |w|_D,  q_{j+1} = w / beta_{j+1}."""
+        beta_{j+1} = |w|_D,  q_{j+1} = w / beta_{j+1}.
+    When beta_{j+1} <= 1e-10 |alpha_j| the Krylov space is invariant (the
+    symmetric start vector can span a small invariant subspace on small
+    grids): the recurrence restarts from the D-normalised restart vector with
+    beta_{j+1} = 0, so the tridiagonal matrix splits into independent runs."""
     v = start_vector(L.d, L.m)
     q = v / np.sqrt(v @ (L.D * v))
+    r = restart_vector(q.size)
+    r = r / np.sqrt(r @ (L.D * r))
     qprev = np.zeros_like(q)
     alpha, beta = [], [0.0]
     for _ in range(steps):
@@ -120,10 +135,12 @@ def lanczos_estimate(L, steps):
         w = Kq / L.D - a * q - beta[-1] * qprev
         alpha.append(a)
         b = np.sqrt(w @ (L.D * w))
-        beta.append(b)
-        if b == 0.0:
-            break
-        qprev, q = q, w / b
+        if b <= LANCZOS_BREAKDOWN * abs(a):
+            beta.append(0.0)
+            qprev, q = q, r
+        else:
+            beta.append(b)
+            qprev, q = q, w / b
     k = len(alpha)
     return sla.eigvalsh_tridiagonal(np.array(alpha), np.array(beta[1:k]))[-1]
 

@@ -1091,19 +1091,42 @@ __global__ __launch_bounds__(kThreads) void k_dense_operator(OpDev<double> op, d
     }
 }
 
+// Breakdown test of the Lanczos recurrence: beta <= kLanczosBreakdown |alpha|
+// (in squares, beta2 <= tol^2 alpha^2) means the Krylov space is invariant.
+constexpr double kLanczosBreakdown = 1e-10;
+
+__device__ inline bool lanczos_broke(double beta2, double alpha) {
+    return beta2 <= kLanczosBreakdown * kLanczosBreakdown * alpha * alpha;
+}
+
 // One Lanczos step on D^{-1} A in the D inner product: w holds A q on entry
-// and w = D^{-1} A q - alpha q - beta qp on exit, beta = sqrt(beta2).
+// and w = D^{-1} A q - alpha q - beta qp on exit, beta = sqrt(beta2), or 0
+// when the previous step broke down (q is then the restart vector).
 __global__ __launch_bounds__(kThreads) void k_lanczos_step(OpDev<double> op, const double* __restrict__ alpha,
+                                                           const double* __restrict__ alpha_prev,
                                                            const double* __restrict__ beta2,
                                                            const double* __restrict__ q,
                                                            const double* __restrict__ qp, double* __restrict__ w,
                                                            size_t n) {
-    const double a = alpha[0], b = sqrt(beta2[0]);
+    const double a = alpha[0], b = lanczos_broke(beta2[0], alpha_prev[0]) ? 0.0 : sqrt(beta2[0]);
     for (size_t id = size_t(blockIdx.x) * kThreads + threadIdx.x; id < n; id += size_t(gridDim.x) * kThreads) {
         int c, i0, i1, i2;
         unflatten(op, id, c, i0, i1, i2);
         w[id] = w[id] / diag_entry(op, c, i0, i1, i2) - a * q[id] - b * qp[id];
     }
+}
+
+// Next Lanczos vector: w / beta (beta2 = |w|_D^2), or the D-normalised
+// restart vector r when the step broke down.
+__global__ __launch_bounds__(kThreads) void k_lanczos_next(const double* __restrict__ alpha,
+                                                           const double* __restrict__ beta2,
+                                                           const double* __restrict__ w,
+                                                           const double* __restrict__ r, double* __restrict__ q,
+                                                           size_t n) {
+    const bool broke = lanczos_broke(beta2[0], alpha[0]);
+    const double sc = broke ? 0.0 : 1.0 / sqrt(beta2[0]);
+    for (size_t i = size_t(blockIdx.x) * kThreads + threadIdx.x; i < n; i += size_t(gridDim.x) * kThreads)
+        q[i] = broke ? r[i] : w[i] * sc;
 }
 
 template <typename T>
@@ -1598,11 +1621,18 @@ void launch_dense_operator(const OpDev<double>& op, double* out, int ld, hipStre
     check_launch("dense_operator");
 }
 
-void launch_lanczos_step(const OpDev<double>& op, const double* alpha, const double* beta2, const double* q,
-                         const double* qp, double* w, hipStream_t s) {
+void launch_lanczos_step(const OpDev<double>& op, const double* alpha, const double* alpha_prev, const double* beta2,
+                         const double* q, const double* qp, double* w, hipStream_t s) {
     const size_t n = op_len(op);
-    hipLaunchKernelGGL(k_lanczos_step, dim3(grid_for(n)), dim3(kThreads), 0, s, op, alpha, beta2, q, qp, w, n);
+    hipLaunchKernelGGL(k_lanczos_step, dim3(grid_for(n)), dim3(kThreads), 0, s, op, alpha, alpha_prev, beta2, q, qp,
+                       w, n);
     check_launch("lanczos_step");
+}
+
+void launch_lanczos_next(const double* alpha, const double* beta2, const double* w, const double* r, double* q,
+                         size_t n, hipStream_t s) {
+    hipLaunchKernelGGL(k_lanczos_next, dim3(grid_for(n)), dim3(kThreads), 0, s, alpha, beta2, w, r, q, n);
+    check_launch("lanczos_next");
 }
 
 template <typename T>

@@ -131,10 +131,14 @@ void launch_diag_dot(const OpDev<T>& op, const T* x, double* part, hipStream_t s
 // out (ld x ld, row-major) = the level operator as a dense matrix in its
 // leading block, identity in the tail; ld >= the operator's order
 void launch_dense_operator(const OpDev<double>& op, double* out, int ld, hipStream_t s);
-// Lanczos step on D^{-1} A (D inner product): w = D^{-1} w - alpha q - sqrt(beta2) qp,
-// with alpha, beta2 read from device memory
-void launch_lanczos_step(const OpDev<double>& op, const double* alpha, const double* beta2, const double* q,
-                         const double* qp, double* w, hipStream_t s);
+// Lanczos step on D^{-1} A (D inner product): w = D^{-1} w - alpha q - beta qp,
+// beta = sqrt(beta2), or 0 when beta2 <= (1e-10 alpha_prev)^2 (breakdown);
+// scalars read from device memory
+void launch_lanczos_step(const OpDev<double>& op, const double* alpha, const double* alpha_prev, const double* beta2,
+                         const double* q, const double* qp, double* w, hipStream_t s);
+// q = w / sqrt(beta2), or q = r (restart) when beta2 <= (1e-10 alpha)^2
+void launch_lanczos_next(const double* alpha, const double* beta2, const double* w, const double* r, double* q,
+                         size_t n, hipStream_t s);
 // First Chebyshev step from x = 0: u = D^{-1} b / theta; x = u
 template <typename T>
 void launch_cheb_first(const OpDev<T>& op, const T* b, T* u, T* x, T inv_theta, hipStream_t s);

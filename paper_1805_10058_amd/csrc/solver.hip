@@ -692,8 +692,11 @@ double tridiag_max_eig(const std::vector<double>& a, const std::vector<double>& 
 
 // Smoother eigenvalue bounds: lanczos_steps steps of Lanczos on D^{-1} A_l in
 // the D inner product (no reorthogonalisation) from v0 = (-1)^{i_1+...+i_d}
-// in every component; the estimate is the largest Ritz value.  The
-// recurrence coefficients stay on the device until the last step.
+// in every component; the estimate is the largest Ritz value.  Where
+// beta_{j+1} <= 1e-10 |alpha_j| the Krylov space is invariant and the
+// recurrence restarts from r_i = cos(0.7 i + 0.3) (D-normalised) with
+// beta_{j+1} = 0.  The recurrence coefficients stay on the device until the
+// last step.
 void estimate_bounds(cd_solver* s) {
     hipStream_t st = s->stream;
     const int L = int(s->lv.size());
@@ -702,6 +705,7 @@ void estimate_bounds(cd_solver* s) {
     double* qa = tmp.alloc<double>(s->N);
     double* qb = tmp.alloc<double>(s->N);
     double* w = tmp.alloc<double>(s->N);
+    double* rr = tmp.alloc<double>(s->N);
     const int nbmax = std::max(cd::reduce_blocks(s->N), cd::apply_blocks<double>(s->ld64[0].op));
     double* part = tmp.alloc<double>(nbmax);
     double* coef = tmp.alloc<double>(2 * size_t(ks) + 1);  // alpha[0..ks), beta2[0..ks]
@@ -720,23 +724,28 @@ void estimate_bounds(cd_solver* s) {
             const int i0 = int(rem / m1);
             v0[id] = ((i0 + i1 + i2) % 2 == 0) ? 1.0 : -1.0;
         }
+        std::vector<double> r0(n);
+        for (size_t id = 0; id < n; ++id) r0[id] = std::cos(0.7 * double(id) + 0.3);
         hip_check(hipMemcpyAsync(w, v0.data(), n * sizeof(double), hipMemcpyHostToDevice, st), "upload v0");
+        hip_check(hipMemcpyAsync(rr, r0.data(), n * sizeof(double), hipMemcpyHostToDevice, st), "upload r");
         const int nbr = cd::reduce_blocks(n);
         const int nba = cd::apply_blocks<double>(op);
         double* alpha = coef;
         double* beta2 = coef + ks;
         cd::launch_fill<double>(qa, 0.0, n, st);
         cd::launch_fill<double>(beta2, 0.0, 1, st);
+        cd::launch_diag_dot<double>(op, rr, part, st);
+        cd::launch_normalize<double>(part, nbr, rr, rr, n, st);
         cd::launch_diag_dot<double>(op, w, part, st);
         cd::launch_normalize<double>(part, nbr, w, qb, n, st);
         // qa = q_{j-1}, qb = q_j
         for (int j = 0; j < ks; ++j) {
             cd::launch_apply<double>(op, kApplyYDot, qb, w, nullptr, nullptr, nullptr, 0.0, 0.0, part, st);
             cd::launch_finalize(part, nba, alpha + j, st);
-            cd::launch_lanczos_step(op, alpha + j, beta2 + j, qb, qa, w, st);
+            cd::launch_lanczos_step(op, alpha + j, alpha + (j > 0 ? j - 1 : 0), beta2 + j, qb, qa, w, st);
             cd::launch_diag_dot<double>(op, w, part, st);
             cd::launch_finalize(part, nbr, beta2 + j + 1, st);
-            cd::launch_normalize<double>(part, nbr, w, qa, n, st);
+            cd::launch_lanczos_next(alpha + j, beta2 + j + 1, w, rr, qa, n, st);
             std::swap(qa, qb);
         }
         std::vector<double> h(2 * size_t(ks) + 1);
@@ -744,7 +753,9 @@ void estimate_bounds(cd_solver* s) {
                   "read lanczos coefficients");
         hip_check(hipStreamSynchronize(st), "sync");
         std::vector<double> a(h.begin(), h.begin() + ks), b(ks, 0.0);
-        for (int j = 1; j < ks; ++j) b[j] = std::sqrt(std::max(h[ks + j], 0.0));
+        const double tol = 1e-10;  // breakdown test, as in the kernels
+        for (int j = 1; j < ks; ++j)
+            b[j] = (h[ks + j] <= tol * tol * a[j - 1] * a[j - 1]) ? 0.0 : std::sqrt(std::max(h[ks + j], 0.0));
         if (!(a[0] > 0.0)) throw CdError(CD_EINVAL, "operator is not positive definite");
         H.lam = tridiag_max_eig(a, b);
         if (!(H.lam > 0.0) || !std::isfinite(H.lam)) throw CdError(CD_EINVAL, "operator is not positive definite");

@@ -183,6 +183,21 @@ def test_vcycle_light_smoothing_one_degree_everywhere(case):
     assert relerr(host(z), m.vcycle(r)) <= 1e-10
 
 
+@pytest.mark.parametrize("case", [(2, 1, 8, 0.3, "knot", 1), (2, 1, 4, 0.5, "knot", 1)],
+                         ids=["d2p1n8b0.3", "d2p1n4b0.5"])
+def test_lanczos_breakdown_restart_on_tiny_levels(case):
+    # levels of 18 unknowns: the Lanczos recurrence from the symmetric start
+    # vector breaks down there and restarts from the fixed vector, the same
+    # way on both sides
+    s, m = setup_case(case)
+    for l, L in enumerate(m.levels[:-1]):
+        assert abs(s.get_lambda(l) - L.lam) <= 1e-10 * L.lam, l
+    r = np.random.default_rng(19).uniform(-1, 1, m.K.shape[0])
+    rd, z = dev(r), empty(m.K.shape[0])
+    s.precondition(rd.data_ptr(), z.data_ptr())
+    assert relerr(host(z), m.vcycle(r)) <= 1e-10
+
+
 @pytest.mark.parametrize("case", CASES, ids=IDS)
 def test_solve_matches_direct(case):
     s, m = setup_case(case, rtol=1e-12)

@@ -64,6 +64,33 @@ def test_lanczos_estimate_bounded_by_krylov_optimality(d, p, n, beta):
     assert method.lanczos_estimate(L, 60) >= 0.999 * lmax
 
 
+def test_lanczos_restarts_when_the_start_vector_spans_an_invariant_subspace():
+    # 3D p=2 n=4, level 1: the symmetric start vector spans a two-dimensional
+    # invariant subspace of D^{-1} K (the recurrence breaks down at its second
+    # step) whose Ritz values stay well below the top of the spectrum; the
+    # restart from the fixed vector still finds it
+    meth = method.Method(3, 2, 4, 1.0, 0.1, coarse_max_dofs=1)
+    L = meth.levels[1]
+    v = method.start_vector(L.d, L.m)
+    q = v / np.sqrt(v @ (L.D * v))
+    qprev, b = np.zeros_like(q), 0.0
+    alpha, beta = [], []
+    for _ in range(2):
+        Kq = L.K @ q
+        a = q @ Kq
+        w = Kq / L.D - a * q - b * qprev
+        b = np.sqrt(w @ (L.D * w))
+        alpha.append(a)
+        beta.append(b)
+        qprev, q = q, w / b
+    assert beta[0] > method.LANCZOS_BREAKDOWN * abs(alpha[0])
+    assert beta[1] <= method.LANCZOS_BREAKDOWN * abs(alpha[1])
+    lmax = sla.eigh(L.K.toarray(), np.diag(L.D), eigvals_only=True)[-1]
+    sub = sla.eigvalsh_tridiagonal(np.array(alpha), np.array(beta[:1]))[-1]
+    assert sub < 0.9 * lmax
+    assert 0.999 * lmax <= L.lam <= lmax * (1 + 1e-12)
+
+
 def test_lanczos_estimate_on_levels_is_close_to_lambda_max():
     meth = method.Method(2, 3, 16, 1.0, 0.1, coarse_max_dofs=100)
     for L in meth.levels[:-1]:
