@@ -345,3 +345,35 @@ def test_live_timing_counts_and_leaves_results_unchanged(graphs):
     ts2 = s_t.profile_read_tsolve(True)
     assert ts2.launches == ((rt2.iterations + 1) // 2) * p * d
     s_t.profile_enable(False)
+
+
+# alpha != 1, including beta > alpha (the curl weight below the div weight)
+ALPHA_CASES = [(2, 3, 24, 2.5, 0.05), (3, 2, 10, 0.4, 3.0), (2, 2, 30, 0.3, 7.0)]
+
+
+@pytest.mark.parametrize("case", ALPHA_CASES, ids=[f"d{c[0]}p{c[1]}n{c[2]}a{c[3]}b{c[4]}" for c in ALPHA_CASES])
+def test_alpha_not_one(case):
+    d, p, n, alpha, beta = case
+    opt = capi.options(coarse_max_dofs=200, rtol=1e-12)
+    s = capi.Solver(capi.problem(d, p, n, alpha, beta), opt, stream())
+    m = method.Method(d, p, n, alpha, beta, coarse_max_dofs=200, nu=opt.cheb_degree,
+                      nu_coarse=opt.cheb_degree_coarse if opt.cheb_degree_coarse > 0 else None,
+                      ratio=opt.cheb_ratio, lanczos_steps=opt.lanczos_steps)
+    assert s.num_levels() == len(m.levels)
+    rng = np.random.default_rng(23)
+    for l, L in enumerate(m.levels):
+        x = rng.uniform(-1, 1, L.K.shape[0])
+        xd, y = dev(x), empty(L.K.shape[0])
+        s.apply(l, xd.data_ptr(), y.data_ptr())
+        assert relerr(host(y), L.K @ x) <= 1e-12, l
+        if l + 1 < len(m.levels):
+            assert abs(s.get_lambda(l) - L.lam) <= 1e-10 * L.lam, l
+    r = rng.uniform(-1, 1, m.K.shape[0])
+    rd, z = dev(r), empty(m.K.shape[0])
+    s.precondition(rd.data_ptr(), z.data_ptr())
+    assert relerr(host(z), m.vcycle(r)) <= 1e-10
+    x = empty(m.K.shape[0])
+    res = s.solve(rd.data_ptr(), x.data_ptr())
+    assert res.status == capi.CD_OK
+    assert relerr(host(x), solvers.solve_direct(m.K, r)) <= 1e-9
+    s.close()
