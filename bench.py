@@ -94,7 +94,7 @@ def main():
                     help="also run a plain 256 MiB device copy 5 times (calibrates HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py measures one GPU: this build has no multi-GPU path (see DESIGN.md, sharding)",
+        print("bench.py measures one GPU: the solver has no multi-GPU path (--gpus 1 only)",
               file=sys.stderr)
         sys.exit(2)
 
