@@ -15,6 +15,9 @@ ROOT = os.path.dirname(HERE)
 BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(HERE, "libcurldiv.so")
 SOURCES = ["csrc/setup.cpp", "csrc/kernels.hip", "csrc/coarse.hip", "csrc/solver.hip"]
+# the operator kernels: one object per (source, precision, half bandwidth)
+APPLY_SOURCES = ["csrc/apply2d.hip", "csrc/apply3d.hip"]
+APPLY_VARIANTS = [(t, hb) for t in ("double", "float") for hb in range(1, 7)]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [
@@ -26,9 +29,11 @@ FLAGS = [
 ]
 
 
-def _compile(src):
-    obj = os.path.join(BUILD, os.path.basename(src) + ".o")
-    cmd = [HIPCC] + FLAGS + ["-c", os.path.join(HERE, src), "-o", obj]
+def _compile(job):
+    src, defs = job
+    tag = "".join(f"_{v}" for _, v in defs)
+    obj = os.path.join(BUILD, os.path.basename(src) + tag + ".o")
+    cmd = [HIPCC] + FLAGS + [f"-D{k}={v}" for k, v in defs] + ["-c", os.path.join(HERE, src), "-o", obj]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError(f"compile failed: {' '.join(cmd)}\n{r.stdout}\n{r.stderr}")
@@ -37,8 +42,11 @@ def _compile(src):
 
 def build(verbose=False):
     os.makedirs(BUILD, exist_ok=True)
-    with ThreadPoolExecutor(max_workers=len(SOURCES)) as ex:
-        objs = list(ex.map(_compile, SOURCES))
+    jobs = [(src, [("CD_T", t), ("CD_HB", hb)]) for src in APPLY_SOURCES for t, hb in APPLY_VARIANTS]
+    jobs += [(src, []) for src in SOURCES]
+    workers = max(1, min(len(jobs), int(os.environ.get("MAX_JOBS", os.cpu_count() or 4))))
+    with ThreadPoolExecutor(max_workers=workers) as ex:
+        objs = list(ex.map(_compile, jobs))
     tmp = LIB + ".tmp"
     cmd = [HIPCC, "--offload-arch=gfx950", "-shared", "-fPIC", "-o", tmp] + objs
     r = subprocess.run(cmd, capture_output=True, text=True)

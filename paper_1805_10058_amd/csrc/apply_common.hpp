@@ -1,0 +1,139 @@
+// Operator-apply helpers shared by the 2D and 3D kernels (internal header):
+// launch geometry, the fused epilogue modes and the per-block dot products.
+#pragma once
+
+#include "device_common.hpp"
+
+namespace cd {
+
+// Launch entry points of the operator kernels, one explicit instantiation per
+// (precision, half bandwidth) in its own object (apply2d.hip, apply3d.hip).
+template <typename T, int HB>
+void apply3d_run(const OpDev<T>& op, int mode, const T* x, T* y, const T* b, T* u, T* xout, T c1, T c2,
+                 double* part, int nv, unsigned long long* stamp, hipStream_t s);
+template <typename T, int HB>
+void apply2d_run(const OpDev<T>& op, int mode, const T* x, T* y, const T* b, T* u, T* xout, T c1, T c2,
+                 double* part, int nv, unsigned long long* stamp, hipStream_t s);
+
+constexpr int kT1 = 8, kT2 = 32;  // 2D output tile: kT1 * kT2 = kThreads points
+
+namespace {
+
+// 3D output tile: k3T2 rows (x2) of k3T3(HB) = 32 - 2HB columns (x3), so that
+// the stage-A positions (k3T2 rows of 32 tile columns) are exactly one per thread.
+constexpr int k3T2 = 8, k3E3 = 32;
+__host__ __device__ constexpr int k3T3(int hb) { return k3E3 - 2 * hb; }
+
+// Launch geometry of the 3D operator kernel: tiles of the (x2, x3) plane times
+// ranges of x1 planes, about as many blocks as fit on the device at once (two
+// per compute unit in FP64, four in FP32, set by the register footprint).
+struct Apply3dGeom {
+    int nt2, nt3, c1len, nblocks;
+};
+
+inline Apply3dGeom apply3d_geom(const int* m, int hb, size_t elem) {
+    const int kTargetBlocks = elem == 4 ? 1024 : 512;
+    Apply3dGeom g;
+    g.nt2 = (m[1] + k3T2 - 1) / k3T2;
+    g.nt3 = (m[2] + k3T3(hb) - 1) / k3T3(hb);
+    const int planar = g.nt2 * g.nt3;
+    const int nx1 = std::max(1, std::min(m[0], kTargetBlocks / planar));
+    g.c1len = (m[0] + nx1 - 1) / nx1;
+    g.nblocks = planar * ((m[0] + g.c1len - 1) / g.c1len);
+    return g;
+}
+
+// Partial dot products an operator kernel accumulates per thread.
+template <int MODE>
+constexpr int apply_ndots() {
+    return MODE == kApplyYMulti ? kMaxBasis + 1 : 1;
+}
+
+// Operands the epilogue of an operator kernel reads at one output entry,
+// loaded as early as the kernel knows the entry (the 2D kernel: before its
+// input tile), so their latency hides behind the contractions.
+template <typename T>
+struct EpiIn {
+    T b, u, x;
+    T v[kMaxBasis];
+};
+
+template <typename T, int MODE>
+__device__ inline void epilogue_load(EpiIn<T>& e, size_t idx, const T* __restrict__ x, const T* __restrict__ b,
+                                     const T* __restrict__ u, T c1, int nv, size_t ntot) {
+    if (MODE == kApplyRes || MODE == kApplyResDot || MODE == kApplyCheb) e.b = b[idx];
+    if (MODE == kApplyCheb) {
+        e.u = (c1 != T(0)) ? u[idx] : T(0);  // u is not read on a first step
+        e.x = x[idx];
+    }
+    if (MODE == kApplyYDot) e.x = x[idx];
+    if (MODE == kApplyYMulti) {
+#pragma unroll
+        for (int i = 0; i < kMaxBasis; ++i) e.v[i] = (i < nv) ? b[size_t(i) * ntot + idx] : T(0);
+    }
+}
+
+// Epilogue at one output entry idx (component c, grid point (i1, i2, i3))
+// with kx = (A x)[idx] and the entry's operands e.
+template <typename T, int MODE>
+__device__ inline void epilogue_store(const OpDev<T>& op, int c, size_t idx, T kx, int i1, int i2, int i3,
+                                      const EpiIn<T>& e, T* __restrict__ y, T* __restrict__ u,
+                                      T* __restrict__ xout, T c1, T c2, int nv, double* dots) {
+    if (MODE == kApplyY) {
+        y[idx] = kx;
+    } else if (MODE == kApplyRes) {
+        y[idx] = e.b - kx;
+    } else if (MODE == kApplyResDot) {
+        const T r = e.b - kx;
+        y[idx] = r;
+        dots[0] += double(r) * double(r);
+    } else if (MODE == kApplyYMulti) {
+        y[idx] = kx;
+#pragma unroll
+        for (int i = 0; i < kMaxBasis; ++i)
+            if (i < nv) dots[i] += double(e.v[i]) * double(kx);
+        dots[kMaxBasis] += double(kx) * double(kx);
+    } else if (MODE == kApplyCheb) {
+        const T r = e.b - kx;
+        const T dg = diag_entry(op, c, i1, i2, i3);
+        const T un = c1 * e.u + c2 * r / dg;
+        u[idx] = un;
+        xout[idx] = e.x + un;
+    } else {
+        y[idx] = kx;
+        dots[0] += double(e.x) * double(kx);
+    }
+}
+
+// Both at once (the 3D kernel, whose output entries change plane by plane).
+template <typename T, int MODE>
+__device__ inline void apply_epilogue(const OpDev<T>& op, int c, size_t idx, T kx, int i1, int i2, int i3,
+                                      const T* __restrict__ x, T* __restrict__ y, const T* __restrict__ b,
+                                      T* __restrict__ u, T* __restrict__ xout, T c1, T c2, int nv, size_t ntot,
+                                      double* dots) {
+    EpiIn<T> e;
+    epilogue_load<T, MODE>(e, idx, x, b, u, c1, nv, ntot);
+    epilogue_store<T, MODE>(op, c, idx, kx, i1, i2, i3, e, y, u, xout, c1, c2, nv, dots);
+}
+
+// Block sums of the per-thread partial dots: part[i * gridDim.x + block].
+template <int MODE>
+__device__ inline void apply_write_dots(const double* dots, int nv, double* __restrict__ part) {
+    if (MODE == kApplyYDot || MODE == kApplyResDot) {
+        const double tot = block_sum(dots[0]);
+        if (threadIdx.x == 0) part[blockIdx.x] = tot;
+    } else if (MODE == kApplyYMulti) {
+#pragma unroll
+        for (int i = 0; i < kMaxBasis; ++i) {
+            if (i < nv) {  // block-uniform
+                const double tot = block_sum(dots[i]);
+                if (threadIdx.x == 0) part[size_t(i) * gridDim.x + blockIdx.x] = tot;
+            }
+        }
+        const double ww = block_sum(dots[kMaxBasis]);
+        if (threadIdx.x == 0) part[size_t(nv) * gridDim.x + blockIdx.x] = ww;
+    }
+}
+
+}  // namespace
+}  // namespace cd

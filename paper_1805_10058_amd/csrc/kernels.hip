@@ -1,640 +1,14 @@
-// HIP kernels for gfx950: sum-factorized curl-div operator, grid transfers,
-// banded Toeplitz line solves, reductions and the small Krylov helpers.
+// HIP kernels for gfx950: grid transfers, banded Toeplitz line solves,
+// reductions and the small Krylov helpers; the dispatch of the operator
+// kernels (apply2d.hip, apply3d.hip).
 //
 // Every reduction accumulates in FP64 and combines partial sums in a fixed
 // order, so results are bitwise reproducible run to run.
-#include <algorithm>
-#include <map>
-#include <mutex>
-#include <stdexcept>
-#include <string>
-
-#include "kernels.hpp"
+#include "apply_common.hpp"
 
 namespace cd {
 
 namespace {
-
-constexpr int kThreads = 256;  // block size of every kernel in this file
-
-void check_launch(const char* what) {
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess) throw std::runtime_error(std::string(what) + ": " + hipGetErrorString(e));
-}
-
-__device__ inline double wave_sum(double v) {
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
-    return v;
-}
-
-// Sum over the block; the result is returned to every thread.
-__device__ inline double block_sum(double v) {
-    __shared__ double red[kThreads / 64];
-    __shared__ double total;
-    v = wave_sum(v);
-    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-    if (lane == 0) red[wid] = v;
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        double s = 0.0;
-        for (int i = 0; i < int(blockDim.x) / 64; ++i) s += red[i];
-        total = s;
-    }
-    __syncthreads();
-    const double r = total;
-    __syncthreads();
-    return r;
-}
-
-__device__ inline double sum_partials(const double* part, int np) {
-    double v = 0.0;
-    for (int i = threadIdx.x; i < np; i += blockDim.x) v += part[i];
-    return block_sum(v);
-}
-
-// Kernel-side timing on the constant-rate wall clock.  A timing slot is
-// kStampWords words: [0] = start of block 0 (the first block dispatched),
-// [1 + b % kStampEnds] = latest end of the blocks b mapped there, taken after
-// the block's memory operations completed.  The end words start at zero
-// (k_stamp_reduce clears them after use).  stamp == nullptr: no timing.
-// stamp_end must be reached by every thread of the block.
-__device__ inline void stamp_begin(unsigned long long* stamp) {
-    if (stamp != nullptr && blockIdx.x == 0 && threadIdx.x == 0) stamp[0] = (unsigned long long)wall_clock64();
-}
-
-__device__ inline void stamp_end(unsigned long long* stamp) {
-    if (stamp != nullptr) {
-        __builtin_amdgcn_s_waitcnt(0);  // this wave's loads and stores are done
-        __syncthreads();
-        if (threadIdx.x == 0) atomicMax(stamp + 1 + blockIdx.x % kStampEnds, (unsigned long long)wall_clock64());
-    }
-}
-
-template <typename T>
-__device__ inline T band_at(const OpDev<T>& op, int axis, int which, int k, int i) {
-    return op.band[axis][which][k * op.m[axis] + i];
-}
-
-// Diagonal entry of block (c,c) at multi-index (i0,i1,i2):
-// beta * prod(S on axis c, M elsewhere) + alpha * sum_{e != c} prod(S on e, M elsewhere).
-template <typename T>
-__device__ inline T diag_entry(const OpDev<T>& op, int c, int i0, int i1, int i2) {
-    const int hb = op.hb;
-    const T m0 = band_at(op, 0, 0, hb, i0), s0 = band_at(op, 0, 2, hb, i0);
-    const T m1 = band_at(op, 1, 0, hb, i1), s1 = band_at(op, 1, 2, hb, i1);
-    if (op.dim == 2) {
-        const T t0 = s0 * m1, t1 = m0 * s1;
-        return (c == 0) ? op.beta * t0 + op.alpha * t1 : op.alpha * t0 + op.beta * t1;
-    }
-    const T m2 = band_at(op, 2, 0, hb, i2), s2 = band_at(op, 2, 2, hb, i2);
-    const T t0 = s0 * m1 * m2, t1 = m0 * s1 * m2, t2 = m0 * m1 * s2;
-    return (c == 0 ? op.beta : op.alpha) * t0 + (c == 1 ? op.beta : op.alpha) * t1 +
-           (c == 2 ? op.beta : op.alpha) * t2;
-}
-
-// 3D output tile: k3T2 rows (x2) of k3T3(HB) = 32 - 2HB columns (x3), so that
-// the stage-A positions (k3T2 rows of 32 tile columns) are exactly one per thread.
-constexpr int k3T2 = 8, k3E3 = 32;
-__host__ __device__ constexpr int k3T3(int hb) { return k3E3 - 2 * hb; }
-constexpr int kXcds = 8;
-
-// Launch geometry of the 3D operator kernel: tiles of the (x2, x3) plane times
-// ranges of x1 planes, about as many blocks as fit on the device at once (two
-// per compute unit in FP64, four in FP32, set by the register footprint).
-struct Apply3dGeom {
-    int nt2, nt3, c1len, nblocks;
-};
-
-Apply3dGeom apply3d_geom(const int* m, int hb, size_t elem) {
-    const int kTargetBlocks = elem == 4 ? 1024 : 512;
-    Apply3dGeom g;
-    g.nt2 = (m[1] + k3T2 - 1) / k3T2;
-    g.nt3 = (m[2] + k3T3(hb) - 1) / k3T3(hb);
-    const int planar = g.nt2 * g.nt3;
-    const int nx1 = std::max(1, std::min(m[0], kTargetBlocks / planar));
-    g.c1len = (m[0] + nx1 - 1) / nx1;
-    g.nblocks = planar * ((m[0] + g.c1len - 1) / g.c1len);
-    return g;
-}
-
-// Partial dot products an operator kernel accumulates per thread.
-template <int MODE>
-constexpr int apply_ndots() {
-    return MODE == kApplyYMulti ? kMaxBasis + 1 : 1;
-}
-
-// Operands the epilogue of an operator kernel reads at one output entry,
-// loaded as early as the kernel knows the entry (the 2D kernel: before its
-// input tile), so their latency hides behind the contractions.
-template <typename T>
-struct EpiIn {
-    T b, u, x;
-    T v[kMaxBasis];
-};
-
-template <typename T, int MODE>
-__device__ inline void epilogue_load(EpiIn<T>& e, size_t idx, const T* __restrict__ x, const T* __restrict__ b,
-                                     const T* __restrict__ u, T c1, int nv, size_t ntot) {
-    if (MODE == kApplyRes || MODE == kApplyResDot || MODE == kApplyCheb) e.b = b[idx];
-    if (MODE == kApplyCheb) {
-        e.u = (c1 != T(0)) ? u[idx] : T(0);  // u is not read on a first step
-        e.x = x[idx];
-    }
-    if (MODE == kApplyYDot) e.x = x[idx];
-    if (MODE == kApplyYMulti) {
-#pragma unroll
-        for (int i = 0; i < kMaxBasis; ++i) e.v[i] = (i < nv) ? b[size_t(i) * ntot + idx] : T(0);
-    }
-}
-
-// Epilogue at one output entry idx (component c, grid point (i1, i2, i3))
-// with kx = (A x)[idx] and the entry's operands e.
-template <typename T, int MODE>
-__device__ inline void epilogue_store(const OpDev<T>& op, int c, size_t idx, T kx, int i1, int i2, int i3,
-                                      const EpiIn<T>& e, T* __restrict__ y, T* __restrict__ u,
-                                      T* __restrict__ xout, T c1, T c2, int nv, double* dots) {
-    if (MODE == kApplyY) {
-        y[idx] = kx;
-    } else if (MODE == kApplyRes) {
-        y[idx] = e.b - kx;
-    } else if (MODE == kApplyResDot) {
-        const T r = e.b - kx;
-        y[idx] = r;
-        dots[0] += double(r) * double(r);
-    } else if (MODE == kApplyYMulti) {
-        y[idx] = kx;
-#pragma unroll
-        for (int i = 0; i < kMaxBasis; ++i)
-            if (i < nv) dots[i] += double(e.v[i]) * double(kx);
-        dots[kMaxBasis] += double(kx) * double(kx);
-    } else if (MODE == kApplyCheb) {
-        const T r = e.b - kx;
-        const T dg = diag_entry(op, c, i1, i2, i3);
-        const T un = c1 * e.u + c2 * r / dg;
-        u[idx] = un;
-        xout[idx] = e.x + un;
-    } else {
-        y[idx] = kx;
-        dots[0] += double(e.x) * double(kx);
-    }
-}
-
-// Both at once (the 3D kernel, whose output entries change plane by plane).
-template <typename T, int MODE>
-__device__ inline void apply_epilogue(const OpDev<T>& op, int c, size_t idx, T kx, int i1, int i2, int i3,
-                                      const T* __restrict__ x, T* __restrict__ y, const T* __restrict__ b,
-                                      T* __restrict__ u, T* __restrict__ xout, T c1, T c2, int nv, size_t ntot,
-                                      double* dots) {
-    EpiIn<T> e;
-    epilogue_load<T, MODE>(e, idx, x, b, u, c1, nv, ntot);
-    epilogue_store<T, MODE>(op, c, idx, kx, i1, i2, i3, e, y, u, xout, c1, c2, nv, dots);
-}
-
-// Block sums of the per-thread partial dots: part[i * gridDim.x + block].
-template <int MODE>
-__device__ inline void apply_write_dots(const double* dots, int nv, double* __restrict__ part) {
-    if (MODE == kApplyYDot || MODE == kApplyResDot) {
-        const double tot = block_sum(dots[0]);
-        if (threadIdx.x == 0) part[blockIdx.x] = tot;
-    } else if (MODE == kApplyYMulti) {
-#pragma unroll
-        for (int i = 0; i < kMaxBasis; ++i) {
-            if (i < nv) {  // block-uniform
-                const double tot = block_sum(dots[i]);
-                if (threadIdx.x == 0) part[size_t(i) * gridDim.x + blockIdx.x] = tot;
-            }
-        }
-        const double ww = block_sum(dots[kMaxBasis]);
-        if (threadIdx.x == 0) part[size_t(nv) * gridDim.x + blockIdx.x] = ww;
-    }
-}
-
-// ------------------------------------------------------------------------------
-// 3D operator apply.
-//
-// A block owns an output tile of k3T2 x (32 - 2HB) columns of the (x2, x3)
-// plane (one per thread; the other threads only help with loads and stage A)
-// and the output planes x1 in [o0, o1); it marches over the input planes
-// t = 0, 1, ... (x1 = o0 - HB + t) up to o1 + HB.  Per input plane:
-//   (A) contract axis 2 (stride m3): M2 x, A2 x, S2 x of the three components
-//       at one position per thread: the tile rows times all 32 tile columns
-//       (LDS tile of the plane with a +-HB halo on both in-plane axes);
-//   (B) contract axis 3 at the thread's column and combine the raw products
-//       with alpha, beta, alpha-beta into W[c][{S,M,A}], the inputs of the
-//       axis-1 contraction of output component c;
-//   (C) scatter W into a ring of 2HB+1 per-plane accumulators in registers:
-//       acc(i) += X1(i, j) W for i in [j-HB, j+HB].
-// After plane j the accumulator of output plane j-HB is complete and goes
-// through the epilogue.  33 band contractions per point.
-//
-// Software pipeline, one barrier per plane: phase t runs stage A of plane
-// t+1 and stage B of plane t (independent work for the scheduler), stores the
-// prefetched plane t+2 into the input buffer plane t has vacated, and issues
-// the loads of plane t+3.  Input tiles and stage-A results are double
-// buffered in LDS.
-//
-// Tiles are numbered with x2 fastest, then x3, then the x1 range, and block b
-// takes tile (b mod 8) * ceil-share + b / 8: consecutive blocks land on
-// different XCDs, so this keeps spatially adjacent tiles, whose halos overlap,
-// on the same XCD and its L2.
-// ------------------------------------------------------------------------------
-template <typename T, int HB>
-constexpr size_t apply3d_lds_words() {
-    return 2 * 3 * size_t(k3T2 + 2 * HB) * k3E3 + 2 * 9 * size_t(k3T2) * k3E3 + 3 * size_t(2 * HB + 1) * k3T2;
-}
-
-template <typename T, int HB, int MODE>
-__global__ __launch_bounds__(kThreads) void k_apply3d(OpDev<T> op, const T* __restrict__ x, T* __restrict__ y,
-                                                      const T* __restrict__ b, T* __restrict__ u,
-                                                      T* __restrict__ xout, T c1, T c2, double* __restrict__ part,
-                                                      int nv, Apply3dGeom g, unsigned long long* stamp) {
-    stamp_begin(stamp);
-    constexpr int R = 2 * HB + 1;
-    constexpr int T3 = k3T3(HB);
-    constexpr int E2 = k3T2 + 2 * HB, E3 = k3E3;
-    constexpr int NIN = E2 * E3;  // input tile per component and plane
-    constexpr int NLD = (3 * NIN + kThreads - 1) / kThreads;
-    constexpr int NA = k3T2 * E3;  // stage-A positions
-    static_assert(NA == kThreads, "one stage-A position per thread");
-    extern __shared__ __align__(16) unsigned char smem_raw[];
-    T* xs = reinterpret_cast<T*>(smem_raw);  // [2][3][E2][E3] input tiles
-    T* st = xs + 2 * 3 * NIN;                // [2][9][k3T2][E3]: M2x A2x S2x of components 0, 1, 2
-    T* ca = st + 2 * 9 * NA;                 // [3][R][k3T2] axis-2 band rows of the tile
-    const int m1 = op.m[0], m2 = op.m[1], m3 = op.m[2];
-    const size_t PL = size_t(m2) * m3, G = size_t(m1) * PL;
-    const int xcd = int(blockIdx.x % kXcds), slot = int(blockIdx.x / kXcds);
-    const int per = g.nblocks / kXcds, rem = g.nblocks % kXcds;
-    const int tile = xcd * per + min(xcd, rem) + slot;
-    const int o2 = (tile % g.nt2) * k3T2;
-    const int o3 = ((tile / g.nt2) % g.nt3) * T3;
-    const int o0 = (tile / (g.nt2 * g.nt3)) * g.c1len;
-    const int o1 = min(o0 + g.c1len, m1);
-    const int tid = threadIdx.x;
-    for (int e = tid; e < 3 * R * k3T2; e += kThreads) {
-        const int i = e % k3T2, k = (e / k3T2) % R, w = e / (k3T2 * R);
-        ca[e] = op.band[1][w][k * m2 + min(o2 + i, m2 - 1)];  // rows past the grid feed unused outputs
-    }
-    // stage-A position of this thread
-    const int ai = tid / E3, aq = tid % E3;
-    // output column of this thread and its axis-3 band row
-    const int ty = tid / E3, tx = tid % E3;
-    const int i2 = o2 + ty, i3 = o3 + tx;
-    const bool active = (tx < T3) && (i2 < m2) && (i3 < m3);
-    T cb[3][R];
-#pragma unroll
-    for (int w = 0; w < 3; ++w)
-#pragma unroll
-        for (int k = 0; k < R; ++k) cb[w][k] = active ? op.band[2][w][k * m3 + i3] : T(0);
-    T acc[3][R];
-#pragma unroll
-    for (int c = 0; c < 3; ++c)
-#pragma unroll
-        for (int r = 0; r < R; ++r) acc[c][r] = T(0);
-    double dots[apply_ndots<MODE>()];
-#pragma unroll
-    for (int i = 0; i < apply_ndots<MODE>(); ++i) dots[i] = 0.0;
-    const T al = op.alpha, be = op.beta, ab = op.alpha - op.beta;
-    const T* __restrict__ colM = op.col0[0];
-    const T* __restrict__ colA = op.col0[1];
-    const T* __restrict__ colS = op.col0[2];
-
-    // the thread's loads of the input tile: offsets within a plane of the
-    // component stack (the same for every plane), -1 outside the grid
-    long long loff[NLD];
-#pragma unroll
-    for (int q = 0; q < NLD; ++q) {
-        const int e = min(tid + q * kThreads, 3 * NIN - 1);
-        const int c = e / NIN, rr = e % NIN;
-        const int g2 = o2 - HB + rr / E3, g3 = o3 - HB + rr % E3;
-        const bool in = g2 >= 0 && g2 < m2 && g3 >= 0 && g3 < m3;
-        loff[q] = in ? (long long)(size_t(c) * G + size_t(g2) * m3 + g3) : -1;
-    }
-    T v[NLD];
-    auto load_plane = [&](int t) {
-        const int j = o0 - HB + t;
-        const bool jin = (j >= 0 && j < m1);  // block-uniform
-        const size_t jo = size_t(jin ? j : 0) * PL;
-#pragma unroll
-        for (int q = 0; q < NLD; ++q) {
-            const bool in = jin && loff[q] >= 0;
-            const T val = x[in ? jo + size_t(loff[q]) : 0];
-            v[q] = in ? val : T(0);
-        }
-    };
-    auto store_plane = [&](int t) {
-        T* dst = xs + (t & 1) * 3 * NIN;
-#pragma unroll
-        for (int q = 0; q < NLD; ++q) {
-            const int e = tid + q * kThreads;
-            if (e < 3 * NIN) dst[e] = v[q];
-        }
-    };
-    auto live = [&](int t) {
-        const int j = o0 - HB + t;
-        return j >= 0 && j < m1;
-    };
-    auto stage_a = [&](int t) {
-        const T* src = xs + (t & 1) * 3 * NIN;
-        T* dst = st + (t & 1) * 9 * NA;
-#pragma unroll
-        for (int c = 0; c < 3; ++c) {
-            T aM = T(0), aA = T(0), aS = T(0);
-#pragma unroll
-            for (int k = 0; k < R; ++k) {
-                const T xv = src[c * NIN + (ai + k) * E3 + aq];
-                aM += ca[(0 * R + k) * k3T2 + ai] * xv;
-                aA += ca[(1 * R + k) * k3T2 + ai] * xv;
-                aS += ca[(2 * R + k) * k3T2 + ai] * xv;
-            }
-            dst[(3 * c + 0) * NA + tid] = aM;
-            dst[(3 * c + 1) * NA + tid] = aA;
-            dst[(3 * c + 2) * NA + tid] = aS;
-        }
-    };
-
-    const int TI = (o1 - o0) + 2 * HB;  // input planes of the block
-    load_plane(0);
-    store_plane(0);
-    if (TI > 1) {
-        load_plane(1);
-        store_plane(1);
-    }
-    if (TI > 2) load_plane(2);
-    __syncthreads();
-    if (live(0)) stage_a(0);
-    __syncthreads();
-    for (int t0 = 0; t0 < TI; t0 += R) {
-#pragma unroll
-        for (int uu = 0; uu < R; ++uu) {
-            const int t = t0 + uu;
-            if (t < TI) {  // block-uniform
-                const int j = o0 - HB + t;
-                const int io = j - HB;  // output plane completed in this phase
-                const bool emit = (io >= o0 && io < o1);
-                // operands of this phase's epilogue, loaded before the contractions
-                // (not for the Krylov-dot mode: its basis rows would cost too many registers)
-                constexpr bool kPre = (MODE != kApplyYMulti);
-                EpiIn<T> ep[3];
-                if (kPre && emit && active) {
-#pragma unroll
-                    for (int c = 0; c < 3; ++c)
-                        epilogue_load<T, MODE>(ep[c], size_t(c) * G + size_t(io) * PL + size_t(i2) * m3 + i3, x, b, u,
-                                               c1, nv, 3 * G);
-                }
-                if (t + 1 < TI && live(t + 1)) stage_a(t + 1);
-                if (live(t)) {
-                    const T* sb = st + (t & 1) * 9 * NA;
-                    T W[3][3];
-#pragma unroll
-                    for (int c = 0; c < 3; ++c)
-#pragma unroll
-                        for (int w = 0; w < 3; ++w) W[c][w] = T(0);
-                    if (active) {
-                        // raw products per input component c: M3(M2x), S3(M2x), A3(M2x), M3(S2x), M3(A2x), A3(A2x)
-                        T mm[3], sm[3], am[3], ms[3], ma[3], aa[3];
-                        const int q0 = ty * E3 + tx;
-#pragma unroll
-                        for (int c = 0; c < 3; ++c) {
-                            mm[c] = sm[c] = am[c] = ms[c] = ma[c] = aa[c] = T(0);
-#pragma unroll
-                            for (int k = 0; k < R; ++k) {
-                                const T vM = sb[(3 * c + 0) * NA + q0 + k];
-                                const T vA = sb[(3 * c + 1) * NA + q0 + k];
-                                const T vS = sb[(3 * c + 2) * NA + q0 + k];
-                                mm[c] += cb[0][k] * vM;
-                                sm[c] += cb[2][k] * vM;
-                                if (c != 1) am[c] += cb[1][k] * vM;
-                                ms[c] += cb[0][k] * vS;
-                                if (c != 2) ma[c] += cb[0][k] * vA;
-                                if (c != 0) aa[c] += cb[1][k] * vA;
-                            }
-                        }
-                        W[0][0] = be * mm[0];
-                        W[0][1] = al * (sm[0] + ms[0]);
-                        W[0][2] = ab * (ma[1] + am[2]);
-                        W[1][0] = al * mm[1];
-                        W[1][1] = al * sm[1] + be * ms[1] + ab * aa[2];
-                        W[1][2] = ab * ma[0];
-                        W[2][0] = al * mm[2];
-                        W[2][1] = be * sm[2] + al * ms[2] + ab * aa[1];
-                        W[2][2] = ab * am[0];
-                    }
-#pragma unroll
-                    for (int k = 0; k < R; ++k) {
-                        const int i = j - HB + k;
-                        if (i >= o0 && i < o1) {
-                            const T cS = colS[j * R + k];  // X1(i, j)
-                            const T cM = colM[j * R + k];
-                            const T cA = colA[j * R + k];
-                            const int sl = (uu + k + 1) % R;
-#pragma unroll
-                            for (int c = 0; c < 3; ++c)
-#pragma unroll
-                                for (int r = 0; r < R; ++r)
-                                    if (r == sl) acc[c][r] += cS * W[c][0] + cM * W[c][1] + cA * W[c][2];
-                        }
-                    }
-                }
-                if (emit) {
-                    const int sl = (uu + 1) % R;
-#pragma unroll
-                    for (int c = 0; c < 3; ++c) {
-                        T kx = T(0);
-#pragma unroll
-                        for (int r = 0; r < R; ++r)
-                            if (r == sl) {
-                                kx = acc[c][r];
-                                acc[c][r] = T(0);
-                            }
-                        if (active) {
-                            const size_t idx = size_t(c) * G + size_t(io) * PL + size_t(i2) * m3 + i3;
-                            if (kPre)
-                                epilogue_store<T, MODE>(op, c, idx, kx, io, i2, i3, ep[c], y, u, xout, c1, c2, nv,
-                                                        dots);
-                            else
-                                apply_epilogue<T, MODE>(op, c, idx, kx, io, i2, i3, x, y, b, u, xout, c1, c2, nv,
-                                                        3 * G, dots);
-                        }
-                    }
-                }
-                if (t + 2 < TI) store_plane(t + 2);  // into the buffer plane t vacated
-                if (t + 3 < TI) load_plane(t + 3);
-                __syncthreads();
-            }
-        }
-    }
-    apply_write_dots<MODE>(dots, nv, part);
-    stamp_end(stamp);
-}
-
-// ------------------------------------------------------------------------------
-// 2D operator apply on tiles of kT1 x kT2 output points (x1 rows, x2 columns;
-// x2 contiguous).  The block issues the loads of its input tile (both
-// components, +-HB halo on both axes, zero outside the grid) before storing
-// any of them to LDS, then
-//   (A) contracts axis 1: S1 x, M1 x, A1 x of both components at the kT1
-//       output rows and all kT2 + 2HB tile columns;
-//   (B) contracts axis 2 at the output point:
-//   y1 = beta M2(S1 x1) + alpha S2(M1 x1) + (alpha-beta) A2(A1 x2)
-//   y2 = alpha M2(S1 x2) + beta S2(M1 x2) + (alpha-beta) A2(A1 x1)
-// 12 band contractions per point.
-// ------------------------------------------------------------------------------
-constexpr int kT1 = 8, kT2 = 32;  // 2D output tile: kT1 * kT2 = kThreads points
-
-template <typename T, int HB, int MODE>
-__global__ __launch_bounds__(kThreads) void k_apply2d(OpDev<T> op, const T* __restrict__ x, T* __restrict__ y,
-                                                      const T* __restrict__ b, T* __restrict__ u,
-                                                      T* __restrict__ xout, T c1, T c2, double* __restrict__ part,
-                                                      int nv, unsigned long long* stamp) {
-    stamp_begin(stamp);
-    constexpr int R = 2 * HB + 1;
-    constexpr int E1 = kT1 + 2 * HB, E2 = kT2 + 2 * HB;  // input tile rows, columns
-    constexpr int NIN = E1 * E2;                         // input tile size per component
-    constexpr int NLD = (2 * NIN + kThreads - 1) / kThreads;
-    constexpr int NA = kT1 * E2;                         // stage-A positions
-    __shared__ T xs[2 * NIN];
-    __shared__ T st[6 * NA];  // S1x1 M1x1 A1x1 S1x2 M1x2 A1x2, each [kT1][E2]
-    const int m1 = op.m[0], m2 = op.m[1];
-    const int G = m1 * m2;
-    const int nt2 = (m2 + kT2 - 1) / kT2;
-    // blocks go to the XCDs round robin; each XCD takes a contiguous run of
-    // row-major tiles, so most of a tile's input was written through the same
-    // L2 by the previous launch
-    const int xcd = int(blockIdx.x % kXcds), slot = int(blockIdx.x / kXcds);
-    const int per = int(gridDim.x) / kXcds, rem = int(gridDim.x) % kXcds;
-    const int tile = xcd * per + min(xcd, rem) + slot;
-    const int o1 = (tile / nt2) * kT1, o2 = (tile % nt2) * kT2;
-    const int tid = threadIdx.x;
-    // the thread's output point and its epilogue operands, loaded first
-    const int i = tid / kT2, j = tid % kT2;
-    const int i1 = o1 + i, i2 = o2 + j;
-    const bool own = (i1 < m1 && i2 < m2);
-    const int f = own ? i1 * m2 + i2 : 0;
-    EpiIn<T> ep[2];
-    if (own) {
-#pragma unroll
-        for (int c = 0; c < 2; ++c)
-            epilogue_load<T, MODE>(ep[c], size_t(c) * G + f, x, b, u, c1, nv, size_t(2) * G);
-    }
-    {
-        T v[NLD];
-#pragma unroll
-        for (int q = 0; q < NLD; ++q) {
-            const int e = min(tid + q * kThreads, 2 * NIN - 1);
-            const int c = e / NIN, r = (e % NIN) / E2, cc = e % E2;
-            const int g1 = o1 - HB + r, g2 = o2 - HB + cc;
-            const bool in = g1 >= 0 && g1 < m1 && g2 >= 0 && g2 < m2;
-            const T val = x[size_t(c) * G + size_t(in ? g1 : 0) * m2 + (in ? g2 : 0)];
-            v[q] = in ? val : T(0);
-        }
-#pragma unroll
-        for (int q = 0; q < NLD; ++q) {
-            const int e = tid + q * kThreads;
-            if (e < 2 * NIN) xs[e] = v[q];
-        }
-    }
-    __syncthreads();
-    for (int p = tid; p < NA; p += kThreads) {
-        const int i = p / E2, j = p % E2;
-        const int r1 = min(o1 + i, m1 - 1);  // rows past the grid produce unused values
-        T v[6] = {T(0), T(0), T(0), T(0), T(0), T(0)};
-#pragma unroll
-        for (int k = 0; k < R; ++k) {
-            const T cS = op.band[0][2][k * m1 + r1];
-            const T cM = op.band[0][0][k * m1 + r1];
-            const T cA = op.band[0][1][k * m1 + r1];
-            const T x1 = xs[(i + k) * E2 + j], x2 = xs[NIN + (i + k) * E2 + j];
-            v[0] += cS * x1;
-            v[1] += cM * x1;
-            v[2] += cA * x1;
-            v[3] += cS * x2;
-            v[4] += cM * x2;
-            v[5] += cA * x2;
-        }
-#pragma unroll
-        for (int w = 0; w < 6; ++w) st[w * NA + p] = v[w];
-    }
-    __syncthreads();
-    double dots[apply_ndots<MODE>()];
-#pragma unroll
-    for (int q = 0; q < apply_ndots<MODE>(); ++q) dots[q] = 0.0;
-    if (own) {
-        T mS1 = T(0), sM1 = T(0), aA2 = T(0), mS2 = T(0), sM2 = T(0), aA1 = T(0);
-        const int q0 = i * E2 + j;
-#pragma unroll
-        for (int k = 0; k < R; ++k) {
-            const T cM = op.band[1][0][k * m2 + i2];
-            const T cA = op.band[1][1][k * m2 + i2];
-            const T cS = op.band[1][2][k * m2 + i2];
-            mS1 += cM * st[0 * NA + q0 + k];
-            sM1 += cS * st[1 * NA + q0 + k];
-            aA1 += cA * st[2 * NA + q0 + k];
-            mS2 += cM * st[3 * NA + q0 + k];
-            sM2 += cS * st[4 * NA + q0 + k];
-            aA2 += cA * st[5 * NA + q0 + k];
-        }
-        const T al = op.alpha, be = op.beta, ab = op.alpha - op.beta;
-        const T kx[2] = {be * mS1 + al * sM1 + ab * aA2, al * mS2 + be * sM2 + ab * aA1};
-#pragma unroll
-        for (int c = 0; c < 2; ++c)
-            epilogue_store<T, MODE>(op, c, size_t(c) * G + f, kx[c], i1, i2, 0, ep[c], y, u, xout, c1, c2, nv, dots);
-    }
-    apply_write_dots<MODE>(dots, nv, part);
-    stamp_end(stamp);
-}
-
-// Raise a kernel's dynamic-LDS limit (default 64 KiB) to what a launch needs,
-// once per kernel and size.  The first launch of every kernel with a given
-// problem happens in setup or in the first, uncaptured outer iteration, so
-// this never runs inside a stream capture.
-void allow_lds(const void* kern, size_t lds) {
-    if (lds <= 64 * 1024) return;
-    static std::mutex mu;
-    static std::map<const void*, size_t> done;
-    std::lock_guard<std::mutex> g(mu);
-    auto it = done.find(kern);
-    if (it != done.end() && it->second >= lds) return;
-    const hipError_t e = hipFuncSetAttribute(kern, hipFuncAttributeMaxDynamicSharedMemorySize, int(lds));
-    if (e != hipSuccess) {
-        (void)hipGetLastError();
-        throw std::runtime_error(std::string("hipFuncSetAttribute: ") + hipGetErrorString(e));
-    }
-    done[kern] = lds;
-}
-
-template <typename T, int HB, int MODE>
-void apply_dispatch(const OpDev<T>& op, const T* x, T* y, const T* b, T* u, T* xout, T c1, T c2, double* part,
-                    int nv, unsigned long long* stamp, hipStream_t s) {
-    if (op.dim == 3) {
-        const Apply3dGeom g = apply3d_geom(op.m, HB, sizeof(T));
-        const size_t lds = apply3d_lds_words<T, HB>() * sizeof(T);
-        auto kern = k_apply3d<T, HB, MODE>;
-        allow_lds(reinterpret_cast<const void*>(kern), lds);
-        hipLaunchKernelGGL(kern, dim3(g.nblocks), dim3(kThreads), lds, s, op, x, y, b, u, xout, c1, c2, part, nv, g,
-                           stamp);
-    } else {
-        static_assert(kT1 * kT2 == kThreads, "2D tile must match the block size");
-        const int tiles = ((op.m[0] + kT1 - 1) / kT1) * ((op.m[1] + kT2 - 1) / kT2);
-        hipLaunchKernelGGL((k_apply2d<T, HB, MODE>), dim3(tiles), dim3(kThreads), 0, s, op, x, y, b, u, xout, c1,
-                           c2, part, nv, stamp);
-    }
-    check_launch("apply");
-}
-
-template <typename T, int HB>
-void apply_mode(const OpDev<T>& op, int mode, const T* x, T* y, const T* b, T* u, T* xout, T c1, T c2, double* part,
-                int nv, unsigned long long* stamp, hipStream_t s) {
-    switch (mode) {
-        case kApplyY: apply_dispatch<T, HB, kApplyY>(op, x, y, b, u, xout, c1, c2, part, nv, stamp, s); break;
-        case kApplyRes: apply_dispatch<T, HB, kApplyRes>(op, x, y, b, u, xout, c1, c2, part, nv, stamp, s); break;
-        case kApplyCheb: apply_dispatch<T, HB, kApplyCheb>(op, x, y, b, u, xout, c1, c2, part, nv, stamp, s); break;
-        case kApplyYDot: apply_dispatch<T, HB, kApplyYDot>(op, x, y, b, u, xout, c1, c2, part, nv, stamp, s); break;
-        case kApplyResDot: apply_dispatch<T, HB, kApplyResDot>(op, x, y, b, u, xout, c1, c2, part, nv, stamp, s); break;
-        case kApplyYMulti: apply_dispatch<T, HB, kApplyYMulti>(op, x, y, b, u, xout, c1, c2, part, nv, stamp, s); break;
-        default: throw std::runtime_error("bad apply mode");
-    }
-}
 
 // ------------------------------------------------------------------------------
 // Grid transfers: Kronecker products of 1D prolongators, one thread per
@@ -1395,18 +769,26 @@ int apply_blocks(const OpDev<T>& op) {
 
 template <typename T>
 void launch_apply(const OpDev<T>& op, int mode, const T* x, T* y, const T* b, T* u, T* xout, T c1, T c2, double* part,
-                  hipStream_t s, int nv,
-                  unsigned long long* stamp) {
+                  hipStream_t s, int nv, unsigned long long* stamp) {
     if (mode == kApplyYMulti && (nv < 1 || nv > kMaxBasis)) throw std::runtime_error("bad number of dot vectors");
+    if (mode < kApplyY || mode > kApplyYMulti) throw std::runtime_error("bad apply mode");
+#define CD_APPLY_CASE(H)                                                                      \
+    case H:                                                                                   \
+        if (op.dim == 3)                                                                      \
+            apply3d_run<T, H>(op, mode, x, y, b, u, xout, c1, c2, part, nv, stamp, s);        \
+        else                                                                                  \
+            apply2d_run<T, H>(op, mode, x, y, b, u, xout, c1, c2, part, nv, stamp, s);        \
+        break;
     switch (op.hb) {
-        case 1: apply_mode<T, 1>(op, mode, x, y, b, u, xout, c1, c2, part, nv, stamp, s); break;
-        case 2: apply_mode<T, 2>(op, mode, x, y, b, u, xout, c1, c2, part, nv, stamp, s); break;
-        case 3: apply_mode<T, 3>(op, mode, x, y, b, u, xout, c1, c2, part, nv, stamp, s); break;
-        case 4: apply_mode<T, 4>(op, mode, x, y, b, u, xout, c1, c2, part, nv, stamp, s); break;
-        case 5: apply_mode<T, 5>(op, mode, x, y, b, u, xout, c1, c2, part, nv, stamp, s); break;
-        case 6: apply_mode<T, 6>(op, mode, x, y, b, u, xout, c1, c2, part, nv, stamp, s); break;
+        CD_APPLY_CASE(1)
+        CD_APPLY_CASE(2)
+        CD_APPLY_CASE(3)
+        CD_APPLY_CASE(4)
+        CD_APPLY_CASE(5)
+        CD_APPLY_CASE(6)
         default: throw std::runtime_error("degree out of range (1..6)");
     }
+#undef CD_APPLY_CASE
 }
 
 // Fixed-width kernel when every real axis has the same window width w
