@@ -144,3 +144,50 @@ def test_toeplitz_T(p):
     ev = np.linalg.eigvalsh(T)
     sym = sy.m_sym(p - 1, th)
     assert ev.min() >= sym.min() - 1e-12 and ev.max() <= sym.max() + 1e-12
+
+
+@pytest.mark.parametrize("d", [2, 3])
+@pytest.mark.parametrize("p", range(1, 6))
+def test_g_p_is_the_symbol_of_the_d_level_T(d, p):
+    # g_p = prod_i m_{p-1}(theta_i) (Sec. 6.1) must be the generating function of
+    # T_m(m_{p-1})^{(x) d}: its Fourier coefficients are products of the entries
+    # phi_{2p-1}(p - i + j) of the 1D Toeplitz matrix
+    m = 4 * p + 3
+    T1 = mt.toeplitz_T(m, p)
+    c = m // 2
+    coef = {k: T1[c, c + k] for k in range(-(p - 1), p)}
+    rng = np.random.default_rng(p + 10 * d)
+    th = [rng.uniform(-np.pi, np.pi, 50) for _ in range(d)]
+    ref = np.ones(50, dtype=complex)
+    for t in th:
+        ref = ref * sum(v * np.exp(1j * k * t) for k, v in coef.items())
+    np.testing.assert_allclose(sy.g_sym(p, th), ref.real, atol=1e-14)
+    assert np.abs(ref.imag).max() < 1e-14
+    # the d-level T is spectrally distributed as g_p: its eigenvalues stay in the symbol's range
+    ev = np.linalg.eigvalsh(T1)
+    gmin, gmax = sy.m_sym(p - 1, np.pi) ** d, 1.0
+    assert ev.min() ** d >= gmin - 1e-12 and ev.max() ** d <= gmax + 1e-12
+
+
+@pytest.mark.parametrize("d", [2, 3])
+@pytest.mark.parametrize("beta", [1.0, 0.1])
+def test_preconditioned_symbol_loses_the_zeros_at_pi(d, beta):
+    # Sec. 6.1: f^{p,alpha,beta} has numerical zeros where some theta_i = +-pi
+    # (its smallest eigenvalue there decays geometrically in p), while
+    # f / g_p stays bounded away from zero there, uniformly in p
+    t = np.linspace(-np.pi, np.pi, 201 if d == 2 else 41)
+    if d == 2:
+        th = [np.full_like(t, np.pi), t]
+    else:
+        T2, T3 = np.meshgrid(t, t, indexing="ij")
+        th = [np.full_like(T2, np.pi), T2, T3]
+    fmin, qmin = [], []
+    for p in range(1, 8):
+        f = sy.curl_div_symbol(p, 1.0, beta, th)
+        g = sy.g_sym(p, th)
+        fmin.append(np.linalg.eigvalsh(f)[..., 0].min())
+        qmin.append(np.linalg.eigvalsh(f / g[..., None, None])[..., 0].min())
+    for p in range(2, 7):
+        assert fmin[p] < fmin[p - 1] / 4  # p -> p + 1 (list index p is degree p + 1)
+    assert min(qmin) >= min(1.0, beta) * 0.999
+    assert max(qmin) / min(qmin) < 1.6
