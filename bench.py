@@ -1,14 +1,19 @@
 """Benchmark of the curl-div solver on one MI355X.
 
-A step solves one batch of the 2D workload (p = 3, n = 256 intervals per
-direction, alpha = 1, beta in {1, 1e-4}, uniform [-1, 1] right-hand sides)
-to relative residual 1e-8 with the mixed-precision solver (FP32 V-cycle
-inside FP64 flexible CG).  Right-hand sides are resident in HBM before the
-timed region; solver setup is outside it.  Prints one JSON line.
+A step solves one right-hand side of the 3D workload (p = 3, n = 128
+intervals per direction: 6,440,067 unknowns; alpha = 1, beta = 1e-6; Gaussian
+right-hand side) to relative residual 1e-8 with the mixed-precision solver
+(FP32 V-cycle inside FP64 flexible CG).  Right-hand sides are resident in HBM
+before the timed region; solver setup is outside it and reported apart.  The
+same right-hand sides are then solved by the plain FP64 path, and the two
+solutions are compared.  The other workloads (2D p=2 n=16 latency, 2D p=3
+n=256, 3D p=2 n=64, the serving stream) are reported as extra keys.  Prints
+one JSON line.
 """
 import argparse
 import json
 import os
+import platform
 import sys
 import time
 
@@ -18,6 +23,7 @@ if ROOT not in sys.path:
 
 HBM_PEAK_GBS = 8000.0
 PROF_PERIOD = 8  # outer iterations per timed one in the timed region
+HEADLINE = "c4_3d_p3_n128"
 
 
 def percentile(v, q):
@@ -29,44 +35,179 @@ def percentile(v, q):
     return v[lo] + (v[hi] - v[lo]) * (k - lo)
 
 
-# HBM bytes per launch of the FP32 V-cycle applies of the 2D p=3 n=256 mixed
-# solve (all levels, the timed solves' launch mix), from FETCH_SIZE and
-# WRITE_SIZE counter runs scaled by a plain copy kernel's readings (factors
-# 2.000 and 1.000): 581.9 KiB x 2 + 537.0 KiB.  The counters were read with
-# the kernels of this source; a change to k_apply2d voids the figure.
-C2_APPLY_HBM_BYTES_PER_LAUNCH = 1741471
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
-def cpu_baseline(cfg, its_gpu):
-    """Oracle timed on the host: one full solve at beta = 1 and a bounded
-    number of outer iterations at beta = 1e-4, projected to the iteration
-    count the GPU solver needed (setup excluded on both sides)."""
+def cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return platform.processor() or "unknown"
+
+
+def finest_apply_equivalents(opt, p, levels):
+    """Operator applies of one outer iteration, in units of a finest-level
+    apply: on level 0 the Chebyshev steps after the first (the first rides on
+    the input conversion), the residual before the coarse correction, the
+    GMRES post-smoother's residual and p Krylov applies, and the outer
+    iteration's A d; on each smoothed coarser level l two smoothing
+    applications and a residual, weighted by the level's size 8^-l (3D,
+    knot insertion halves n per axis)."""
+    fine = (opt.cheb_degree - 1) + 1 + 1 + p + 1
+    coarse = 0.0
+    for l in range(1, levels - 1):
+        coarse += (2 * opt.cheb_degree_coarse - 1 + 1) * 8.0 ** (-l)
+    return fine + coarse
+
+
+def cpu_baseline(its_gpu, levels):
+    """The oracle's tier-2 Kronecker apply (FP64, one host thread) timed at
+    the 3D p=3 n=128 size, times the operator applies one outer iteration of
+    the method needs, times the outer iterations the GPU solver took: a
+    projection of the oracle's solve time that counts operator applies only
+    (T-solves, transfers and vector updates left out, so it favours the
+    host)."""
     import numpy as np
     from threadpoolctl import threadpool_limits
 
     import curldiv_inputs as ci
-    from oracle import method
+    from oracle import assembly as asm
+    from oracle import matrices as mt
     from paper_1805_10058_amd import capi
 
-    d, p, n, alpha, betas, dist, tol = cfg
-    opt = capi.options()  # the GPU solver's defaults, so both run the same method
-    times = []
+    d, p, n, alpha, betas, dist, tol = ci.CONFIGS[HEADLINE]
+    x = ci.rhs(d, p, n, 99, dist)
+    reps = 5
     with threadpool_limits(limits=1):
-        for beta in betas:
-            meth = method.Method(d, p, n, alpha, beta, coarse_max_dofs=opt.coarse_max_dofs, nu=opt.cheb_degree,
-                                 nu_coarse=opt.cheb_degree_coarse if opt.cheb_degree_coarse > 0 else None,
-                                 ratio=opt.cheb_ratio, lanczos_steps=opt.lanczos_steps)
-            b = ci.rhs(d, p, n, 0, dist)
-            cap = 6 if beta < 1e-2 else 10000
-            t0 = time.perf_counter()
-            _, it, _ = meth.solve(b, tol, maxiter=cap)
-            dt = time.perf_counter() - t0
-            target = its_gpu.get(beta, it)
-            times.append(dt / it * max(it, target))
-    return {"value": len(betas) / sum(times), "unit": "solves/s", "cores": 1, "kind": "oracle",
-            "sample": f"FP64 oracle P_MIM (FCG + V-cycle, same algorithm) on the {d}D p={p} n={n} workload, "
-                      f"one solve per beta in {betas}; beta=1 run to completion, beta<1e-2 run for 6 outer "
-                      f"iterations and projected to the GPU iteration count; setup excluded; 1 thread"}
+        M, A, S = mt.mass_adv_stiff(n, p)
+        asm.kron_apply({"M": M, "A": A, "S": S}, x, d, alpha, betas[0])  # warm
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            asm.kron_apply({"M": M, "A": A, "S": S}, x, d, alpha, betas[0])
+        t_apply = (time.perf_counter() - t0) / reps
+    opt = capi.options()
+    per_iter = finest_apply_equivalents(opt, p, levels)
+    t_solve = t_apply * per_iter * its_gpu
+    return {"value": 1.0 / t_solve, "unit": "solves/s", "cores": 1, "kind": "oracle",
+            "cpu_model": cpu_model(), "host_cores_available": len(os.sched_getaffinity(0)),
+            "sample": f"{reps} FP64 oracle Kronecker applies y = A x at 3D p=3 n=128 (6,440,067 unknowns) on one "
+                      f"thread, {t_apply:.3f} s each, times {per_iter:.1f} finest-level-equivalent applies per outer "
+                      f"iteration times {its_gpu} outer iterations (the GPU solver's count); T-solves, transfers "
+                      f"and vector updates not counted",
+            "oracle_apply_s": t_apply, "projected_solve_s": t_solve}
+
+
+def headline(capi, torch, st, steps, warmup):
+    """The 3D p=3 n=128 workload: `warmup` + `steps` mixed solves of distinct
+    seeded right-hand sides, live kernel timing of the FP32 operator applies
+    in the timed solves, then the FP64 path on the timed right-hand sides."""
+    import numpy as np
+
+    import curldiv_inputs as ci
+
+    d, p, n, alpha, betas, dist, tol = ci.CONFIGS[HEADLINE]
+    beta = betas[0]
+    N = ci.num_dofs(d, p, n)
+    prob = capi.problem(d, p, n, alpha, beta)
+    nsteps = warmup + steps
+    rhs = [torch.as_tensor(ci.rhs(d, p, n, 2000 + k, dist)).cuda() for k in range(nsteps)]
+    xm = [torch.zeros(N, dtype=torch.float64, device="cuda") for _ in range(nsteps)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    mixed = capi.Solver(prob, capi.options(precision=capi.CD_MIXED_FP32, rtol=tol), st)
+    torch.cuda.synchronize()
+    setup_mixed = time.perf_counter() - t0
+    levels = mixed.num_levels()
+    # live timing on from the warm-up on, so that the timed region replays
+    # graphs captured (with their timing nodes) before it
+    mixed.profile_enable(True, PROF_PERIOD)
+    for k in range(warmup):
+        r = mixed.solve(rhs[k].data_ptr(), xm[k].data_ptr())
+        log(f"warm-up solve {k}: {r.iterations} iterations, status {r.status}")
+    mixed.profile_enable(False)
+    mixed.profile_enable(True, PROF_PERIOD)
+    lat, res = [], []
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(warmup, nsteps):
+        ts = time.perf_counter()
+        r = mixed.solve(rhs[k].data_ptr(), xm[k].data_ptr())
+        lat.append(time.perf_counter() - ts)
+        res.append(r)
+        log(f"timed solve {k}: {r.iterations} iterations, {lat[-1]:.3f} s, status {r.status}")
+        if r.status != capi.CD_OK:
+            raise RuntimeError(f"mixed solve did not converge: status {r.status}")
+    torch.cuda.synchronize()
+    T = time.perf_counter() - t0
+    cheb = mixed.profile_read_smoother(0, True)
+    per_level = {}
+    for lvl in range(levels):
+        a = mixed.profile_read(lvl, True)
+        per_level[str(lvl)] = {"launches": a.launches, "avg_us": 1e3 * a.total_ms / max(a.launches, 1),
+                               "GB_s": a.bytes / (a.total_ms * 1e-3) / 1e9 if a.total_ms > 0 else 0.0}
+    ts = mixed.profile_read_tsolve(True)
+    mixed.profile_enable(False)
+    mixed.close()
+
+    # plain FP64 path on the same right-hand sides
+    t0 = time.perf_counter()
+    fp64 = capi.Solver(prob, capi.options(precision=capi.CD_FP64, rtol=tol), st)
+    torch.cuda.synchronize()
+    setup_fp64 = time.perf_counter() - t0
+    x64 = torch.zeros(N, dtype=torch.float64, device="cuda")
+    lat64, res64, err = [], [], []
+    t0 = time.perf_counter()
+    for k in range(warmup, nsteps):
+        ts0 = time.perf_counter()
+        r = fp64.solve(rhs[k].data_ptr(), x64.data_ptr())
+        lat64.append(time.perf_counter() - ts0)
+        res64.append(r)
+        err.append(float(torch.linalg.vector_norm(xm[k] - x64) / torch.linalg.vector_norm(x64)))
+        log(f"fp64 solve {k}: {r.iterations} iterations, {lat64[-1]:.3f} s, |x_mixed - x_64|/|x_64| = {err[-1]:.2e}")
+    torch.cuda.synchronize()
+    T64 = time.perf_counter() - t0
+    fp64.close()
+
+    ach = cheb.bytes / (cheb.total_ms * 1e-3) / 1e9 if cheb.total_ms > 0 else 0.0
+    flops = 22 * (2 * p + 1) * N  # 33 band contractions of 2p+1 terms per point, 2 flops each
+    out = {
+        "value": steps / T,
+        "ms_per_step": 1e3 * T / steps,
+        "config": {"workload": "3D curl-div, p=3, n=128 (6,440,067 unknowns), alpha=1, beta=1e-6, Gaussian RHS, "
+                               "rel. residual 1e-8, FP32 V-cycle in FP64 flexible CG",
+                   "dim": d, "degree": p, "n": n, "beta": beta, "solves_per_step": 1},
+        "latency_ms": {"p50": 1e3 * percentile(lat, 50), "p99": 1e3 * percentile(lat, 99)},
+        "iterations": [r.iterations for r in res],
+        "max_true_rel_residual": max(r.true_rel_residual for r in res),
+        "kappa_estimate": [r.kappa_estimate for r in res],
+        "setup_ms": 1e3 * setup_mixed,
+        "levels": levels,
+        "fp64_path": {"solves_per_s": steps / T64, "p50_ms": 1e3 * percentile(lat64, 50),
+                      "p99_ms": 1e3 * percentile(lat64, 99), "iterations": [r.iterations for r in res64],
+                      "max_true_rel_residual": max(r.true_rel_residual for r in res64),
+                      "kappa_estimate": [r.kappa_estimate for r in res64], "setup_ms": 1e3 * setup_fp64},
+        "error_vs_fp64": {"max_rel_diff": max(err), "per_solve": err,
+                          "note": "||x_mixed - x_fp64||_2 / ||x_fp64||_2 per right-hand side; both solutions meet "
+                                  "rel. residual 1e-8, and the forward error of each is at most kappa_2(A) times "
+                                  "its residual"},
+        "roofline": {"bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": ach / HBM_PEAK_GBS, "traffic": None,
+                     "kernel": "FP32 Chebyshev-step operator apply k_apply3d<float,3,2> on level 0, inside the timed "
+                               f"solves (every {PROF_PERIOD}th outer iteration timed by the kernel's own stamps)",
+                     "bytes_per_unit": "4 N s per step (read x_k, x_{k-1}, b; write x_{k+1}), N = 6,440,067, s = 4",
+                     "launches": cheb.launches, "avg_us": 1e3 * cheb.total_ms / max(cheb.launches, 1),
+                     "bytes_per_launch": cheb.bytes / max(cheb.launches, 1),
+                     "TFLOP_s": flops * cheb.launches / (cheb.total_ms * 1e-3) / 1e12 if cheb.total_ms > 0 else 0.0},
+        "fp32_applies_per_level": per_level,
+        "tsolve": {"kernel": "FP32 T-solve axis passes k_tsolve_line<float,2,*>", "launches": ts.launches,
+                   "avg_us": 1e3 * ts.total_ms / max(ts.launches, 1),
+                   "GB_s": ts.bytes / (ts.total_ms * 1e-3) / 1e9 if ts.total_ms > 0 else 0.0},
+    }
+    return out, levels
 
 
 def main():
@@ -75,21 +216,21 @@ def main():
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--no-c4", action="store_true", help="skip the 3D p=3 n=128 operator-apply measurement")
-    ap.add_argument("--only-c4", action="store_true", help="run only the 3D p=3 n=128 operator-apply measurement")
+    ap.add_argument("--no-extras", action="store_true", help="only the headline workload")
     ap.add_argument("--serve", type=int, default=32, help="requests of the serving stream to run (0: skip)")
     ap.add_argument("--serve-rate", type=float, default=8.0, help="Poisson arrival rate of the stream, 1/s (0: burst)")
     ap.add_argument("--serve-max-iter", type=int, default=4000)
     ap.add_argument("--batched", type=int, default=8,
-                    help="also solve this many right-hand sides of the 2D workload at once through the "
+                    help="also solve this many right-hand sides of the 2D p=3 n=256 workload at once through the "
                          "continuous-batching server (0: skip)")
-    ap.add_argument("--only-c4-solve", action="store_true",
-                    help="run only the mixed solve of the 3D p=3 n=128 workload (beta = 1e-6)")
-    ap.add_argument("--c4-max-iter", type=int, default=20000,
-                    help="outer-iteration cap of that solve (a small cap gives a short profiling run)")
+    ap.add_argument("--only-c4-apply", action="store_true",
+                    help="run only the operator-apply measurement at 3D p=3 n=128 (FP64 and FP32)")
+    ap.add_argument("--only-c4-solve", type=int, default=0, metavar="MAX_ITER",
+                    help="run only one mixed solve of the headline workload, cut at MAX_ITER outer iterations "
+                         "(a short program for profiling)")
     ap.add_argument("--pmc-pass", action="store_true",
-                    help="only run 6 eager outer iterations of each mixed 2D workload solve (and --copy-cal): a "
-                         "short program for the HBM byte counters of the V-cycle kernels")
+                    help="only run 6 eager outer iterations of the headline mixed solve (and --copy-cal): a short "
+                         "program for the HBM byte counters of the V-cycle kernels")
     ap.add_argument("--copy-cal", action="store_true",
                     help="also run a plain 256 MiB device copy 5 times (calibrates HBM byte counters)")
     args = ap.parse_args()
@@ -98,7 +239,6 @@ def main():
               file=sys.stderr)
         sys.exit(2)
 
-    import numpy as np
     import torch
 
     import curldiv_inputs as ci
@@ -108,174 +248,111 @@ def main():
     st = torch.cuda.current_stream().cuda_stream
     if args.copy_cal:
         copy_calibration(torch)
-    if args.only_c4:
+    if args.only_c4_apply:
         print(json.dumps({"operator_apply_c4": c4_apply(capi, torch, st)}), flush=True)
         return
-    if args.only_c4_solve:
-        print(json.dumps({"solve_c4": c4_solve(capi, torch, st, args.c4_max_iter)}), flush=True)
-        return
-    name = "c2_2d_p3_n256"
-    cfg = ci.CONFIGS[name]
-    d, p, n, alpha, betas, dist, tol = cfg
-    N = ci.num_dofs(d, p, n)
-
-    def make(beta, precision):
-        opt = capi.options(precision=precision, rtol=tol)
-        return capi.Solver(capi.problem(d, p, n, alpha, beta), opt, st)
-
-    if args.pmc_pass:
-        # the same kernels and per-iteration launch mix as the timed solves,
-        # launched eagerly and cut to a few outer iterations
-        b0 = torch.as_tensor(ci.rhs(d, p, n, 0, dist)).cuda()
-        x0 = torch.zeros(N, dtype=torch.float64, device="cuda")
-        for beta in betas:
-            opt = capi.options(precision=capi.CD_MIXED_FP32, rtol=tol, max_iter=6, graphs=0)
-            s = capi.Solver(capi.problem(d, p, n, alpha, beta), opt, st)
-            r = s.solve(b0.data_ptr(), x0.data_ptr())
-            s.close()
-            print(f"[bench] counter pass: beta={beta} iterations={r.iterations}", file=sys.stderr, flush=True)
-        torch.cuda.synchronize()
+    if args.only_c4_solve or args.pmc_pass:
+        print(json.dumps({"solve_c4": c4_solve(capi, torch, st, args.only_c4_solve or 6,
+                                                graphs=0 if args.pmc_pass else 1)}), flush=True)
         return
 
-    mixed = {beta: make(beta, capi.CD_MIXED_FP32) for beta in betas}
-    fp64 = {beta: make(beta, capi.CD_FP64) for beta in betas}
-    nsteps = args.warmup + args.steps
-    rhs = [[torch.as_tensor(ci.rhs(d, p, n, 1000 * k + j, dist)).cuda() for j in range(len(betas))]
-           for k in range(nsteps)]
-    xs = [torch.zeros(N, dtype=torch.float64, device="cuda") for _ in betas]
-    torch.cuda.synchronize()
+    out = {"metric": "solves/sec + p50/p99 latency to rel. residual 1e-8; operator-apply HBM GB/s",
+           "value": None, "unit": "solves/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+           "ms_per_step": None, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+           "dtype": "f32+f64", "data": "synthetic"}
+    head, levels = headline(capi, torch, st, args.steps, args.warmup)
+    out.update(head)
 
-    def step(k, solvers, lat, its, res_out):
-        for j, beta in enumerate(betas):
-            t0 = time.perf_counter()
-            r = solvers[beta].solve(rhs[k][j].data_ptr(), xs[j].data_ptr())
-            lat.append(time.perf_counter() - t0)
-            its[beta] = r.iterations
-            res_out.append(r.true_rel_residual)
-            if r.status != capi.CD_OK:
-                raise RuntimeError(f"solve did not converge: beta={beta} status={r.status}")
-
-    lat, its, tres = [], {}, []
-    def log(msg):
-        print(f"[bench] {msg}", file=sys.stderr, flush=True)
-
-    # live timing on from the warm-up on, so that the timed region replays
-    # graphs that were captured (with their timing event nodes) before it;
-    # every PROF_PERIOD-th outer iteration carries the timing events
-    for s in mixed.values():
-        s.profile_enable(True, PROF_PERIOD)
-    for k in range(args.warmup):
-        step(k, mixed, [], its, [])
-        log(f"warmup step {k} done, iterations {its}")
-    for s in mixed.values():  # restart the counters
-        s.profile_enable(False)
-        s.profile_enable(True, PROF_PERIOD)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for k in range(args.warmup, nsteps):
-        step(k, mixed, lat, its, tres)
-        log(f"timed step {k} done")
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    T = t1 - t0
-    nsolves = args.steps * len(betas)
-
-    # live kernel timing (stamps written by the kernels themselves, sampled
-    # outer iterations of the timed region) of the FP32 V-cycle operator apply
-    # (k_apply2d<float, 3, *> on every level), the kernel that takes the most
-    # GPU time in the timed solves, and of the FP32 T-solve passes
-    nlev = {beta: mixed[beta].num_levels() for beta in betas}
-    tot_ms = tot_b = 0.0
-    launches = 0
-    per_level = {}
-    ts_ms = ts_b = 0.0
-    ts_n = 0
-    for beta, s in mixed.items():
-        for lvl in range(nlev[beta]):
-            stt = s.profile_read(lvl, True)
-            tot_ms += stt.total_ms
-            tot_b += stt.bytes
-            launches += stt.launches
-            pl = per_level.setdefault(lvl, [0, 0.0, 0.0])
-            pl[0] += stt.launches
-            pl[1] += stt.total_ms
-            pl[2] += stt.bytes
-        tst = s.profile_read_tsolve(True)
-        ts_ms += tst.total_ms
-        ts_b += tst.bytes
-        ts_n += tst.launches
-        s.profile_enable(False)
-    ach = (tot_b / (tot_ms * 1e-3)) / 1e9 if tot_ms > 0 else 0.0
-    ts_gbs = (ts_b / (ts_ms * 1e-3)) / 1e9 if ts_ms > 0 else 0.0
-
-    # plain FP64 single-solve path on the same inputs (comparison, not the headline)
-    lat64, its64, tres64 = [], {}, []
-    step(0, fp64, [], its64, [])
-    t2 = time.perf_counter()
-    for k in range(args.warmup, nsteps):
-        step(k, fp64, lat64, its64, tres64)
-    torch.cuda.synchronize()
-    T64 = time.perf_counter() - t2
-    log(f"fp64 comparison done, iterations {its64}")
-
-    out = {
-        "metric": "solves/sec + p50/p99 latency to rel. residual 1e-8; operator-apply HBM GB/s",
-        "value": nsolves / T,
-        "unit": "solves/s",
-        "n_gpus": 1,
-        "steps": args.steps,
-        "warmup": args.warmup,
-        "ms_per_step": 1e3 * T / args.steps,
-        "higher_is_better": True,
-        "scaling": "weak",
-        "vs_baseline": None,
-        "dtype": "f32+f64",
-        "data": "synthetic",
-        "config": {"workload": "2D curl-div, p=3, n=256 (132,098 unknowns), alpha=1, beta in {1, 1e-4}, "
-                               "uniform[-1,1] RHS, rel. residual 1e-8, FP32 V-cycle in FP64 flexible CG",
-                   "dim": d, "degree": p, "n": n, "betas": betas, "solves_per_step": len(betas)},
-        "latency_ms": {"p50": 1e3 * percentile(lat, 50), "p99": 1e3 * percentile(lat, 99)},
-        "iterations": {str(b): its[b] for b in betas},
-        "max_true_rel_residual": max(tres),
-        "fp64_path": {"solves_per_s": nsolves / T64, "p50_ms": 1e3 * percentile(lat64, 50),
-                      "p99_ms": 1e3 * percentile(lat64, 99), "iterations": {str(b): its64[b] for b in betas},
-                      "max_true_rel_residual": max(tres64)},
-        "roofline": {"bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": ach / HBM_PEAK_GBS, "traffic": C2_APPLY_HBM_BYTES_PER_LAUNCH,
-                     "kernel": "FP32 V-cycle operator apply k_apply2d<float,3,*>, all levels, inside the timed solves "
-                               f"(every {PROF_PERIOD}th outer iteration timed)",
-                     "launches": launches, "avg_us": 1e3 * tot_ms / max(launches, 1),
-                     "bytes_per_launch": tot_b / max(launches, 1),
-                     "per_level": {str(l): {"launches": v[0], "avg_us": 1e3 * v[1] / max(v[0], 1),
-                                            "GB_s": (v[2] / (v[1] * 1e-3)) / 1e9 if v[1] > 0 else 0.0}
-                                   for l, v in sorted(per_level.items())}},
-        "tsolve": {"kernel": "FP32 T-solve axis passes k_tsolve_line<float,2,*>", "launches": ts_n,
-                   "avg_us": 1e3 * ts_ms / max(ts_n, 1), "GB_s": ts_gbs, "hbm_frac": ts_gbs / HBM_PEAK_GBS},
-    }
-
-    if args.batched > 0:
-        out["batched"] = c2_batched(capi, torch, cfg, args.batched, log)
-        log(f"batched: {out['batched']}")
-
-    if not args.no_c4:
+    if not args.no_extras:
         out["operator_apply_c4"] = c4_apply(capi, torch, st)
         log(f"3D p=3 n=128 operator apply: {out['operator_apply_c4']}")
-        out["solve_c4"] = c4_solve(capi, torch, st, args.c4_max_iter)
-        log(f"3D p=3 n=128 solve: {out['solve_c4']}")
-
-    if args.serve > 0:
-        # Poisson arrivals measure latency under load (throughput is then the
-        # arrival rate); a burst of the same requests measures capacity.
-        out["serving"] = serve_bench(capi, torch, st, args.serve, args.serve_max_iter, log, args.serve_rate)
-        log(f"serving: {out['serving']}")
-        if args.serve_rate > 0:
-            out["serving"]["burst"] = serve_bench(capi, torch, st, args.serve, args.serve_max_iter, log, 0.0)
-            log(f"serving burst: {out['serving']['burst']}")
+        out["c1_2d_p2_n16"] = c1_latency(capi, torch, st)
+        log(f"2D p=2 n=16: {out['c1_2d_p2_n16']}")
+        out["c2_2d_p3_n256"] = c2_solves(capi, torch, st, args.steps, args.warmup)
+        log(f"2D p=3 n=256: {out['c2_2d_p3_n256']}")
+        out["c3_3d_p2_n64"] = c3_solves(capi, torch, st)
+        log(f"3D p=2 n=64: {out['c3_3d_p2_n64']}")
+        if args.batched > 0:
+            out["batched"] = c2_batched(capi, torch, ci.CONFIGS["c2_2d_p3_n256"], args.batched, log)
+            log(f"batched: {out['batched']}")
+        if args.serve > 0:
+            # Poisson arrivals measure latency under load (throughput is then the
+            # arrival rate); a burst of the same requests measures capacity.
+            out["serving"] = serve_bench(capi, torch, st, args.serve, args.serve_max_iter, log, args.serve_rate)
+            log(f"serving: {out['serving']}")
+            if args.serve_rate > 0:
+                out["serving"]["burst"] = serve_bench(capi, torch, st, args.serve, args.serve_max_iter, log, 0.0)
+                log(f"serving burst: {out['serving']['burst']}")
 
     if not args.no_cpu_baseline:
         log("timing the oracle on the host")
-        out["cpu_baseline"] = cpu_baseline(cfg, its)
+        out["cpu_baseline"] = cpu_baseline(int(percentile(out["iterations"], 50)), levels)
     print(json.dumps(out), flush=True)
+
+
+def run_solves(capi, torch, st, name, precision, seeds, **kw):
+    """Solve the workload `name` once per seed (per beta of the workload);
+    returns (wall seconds, latencies, results)."""
+    import curldiv_inputs as ci
+
+    d, p, n, alpha, betas, dist, tol = ci.CONFIGS[name]
+    N = ci.num_dofs(d, p, n)
+    solvers = {b: capi.Solver(capi.problem(d, p, n, alpha, b), capi.options(precision=precision, rtol=tol, **kw), st)
+               for b in betas}
+    rhs = [[torch.as_tensor(ci.rhs(d, p, n, s * 10 + j, dist)).cuda() for j in range(len(betas))] for s in seeds]
+    x = torch.zeros(N, dtype=torch.float64, device="cuda")
+    for j, b in enumerate(betas):  # warm-up: graph capture
+        solvers[b].solve(rhs[0][j].data_ptr(), x.data_ptr())
+    torch.cuda.synchronize()
+    lat, res = [], []
+    t0 = time.perf_counter()
+    for k in range(len(seeds)):
+        for j, b in enumerate(betas):
+            ts = time.perf_counter()
+            r = solvers[b].solve(rhs[k][j].data_ptr(), x.data_ptr())
+            lat.append(time.perf_counter() - ts)
+            res.append((b, r))
+    torch.cuda.synchronize()
+    T = time.perf_counter() - t0
+    for s in solvers.values():
+        s.close()
+    return T, lat, res
+
+
+def summarize(capi, T, lat, res):
+    return {"solves_per_s": len(lat) / T, "p50_ms": 1e3 * percentile(lat, 50), "p99_ms": 1e3 * percentile(lat, 99),
+            "iterations": {str(b): r.iterations for b, r in res},
+            "converged": sum(1 for _, r in res if r.status == capi.CD_OK), "solves": len(res),
+            "max_true_rel_residual": max(r.true_rel_residual for _, r in res)}
+
+
+def c1_latency(capi, torch, st, reps=100):
+    """2D p=2 n=16 (512 unknowns), FP64 to rel. residual 1e-10: latency of
+    one solve, with the outer iterations replayed from a HIP graph and
+    launched one kernel at a time."""
+    out = {}
+    for graphs in (1, 0):
+        T, lat, res = run_solves(capi, torch, st, "c1_2d_p2_n16", capi.CD_FP64, list(range(reps)), graphs=graphs)
+        out["graph" if graphs else "eager"] = summarize(capi, T, lat, res)
+    out["workload"] = "2D p=2 n=16 (512 unknowns), alpha=beta=1, FP64, rel. residual 1e-10, one solve at a time"
+    return out
+
+
+def c2_solves(capi, torch, st, steps, warmup):
+    """2D p=3 n=256 (132,098 unknowns), beta in {1, 1e-4}: mixed and FP64."""
+    seeds = list(range(max(steps, 3)))
+    out = {"workload": "2D p=3 n=256 (132,098 unknowns), alpha=1, beta in {1, 1e-4}, rel. residual 1e-8"}
+    for name, prec in (("mixed", capi.CD_MIXED_FP32), ("fp64", capi.CD_FP64)):
+        out[name] = summarize(capi, *run_solves(capi, torch, st, "c2_2d_p3_n256", prec, seeds))
+    return out
+
+
+def c3_solves(capi, torch, st):
+    """3D p=2 n=64 (786,432 unknowns), beta in {1, 1e-2}: mixed and FP64."""
+    out = {"workload": "3D p=2 n=64 (786,432 unknowns), alpha=1, beta in {1, 1e-2}, rel. residual 1e-8"}
+    for name, prec in (("mixed", capi.CD_MIXED_FP32), ("fp64", capi.CD_FP64)):
+        out[name] = summarize(capi, *run_solves(capi, torch, st, "c3_3d_p2_n64", prec, [0, 1, 2]))
+    return out
 
 
 def c2_batched(capi, torch, cfg, count, log):
@@ -409,7 +486,7 @@ def c4_apply(capi, torch, st, reps=20):
     return res
 
 
-def c4_solve(capi, torch, st, max_iter):
+def c4_solve(capi, torch, st, max_iter, graphs=1):
     """One mixed-precision solve of the 3D p=3 n=128 workload (beta = 1e-6,
     Gaussian right-hand side, rel. residual 1e-8): setup and solve times."""
     import curldiv_inputs as ci
@@ -421,7 +498,7 @@ def c4_solve(capi, torch, st, max_iter):
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     s = capi.Solver(capi.problem(d, p, n, alpha, betas[0]),
-                    capi.options(precision=capi.CD_MIXED_FP32, rtol=tol, max_iter=max_iter), st)
+                    capi.options(precision=capi.CD_MIXED_FP32, rtol=tol, max_iter=max_iter, graphs=graphs), st)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     r = s.solve(b.data_ptr(), x.data_ptr())

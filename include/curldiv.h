@@ -92,11 +92,16 @@ typedef struct {
     int graphs;           /* 1: replay outer iterations from a captured HIP graph
                              (identical arithmetic); 0: launch every kernel eagerly */
     int cheb_degree_coarse; /* Chebyshev degree on levels >= 1; <= 0 means cheb_degree */
+    int apply_x1_chunk;   /* 3D operator kernel: x1 planes each block marches over (the
+                             launch geometry only; results do not depend on it up to
+                             rounding of the per-block partial dot products); 0 = chosen
+                             from the grid size */
 } cd_options;
 
 /* Fill *opt with the defaults: P_MIM, knot insertion, FP64, rtol 1e-8,
  * max_iter 10000, coarse_max_dofs 2500, cheb_degree 48, cheb_ratio 1000,
- * lanczos_steps 20, krylov_steps = p, graphs 1, cheb_degree_coarse 16.  The
+ * lanczos_steps 20, krylov_steps = p, graphs 1, cheb_degree_coarse 16,
+ * apply_x1_chunk 0.  The
  * smoother settings were chosen by measured solve rate on 2D and 3D
  * problems; a wide interval needs the eigenvalue bound to cover the top of
  * the spectrum, which the Lanczos estimate times 1.1 does on every tested
@@ -104,11 +109,22 @@ typedef struct {
  * cheb_degree_coarse 0) is the classical setting. */
 void cd_default_options(cd_options* opt);
 
+/* Result of a solve.  kappa_estimate is the ratio of the extreme Ritz values
+ * of the Lanczos matrix that the outer iteration's step lengths a_j and
+ * direction coefficients b_j define (diagonal 1/a_j + b_j/a_{j-1},
+ * off-diagonal sqrt(b_{j+1})/a_j): an estimate from below of the condition
+ * number of the preconditioned operator B A (of A itself for CD_METHOD_CG),
+ * exact in the limit for a linear SPD preconditioner; 0 when the solve ran no
+ * iteration.  With x* the exact solution and r = b - A x, the forward error
+ * obeys ||x - x*||_2 / ||x*||_2 <= kappa_2(A) ||r||_2 / ||b||_2, and in the
+ * energy norm ||x - x*||_A / ||x*||_A <= sqrt(kappa(B A)) ||r||_B / ||b||_B
+ * for an SPD B; kappa_estimate estimates kappa(B A) (kappa_2(A) for CG). */
 typedef struct {
     int status;                 /* CD_OK, CD_NOT_CONVERGED or an error code  */
     int iterations;             /* outer iterations performed                 */
     double rel_residual;        /* recursive ||r_k|| / ||r_0|| at exit        */
     double true_rel_residual;   /* ||b - A x||_2 / ||b||_2 recomputed in FP64 */
+    double kappa_estimate;      /* Lanczos estimate of the condition number (see above) */
 } cd_result;
 
 /* Number of unknowns d * prod_l (n_l + p - 2); 0 for an invalid problem. */
@@ -186,7 +202,8 @@ int cd_precondition(cd_solver* s, const double* r_dev, double* z_dev);
  * are always timed; during cd_solve every `on`-th outer iteration is (on = 1:
  * all of them).  `bytes` accumulates the algorithmic traffic of those
  * launches: the vectors each launch must read and write once (2 N s for
- * y = A x, 3 N s for the residual, 5 N s for a Chebyshev step, (2 + k) N s
+ * y = A x, 3 N s for the residual, 4 N s for a Chebyshev step (3 N s on its
+ * first step), (2 + k) N s
  * for y = A x fused with k Krylov-basis dot products, 2 N s per T-solve axis
  * pass; s = 8 or 4 bytes). */
 typedef struct {
@@ -199,6 +216,11 @@ typedef struct {
 int cd_profile_enable(cd_solver* s, int on);
 /* Totals of level `level` applies in FP64 (fp32 = 0) or FP32 (fp32 = 1). */
 int cd_profile_read(const cd_solver* s, int level, int fp32, cd_kernel_stats* out);
+/* Totals of the Chebyshev-step applies of level `level` alone (a subset of
+ * what cd_profile_read counts): each reads x_k, b and (after the first step)
+ * x_{k-1} and writes x_{k+1}, so its bytes are 4 N s (3 N s on a first
+ * step). */
+int cd_profile_read_smoother(const cd_solver* s, int level, int fp32, cd_kernel_stats* out);
 /* Totals of the finest-level T-solve axis passes (Sec. 6.1 preconditioner
  * T of the Krylov post-smoother), one launch per axis pass. */
 int cd_profile_read_tsolve(const cd_solver* s, int fp32, cd_kernel_stats* out);

@@ -39,7 +39,8 @@ class cd_options(ctypes.Structure):
     _fields_ = [("method", ctypes.c_int), ("transfer", ctypes.c_int), ("precision", ctypes.c_int),
                 ("rtol", ctypes.c_double), ("max_iter", ctypes.c_int), ("coarse_max_dofs", ctypes.c_int),
                 ("cheb_degree", ctypes.c_int), ("cheb_ratio", ctypes.c_double), ("lanczos_steps", ctypes.c_int),
-                ("krylov_steps", ctypes.c_int), ("graphs", ctypes.c_int), ("cheb_degree_coarse", ctypes.c_int)]
+                ("krylov_steps", ctypes.c_int), ("graphs", ctypes.c_int), ("cheb_degree_coarse", ctypes.c_int),
+                ("apply_x1_chunk", ctypes.c_int)]
 
 
 class cd_kernel_stats(ctypes.Structure):
@@ -48,7 +49,7 @@ class cd_kernel_stats(ctypes.Structure):
 
 class cd_result(ctypes.Structure):
     _fields_ = [("status", ctypes.c_int), ("iterations", ctypes.c_int), ("rel_residual", ctypes.c_double),
-                ("true_rel_residual", ctypes.c_double)]
+                ("true_rel_residual", ctypes.c_double), ("kappa_estimate", ctypes.c_double)]
 
 
 class cd_server_options(ctypes.Structure):
@@ -86,6 +87,7 @@ SIGNATURES = {
     "cd_precondition": (_I, [_P, _P, _P]),
     "cd_profile_enable": (_I, [_P, _I]),
     "cd_profile_read": (_I, [_P, _I, _I, ctypes.POINTER(cd_kernel_stats)]),
+    "cd_profile_read_smoother": (_I, [_P, _I, _I, ctypes.POINTER(cd_kernel_stats)]),
     "cd_profile_read_tsolve": (_I, [_P, _I, ctypes.POINTER(cd_kernel_stats)]),
     "cd_server_default_options": (None, [ctypes.POINTER(cd_server_options)]),
     "cd_server_create": (_I, [ctypes.POINTER(cd_server_options), ctypes.POINTER(_P)]),
@@ -243,6 +245,11 @@ class Solver:
     def profile_read(self, level, fp32):
         st = cd_kernel_stats()
         check(lib().cd_profile_read(self._h, level, 1 if fp32 else 0, ctypes.byref(st)))
+        return st
+
+    def profile_read_smoother(self, level, fp32):
+        st = cd_kernel_stats()
+        check(lib().cd_profile_read_smoother(self._h, level, 1 if fp32 else 0, ctypes.byref(st)))
         return st
 
     def profile_read_tsolve(self, fp32=False):

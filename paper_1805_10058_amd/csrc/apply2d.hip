@@ -20,8 +20,8 @@ namespace {
 
 template <typename T, int HB, int MODE>
 __global__ __launch_bounds__(kThreads) void k_apply2d(OpDev<T> op, const T* __restrict__ x, T* __restrict__ y,
-                                                      const T* __restrict__ b, T* __restrict__ u,
-                                                      T* __restrict__ xout, T c1, T c2, double* __restrict__ part,
+                                                      const T* __restrict__ b, T* u,
+                                                      T* xout, T c1, T c2, double* __restrict__ part,
                                                       int nv, unsigned long long* stamp) {
     stamp_begin(stamp);
     constexpr int R = 2 * HB + 1;

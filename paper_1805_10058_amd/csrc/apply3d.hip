@@ -41,8 +41,8 @@ constexpr size_t apply3d_lds_words() {
 
 template <typename T, int HB, int MODE>
 __global__ __launch_bounds__(kThreads) void k_apply3d(OpDev<T> op, const T* __restrict__ x, T* __restrict__ y,
-                                                      const T* __restrict__ b, T* __restrict__ u,
-                                                      T* __restrict__ xout, T c1, T c2, double* __restrict__ part,
+                                                      const T* __restrict__ b, T* u,
+                                                      T* xout, T c1, T c2, double* __restrict__ part,
                                                       int nv, Apply3dGeom g, unsigned long long* stamp) {
     stamp_begin(stamp);
     constexpr int R = 2 * HB + 1;
@@ -266,7 +266,7 @@ __global__ __launch_bounds__(kThreads) void k_apply3d(OpDev<T> op, const T* __re
 template <typename T, int HB, int MODE>
 void launch3d(const OpDev<T>& op, const T* x, T* y, const T* b, T* u, T* xout, T c1, T c2, double* part, int nv,
               unsigned long long* stamp, hipStream_t s) {
-    const Apply3dGeom g = apply3d_geom(op.m, HB, sizeof(T));
+    const Apply3dGeom g = apply3d_geom(op.m, HB, sizeof(T), op.x1chunk);
     const size_t lds = apply3d_lds_words<T, HB>() * sizeof(T);
     auto kern = k_apply3d<T, HB, MODE>;
     allow_lds(reinterpret_cast<const void*>(kern), lds);

@@ -31,14 +31,20 @@ struct Apply3dGeom {
     int nt2, nt3, c1len, nblocks;
 };
 
-inline Apply3dGeom apply3d_geom(const int* m, int hb, size_t elem) {
+// x1chunk > 0 fixes the number of x1 planes per block (the last block of a
+// column takes the remainder).
+inline Apply3dGeom apply3d_geom(const int* m, int hb, size_t elem, int x1chunk = 0) {
     const int kTargetBlocks = elem == 4 ? 1024 : 512;
     Apply3dGeom g;
     g.nt2 = (m[1] + k3T2 - 1) / k3T2;
     g.nt3 = (m[2] + k3T3(hb) - 1) / k3T3(hb);
     const int planar = g.nt2 * g.nt3;
-    const int nx1 = std::max(1, std::min(m[0], kTargetBlocks / planar));
-    g.c1len = (m[0] + nx1 - 1) / nx1;
+    if (x1chunk > 0) {
+        g.c1len = std::min(x1chunk, m[0]);
+    } else {
+        const int nx1 = std::max(1, std::min(m[0], kTargetBlocks / planar));
+        g.c1len = (m[0] + nx1 - 1) / nx1;
+    }
     g.nblocks = planar * ((m[0] + g.c1len - 1) / g.c1len);
     return g;
 }
@@ -60,10 +66,12 @@ struct EpiIn {
 
 template <typename T, int MODE>
 __device__ inline void epilogue_load(EpiIn<T>& e, size_t idx, const T* __restrict__ x, const T* __restrict__ b,
-                                     const T* __restrict__ u, T c1, int nv, size_t ntot) {
+                                     const T* u, T c1, int nv, size_t ntot) {
     if (MODE == kApplyRes || MODE == kApplyResDot || MODE == kApplyCheb) e.b = b[idx];
     if (MODE == kApplyCheb) {
-        e.u = (c1 != T(0)) ? u[idx] : T(0);  // u is not read on a first step
+        // the previous iterate (u holds it; nullptr: zero, the step after a start from zero);
+        // not read on a first step (c1 = 0)
+        e.u = (c1 != T(0) && u != nullptr) ? u[idx] : T(0);
         e.x = x[idx];
     }
     if (MODE == kApplyYDot) e.x = x[idx];
@@ -77,8 +85,8 @@ __device__ inline void epilogue_load(EpiIn<T>& e, size_t idx, const T* __restric
 // with kx = (A x)[idx] and the entry's operands e.
 template <typename T, int MODE>
 __device__ inline void epilogue_store(const OpDev<T>& op, int c, size_t idx, T kx, int i1, int i2, int i3,
-                                      const EpiIn<T>& e, T* __restrict__ y, T* __restrict__ u,
-                                      T* __restrict__ xout, T c1, T c2, int nv, double* dots) {
+                                      const EpiIn<T>& e, T* __restrict__ y, T* u,
+                                      T* xout, T c1, T c2, int nv, double* dots) {
     if (MODE == kApplyY) {
         y[idx] = kx;
     } else if (MODE == kApplyRes) {
@@ -96,9 +104,7 @@ __device__ inline void epilogue_store(const OpDev<T>& op, int c, size_t idx, T k
     } else if (MODE == kApplyCheb) {
         const T r = e.b - kx;
         const T dg = diag_entry(op, c, i1, i2, i3);
-        const T un = c1 * e.u + c2 * r / dg;
-        u[idx] = un;
-        xout[idx] = e.x + un;
+        xout[idx] = e.x + (c1 * (e.x - e.u) + c2 * r / dg);
     } else {
         y[idx] = kx;
         dots[0] += double(e.x) * double(kx);
@@ -109,7 +115,7 @@ __device__ inline void epilogue_store(const OpDev<T>& op, int c, size_t idx, T k
 template <typename T, int MODE>
 __device__ inline void apply_epilogue(const OpDev<T>& op, int c, size_t idx, T kx, int i1, int i2, int i3,
                                       const T* __restrict__ x, T* __restrict__ y, const T* __restrict__ b,
-                                      T* __restrict__ u, T* __restrict__ xout, T c1, T c2, int nv, size_t ntot,
+                                      T* u, T* xout, T c1, T c2, int nv, size_t ntot,
                                       double* dots) {
     EpiIn<T> e;
     epilogue_load<T, MODE>(e, idx, x, b, u, c1, nv, ntot);

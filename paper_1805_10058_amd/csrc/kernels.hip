@@ -99,7 +99,7 @@ __global__ __launch_bounds__(kThreads) void k_prolong_add(XferDev<T> X, int ncom
 template <typename T, int W0, int W1, int W2, bool CHEB>
 __global__ __launch_bounds__(kThreads) void k_restrict_w(XferDev<T> X, int ncomp, const T* __restrict__ rf,
                                                          T* __restrict__ rc, OpDev<T> opc, T inv_theta,
-                                                         T* __restrict__ u, T* __restrict__ xo) {
+                                                         T* __restrict__ xo) {
     const XferAxisDev<T>& a0 = X.ax[0];
     const XferAxisDev<T>& a1 = X.ax[1];
     const XferAxisDev<T>& a2 = X.ax[2];
@@ -129,11 +129,7 @@ __global__ __launch_bounds__(kThreads) void k_restrict_w(XferDev<T> X, int ncomp
         }
     }
     rc[id] = acc;
-    if (CHEB) {
-        const T v = inv_theta * acc / diag_entry(opc, c, J0, J1, J2);
-        u[id] = v;
-        xo[id] = v;
-    }
+    if (CHEB) xo[id] = inv_theta * acc / diag_entry(opc, c, J0, J1, J2);
 }
 
 template <typename T, int W0, int W1, int W2>
@@ -504,30 +500,25 @@ __global__ __launch_bounds__(kThreads) void k_lanczos_next(const double* __restr
 }
 
 template <typename T>
-__global__ __launch_bounds__(kThreads) void k_cheb_first(OpDev<T> op, const T* __restrict__ b, T* __restrict__ u,
-                                                         T* __restrict__ x, T inv_theta, size_t n) {
+__global__ __launch_bounds__(kThreads) void k_cheb_first(OpDev<T> op, const T* __restrict__ b, T* __restrict__ x,
+                                                         T inv_theta, size_t n) {
     for (size_t id = size_t(blockIdx.x) * kThreads + threadIdx.x; id < n; id += size_t(gridDim.x) * kThreads) {
         int c, i0, i1, i2;
         unflatten(op, id, c, i0, i1, i2);
-        const T v = inv_theta * b[id] / diag_entry(op, c, i0, i1, i2);
-        u[id] = v;
-        x[id] = v;
+        x[id] = inv_theta * b[id] / diag_entry(op, c, i0, i1, i2);
     }
 }
 
 // y = x (converted) and the first Chebyshev step from zero on y.
 template <typename TO, typename TI>
 __global__ __launch_bounds__(kThreads) void k_cast_cheb(const TI* __restrict__ x, TO* __restrict__ y, size_t n,
-                                                        OpDev<TO> op, TO inv_theta, TO* __restrict__ u,
-                                                        TO* __restrict__ xo) {
+                                                        OpDev<TO> op, TO inv_theta, TO* __restrict__ xo) {
     for (size_t id = size_t(blockIdx.x) * kThreads + threadIdx.x; id < n; id += size_t(gridDim.x) * kThreads) {
         const TO b = TO(x[id]);
         y[id] = b;
         int c, i0, i1, i2;
         unflatten(op, id, c, i0, i1, i2);
-        const TO v = inv_theta * b / diag_entry(op, c, i0, i1, i2);
-        u[id] = v;
-        xo[id] = v;
+        xo[id] = inv_theta * b / diag_entry(op, c, i0, i1, i2);
     }
 }
 
@@ -561,13 +552,14 @@ __global__ __launch_bounds__(kThreads) void k_fcg_direction(int first, const dou
                                                             const double* __restrict__ pzq, int npzq,
                                                             const double* __restrict__ dq_prev, double* __restrict__ d,
                                                             const double* __restrict__ r, double* __restrict__ pdr,
-                                                            size_t n) {
+                                                            double* __restrict__ beta_out, size_t n) {
     double beta = 0.0;
     if (!first) {
         const double zq = sum_partials(pzq, npzq);
         const double dq = dq_prev[0];
         beta = (dq != 0.0) ? zq / dq : 0.0;
     }
+    if (blockIdx.x == 0 && threadIdx.x == 0) beta_out[0] = beta;
     double s = 0.0;
     for (size_t i = size_t(blockIdx.x) * kThreads + threadIdx.x; i < n; i += size_t(gridDim.x) * kThreads) {
         const double dn = first ? z[i] : z[i] - beta * d[i];
@@ -583,11 +575,14 @@ __global__ __launch_bounds__(kThreads) void k_fcg_update(const double* __restric
                                                          double* __restrict__ dq_out, double* __restrict__ x,
                                                          double* __restrict__ r, const double* __restrict__ d,
                                                          const double* __restrict__ q, double* __restrict__ prr,
-                                                         size_t n) {
+                                                         double* __restrict__ a_out, size_t n) {
     const double dr = sum_partials(pdr, npdr);
     const double dq = sum_partials(pdq, npdq);
     const double a = (dq != 0.0) ? dr / dq : 0.0;
-    if (blockIdx.x == 0 && threadIdx.x == 0) dq_out[0] = dq;
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        dq_out[0] = dq;
+        a_out[0] = a;
+    }
     double s = 0.0;
     for (size_t i = size_t(blockIdx.x) * kThreads + threadIdx.x; i < n; i += size_t(gridDim.x) * kThreads) {
         x[i] += a * d[i];
@@ -763,7 +758,7 @@ int reduce_blocks(size_t n) {
 
 template <typename T>
 int apply_blocks(const OpDev<T>& op) {
-    if (op.dim == 3) return apply3d_geom(op.m, op.hb, sizeof(T)).nblocks;
+    if (op.dim == 3) return apply3d_geom(op.m, op.hb, sizeof(T), op.x1chunk).nblocks;
     return ((op.m[0] + kT1 - 1) / kT1) * ((op.m[1] + kT2 - 1) / kT2);
 }
 
@@ -802,19 +797,19 @@ bool launch_xfer_w(const XferDev<T>& X, int ncomp, const T* in, T* out, size_t n
     if (X.dim == 2) {
         if (Restrict && cf)
             hipLaunchKernelGGL((k_restrict_w<T, W, W, 1, true>), grid, dim3(kThreads), 0, s, X, ncomp, in, out, c.op,
-                               c.inv_theta, c.u, c.x);
+                               c.inv_theta, c.x);
         else if (Restrict)
             hipLaunchKernelGGL((k_restrict_w<T, W, W, 1, false>), grid, dim3(kThreads), 0, s, X, ncomp, in, out, c.op,
-                               c.inv_theta, c.u, c.x);
+                               c.inv_theta, c.x);
         else
             hipLaunchKernelGGL((k_prolong_add_w<T, W, W, 1>), grid, dim3(kThreads), 0, s, X, ncomp, in, out);
     } else {
         if (Restrict && cf)
             hipLaunchKernelGGL((k_restrict_w<T, W, W, W, true>), grid, dim3(kThreads), 0, s, X, ncomp, in, out, c.op,
-                               c.inv_theta, c.u, c.x);
+                               c.inv_theta, c.x);
         else if (Restrict)
             hipLaunchKernelGGL((k_restrict_w<T, W, W, W, false>), grid, dim3(kThreads), 0, s, X, ncomp, in, out, c.op,
-                               c.inv_theta, c.u, c.x);
+                               c.inv_theta, c.x);
         else
             hipLaunchKernelGGL((k_prolong_add_w<T, W, W, W>), grid, dim3(kThreads), 0, s, X, ncomp, in, out);
     }
@@ -848,7 +843,7 @@ void launch_restrict(const XferDev<T>& X, int ncomp, const T* rf, T* rc, hipStre
     if (!launch_xfer_fixed<T, true>(X, ncomp, rf, rc, n, cf, s)) {
         hipLaunchKernelGGL(k_restrict<T>, dim3((n + kThreads - 1) / kThreads), dim3(kThreads), 0, s, X, ncomp, rf,
                            rc);
-        if (cf) launch_cheb_first<T>(cf->op, rc, cf->u, cf->x, cf->inv_theta, s);
+        if (cf) launch_cheb_first<T>(cf->op, rc, cf->x, cf->inv_theta, s);
     }
     check_launch("restrict");
 }
@@ -937,7 +932,7 @@ void launch_finalize(const double* part, int np, double* out, hipStream_t s) {
 template <typename TO, typename TI>
 void launch_cast_cheb(const TI* x, TO* y, size_t n, const ChebFirst<TO>& cf, hipStream_t s) {
     hipLaunchKernelGGL((k_cast_cheb<TO, TI>), dim3(grid_for(n)), dim3(kThreads), 0, s, x, y, n, cf.op, cf.inv_theta,
-                       cf.u, cf.x);
+                       cf.x);
     check_launch("cast_cheb");
 }
 
@@ -1018,9 +1013,9 @@ void launch_lanczos_next(const double* alpha, const double* beta2, const double*
 }
 
 template <typename T>
-void launch_cheb_first(const OpDev<T>& op, const T* b, T* u, T* x, T inv_theta, hipStream_t s) {
+void launch_cheb_first(const OpDev<T>& op, const T* b, T* x, T inv_theta, hipStream_t s) {
     const size_t n = op_len(op);
-    hipLaunchKernelGGL(k_cheb_first<T>, dim3(grid_for(n)), dim3(kThreads), 0, s, op, b, u, x, inv_theta, n);
+    hipLaunchKernelGGL(k_cheb_first<T>, dim3(grid_for(n)), dim3(kThreads), 0, s, op, b, x, inv_theta, n);
     check_launch("cheb_first");
 }
 
@@ -1031,16 +1026,16 @@ void launch_coarse_gemv(const double* Kinv, int N, int ld, const T* r, T* z, hip
 }
 
 void launch_fcg_direction(bool first, const double* z, const double* pzq, int npzq, const double* dq_prev, double* d,
-                          const double* r, double* pdr, size_t n, hipStream_t s) {
+                          const double* r, double* pdr, double* beta_out, size_t n, hipStream_t s) {
     hipLaunchKernelGGL(k_fcg_direction, dim3(reduce_blocks(n)), dim3(kThreads), 0, s, first ? 1 : 0, z, pzq, npzq,
-                       dq_prev, d, r, pdr, n);
+                       dq_prev, d, r, pdr, beta_out, n);
     check_launch("fcg_direction");
 }
 
 void launch_fcg_update(const double* pdr, int npdr, const double* pdq, int npdq, double* dq_out, double* x, double* r,
-                       const double* d, const double* q, double* prr, size_t n, hipStream_t s) {
+                       const double* d, const double* q, double* prr, double* a_out, size_t n, hipStream_t s) {
     hipLaunchKernelGGL(k_fcg_update, dim3(reduce_blocks(n)), dim3(kThreads), 0, s, pdr, npdr, pdq, npdq, dq_out, x, r,
-                       d, q, prr, n);
+                       d, q, prr, a_out, n);
     check_launch("fcg_update");
 }
 
@@ -1097,7 +1092,7 @@ void launch_lsq_combine_add(const double* H, int ld, int k, const double* beta0s
     template void launch_normalize<T>(const double*, int, const T*, T*, size_t, hipStream_t);                        \
     template void launch_diag_scale<T>(const OpDev<T>&, bool, const T*, T*, hipStream_t);                            \
     template void launch_diag_dot<T>(const OpDev<T>&, const T*, double*, hipStream_t);                               \
-    template void launch_cheb_first<T>(const OpDev<T>&, const T*, T*, T*, T, hipStream_t);                           \
+    template void launch_cheb_first<T>(const OpDev<T>&, const T*, T*, T, hipStream_t);                           \
     template void launch_coarse_gemv<T>(const double*, int, int, const T*, T*, hipStream_t);                              \
     template void launch_gs_normscale<T>(const double*, int, int, double*, const T*, const T*, T*, size_t,            \
                                          hipStream_t);                                                               \

@@ -16,8 +16,13 @@ struct OpDev {
     // axis-0 columns, row-window form: col0[w][j * (2hb+1) + k] = X(j - hb + k, j)
     // (zero outside the matrix), so one plane's coefficients are contiguous
     const T* col0[3];
+    // axis-0 table of the 3D kernel, one row of 3(2hb+1)+2 entries per plane j
+    // in [-hb, m[0]+hb): X(j-hb+k, j) for X = M, A, S and k < 2hb+1, then
+    // M(j-hb, j-hb) and S(j-hb, j-hb); zero where an index leaves [0, m[0])
+    const T* c1p;
     int m[3];   // unknowns per axis (m[2] = 1 in 2D)
     int hb;     // half bandwidth (= p on every level)
+    int x1chunk;  // 3D kernel: x1 planes per block (0: chosen from the grid size)
     int dim;
     T alpha, beta;
 };
@@ -50,7 +55,8 @@ struct TFacDev {
 enum ApplyMode : int {
     kApplyY = 0,     // y = A x
     kApplyRes = 1,   // y = b - A x
-    kApplyCheb = 2,  // u = c1 u + c2 D^{-1}(b - A x); xout = x + u
+    kApplyCheb = 2,  // xout = x + c1 (x - xprev) + c2 D^{-1}(b - A x), xprev passed as u (nullptr:
+                     // zero); xout may alias xprev (each entry is read before it is written)
     kApplyYDot = 3,  // y = A x; part[block] = sum x.y (FP64)
     kApplyResDot = 4,  // y = b - A x; part[block] = sum y.y (FP64)
     kApplyYMulti = 5,  // y = A x; part[i*nblocks + block] = sum V_i.y, i < nv, V_i = b + i*n, and
@@ -77,12 +83,11 @@ void launch_apply(const OpDev<T>& op, int mode, const T* x, T* y, const T* b, T*
 // nslots); clears those slots for reuse.
 void launch_stamp_reduce(unsigned long long* st, int slot0, int nslots, unsigned long long* pairs, hipStream_t s);
 
-// First Chebyshev step from zero on a level: u = x = inv_theta D^{-1} b.
+// First Chebyshev step from zero on a level: x = inv_theta D^{-1} b.
 template <typename T>
 struct ChebFirst {
     OpDev<T> op;
     T inv_theta;
-    T* u;
     T* x;
 };
 
@@ -141,7 +146,7 @@ void launch_lanczos_next(const double* alpha, const double* beta2, const double*
                          size_t n, hipStream_t s);
 // First Chebyshev step from x = 0: u = D^{-1} b / theta; x = u
 template <typename T>
-void launch_cheb_first(const OpDev<T>& op, const T* b, T* u, T* x, T inv_theta, hipStream_t s);
+void launch_cheb_first(const OpDev<T>& op, const T* b, T* x, T inv_theta, hipStream_t s);
 
 // ---- coarse level -------------------------------------------------------------
 // z = Kinv r, Kinv N x N inside an ld x ld row-major array
@@ -150,12 +155,13 @@ void launch_coarse_gemv(const double* Kinv, int N, int ld, const T* r, T* z, hip
 
 // ---- flexible CG (FP64) ---------------------------------------------------------
 // d = z - (sum pzq / *dq_prev) d   (first = true: d = z); pdr[block] = d.r
+// (*beta_out = the coefficient b of d = z - b d_prev, 0 on the first step)
 void launch_fcg_direction(bool first, const double* z, const double* pzq, int npzq, const double* dq_prev,
-                          double* d, const double* r, double* pdr, size_t n, hipStream_t s);
-// a = sum pdr / sum pdq; x += a d; r -= a q; prr[block] = r.r; *dq_out = sum pdq
+                          double* d, const double* r, double* pdr, double* beta_out, size_t n, hipStream_t s);
+// a = sum pdr / sum pdq; x += a d; r -= a q; prr[block] = r.r; *dq_out = sum pdq; *a_out = a
 void launch_fcg_update(const double* pdr, int npdr, const double* pdq, int npdq, double* dq_out,
-                       double* x, double* r, const double* d, const double* q, double* prr, size_t n,
-                       hipStream_t s);
+                       double* x, double* r, const double* d, const double* q, double* prr, double* a_out,
+                       size_t n, hipStream_t s);
 
 // ---- GMRES helpers (vectors of type T, scalars FP64) ----------------------------
 // Classical Gram-Schmidt step with the Pythagorean norm: h_i = sum of the

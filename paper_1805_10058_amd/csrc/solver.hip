@@ -102,7 +102,6 @@ struct VWork {
         T* b = nullptr;
         T* xa = nullptr;
         T* xb = nullptr;
-        T* u = nullptr;
         T* r = nullptr;
         T* xcur = nullptr;
     };
@@ -129,6 +128,7 @@ struct SolveState {
     double r0 = 0.0, rel = 1.0;
     int k = 0, status = CD_NOT_CONVERGED;
     bool done = true;
+    std::vector<double> alpha, beta;  // step lengths and direction coefficients, one per outer iteration
 };
 
 struct cd_solver {
@@ -158,7 +158,9 @@ struct cd_solver {
     // outer FCG (FP64)
     double *r = nullptr, *z = nullptr, *dd = nullptr, *q = nullptr;
     double *pzq = nullptr, *pdr = nullptr, *pdq = nullptr, *prr = nullptr, *scal = nullptr;
-    double* host_scal = nullptr;  // pinned: [0] r.r, [1] d.q
+    // device and pinned host scalars of the outer iteration: [0] r.r, [1] d.q,
+    // [2] step length a, [3] direction coefficient b (d = z - b d_prev), [4] ||b - A x||^2
+    double* host_scal = nullptr;
     int nbr = 0, nba = 0;
 
     // live kernel timing (cd_profile_enable): every timed launch gets a slot,
@@ -172,7 +174,7 @@ struct cd_solver {
         int cls;  // kind * 2L + 2 level + fp32; kind 0 = operator apply, 1 = T-solve pass
         double bytes;
     };
-    static constexpr int kGraphSlots = 128, kStampSlots = 512, kUnitSlots = 128;
+    static constexpr int kGraphSlots = 256, kStampSlots = 1024, kUnitSlots = 256;
     unsigned long long* stamps = nullptr;       // device, kStampSlots slots of cd::kStampWords words
     unsigned long long* pairs = nullptr;        // device, 2 kStampSlots: (start, end) per slot
     unsigned long long* stamps_host = nullptr;  // pinned copy of pairs
@@ -231,6 +233,7 @@ void validate(const cd_problem* pr, const cd_options* op) {
     if (op->lanczos_steps < 1 || op->lanczos_steps > 200) throw CdError(CD_EINVAL, "lanczos_steps must be in 1..200");
     if (op->krylov_steps > 7) throw CdError(CD_EINVAL, "krylov_steps must be <= 7");
     if (op->graphs != 0 && op->graphs != 1) throw CdError(CD_EINVAL, "graphs must be 0 or 1");
+    if (op->apply_x1_chunk < 0) throw CdError(CD_EINVAL, "apply_x1_chunk must be >= 0");
     if (op->coarse_max_dofs < 1 || op->coarse_max_dofs > 8192)
         throw CdError(CD_EINVAL, "coarse_max_dofs must be in 1..8192");
     // the operator kernels keep a plane chunk with a +-p row halo in LDS
@@ -303,6 +306,7 @@ cd::OpDev<T> make_op(cd_solver* s, const LevelHost& L, hipStream_t st) {
     cd::OpDev<T> op{};
     op.dim = s->d;
     op.hb = s->p;
+    op.x1chunk = s->opt.apply_x1_chunk;
     op.alpha = T(s->prob.alpha);
     op.beta = T(s->prob.beta);
     for (int l = 0; l < 3; ++l) op.m[l] = L.m[l];
@@ -324,6 +328,19 @@ cd::OpDev<T> make_op(cd_solver* s, const LevelHost& L, hipStream_t st) {
                 }
             op.col0[w] = s->arena.upload(convert<T>(col), st);
         }
+        // the same columns as one row per plane j in [-hb, m0 + hb), with the
+        // diagonal entries of M and S at plane j - hb (the 3D kernel's table)
+        const int NC = 3 * R + 2;
+        std::vector<double> tab(size_t(m0 + 2 * hb) * NC, 0.0);
+        auto at = [&](int w, int i, int j) { return (i >= 0 && i < m0 && j >= 0 && j < m0) ? mats[w]->get(i, j) : 0.0; };
+        for (int j = -hb; j < m0 + hb; ++j) {
+            double* row = tab.data() + size_t(j + hb) * NC;
+            for (int w = 0; w < 3; ++w)
+                for (int k = 0; k < R; ++k) row[w * R + k] = at(w, j - hb + k, j);
+            row[3 * R] = at(0, j - hb, j - hb);
+            row[3 * R + 1] = at(2, j - hb, j - hb);
+        }
+        op.c1p = s->arena.upload(convert<T>(tab), st);
     }
     if (s->d == 2) {  // unused third axis: a 1x1 identity band keeps pointers valid
         std::vector<double> id(2 * s->p + 1, 0.0);
@@ -392,7 +409,6 @@ std::unique_ptr<VWork<T>> make_work(cd_solver* s, DevArena& ar) {
         W.xa = ar.alloc<T>(n);
         if (l < L - 1) {
             W.xb = ar.alloc<T>(n);
-            W.u = ar.alloc<T>(n);
             W.r = ar.alloc<T>(n);
         }
     }
@@ -420,6 +436,10 @@ template <>
 const cd::TFacDev<float>* tfacs<float>(cd_solver* s) { return s->tfd32; }
 
 // ---- live kernel timing ----------------------------------------------------------------
+// Classes of timed launches: kind 0 = operator applies other than Chebyshev
+// steps, 1 = T-solve axis passes (level 0), 2 = Chebyshev-step applies; per
+// level and precision.
+constexpr int kProfKinds = 3;
 int prof_class(const cd_solver* s, int kind, int level, bool fp32) {
     return kind * 2 * int(s->lv.size()) + 2 * level + (fp32 ? 1 : 0);
 }
@@ -438,7 +458,8 @@ void prof_add(cd_solver* s, const std::vector<cd_solver::ProfRec>& recs) {
 
 // Call after a stream sync.
 void prof_flush(cd_solver* s) {
-    if (s->prof_stats.size() < 4 * s->lv.size()) s->prof_stats.resize(4 * s->lv.size(), cd_kernel_stats{0, 0.0, 0.0});
+    if (s->prof_stats.size() < kProfKinds * 2 * s->lv.size())
+        s->prof_stats.resize(kProfKinds * 2 * s->lv.size(), cd_kernel_stats{0, 0.0, 0.0});
     prof_add(s, s->prof_pending);
     s->prof_pending.clear();
     s->eager_next = cd_solver::kGraphSlots;
@@ -501,11 +522,13 @@ void apply_op(cd_solver* s, int level, int mode, const T* x, T* y, const T* b, T
     }
     const bool own = !s->unit_open;
     if (own) prof_unit_begin(s);
+    // vectors read and written once: the residual reads b; a Chebyshev step
+    // reads b and the previous iterate (not on a first step, c1 = 0)
     const double nvec = (mode == kApplyRes || mode == cd::kApplyResDot) ? 3.0
-                        : (mode == kApplyCheb)                         ? 5.0
+                        : (mode == kApplyCheb)                         ? ((c1 != T(0) && u) ? 4.0 : 3.0)
                         : (mode == cd::kApplyYMulti)                   ? 2.0 + nv
                                                                        : 2.0;
-    unsigned long long* st = prof_slots(s, 1, prof_class(s, 0, level, sizeof(T) == 4),
+    unsigned long long* st = prof_slots(s, 1, prof_class(s, mode == kApplyCheb ? 2 : 0, level, sizeof(T) == 4),
                                         nvec * double(s->lv[level].N) * sizeof(T));
     cd::launch_apply<T>(op, mode, x, y, b, u, xout, c1, c2, part, s->stream, nv, st);
     if (own) prof_unit_end(s);
@@ -531,11 +554,14 @@ void tsolve_op(cd_solver* s, const T* v, T* tmp, T* z) {
 
 // Chebyshev smoothing on level l (Sec. 6.1 smoother reading): cheb_degree
 // steps on D^{-1} A_l on the finest level, cheb_degree_coarse (when set) on
-// the others, interval [lo, hi].  Starts from zero when x == nullptr
-// (first step without an operator apply), else from *x; the result pointer
-// is returned (one of the level's two iterate buffers).
+// the others, interval [lo, hi], in the three-term form
+//   x_{k+1} = x_k + c1_k (x_k - x_{k-1}) + c2_k D^{-1} (b - A_l x_k),
+// so a step reads x_k, x_{k-1} and b and writes x_{k+1} over x_{k-1}.
+// Starts from zero when from_zero (the first step needs no operator apply:
+// x_1 = D^{-1} b / theta; first_done: the producer of b already wrote it into
+// x), else from *x; the result pointer is returned (x or other).
 template <typename T>
-T* chebyshev(cd_solver* s, int l, const T* b, T* x, T* other, T* u, bool from_zero, bool first_done = false) {
+T* chebyshev(cd_solver* s, int l, const T* b, T* x, T* other, bool from_zero, bool first_done = false) {
     const LevelHost& L = s->lv[l];
     const cd::OpDev<T>& op = devlevels<T>(s)[l].op;
     const double theta = 0.5 * (L.hi + L.lo), delta = 0.5 * (L.hi - L.lo);
@@ -544,28 +570,31 @@ T* chebyshev(cd_solver* s, int l, const T* b, T* x, T* other, T* u, bool from_ze
     const int nu = (l > 0 && s->opt.cheb_degree_coarse > 0) ? s->opt.cheb_degree_coarse : s->opt.cheb_degree;
     T* cur = x;
     T* nxt = other;
+    const T* prev = nullptr;  // x_{k-1}; nullptr: zero
     if (from_zero) {
-        // first_done: the producer of b already wrote x = u = D^{-1} b / theta
-        if (!first_done) cd::launch_cheb_first<T>(op, b, u, cur, T(1.0 / theta), s->stream);
+        if (!first_done) cd::launch_cheb_first<T>(op, b, cur, T(1.0 / theta), s->stream);
     } else {
-        apply_op<T>(s, l, kApplyCheb, cur, nullptr, b, u, nxt, T(0), T(1.0 / theta), nullptr);
+        apply_op<T>(s, l, kApplyCheb, cur, nullptr, b, nullptr, nxt, T(0), T(1.0 / theta), nullptr);
         std::swap(cur, nxt);
+        prev = nxt;
     }
     for (int k = 1; k < nu; ++k) {
         const double rn = 1.0 / (2.0 * sigma - rho);
-        apply_op<T>(s, l, kApplyCheb, cur, nullptr, b, u, nxt, T(rn * rho), T(2.0 * rn / delta), nullptr);
+        apply_op<T>(s, l, kApplyCheb, cur, nullptr, b, const_cast<T*>(prev), nxt, T(rn * rho), T(2.0 * rn / delta),
+                    nullptr);
         std::swap(cur, nxt);
+        prev = nxt;
         rho = rn;
     }
     return cur;
 }
 
 // The first Chebyshev step from zero on level l, to be fused into the kernel
-// that produces the level's right-hand side; result in the level's xa and u.
+// that produces the level's right-hand side; result in the level's xa.
 template <typename T>
 cd::ChebFirst<T> cheb_first_of(cd_solver* s, VWork<T>& W, int l) {
     const LevelHost& L = s->lv[l];
-    return cd::ChebFirst<T>{devlevels<T>(s)[l].op, T(1.0 / (0.5 * (L.hi + L.lo))), W.lv[l].u, W.lv[l].xa};
+    return cd::ChebFirst<T>{devlevels<T>(s)[l].op, T(1.0 / (0.5 * (L.hi + L.lo))), W.lv[l].xa};
 }
 
 // p steps of GMRES on A_0 e = b - A_0 x from e = 0, right preconditioner T
@@ -607,7 +636,7 @@ void vcycle(cd_solver* s, VWork<T>& W, int l, bool first_done = false) {
         return;
     }
     const auto& D = devlevels<T>(s)[l];
-    T* x = chebyshev<T>(s, l, Wl.b, Wl.xa, Wl.xb, Wl.u, true, first_done);
+    T* x = chebyshev<T>(s, l, Wl.b, Wl.xa, Wl.xb, true, first_done);
     T* other = (x == Wl.xa) ? Wl.xb : Wl.xa;
     apply_op<T>(s, l, kApplyRes, x, Wl.r, Wl.b, nullptr, nullptr, T(0), T(0), nullptr);
     const bool fuse = (l + 1 < L - 1);  // the next level smooths (it is not the coarsest)
@@ -618,7 +647,7 @@ void vcycle(cd_solver* s, VWork<T>& W, int l, bool first_done = false) {
     if (l == 0 && s->ksteps > 0) {
         gmres_post<T>(s, W, Wl.b, x);
     } else {
-        x = chebyshev<T>(s, l, Wl.b, x, other, Wl.u, false);
+        x = chebyshev<T>(s, l, Wl.b, x, other, false);
     }
     Wl.xcur = x;
 }
@@ -688,6 +717,30 @@ double tridiag_max_eig(const std::vector<double>& a, const std::vector<double>& 
         if (below(mid) >= k) hi = mid; else lo = mid;
     }
     return hi;
+}
+
+// Condition-number estimate from the outer iteration's coefficients: the
+// step lengths a_j and direction coefficients b_j (d_j = z_j + b_j d_{j-1})
+// of a conjugate-gradient iteration define the Lanczos matrix of the
+// (preconditioned) operator, diagonal 1/a_j + b_j/a_{j-1}, off-diagonal
+// sqrt(b_{j+1})/a_j; its extreme eigenvalues (Ritz values) approach the
+// extreme eigenvalues of the operator from inside.  Returns their ratio, or
+// 0 when there is no coefficient to use.  A non-positive b_j (possible with
+// a nonlinear preconditioner) splits the matrix there.
+double lanczos_kappa(const std::vector<double>& a, const std::vector<double>& b) {
+    const int k = int(a.size());
+    if (k == 0 || !(a[0] > 0.0)) return 0.0;
+    std::vector<double> diag(k), off(k, 0.0);
+    for (int j = 0; j < k; ++j) {
+        if (!(a[j] > 0.0) || !std::isfinite(a[j])) return 0.0;
+        diag[j] = 1.0 / a[j] + (j > 0 ? std::max(b[j], 0.0) / a[j - 1] : 0.0);
+        if (j > 0) off[j] = std::sqrt(std::max(b[j], 0.0)) / a[j - 1];
+    }
+    const double hi = tridiag_max_eig(diag, off);
+    std::vector<double> neg(k);
+    for (int j = 0; j < k; ++j) neg[j] = -diag[j];
+    const double lo = -tridiag_max_eig(neg, off);
+    return (lo > 0.0) ? hi / lo : 0.0;
 }
 
 // Smoother eigenvalue bounds: lanczos_steps steps of Lanczos on D^{-1} A_l in
@@ -838,9 +891,9 @@ void create(cd_solver* s, const cd_problem* pr, const cd_options* op, void* stre
     s->pdr = s->arena.alloc<double>(s->nbr);
     s->prr = s->arena.alloc<double>(s->nbr);
     s->pdq = s->arena.alloc<double>(std::max(s->nba, s->nbr));
-    s->scal = s->arena.alloc<double>(4);
+    s->scal = s->arena.alloc<double>(6);
     void* hp = nullptr;
-    hip_check(hipHostMalloc(&hp, 4 * sizeof(double), hipHostMallocDefault), "hipHostMalloc");
+    hip_check(hipHostMalloc(&hp, 6 * sizeof(double), hipHostMallocDefault), "hipHostMalloc");
     s->host_scal = static_cast<double*>(hp);
     if (L > 1 && op->method == CD_METHOD_PMIM) estimate_bounds(s);
     if (op->method == CD_METHOD_PMIM) {
@@ -893,11 +946,12 @@ void enqueue_iteration(cd_solver* s, bool first) {
     } else {
         precondition(s, s->r, s->z, first ? nullptr : s->q, s->pzq);
     }
-    cd::launch_fcg_direction(first, s->z, s->pzq, s->nbr, s->scal + 1, s->dd, s->r, s->pdr, N, st);
+    cd::launch_fcg_direction(first, s->z, s->pzq, s->nbr, s->scal + 1, s->dd, s->r, s->pdr, s->scal + 3, N, st);
     apply_op<double>(s, 0, kApplyYDot, s->dd, s->q, nullptr, nullptr, nullptr, 0.0, 0.0, s->pdq);
-    cd::launch_fcg_update(s->pdr, s->nbr, s->pdq, s->nba, s->scal + 1, s->xw, s->r, s->dd, s->q, s->prr, N, st);
+    cd::launch_fcg_update(s->pdr, s->nbr, s->pdq, s->nba, s->scal + 1, s->xw, s->r, s->dd, s->q, s->prr, s->scal + 2,
+                          N, st);
     cd::launch_finalize(s->prr, s->nbr, s->scal, st);
-    hip_check(hipMemcpyAsync(s->host_scal, s->scal, 2 * sizeof(double), hipMemcpyDeviceToHost, st), "read");
+    hip_check(hipMemcpyAsync(s->host_scal, s->scal, 4 * sizeof(double), hipMemcpyDeviceToHost, st), "read");
 }
 
 // Enqueue one outer iteration.  Every iteration after the first reads and
@@ -952,6 +1006,8 @@ bool solve_check(cd_solver* s) {
     if (s->prof) prof_flush(s);
     ++S.k;
     const double rr = s->host_scal[0], dq = s->host_scal[1];
+    S.alpha.push_back(s->host_scal[2]);
+    S.beta.push_back(-s->host_scal[3]);  // d = z + beta_cg d_prev
     S.rel = std::sqrt(rr) / S.r0;
     if (!std::isfinite(rr) || !std::isfinite(dq) || !(dq > 0.0)) {
         S.status = CD_EBREAKDOWN;
@@ -978,10 +1034,11 @@ cd_result solve_finish(cd_solver* s) {
     if (S.r0 > 0.0) {
         cd::launch_apply<double>(s->ld64[0].op, kApplyRes, S.x, s->z, S.b, nullptr, nullptr, 0.0, 0.0, nullptr, st);
         cd::launch_dot_partial<double, double>(s->z, s->z, N, s->prr, st);
-        cd::launch_finalize(s->prr, s->nbr, s->scal + 2, st);
-        hip_check(hipMemcpyAsync(s->host_scal + 2, s->scal + 2, sizeof(double), hipMemcpyDeviceToHost, st), "read");
+        cd::launch_finalize(s->prr, s->nbr, s->scal + 4, st);
+        hip_check(hipMemcpyAsync(s->host_scal + 4, s->scal + 4, sizeof(double), hipMemcpyDeviceToHost, st), "read");
         hip_check(hipStreamSynchronize(st), "sync");
-        out.true_rel_residual = std::sqrt(s->host_scal[2]) / S.r0;
+        out.true_rel_residual = std::sqrt(s->host_scal[4]) / S.r0;
+        out.kappa_estimate = lanczos_kappa(S.alpha, S.beta);
     }
     return out;
 }
@@ -1044,6 +1101,7 @@ void cd_default_options(cd_options* o) {
     o->krylov_steps = -1;
     o->graphs = 1;
     o->cheb_degree_coarse = 16;
+    o->apply_x1_chunk = 0;
 }
 
 size_t cd_num_dofs(const cd_problem* pr) {
@@ -1076,7 +1134,7 @@ size_t cd_footprint_bytes(const cd_problem* pr, const cd_options* op) {
         const size_t N = tmp.lv[0].N;
         const size_t es = (op->precision == CD_FP64) ? 8 : 4;
         size_t vw = 0;
-        for (size_t l = 0; l < tmp.lv.size(); ++l) vw += tmp.lv[l].N * ((l + 1 < tmp.lv.size()) ? 5 : 2);
+        for (size_t l = 0; l < tmp.lv.size(); ++l) vw += tmp.lv[l].N * ((l + 1 < tmp.lv.size()) ? 4 : 2);
         const size_t ks = size_t(std::max(tmp.ksteps, 1));
         vw += N * (2 * ks + 5);                             // V (ks+1), Z (ks), w, z, io_in, tmp
         total = 5 * N * 8                                   // outer r, z, d, q, iterate
@@ -1217,7 +1275,7 @@ int cd_smooth(cd_solver* s, int level, const double* b, const double* x_in, doub
         const size_t n = s->lv[level].N;
         cd::launch_copy<double>(b, Wl.b, n, s->stream);
         cd::launch_copy<double>(x_in, Wl.xa, n, s->stream);
-        double* r = chebyshev<double>(s, level, Wl.b, Wl.xa, Wl.xb, Wl.u, false);
+        double* r = chebyshev<double>(s, level, Wl.b, Wl.xa, Wl.xb, false);
         cd::launch_copy<double>(r, x_out, n, s->stream);
         hip_check(hipStreamSynchronize(s->stream), "sync");
     });
@@ -1305,7 +1363,7 @@ int cd_profile_enable(cd_solver* s, int on) {
         s->prof = (on > 0);
         s->prof_period = std::max(on, 1);
         s->prof_iter = 0;
-        if (s->prof) s->prof_stats.assign(4 * s->lv.size(), cd_kernel_stats{0, 0.0, 0.0});
+        if (s->prof) s->prof_stats.assign(kProfKinds * 2 * s->lv.size(), cd_kernel_stats{0, 0.0, 0.0});
     });
 }
 
@@ -1313,7 +1371,23 @@ int cd_profile_read(const cd_solver* s, int level, int fp32, cd_kernel_stats* ou
     return run([&] {
         need_level(s, level);
         if (!out) throw CdError(CD_EINVAL, "null output");
-        const size_t k = size_t(prof_class(s, 0, level, fp32 != 0));
+        cd_kernel_stats t{0, 0.0, 0.0};
+        for (int kind : {0, 2}) {  // every operator apply of the level: other modes and Chebyshev steps
+            const size_t k = size_t(prof_class(s, kind, level, fp32 != 0));
+            if (k < s->prof_stats.size()) {
+                t.launches += s->prof_stats[k].launches;
+                t.total_ms += s->prof_stats[k].total_ms;
+                t.bytes += s->prof_stats[k].bytes;
+            }
+        }
+        *out = t;
+    });
+}
+int cd_profile_read_smoother(const cd_solver* s, int level, int fp32, cd_kernel_stats* out) {
+    return run([&] {
+        need_level(s, level);
+        if (!out) throw CdError(CD_EINVAL, "null output");
+        const size_t k = size_t(prof_class(s, 2, level, fp32 != 0));
         *out = (k < s->prof_stats.size()) ? s->prof_stats[k] : cd_kernel_stats{0, 0.0, 0.0};
     });
 }

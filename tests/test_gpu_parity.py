@@ -377,3 +377,35 @@ def test_alpha_not_one(case):
     assert res.status == capi.CD_OK
     assert relerr(host(x), solvers.solve_direct(m.K, r)) <= 1e-9
     s.close()
+
+
+@pytest.mark.parametrize("d,p,n,beta", [(2, 2, 10, 0.05), (3, 2, 4, 0.1)])
+def test_kappa_estimate_against_the_spectrum(d, p, n, beta):
+    # Unpreconditioned CG: the Lanczos matrix of its coefficients has Ritz
+    # values inside the spectrum of A, reaching its ends once CG has run long
+    # enough; with a linear SPD preconditioner (the V-cycle without the Krylov
+    # post-smoother) the same holds for B A, B the oracle's V-cycle matrix.
+    K = asm.curl_div_matrix(d, p, n, 1.0, beta)
+    N = K.shape[0]
+    ev = np.linalg.eigvalsh(K.toarray())
+    b = np.random.default_rng(31).uniform(-1, 1, N)
+    bd, x = dev(b), empty(N)
+    opt = capi.options(method=capi.CD_METHOD_CG, rtol=1e-13, max_iter=5000)
+    s = capi.Solver(capi.problem(d, p, n, 1.0, beta), opt, stream())
+    r = s.solve(bd.data_ptr(), x.data_ptr())
+    kap = ev[-1] / ev[0]
+    assert r.status == capi.CD_OK
+    assert 0.9 * kap <= r.kappa_estimate <= kap * (1 + 1e-6), (r.kappa_estimate, kap)
+    s.close()
+    kw = dict(krylov_steps=0, cheb_degree=3, cheb_ratio=30.0, cheb_degree_coarse=0, coarse_max_dofs=60)
+    opt = capi.options(rtol=1e-13, **kw)
+    s = capi.Solver(capi.problem(d, p, n, 1.0, beta), opt, stream())
+    r = s.solve(bd.data_ptr(), x.data_ptr())
+    m = method.Method(d, p, n, 1.0, beta, coarse_max_dofs=60, nu=3, ratio=30.0, krylov_steps=0,
+                      lanczos_steps=opt.lanczos_steps)
+    B = np.column_stack([m.vcycle(e) for e in np.eye(N)])
+    evb = np.sort(np.linalg.eigvals(B @ K.toarray()).real)
+    kapb = evb[-1] / evb[0]
+    assert r.status == capi.CD_OK
+    assert 0.8 * kapb <= r.kappa_estimate <= kapb * (1 + 1e-3), (r.kappa_estimate, kapb)
+    s.close()
