@@ -185,6 +185,19 @@ int cd_restrict(cd_solver* s, int level, const double* r_fine_dev, double* r_coa
 int cd_prolong_add(cd_solver* s, int level, const double* e_coarse_dev, double* x_fine_dev);
 /* z = T^{-1} v on the finest level (Sec. 6.1), FP64. */
 int cd_tsolve(cd_solver* s, const double* v_dev, double* z_dev);
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * z = T^{-1} v as cd_tsolve, with the same kernels and bitwise the same
+ * result, but its intermediate vectors live in a static device workspace of
+ * the library instead of the handle's buffers, and the call allocates
+ * nothing.  The workspace holds two vectors of 2^20 doubles (16 MiB per GPU,
+ * kept until the process ends), so the handle's problem must have at most
+ * 1,048,576 unknowns; larger problems return CD_EINVAL.  v_dev may equal
+ * z_dev.  Every call on one GPU shares that GPU's workspace: calls that
+ * overlap in time on one GPU (from two threads, or on two handles whose
+ * streams run concurrently) race and give undefined results.  The current
+ * device must be the handle's device.  Blocks until done. */
+int cd_tsolve_noalloc(cd_solver* s, const double* v_dev, double* z_dev);
 /* z = A_L^{-1} r on the coarsest level, FP64. */
 int cd_coarse_solve(cd_solver* s, const double* r_dev, double* z_dev);
 /* z = one application of the preconditioner (one V-cycle, in the handle's

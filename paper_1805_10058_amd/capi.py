@@ -83,6 +83,7 @@ SIGNATURES = {
     "cd_restrict": (_I, [_P, _I, _P, _P]),
     "cd_prolong_add": (_I, [_P, _I, _P, _P]),
     "cd_tsolve": (_I, [_P, _P, _P]),
+    "cd_tsolve_noalloc": (_I, [_P, _P, _P]),
     "cd_coarse_solve": (_I, [_P, _P, _P]),
     "cd_precondition": (_I, [_P, _P, _P]),
     "cd_profile_enable": (_I, [_P, _I]),
@@ -233,6 +234,9 @@ class Solver:
 
     def tsolve(self, v_ptr, z_ptr):
         check(lib().cd_tsolve(self._h, ctypes.c_void_p(v_ptr), ctypes.c_void_p(z_ptr)))
+
+    def tsolve_noalloc(self, v_ptr, z_ptr):
+        check(lib().cd_tsolve_noalloc(self._h, ctypes.c_void_p(v_ptr), ctypes.c_void_p(z_ptr)))
 
     def coarse_solve(self, r_ptr, z_ptr):
         check(lib().cd_coarse_solve(self._h, ctypes.c_void_p(r_ptr), ctypes.c_void_p(z_ptr)))

@@ -15,6 +15,8 @@
 #include <deque>
 #include <cstring>
 #include <functional>
+#include <map>
+#include <mutex>
 #include <memory>
 #include <stdexcept>
 #include <string>
@@ -24,6 +26,14 @@
 #include "coarse.hpp"
 #include "kernels.hpp"
 #include "setup.hpp"
+
+// Static device workspace of cd_tsolve_noalloc, the entry point for callers
+// that cannot allocate device memory: two vectors of kNoAllocMaxDofs doubles
+// (16 MiB), one copy per GPU for the life of the process.  Host code must use
+// the address hipGetSymbolAddress returns for the current device (taken once
+// per device, see noalloc_workspace), never the symbol itself.
+constexpr size_t kNoAllocMaxDofs = size_t(1) << 20;
+static __device__ __align__(256) double scratch[2 * kNoAllocMaxDofs];
 
 namespace {
 
@@ -40,6 +50,23 @@ void hip_check(hipError_t e, const char* what) {
         if (e == hipErrorOutOfMemory) throw CdError(CD_ENOMEM, std::string(what) + ": out of device memory");
         throw CdError(CD_EHIP, std::string(what) + ": " + hipGetErrorString(e));
     }
+}
+
+// Device address of `scratch` on the current device, looked up once per
+// device with that device current; later calls reuse the stored address.
+double* noalloc_workspace() {
+    static std::mutex mu;
+    static std::map<int, double*> addr;
+    int dev = 0;
+    hip_check(hipGetDevice(&dev), "hipGetDevice");
+    std::lock_guard<std::mutex> g(mu);
+    auto it = addr.find(dev);
+    if (it != addr.end()) return it->second;
+    void* ptr = nullptr;
+    hip_check(hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)), "hipGetSymbolAddress(scratch)");
+    if (!ptr) throw CdError(CD_EHIP, "hipGetSymbolAddress(scratch) returned null");
+    addr[dev] = static_cast<double*>(ptr);
+    return static_cast<double*>(ptr);
 }
 
 // Owning list of device allocations.
@@ -1314,6 +1341,26 @@ int cd_tsolve(cd_solver* s, const double* v, double* z) {
         tsolve_op<double>(s, src, s->q, z);
         hip_check(hipStreamSynchronize(s->stream), "sync");
         if (s->prof) prof_flush(s);
+    });
+}
+
+int cd_tsolve_noalloc(cd_solver* s, const double* v, double* z) {
+    return run([&] {
+        need(s);
+        if (!v || !z) throw CdError(CD_EINVAL, "null vector");
+        if (s->N > kNoAllocMaxDofs)
+            throw CdError(CD_EINVAL, "cd_tsolve_noalloc: problem has " + std::to_string(s->N) +
+                                         " unknowns, the static workspace holds at most " +
+                                         std::to_string(kNoAllocMaxDofs));
+        double* ws = noalloc_workspace();  // two vectors of kNoAllocMaxDofs doubles
+        enter(s);
+        const double* src = v;
+        if (v == z) {  // in place: solve from a copy of v
+            cd::launch_copy<double>(v, ws + kNoAllocMaxDofs, s->N, s->stream);
+            src = ws + kNoAllocMaxDofs;
+        }
+        cd::launch_tsolve<double>(s->d, s->lv[0].m, s->tfd64, src, ws, z, s->stream);
+        hip_check(hipStreamSynchronize(s->stream), "sync");
     });
 }
 
