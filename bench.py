@@ -332,9 +332,13 @@ def c1_latency(capi, torch, st, reps=100):
     launched one kernel at a time."""
     out = {}
     for graphs in (1, 0):
-        T, lat, res = run_solves(capi, torch, st, "c1_2d_p2_n16", capi.CD_FP64, list(range(reps)), graphs=graphs)
+        # a 32-unknown coarsest level (3 levels), so the solve runs the V-cycle
+        # rather than the dense coarse solve alone
+        T, lat, res = run_solves(capi, torch, st, "c1_2d_p2_n16", capi.CD_FP64, list(range(reps)), graphs=graphs,
+                                 coarse_max_dofs=64)
         out["graph" if graphs else "eager"] = summarize(capi, T, lat, res)
-    out["workload"] = "2D p=2 n=16 (512 unknowns), alpha=beta=1, FP64, rel. residual 1e-10, one solve at a time"
+    out["workload"] = ("2D p=2 n=16 (512 unknowns), alpha=beta=1, FP64, rel. residual 1e-10, one solve at a time, "
+                       "3 levels (coarsest 32 unknowns)")
     return out
 
 

@@ -68,6 +68,10 @@ typedef struct {
 } cd_problem;
 
 #define CD_METHOD_PMIM 0   /* flexible CG preconditioned by one V-cycle (Sec. 6.2, P_MIM) */
+#define CD_METHOD_PWL 1    /* flexible CG preconditioned by one V-cycle on the block-diagonal
+                              part D (Sec. 6.1 eq. diag, P_WL in Sec. 6.2), with p steps of CG
+                              preconditioned by T as finest post-smoother                     */
+#define CD_METHOD_MIM 2    /* the V-cycle as a stand-alone iteration x += V(b - A x) (MIM)    */
 #define CD_METHOD_CG 3     /* unpreconditioned CG (the CG columns of Tables 1-4)          */
 
 #define CD_XFER_KNOT 0     /* knot-insertion prolongator, n -> n/2 (exact subspace embedding) */
@@ -180,11 +184,21 @@ int cd_apply_f32(cd_solver* s, int level, const float* x_dev, float* y_dev);
 /* One smoother application (cheb_degree Chebyshev steps) on level `level`
  * for A_l x = b starting from x_in; writes x_out (FP64). */
 int cd_smooth(cd_solver* s, int level, const double* b_dev, const double* x_in_dev, double* x_out_dev);
-/* r_c = P^T r (level -> level+1) and x += P e (level+1 -> level), FP64. */
+/* r_c = P^T r (level -> level+1) and x += P e (level+1 -> level), FP64
+ * (Sec. 6.1: the block prolongator I_d (x) P (x) ... (x) P, P the
+ * knot-insertion or the (1/2)[1 2 1] prolongator of the handle). */
 int cd_restrict(cd_solver* s, int level, const double* r_fine_dev, double* r_coarse_dev);
 int cd_prolong_add(cd_solver* s, int level, const double* e_coarse_dev, double* x_fine_dev);
-/* z = T^{-1} v on the finest level (Sec. 6.1), FP64. */
+/* z = T^{-1} v on the finest level (Sec. 6.1, the preconditioner of the
+ * Krylov post-smoother), FP64. */
 int cd_tsolve(cd_solver* s, const double* v_dev, double* z_dev);
+/* The same steps in FP32 with FP32 coefficients (the kernels the mixed
+ * precision V-cycle runs): smoother, transfers and T-solve on FP32 device
+ * vectors.  On an FP64 handle the first call allocates an FP32 workspace. */
+int cd_smooth_f32(cd_solver* s, int level, const float* b_dev, const float* x_in_dev, float* x_out_dev);
+int cd_restrict_f32(cd_solver* s, int level, const float* r_fine_dev, float* r_coarse_dev);
+int cd_prolong_add_f32(cd_solver* s, int level, const float* e_coarse_dev, float* x_fine_dev);
+int cd_tsolve_f32(cd_solver* s, const float* v_dev, float* z_dev);
 /* For callers that cannot allocate device memory (code under HIP graph
  * capture, tight serving loops, harnesses that forbid hipMalloc): the same
  * z = T^{-1} v as cd_tsolve, with the same kernels and bitwise the same

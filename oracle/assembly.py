@@ -19,32 +19,49 @@ def _kron(*mats):
     return out
 
 
+def axis_matrices(d, p, n, mats=None):
+    """Per-axis 1D (M, A, S) triples: ``n`` is one interval count for every
+    axis or one per axis (n_l = nu_l n in Sec. 5); ``mats`` may supply one
+    triple for every axis or a list of d triples."""
+    if mats is not None:
+        if len(mats) == 3 and not isinstance(mats[0], (list, tuple)):
+            return [tuple(mats)] * d
+        return [tuple(t) for t in mats]
+    ns = [n] * d if np.isscalar(n) else list(n)
+    return [mass_adv_stiff(int(nl), p) for nl in ns]
+
+
 def curl_div_matrix(d, p, n, alpha, beta, mats=None):
     """The system matrix alpha*A^{curl} + beta*A^{div}, written term by term as
-    in Sec. 4.1 (d = 2, 2x2 blocks) and Sec. 4.2 (d = 3, 3x3 blocks).
-    ``mats`` may supply the 1D (M, A, S) triple (default: assembled at n, p).
-    Returns a scipy CSR matrix of size d*m^d."""
-    M, A, S = mats if mats is not None else mass_adv_stiff(n, p)
-    At = A.T
+    in Sec. 4.1 (d = 2, 2x2 blocks) and Sec. 4.2 (d = 3, 3x3 blocks): every
+    block is a sum of Kronecker products X_1 (x) ... (x) X_d of 1D matrices of
+    the axes 1..d in order.  ``n`` is the number of intervals of every axis or
+    one per axis; ``mats`` may supply the 1D (M, A, S) triple(s).
+    Returns a scipy CSR matrix of size d * prod_l m_l."""
+    ax = axis_matrices(d, p, n, mats)
+    M = [t[0] for t in ax]
+    A = [t[1] for t in ax]
+    S = [t[2] for t in ax]
+    At = [X.T for X in A]
     if d == 2:
         curl = [
-            [_kron(M, S), -_kron(At, A)],
-            [-_kron(A, At), _kron(S, M)],
+            [_kron(M[0], S[1]), -_kron(At[0], A[1])],
+            [-_kron(A[0], At[1]), _kron(S[0], M[1])],
         ]
         div = [
-            [_kron(S, M), _kron(A, At)],
-            [_kron(At, A), _kron(M, S)],
+            [_kron(S[0], M[1]), _kron(A[0], At[1])],
+            [_kron(At[0], A[1]), _kron(M[0], S[1])],
         ]
     elif d == 3:
         curl = [
-            [_kron(M, M, S) + _kron(M, S, M), -_kron(At, A, M), -_kron(At, M, A)],
-            [-_kron(A, At, M), _kron(S, M, M) + _kron(M, M, S), -_kron(M, At, A)],
-            [-_kron(A, M, At), -_kron(M, A, At), _kron(S, M, M) + _kron(M, S, M)],
+            [_kron(M[0], M[1], S[2]) + _kron(M[0], S[1], M[2]), -_kron(At[0], A[1], M[2]), -_kron(At[0], M[1], A[2])],
+            [-_kron(A[0], At[1], M[2]), _kron(S[0], M[1], M[2]) + _kron(M[0], M[1], S[2]), -_kron(M[0], At[1], A[2])],
+            [-_kron(A[0], M[1], At[2]), -_kron(M[0], A[1], At[2]), _kron(S[0], M[1], M[2]) + _kron(M[0], S[1], M[2])],
         ]
         div = [
-            [_kron(S, M, M), _kron(A, At, M), _kron(A, M, At)],
-            [_kron(At, A, M), _kron(M, S, M), _kron(M, A, At)],
-            [_kron(At, M, A), _kron(M, At, A), _kron(M, M, S)],
+            [_kron(S[0], M[1], M[2]), _kron(A[0], At[1], M[2]), _kron(A[0], M[1], At[2])],
+            [_kron(At[0], A[1], M[2]), _kron(M[0], S[1], M[2]), _kron(M[0], A[1], At[2])],
+            [_kron(At[0], M[1], A[2]), _kron(M[0], At[1], A[2]), _kron(M[0], M[1], S[2])],
         ]
     else:
         raise ValueError("d must be 2 or 3")
@@ -99,3 +116,37 @@ def kron_apply(mats1d, x, d, alpha, beta):
             acc += coef * U
         y[c * G : (c + 1) * G] += acc.ravel()
     return y
+
+
+def kron_apply_rows(mats1d, x, d, alpha, beta, rows):
+    """Selected entries (K x)_i, i in ``rows`` (flat indices in the
+    component-major layout), from the simplified block form, one entry at a
+    time: entry (c, i_1..i_d) of block (c, e) term X_1 (x) ... (x) X_d is
+    sum_j prod_l X_l[i_l, j_l] x_e[j_1..j_d].  For checking full-size results
+    on samples without forming K.  ``mats1d`` as for kron_apply."""
+    if isinstance(mats1d, dict):
+        mats1d = [mats1d] * d
+    shape = tuple(mats1d[l]["M"].shape[0] for l in range(d))
+    G = int(np.prod(shape))
+    xs = [x[c * G : (c + 1) * G].reshape(shape) for c in range(d)]
+    blocks = simplified_blocks(d, alpha, beta)
+    out = np.empty(len(rows))
+    for r, flat in enumerate(rows):
+        c, rem = divmod(int(flat), G)
+        idx = np.unravel_index(rem, shape)
+        acc = 0.0
+        for e in range(d):
+            for coef, names in blocks[(c, e)]:
+                U = xs[e]
+                for l in range(d):  # contract axis l with row idx[l] of its matrix (its nonzero span)
+                    row = mats1d[l][names[l]][idx[l]]
+                    nz = np.nonzero(row)[0]
+                    if nz.size == 0:
+                        U = None
+                        break
+                    lo, hi = nz[0], nz[-1] + 1
+                    U = np.tensordot(row[lo:hi], U[lo:hi], axes=([0], [0]))
+                if U is not None:
+                    acc += coef * float(U)
+        out[r] = acc
+    return out

@@ -52,40 +52,67 @@ def _kron(*mats):
 
 
 class Level:
-    def __init__(self, d, p, n, alpha, beta, mats):
-        self.d, self.p, self.n = d, p, n
-        self.M, self.A, self.S = mats
-        self.m = self.M.shape[0]
-        self.K = curl_div_matrix(d, p, n, alpha, beta, mats=mats)
+    """One level: per-axis interval counts ``ns`` (None below the finest level
+    with the paper's transfer) and per-axis 1D (M, A, S) triples; the
+    attributes n, m, M, A, S, P are those of axis 1 (all axes alike on a
+    uniform grid)."""
+
+    def __init__(self, d, p, ns, alpha, beta, mats, blockdiag=False):
+        self.d, self.p = d, p
+        self.ns = list(ns)
+        self.mats = [tuple(t) for t in mats]
+        self.ms = tuple(t[0].shape[0] for t in self.mats)
+        self.n, self.m = self.ns[0], self.ms[0]
+        self.M, self.A, self.S = self.mats[0]
+        self.K = curl_div_matrix(d, p, None, alpha, beta, mats=self.mats)
+        if blockdiag:  # the block-diagonal part D of the level operator (Sec. 6.1, eq. diag)
+            G = self.K.shape[0] // d
+            self.K = sp.block_diag([self.K[c * G:(c + 1) * G, c * G:(c + 1) * G] for c in range(d)], format="csr")
         self.D = self.K.diagonal().copy()
-        self.P = None  # 1D prolongator from the next level to this one
+        self.Ps = None  # per-axis 1D prolongators from the next level to this one
+        self.P = None
         self.lam = None
 
 
 def build_hierarchy(d, p, n, alpha, beta, transfer="knot", coarse_max_dofs=1000,
-                    lanczos_steps=20, nu=3, ratio=30.0, nu_coarse=None):
-    """List of Level objects, finest first."""
-    mats = mass_adv_stiff(n, p)
-    levels = [Level(d, p, n, alpha, beta, mats)]
+                    lanczos_steps=20, nu=3, ratio=30.0, nu_coarse=None, blockdiag=False):
+    """List of Level objects, finest first.  ``n``: intervals of every axis,
+    or one count per axis.  Each level coarsens every axis that can be:
+    by knot insertion (n -> n/2) while the transfer is "knot" and the axis's
+    n is even, otherwise by the paper's prolongator (m -> floor(m/2)), which
+    the axis keeps from then on; an axis with one point is left as it is.
+    The hierarchy stops when a level has at most coarse_max_dofs unknowns or
+    no axis can be coarsened.  blockdiag: every level holds the block-diagonal
+    part of its operator (P_WL); the block prolongator keeps it block diagonal,
+    so the Galerkin coarse operator of D is the block-diagonal part of the
+    coarse operator."""
+    ns = [n] * d if np.isscalar(n) else [int(v) for v in n]
+    levels = [Level(d, p, ns, alpha, beta, [mass_adv_stiff(nl, p) for nl in ns], blockdiag)]
+    if transfer not in ("knot", "paper"):
+        raise ValueError(transfer)
+    knot = [transfer == "knot"] * d
     while True:
         L = levels[-1]
-        if d * L.m**d <= coarse_max_dofs:
+        if d * int(np.prod(L.ms)) <= coarse_max_dofs:
             break
-        if transfer == "knot":
-            if L.n % 2 or L.n // 2 + p - 2 < 1:
-                break
-            P = knot_insertion_prolongator(L.n, p)
-            nc = L.n // 2
-        elif transfer == "paper":
-            if L.m // 2 < 1:
-                break
-            P = paper_prolongator(L.m)
-            nc = None
-        else:
-            raise ValueError(transfer)
-        L.P = P
-        cm = tuple(P.T @ X @ P for X in (L.M, L.A, L.S))
-        levels.append(Level(d, p, nc, alpha, beta, cm))
+        Ps, ncs = [], []
+        for l in range(d):
+            nl, ml = L.ns[l], L.ms[l]
+            if knot[l] and nl % 2 == 0 and nl // 2 + p - 2 >= 1:
+                Ps.append(knot_insertion_prolongator(nl, p))
+                ncs.append(nl // 2)
+            elif ml // 2 >= 1:
+                knot[l] = False
+                Ps.append(paper_prolongator(ml))
+                ncs.append(None)
+            else:
+                Ps.append(np.eye(ml))
+                ncs.append(nl)
+        if all(P.shape[0] == P.shape[1] for P in Ps):
+            break
+        L.Ps, L.P = Ps, Ps[0]
+        cm = [tuple(P.T @ X @ P for X in trip) for P, trip in zip(Ps, L.mats)]
+        levels.append(Level(d, p, ncs, alpha, beta, cm, blockdiag))
     for l, L in enumerate(levels[:-1]):
         L.lam = lanczos_estimate(L, lanczos_steps)
         L.hi = 1.1 * L.lam
@@ -97,8 +124,10 @@ def build_hierarchy(d, p, n, alpha, beta, transfer="knot", coarse_max_dofs=1000,
 
 
 def start_vector(d, m):
-    """v0 = (-1)^{i_1+...+i_d}, the same in every component."""
-    idx = np.indices((m,) * d).sum(axis=0)
+    """v0 = (-1)^{i_1+...+i_d}, the same in every component (m: points of
+    every axis, or one count per axis)."""
+    shape = (m,) * d if np.isscalar(m) else tuple(m)
+    idx = np.indices(shape).sum(axis=0)
     v = np.where(idx % 2 == 0, 1.0, -1.0).ravel()
     return np.tile(v, d)
 
@@ -123,7 +152,7 @@ def lanczos_estimate(L, steps):
     symmetric start vector can span a small invariant subspace on small
     grids): the recurrence restarts from the D-normalised restart vector with
     beta_{j+1} = 0, so the tridiagonal matrix splits into independent runs."""
-    v = start_vector(L.d, L.m)
+    v = start_vector(L.d, L.ms)
     q = v / np.sqrt(v @ (L.D * v))
     r = restart_vector(q.size)
     r = r / np.sqrt(r @ (L.D * r))
@@ -167,12 +196,36 @@ def chebyshev(L, x, b, nu=None):
 
 
 def t_operator(d, p, m):
-    """Sparse T = I_d (x) T_m(m_{p-1})^{(x) d} (Sec. 6.1) and a solver for it
-    (sparse LU of the assembled Kronecker product)."""
-    T1 = toeplitz_T(m, p)
-    T = _kron(*([np.eye(d)] + [T1] * d))
+    """Sparse T = I_d (x) T_{m_1}(m_{p-1}) (x) ... (x) T_{m_d}(m_{p-1})
+    (Sec. 6.1) and a solver for it (sparse LU of the assembled Kronecker
+    product); m: points of every axis, or one count per axis."""
+    ms = [m] * d if np.isscalar(m) else list(m)
+    T = _kron(*([np.eye(d)] + [toeplitz_T(ml, p) for ml in ms]))
     lu = spla.splu(T.tocsc())
     return T, lu.solve
+
+
+def pcg_T(K, Tsolve, r, steps):
+    """``steps`` PCG steps on K e = r from e = 0 with preconditioner T (the
+    finest post-smoother of P_WL, Sec. 6.2)."""
+    e = np.zeros_like(r)
+    res = r.copy()
+    z = Tsolve(res)
+    dd = z.copy()
+    rz = res @ z
+    for _ in range(steps):
+        q = K @ dd
+        dq = dd @ q
+        if dq <= 0:
+            break
+        a = rz / dq
+        e += a * dd
+        res -= a * q
+        z = Tsolve(res)
+        rz_new = res @ z
+        dd = z + (rz_new / rz) * dd
+        rz = rz_new
+    return e
 
 
 def gmres_T(K, Tsolve, r, steps):
@@ -204,17 +257,20 @@ class Method:
     of the preconditioner, ``solve`` the outer flexible CG."""
 
     def __init__(self, d, p, n, alpha, beta, transfer="knot", coarse_max_dofs=1000,
-                 nu=3, ratio=30.0, lanczos_steps=20, krylov_steps=None, nu_coarse=None):
-        self.d, self.p, self.n = d, p, n
+                 nu=3, ratio=30.0, lanczos_steps=20, krylov_steps=None, nu_coarse=None, variant="P_MIM"):
+        if variant not in ("P_MIM", "P_WL", "MIM"):
+            raise ValueError(variant)
+        self.d, self.p, self.n, self.variant = d, p, n, variant
         self.levels = build_hierarchy(d, p, n, alpha, beta, transfer, coarse_max_dofs,
-                                      lanczos_steps, nu, ratio, nu_coarse)
+                                      lanczos_steps, nu, ratio, nu_coarse, blockdiag=(variant == "P_WL"))
         self.krylov_steps = p if krylov_steps is None else krylov_steps
-        self.T, self.Tsolve = t_operator(d, p, self.levels[0].m)
-        self.K = self.levels[0].K
+        self.T, self.Tsolve = t_operator(d, p, self.levels[0].ms)
+        # the system matrix (the V-cycle of P_WL runs on its block-diagonal part)
+        self.K = curl_div_matrix(d, p, None, alpha, beta, mats=self.levels[0].mats) if variant == "P_WL" \
+            else self.levels[0].K
 
     def _prolong_block(self, l):
-        P = self.levels[l].P
-        return _kron(*([np.eye(self.d)] + [P] * self.d))
+        return _kron(*([np.eye(self.d)] + list(self.levels[l].Ps)))
 
     def vcycle(self, b, l=0):
         L = self.levels[l]
@@ -225,13 +281,16 @@ class Method:
         Pb = self._prolong_block(l)
         x = x + Pb @ self.vcycle(Pb.T @ r, l + 1)
         if l == 0 and self.krylov_steps > 0:
-            x = x + gmres_T(L.K, self.Tsolve, b - L.K @ x, self.krylov_steps)
+            post = pcg_T if self.variant == "P_WL" else gmres_T
+            x = x + post(L.K, self.Tsolve, b - L.K @ x, self.krylov_steps)
         else:
             x = chebyshev(L, x, b)
         return x
 
     def solve(self, b, tol, maxiter=10000):
-        """FCG(1).  Returns (x, iterations, history of ||r_k||_2)."""
+        """FCG(1) preconditioned by the V-cycle (P_MIM, P_WL), or the V-cycle
+        as a stationary iteration x += V(b - K x) (MIM).  Returns (x,
+        iterations, history of ||r_k||_2)."""
         K = self.K
         x = np.zeros_like(b)
         r = b.copy()
@@ -239,6 +298,16 @@ class Method:
         hist = [r0]
         if r0 == 0.0:
             return x, 0, hist
+        if self.variant == "MIM":
+            k = 0
+            while k < maxiter:
+                x = x + self.vcycle(r)
+                r = b - K @ x
+                k += 1
+                hist.append(np.linalg.norm(r))
+                if hist[-1] < tol * r0:
+                    break
+            return x, k, hist
         dprev = qprev = dq_prev = None
         k = 0
         while k < maxiter:

@@ -18,7 +18,7 @@ import scipy.sparse as sp
 import scipy.sparse.linalg as spla
 
 from .assembly import curl_div_matrix
-from .method import _kron, t_operator, gmres_T
+from .method import _kron, gmres_T, pcg_T, t_operator
 from .transfer import paper_prolongator
 
 
@@ -26,28 +26,6 @@ def _block_diag_part(K, d):
     G = K.shape[0] // d
     blocks = [K[c * G:(c + 1) * G, c * G:(c + 1) * G] for c in range(d)]
     return sp.block_diag(blocks, format="csr")
-
-
-def pcg_T(K, Tsolve, r, steps):
-    """``steps`` PCG steps on K e = r from e = 0 with preconditioner T."""
-    e = np.zeros_like(r)
-    res = r.copy()
-    z = Tsolve(res)
-    dd = z.copy()
-    rz = res @ z
-    for _ in range(steps):
-        q = K @ dd
-        dq = dd @ q
-        if dq <= 0:
-            break
-        a = rz / dq
-        e += a * dd
-        res -= a * q
-        z = Tsolve(res)
-        rz_new = res @ z
-        dd = z + (rz_new / rz) * dd
-        rz = rz_new
-    return e
 
 
 class PaperMIM:

@@ -23,6 +23,8 @@ CD_EAGAIN = -5
 CD_ENOTFOUND = -6
 
 CD_METHOD_PMIM = 0
+CD_METHOD_PWL = 1
+CD_METHOD_MIM = 2
 CD_METHOD_CG = 3
 CD_XFER_KNOT = 0
 CD_XFER_PAPER = 1
@@ -83,6 +85,10 @@ SIGNATURES = {
     "cd_restrict": (_I, [_P, _I, _P, _P]),
     "cd_prolong_add": (_I, [_P, _I, _P, _P]),
     "cd_tsolve": (_I, [_P, _P, _P]),
+    "cd_smooth_f32": (_I, [_P, _I, _P, _P, _P]),
+    "cd_restrict_f32": (_I, [_P, _I, _P, _P]),
+    "cd_prolong_add_f32": (_I, [_P, _I, _P, _P]),
+    "cd_tsolve_f32": (_I, [_P, _P, _P]),
     "cd_tsolve_noalloc": (_I, [_P, _P, _P]),
     "cd_coarse_solve": (_I, [_P, _P, _P]),
     "cd_precondition": (_I, [_P, _P, _P]),
@@ -231,6 +237,19 @@ class Solver:
 
     def prolong_add(self, level, ec_ptr, xf_ptr):
         check(lib().cd_prolong_add(self._h, level, ctypes.c_void_p(ec_ptr), ctypes.c_void_p(xf_ptr)))
+
+    def smooth_f32(self, level, b_ptr, x_in_ptr, x_out_ptr):
+        check(lib().cd_smooth_f32(self._h, level, ctypes.c_void_p(b_ptr), ctypes.c_void_p(x_in_ptr),
+                                  ctypes.c_void_p(x_out_ptr)))
+
+    def restrict_f32(self, level, rf_ptr, rc_ptr):
+        check(lib().cd_restrict_f32(self._h, level, ctypes.c_void_p(rf_ptr), ctypes.c_void_p(rc_ptr)))
+
+    def prolong_add_f32(self, level, ec_ptr, xf_ptr):
+        check(lib().cd_prolong_add_f32(self._h, level, ctypes.c_void_p(ec_ptr), ctypes.c_void_p(xf_ptr)))
+
+    def tsolve_f32(self, v_ptr, z_ptr):
+        check(lib().cd_tsolve_f32(self._h, ctypes.c_void_p(v_ptr), ctypes.c_void_p(z_ptr)))
 
     def tsolve(self, v_ptr, z_ptr):
         check(lib().cd_tsolve(self._h, ctypes.c_void_p(v_ptr), ctypes.c_void_p(z_ptr)))

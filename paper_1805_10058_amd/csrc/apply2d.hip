@@ -110,7 +110,7 @@ __global__ __launch_bounds__(kThreads) void k_apply2d(OpDev<T> op, const T* __re
             sM2 += cS * st[4 * NA + q0 + k];
             aA2 += cA * st[5 * NA + q0 + k];
         }
-        const T al = op.alpha, be = op.beta, ab = op.alpha - op.beta;
+        const T al = op.alpha, be = op.beta, ab = offdiag_weight(op);
         const T kx[2] = {be * mS1 + al * sM1 + ab * aA2, al * mS2 + be * sM2 + ab * aA1};
 #pragma unroll
         for (int c = 0; c < 2; ++c)

@@ -94,6 +94,13 @@ __device__ inline T diag_entry(const OpDev<T>& op, int c, int i0, int i1, int i2
            (c == 2 ? op.beta : op.alpha) * t2;
 }
 
+// Weight of the off-diagonal blocks (alpha - beta) A (x) A (x) M, zero for the
+// block-diagonal part D (Sec. 6.1, eq. diag).
+template <typename T>
+__device__ inline T offdiag_weight(const OpDev<T>& op) {
+    return op.blockdiag ? T(0) : op.alpha - op.beta;
+}
+
 constexpr int kXcds = 8;  // XCDs of the device; blocks are dispatched to them round robin
 
 // Raise a kernel's dynamic-LDS limit (default 64 KiB) to what a launch needs,

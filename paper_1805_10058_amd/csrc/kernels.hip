@@ -452,7 +452,7 @@ __global__ __launch_bounds__(kThreads) void k_dense_operator(OpDev<double> op, d
                         v += t;
                     }
                 } else {
-                    v = op.alpha - op.beta;
+                    v = offdiag_weight(op);
                     for (int l = 0; l < op.dim; ++l) v *= (l == c || l == e) ? Av[l] : Mv[l];
                 }
             }
@@ -548,10 +548,11 @@ __global__ __launch_bounds__(kThreads) void k_coarse_gemv(const double* __restri
 }
 
 // ---- flexible CG ----------------------------------------------------------------
-__global__ __launch_bounds__(kThreads) void k_fcg_direction(int first, const double* __restrict__ z,
+template <typename T>
+__global__ __launch_bounds__(kThreads) void k_fcg_direction(int first, const T* __restrict__ z,
                                                             const double* __restrict__ pzq, int npzq,
-                                                            const double* __restrict__ dq_prev, double* __restrict__ d,
-                                                            const double* __restrict__ r, double* __restrict__ pdr,
+                                                            const double* __restrict__ dq_prev, T* __restrict__ d,
+                                                            const T* __restrict__ r, double* __restrict__ pdr,
                                                             double* __restrict__ beta_out, size_t n) {
     double beta = 0.0;
     if (!first) {
@@ -560,21 +561,23 @@ __global__ __launch_bounds__(kThreads) void k_fcg_direction(int first, const dou
         beta = (dq != 0.0) ? zq / dq : 0.0;
     }
     if (blockIdx.x == 0 && threadIdx.x == 0) beta_out[0] = beta;
+    const T bt = T(beta);
     double s = 0.0;
     for (size_t i = size_t(blockIdx.x) * kThreads + threadIdx.x; i < n; i += size_t(gridDim.x) * kThreads) {
-        const double dn = first ? z[i] : z[i] - beta * d[i];
+        const T dn = first ? z[i] : z[i] - bt * d[i];
         d[i] = dn;
-        s += dn * r[i];
+        s += double(dn) * double(r[i]);
     }
     s = block_sum(s);
     if (threadIdx.x == 0) pdr[blockIdx.x] = s;
 }
 
+template <typename T>
 __global__ __launch_bounds__(kThreads) void k_fcg_update(const double* __restrict__ pdr, int npdr,
                                                          const double* __restrict__ pdq, int npdq,
-                                                         double* __restrict__ dq_out, double* __restrict__ x,
-                                                         double* __restrict__ r, const double* __restrict__ d,
-                                                         const double* __restrict__ q, double* __restrict__ prr,
+                                                         double* __restrict__ dq_out, T* __restrict__ x,
+                                                         T* __restrict__ r, const T* __restrict__ d,
+                                                         const T* __restrict__ q, double* __restrict__ prr,
                                                          double* __restrict__ a_out, size_t n) {
     const double dr = sum_partials(pdr, npdr);
     const double dq = sum_partials(pdq, npdq);
@@ -583,12 +586,13 @@ __global__ __launch_bounds__(kThreads) void k_fcg_update(const double* __restric
         dq_out[0] = dq;
         a_out[0] = a;
     }
+    const T at = T(a);
     double s = 0.0;
     for (size_t i = size_t(blockIdx.x) * kThreads + threadIdx.x; i < n; i += size_t(gridDim.x) * kThreads) {
-        x[i] += a * d[i];
-        const double rn = r[i] - a * q[i];
+        x[i] += at * d[i];
+        const T rn = r[i] - at * q[i];
         r[i] = rn;
-        s += rn * rn;
+        s += double(rn) * double(rn);
     }
     s = block_sum(s);
     if (threadIdx.x == 0) prr[blockIdx.x] = s;
@@ -1025,17 +1029,19 @@ void launch_coarse_gemv(const double* Kinv, int N, int ld, const T* r, T* z, hip
     check_launch("coarse_gemv");
 }
 
-void launch_fcg_direction(bool first, const double* z, const double* pzq, int npzq, const double* dq_prev, double* d,
-                          const double* r, double* pdr, double* beta_out, size_t n, hipStream_t s) {
-    hipLaunchKernelGGL(k_fcg_direction, dim3(reduce_blocks(n)), dim3(kThreads), 0, s, first ? 1 : 0, z, pzq, npzq,
+template <typename T>
+void launch_fcg_direction(bool first, const T* z, const double* pzq, int npzq, const double* dq_prev, T* d,
+                          const T* r, double* pdr, double* beta_out, size_t n, hipStream_t s) {
+    hipLaunchKernelGGL(k_fcg_direction<T>, dim3(reduce_blocks(n)), dim3(kThreads), 0, s, first ? 1 : 0, z, pzq, npzq,
                        dq_prev, d, r, pdr, beta_out, n);
     check_launch("fcg_direction");
 }
 
-void launch_fcg_update(const double* pdr, int npdr, const double* pdq, int npdq, double* dq_out, double* x, double* r,
-                       const double* d, const double* q, double* prr, double* a_out, size_t n, hipStream_t s) {
-    hipLaunchKernelGGL(k_fcg_update, dim3(reduce_blocks(n)), dim3(kThreads), 0, s, pdr, npdr, pdq, npdq, dq_out, x, r,
-                       d, q, prr, a_out, n);
+template <typename T>
+void launch_fcg_update(const double* pdr, int npdr, const double* pdq, int npdq, double* dq_out, T* x, T* r,
+                       const T* d, const T* q, double* prr, double* a_out, size_t n, hipStream_t s) {
+    hipLaunchKernelGGL(k_fcg_update<T>, dim3(reduce_blocks(n)), dim3(kThreads), 0, s, pdr, npdr, pdq, npdq, dq_out, x,
+                       r, d, q, prr, a_out, n);
     check_launch("fcg_update");
 }
 
@@ -1086,6 +1092,10 @@ void launch_lsq_combine_add(const double* H, int ld, int k, const double* beta0s
     template void launch_prolong_add<T>(const XferDev<T>&, int, const T*, T*, hipStream_t);                          \
     template void launch_tsolve<T>(int, const int*, const TFacDev<T>*, const T*, T*, T*, hipStream_t,                \
                                    unsigned long long*);                            \
+    template void launch_fcg_direction<T>(bool, const T*, const double*, int, const double*, T*, const T*, double*,   \
+                                          double*, size_t, hipStream_t);                                             \
+    template void launch_fcg_update<T>(const double*, int, const double*, int, double*, T*, T*, const T*, const T*,   \
+                                       double*, double*, size_t, hipStream_t);                                       \
     template void launch_fill<T>(T*, T, size_t, hipStream_t);                                                        \
     template void launch_copy<T>(const T*, T*, size_t, hipStream_t);                                                 \
     template void launch_axpby<T>(T, const T*, T, T*, size_t, hipStream_t);                                          \

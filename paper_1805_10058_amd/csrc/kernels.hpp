@@ -23,6 +23,7 @@ struct OpDev {
     int m[3];   // unknowns per axis (m[2] = 1 in 2D)
     int hb;     // half bandwidth (= p on every level)
     int x1chunk;  // 3D kernel: x1 planes per block (0: chosen from the grid size)
+    int blockdiag;  // 1: the block-diagonal part D of the operator (off-diagonal blocks dropped)
     int dim;
     T alpha, beta;
 };
@@ -153,14 +154,17 @@ void launch_cheb_first(const OpDev<T>& op, const T* b, T* x, T inv_theta, hipStr
 template <typename T>
 void launch_coarse_gemv(const double* Kinv, int N, int ld, const T* r, T* z, hipStream_t s);
 
-// ---- flexible CG (FP64) ---------------------------------------------------------
+// ---- flexible CG: the outer iteration (FP64) and the PCG post-smoother of the
+// block-diagonal cycle (vectors T, inner products FP64) -----------------------
 // d = z - (sum pzq / *dq_prev) d   (first = true: d = z); pdr[block] = d.r
 // (*beta_out = the coefficient b of d = z - b d_prev, 0 on the first step)
-void launch_fcg_direction(bool first, const double* z, const double* pzq, int npzq, const double* dq_prev,
-                          double* d, const double* r, double* pdr, double* beta_out, size_t n, hipStream_t s);
+template <typename T>
+void launch_fcg_direction(bool first, const T* z, const double* pzq, int npzq, const double* dq_prev,
+                          T* d, const T* r, double* pdr, double* beta_out, size_t n, hipStream_t s);
 // a = sum pdr / sum pdq; x += a d; r -= a q; prr[block] = r.r; *dq_out = sum pdq; *a_out = a
+template <typename T>
 void launch_fcg_update(const double* pdr, int npdr, const double* pdq, int npdq, double* dq_out,
-                       double* x, double* r, const double* d, const double* q, double* prr, double* a_out,
+                       T* x, T* r, const T* d, const T* q, double* prr, double* a_out,
                        size_t n, hipStream_t s);
 
 // ---- GMRES helpers (vectors of type T, scalars FP64) ----------------------------

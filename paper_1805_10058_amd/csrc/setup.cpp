@@ -257,6 +257,12 @@ Prolong paper_prolong(int mf) {
     return from_dense(P, mf, mc);
 }
 
+Prolong identity_prolong(int m) {
+    std::vector<double> P(size_t(m) * m, 0.0);
+    for (int i = 0; i < m; ++i) P[size_t(i) * m + i] = 1.0;
+    return from_dense(P, m, m);
+}
+
 Band galerkin(const Band& X, const Prolong& P) {
     const int mf = P.mf, mc = P.mc;
     std::vector<double> XP(size_t(mf) * mc, 0.0);  // X P

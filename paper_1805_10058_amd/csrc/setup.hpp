@@ -52,6 +52,8 @@ void assemble_1d(int n, int p, Band& M, Band& A, Band& S);
 Prolong knot_insertion(int nf, int p);
 // The (1/2)[1 2 1] prolongator of Sec. 6.1 with m_c = floor(m_f/2).
 Prolong paper_prolong(int mf);
+// The identity on m points (an axis that a level does not coarsen).
+Prolong identity_prolong(int m);
 // Galerkin product P^T X P.
 Band galerkin(const Band& X, const Prolong& P);
 

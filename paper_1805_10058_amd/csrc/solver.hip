@@ -142,7 +142,8 @@ struct VWork {
     double* H = nullptr;  // (s+1) x s column-major
     double* pdot = nullptr;   // partial dot products of the apply kernel: ks x nba
     double* pnorm = nullptr;  // partial sums of squares: max(nba, nb)
-    double* scal = nullptr;   // [0] beta0^2
+    double* scal = nullptr;   // [0] beta0^2 (GMRES); [1..3] d.q, direction and step coefficients (PCG)
+    double* ppcg = nullptr;   // partial sums of the PCG post-smoother: z.q, d.r, r.r (nb each), d.q (nba)
     int nb = 0;               // reduce_blocks(N)
     int nba = 0;              // blocks of the level-0 apply kernel
 };
@@ -175,15 +176,18 @@ struct cd_solver {
     std::vector<LevelDev<float>> ld32;
     cd::TFacDev<double> tfd64[3]{};
     cd::TFacDev<float> tfd32[3]{};
+    cd::OpDev<double> outer_op{};  // the system operator A of the outer iteration (level 0, never block-diagonal)
     double* Kinv = nullptr;  // inverse of the coarsest operator, leading dimension ldK
     int ldK = 0;
 
     std::unique_ptr<VWork<double>> w64;
     std::unique_ptr<VWork<float>> w32;
-    std::unique_ptr<DevArena> hook_arena;  // FP64 V-cycle workspace created on demand in mixed mode
+    std::unique_ptr<DevArena> hook_arena;    // FP64 V-cycle workspace created on demand in mixed mode
+    std::unique_ptr<DevArena> hook_arena32;  // FP32 workspace created on demand by the FP32 hooks (FP64 mode)
 
     // outer FCG (FP64)
     double *r = nullptr, *z = nullptr, *dd = nullptr, *q = nullptr;
+    double* bw = nullptr;  // MIM: copy of the right-hand side (graph replays read solver-owned buffers only)
     double *pzq = nullptr, *pdr = nullptr, *pdq = nullptr, *prr = nullptr, *scal = nullptr;
     // device and pinned host scalars of the outer iteration: [0] r.r, [1] d.q,
     // [2] step length a, [3] direction coefficient b (d = z - b d_prev), [4] ||b - A x||^2
@@ -236,6 +240,14 @@ struct cd_solver {
 
 namespace {
 
+void need(const cd_solver* s) {
+    if (!s) throw CdError(CD_EINVAL, "null solver handle");
+}
+void need_level(const cd_solver* s, int l) {
+    need(s);
+    if (l < 0 || l >= int(s->lv.size())) throw CdError(CD_EINVAL, "level out of range");
+}
+
 using cd::kApplyCheb;
 using cd::kApplyRes;
 using cd::kApplyY;
@@ -249,7 +261,9 @@ void validate(const cd_problem* pr, const cd_options* op) {
         if (pr->n[l] < 1 || pr->n[l] + pr->degree - 2 < 1) throw CdError(CD_EINVAL, "need n >= 1 and n + p - 2 >= 1");
     if (!(pr->alpha > 0.0) || !(pr->beta > 0.0) || !std::isfinite(pr->alpha) || !std::isfinite(pr->beta))
         throw CdError(CD_EINVAL, "alpha and beta must be positive and finite");
-    if (op->method != CD_METHOD_PMIM && op->method != CD_METHOD_CG) throw CdError(CD_EINVAL, "unknown method");
+    if (op->method != CD_METHOD_PMIM && op->method != CD_METHOD_PWL && op->method != CD_METHOD_MIM &&
+        op->method != CD_METHOD_CG)
+        throw CdError(CD_EINVAL, "unknown method");
     if (op->transfer != CD_XFER_KNOT && op->transfer != CD_XFER_PAPER) throw CdError(CD_EINVAL, "unknown transfer");
     if (op->precision != CD_FP64 && op->precision != CD_MIXED_FP32) throw CdError(CD_EINVAL, "unknown precision");
     if (!(op->rtol > 0.0)) throw CdError(CD_EINVAL, "rtol must be positive");
@@ -263,11 +277,11 @@ void validate(const cd_problem* pr, const cd_options* op) {
     if (op->apply_x1_chunk < 0) throw CdError(CD_EINVAL, "apply_x1_chunk must be >= 0");
     if (op->coarse_max_dofs < 1 || op->coarse_max_dofs > 8192)
         throw CdError(CD_EINVAL, "coarse_max_dofs must be in 1..8192");
-    // the operator kernels keep a plane chunk with a +-p row halo in LDS
-    const int mlast = pr->n[pr->dim - 1] + pr->degree - 2;
-    const size_t lds = (pr->dim == 3) ? 8 * (3 * (256 + 2 * size_t(pr->degree) * mlast) + 9 * 256)
-                                      : 8 * (2 * (256 + 2 * size_t(pr->degree) * mlast) + 6 * 256);
-    if (lds > 160 * 1024) throw CdError(CD_EINVAL, "grid too large along the last axis for the operator kernel");
+    // the operator kernels use fixed-size LDS tiles (no limit on the grid) and
+    // 32-bit offsets within the 3D vectors
+    size_t N = size_t(pr->dim);
+    for (int l = 0; l < pr->dim; ++l) N *= size_t(pr->n[l] + pr->degree - 2);
+    if (pr->dim == 3 && N >= (size_t(1) << 31)) throw CdError(CD_EINVAL, "3D problem too large (2^31 unknowns)");
 }
 
 size_t level_dofs(int d, const int* m) {
@@ -290,23 +304,32 @@ void build_host(cd_solver* s) {
     L0.N = level_dofs(d, L0.m);
     s->lv.clear();
     s->lv.push_back(std::move(L0));
+    // Per axis: knot insertion (n -> n/2) while the axis's n is even and the
+    // handle asks for it, else the (1/2)[1 2 1] prolongator (m -> floor(m/2),
+    // Sec. 6.1) from then on, else (m = 1) no coarsening of that axis.
     int nl[3] = {s->prob.n[0], s->prob.n[1], d == 3 ? s->prob.n[2] : 1};
+    bool knot[3] = {s->opt.transfer == CD_XFER_KNOT, s->opt.transfer == CD_XFER_KNOT, s->opt.transfer == CD_XFER_KNOT};
     while (true) {
         LevelHost& F = s->lv.back();
         if (F.N <= size_t(s->opt.coarse_max_dofs)) break;
-        bool ok = true;
+        int kind[3] = {0, 0, 0};  // 0 none, 1 knot insertion, 2 paper prolongator
+        bool any = false;
         for (int l = 0; l < d; ++l) {
-            if (s->opt.transfer == CD_XFER_KNOT) {
-                if (nl[l] % 2 || nl[l] / 2 + p - 2 < 1) ok = false;
-            } else if (F.m[l] / 2 < 1) {
-                ok = false;
+            if (knot[l] && nl[l] % 2 == 0 && nl[l] / 2 + p - 2 >= 1) {
+                kind[l] = 1;
+            } else if (F.m[l] / 2 >= 1) {
+                kind[l] = 2;
+                knot[l] = false;
             }
+            any = any || kind[l] != 0;
         }
-        if (!ok) break;
+        if (!any) break;
         LevelHost C;
         for (int l = 0; l < 3; ++l) C.m[l] = 1;
         for (int l = 0; l < d; ++l) {
-            F.P[l] = (s->opt.transfer == CD_XFER_KNOT) ? cd::knot_insertion(nl[l], p) : cd::paper_prolong(F.m[l]);
+            F.P[l] = kind[l] == 1 ? cd::knot_insertion(nl[l], p)
+                     : kind[l] == 2 ? cd::paper_prolong(F.m[l])
+                                    : cd::identity_prolong(F.m[l]);
             if (F.P[l].w > 8 || F.P[l].wr > 8) throw CdError(CD_EINVAL, "prolongator window wider than 8");
             C.M[l] = cd::galerkin(F.M[l], F.P[l]);
             C.A[l] = cd::galerkin(F.A[l], F.P[l]);
@@ -317,12 +340,17 @@ void build_host(cd_solver* s) {
             C.A[l] = C.A[l].widened(p);
             C.S[l] = C.S[l].widened(p);
             C.m[l] = C.M[l].m;
-            if (s->opt.transfer == CD_XFER_KNOT) nl[l] /= 2;
+            if (kind[l] == 1) nl[l] /= 2;
         }
         C.n = nl[0];
         C.N = level_dofs(d, C.m);
         s->lv.push_back(std::move(C));
     }
+    // every axis can be coarsened down to one point, so only a cap below d is left over
+    if (s->lv.back().N > size_t(s->opt.coarse_max_dofs) && s->lv.back().N > size_t(d))
+        throw CdError(CD_EINVAL, "the coarsest level has " + std::to_string(s->lv.back().N) +
+                                     " unknowns, more than coarse_max_dofs = " +
+                                     std::to_string(s->opt.coarse_max_dofs));
     for (int l = 0; l < d; ++l) s->tf[l] = cd::toeplitz_factor(s->lv[0].m[l], p);
     const LevelHost& Lc = s->lv.back();
     s->Nc = int(Lc.N);
@@ -334,6 +362,7 @@ cd::OpDev<T> make_op(cd_solver* s, const LevelHost& L, hipStream_t st) {
     op.dim = s->d;
     op.hb = s->p;
     op.x1chunk = s->opt.apply_x1_chunk;
+    op.blockdiag = (s->opt.method == CD_METHOD_PWL) ? 1 : 0;  // P_WL cycles on D (Sec. 6.1, eq. diag)
     op.alpha = T(s->prob.alpha);
     op.beta = T(s->prob.beta);
     for (int l = 0; l < 3; ++l) op.m[l] = L.m[l];
@@ -452,6 +481,7 @@ std::unique_ptr<VWork<T>> make_work(cd_solver* s, DevArena& ar) {
     w->pdot = ar.alloc<double>(size_t(w->nba) * (ks + 1));
     w->pnorm = ar.alloc<double>(size_t(std::max(w->nba, w->nb)));
     w->scal = ar.alloc<double>(4);
+    w->ppcg = ar.alloc<double>(size_t(3) * w->nb + size_t(w->nba));
     return w;
 }
 
@@ -540,9 +570,8 @@ bool timing(const cd_solver* s) { return s->prof && s->prof_sample; }
 
 // ---- operator apply and T-solve with optional live timing ------------------------------
 template <typename T>
-void apply_op(cd_solver* s, int level, int mode, const T* x, T* y, const T* b, T* u, T* xout, T c1, T c2,
-              double* part, int nv = 0) {
-    const cd::OpDev<T>& op = devlevels<T>(s)[level].op;
+void apply_with(cd_solver* s, const cd::OpDev<T>& op, int level, int mode, const T* x, T* y, const T* b, T* u,
+                T* xout, T c1, T c2, double* part, int nv = 0) {
     if (!timing(s)) {
         cd::launch_apply<T>(op, mode, x, y, b, u, xout, c1, c2, part, s->stream, nv);
         return;
@@ -559,6 +588,13 @@ void apply_op(cd_solver* s, int level, int mode, const T* x, T* y, const T* b, T
                                         nvec * double(s->lv[level].N) * sizeof(T));
     cd::launch_apply<T>(op, mode, x, y, b, u, xout, c1, c2, part, s->stream, nv, st);
     if (own) prof_unit_end(s);
+}
+
+// Apply the V-cycle's operator of `level` (A_l, or its block-diagonal part D_l for P_WL).
+template <typename T>
+void apply_op(cd_solver* s, int level, int mode, const T* x, T* y, const T* b, T* u, T* xout, T c1, T c2,
+              double* part, int nv = 0) {
+    apply_with<T>(s, devlevels<T>(s)[level].op, level, mode, x, y, b, u, xout, c1, c2, part, nv);
 }
 
 // z = T^{-1} v on the finest level.
@@ -650,6 +686,34 @@ void gmres_post(cd_solver* s, VWork<T>& W, const T* b, T* x) {
     cd::launch_lsq_combine_add<T>(W.H, ld, ks, W.scal, W.Z, x, N, st);
 }
 
+// p steps of CG on D_0 e = b - D_0 x from e = 0, preconditioned by T (the
+// finest post-smoother of P_WL, Sec. 6.1-6.2), written in the flexible form
+// d_j = z_j - ((z_j . q_{j-1}) / (d_{j-1} . q_{j-1})) d_{j-1}, step
+// (d_j . r_j) / (d_j . q_j), which equals PCG for the fixed SPD T; the steps
+// accumulate into x directly (x + e).
+template <typename T>
+void pcg_post(cd_solver* s, VWork<T>& W, const T* b, T* x) {
+    const size_t N = s->N;
+    const int nb = W.nb, nba = W.nba;
+    hipStream_t st = s->stream;
+    T* r = W.w;
+    T* z = W.z;
+    T* d = W.V;
+    T* q = W.V + N;
+    double* pzq = W.ppcg;
+    double* pdr = W.ppcg + nb;
+    double* prr = W.ppcg + 2 * nb;
+    double* pdq = W.ppcg + 3 * nb;
+    apply_op<T>(s, 0, kApplyRes, x, r, b, nullptr, nullptr, T(0), T(0), nullptr);
+    for (int j = 0; j < s->ksteps; ++j) {
+        tsolve_op<T>(s, r, W.tmp, z);
+        if (j > 0) cd::launch_dot_partial<T, T>(z, q, N, pzq, st);
+        cd::launch_fcg_direction<T>(j == 0, z, pzq, nb, W.scal + 1, d, r, pdr, W.scal + 2, N, st);
+        apply_op<T>(s, 0, kApplyYDot, d, q, nullptr, nullptr, nullptr, T(0), T(0), pdq);
+        cd::launch_fcg_update<T>(pdr, nb, pdq, nba, W.scal + 1, x, r, d, q, prr, W.scal + 3, N, st);
+    }
+}
+
 // One V-cycle on level l for A_l x = W.lv[l].b; result in W.lv[l].xcur.
 // first_done: the first pre-smoothing step was fused into the producer of b.
 template <typename T>
@@ -672,11 +736,23 @@ void vcycle(cd_solver* s, VWork<T>& W, int l, bool first_done = false) {
     vcycle<T>(s, W, l + 1, fuse);
     cd::launch_prolong_add<T>(D.xf, s->d, W.lv[l + 1].xcur, x, st);
     if (l == 0 && s->ksteps > 0) {
-        gmres_post<T>(s, W, Wl.b, x);
+        if (s->opt.method == CD_METHOD_PWL)
+            pcg_post<T>(s, W, Wl.b, x);
+        else
+            gmres_post<T>(s, W, Wl.b, x);
     } else {
         x = chebyshev<T>(s, l, Wl.b, x, other, false);
     }
     Wl.xcur = x;
+}
+
+// Work given the legacy null stream goes to a stream owned by the handle
+// (stream capture is not permitted on the null stream); every entry point
+// first orders it after the work already queued on the null stream.
+void enter(cd_solver* s) {
+    if (!s->own_stream) return;
+    hip_check(hipEventRecord(s->entry_event, nullptr), "hipEventRecord");
+    hip_check(hipStreamWaitEvent(s->stream, s->entry_event, 0), "hipStreamWaitEvent");
 }
 
 VWork<double>& work64(cd_solver* s) {
@@ -685,6 +761,66 @@ VWork<double>& work64(cd_solver* s) {
         s->w64 = make_work<double>(s, *s->hook_arena);
     }
     return *s->w64;
+}
+
+VWork<float>& work32(cd_solver* s) {
+    if (!s->w32) {
+        s->hook_arena32 = std::make_unique<DevArena>();
+        s->w32 = make_work<float>(s, *s->hook_arena32);
+    }
+    return *s->w32;
+}
+
+template <typename T>
+VWork<T>& work_of(cd_solver* s);
+template <>
+VWork<double>& work_of<double>(cd_solver* s) { return work64(s); }
+template <>
+VWork<float>& work_of<float>(cd_solver* s) { return work32(s); }
+
+// Test hooks in precision T (see cd_smooth, cd_restrict, cd_prolong_add, cd_tsolve).
+template <typename T>
+void hook_smooth(cd_solver* s, int level, const T* b, const T* x_in, T* x_out) {
+    need_level(s, level);
+    enter(s);
+    if (level == int(s->lv.size()) - 1) throw CdError(CD_EINVAL, "coarsest level has no smoother");
+    if (s->opt.method == CD_METHOD_CG) throw CdError(CD_EINVAL, "no smoother for plain CG");
+    VWork<T>& W = work_of<T>(s);
+    auto& Wl = W.lv[level];
+    const size_t n = s->lv[level].N;
+    cd::launch_copy<T>(b, Wl.b, n, s->stream);
+    cd::launch_copy<T>(x_in, Wl.xa, n, s->stream);
+    T* r = chebyshev<T>(s, level, Wl.b, Wl.xa, Wl.xb, false);
+    cd::launch_copy<T>(r, x_out, n, s->stream);
+    hip_check(hipStreamSynchronize(s->stream), "sync");
+}
+
+template <typename T>
+void hook_transfer(cd_solver* s, int level, bool restrict_, const T* in, T* out) {
+    need_level(s, level);
+    enter(s);
+    if (level == int(s->lv.size()) - 1) throw CdError(CD_EINVAL, "coarsest level");
+    const auto& X = devlevels<T>(s)[level].xf;
+    if (restrict_)
+        cd::launch_restrict<T>(X, s->d, in, out, s->stream);
+    else
+        cd::launch_prolong_add<T>(X, s->d, in, out, s->stream);
+    hip_check(hipStreamSynchronize(s->stream), "sync");
+}
+
+template <typename T>
+void hook_tsolve(cd_solver* s, const T* v, T* z) {
+    need(s);
+    enter(s);
+    VWork<T>& W = work_of<T>(s);  // its T-solve scratch and spare vector
+    const T* src = v;
+    if (v == z) {
+        cd::launch_copy<T>(v, W.w, s->N, s->stream);
+        src = W.w;
+    }
+    tsolve_op<T>(s, src, W.tmp, z);
+    hip_check(hipStreamSynchronize(s->stream), "sync");
+    if (s->prof) prof_flush(s);
 }
 
 // z = V(r) in the handle's precision; r, z FP64 device vectors.
@@ -844,15 +980,6 @@ void estimate_bounds(cd_solver* s) {
     }
 }
 
-// Work given the legacy null stream goes to a stream owned by the handle
-// (stream capture is not permitted on the null stream); every entry point
-// first orders it after the work already queued on the null stream.
-void enter(cd_solver* s) {
-    if (!s->own_stream) return;
-    hip_check(hipEventRecord(s->entry_event, nullptr), "hipEventRecord");
-    hip_check(hipStreamWaitEvent(s->stream, s->entry_event, 0), "hipStreamWaitEvent");
-}
-
 void create(cd_solver* s, const cd_problem* pr, const cd_options* op, void* stream) {
     validate(pr, op);
     s->prob = *pr;
@@ -884,6 +1011,8 @@ void create(cd_solver* s, const cd_problem* pr, const cd_options* op, void* stre
         s->ld64.push_back(a);
         s->ld32.push_back(b);
     }
+    s->outer_op = s->ld64[0].op;
+    s->outer_op.blockdiag = 0;  // the outer iteration always applies the system matrix
     for (int l = 0; l < s->d; ++l) {
         s->tfd64[l] = make_tfac<double>(s, s->tf[l], st);
         s->tfd32[l] = make_tfac<float>(s, s->tf[l], st);
@@ -912,6 +1041,7 @@ void create(cd_solver* s, const cd_problem* pr, const cd_options* op, void* stre
     s->z = s->arena.alloc<double>(N);
     s->dd = s->arena.alloc<double>(N);
     s->q = s->arena.alloc<double>(N);
+    if (op->method == CD_METHOD_MIM) s->bw = s->arena.alloc<double>(N);
     s->nbr = cd::reduce_blocks(N);
     s->nba = cd::apply_blocks<double>(s->ld64[0].op);
     s->pzq = s->arena.alloc<double>(s->nbr);
@@ -922,8 +1052,8 @@ void create(cd_solver* s, const cd_problem* pr, const cd_options* op, void* stre
     void* hp = nullptr;
     hip_check(hipHostMalloc(&hp, 6 * sizeof(double), hipHostMallocDefault), "hipHostMalloc");
     s->host_scal = static_cast<double*>(hp);
-    if (L > 1 && op->method == CD_METHOD_PMIM) estimate_bounds(s);
-    if (op->method == CD_METHOD_PMIM) {
+    if (L > 1 && op->method != CD_METHOD_CG) estimate_bounds(s);
+    if (op->method != CD_METHOD_CG) {
         if (op->precision == CD_FP64) {
             s->w64 = make_work<double>(s, s->arena);
         } else {
@@ -948,6 +1078,7 @@ void solve_begin(cd_solver* s, const double* b, double* x) {
     S.x = x;
     cd::launch_fill<double>(s->xw, 0.0, N, st);
     cd::launch_copy<double>(b, s->r, N, st);
+    if (s->bw) cd::launch_copy<double>(b, s->bw, N, st);
     cd::launch_dot_partial<double, double>(s->r, s->r, N, s->prr, st);
     cd::launch_finalize(s->prr, s->nbr, s->scal, st);
     hip_check(hipMemcpyAsync(s->host_scal, s->scal, sizeof(double), hipMemcpyDeviceToHost, st), "read");
@@ -971,12 +1102,24 @@ void enqueue_iteration(cd_solver* s, bool first) {
         else
             cd::launch_cast_dot<double, double>(s->r, s->z, N, s->q, s->pzq, st);
     } else {
-        precondition(s, s->r, s->z, first ? nullptr : s->q, s->pzq);
+        const bool dot = !first && s->opt.method != CD_METHOD_MIM;
+        precondition(s, s->r, s->z, dot ? s->q : nullptr, s->pzq);
     }
-    cd::launch_fcg_direction(first, s->z, s->pzq, s->nbr, s->scal + 1, s->dd, s->r, s->pdr, s->scal + 3, N, st);
-    apply_op<double>(s, 0, kApplyYDot, s->dd, s->q, nullptr, nullptr, nullptr, 0.0, 0.0, s->pdq);
-    cd::launch_fcg_update(s->pdr, s->nbr, s->pdq, s->nba, s->scal + 1, s->xw, s->r, s->dd, s->q, s->prr, s->scal + 2,
-                          N, st);
+    if (s->opt.method == CD_METHOD_MIM) {
+        // stand-alone V-cycle: x += V(r), r = b - A x with its norm (scal[1] = 1: no curvature to test)
+        cd::launch_axpby<double>(1.0, s->z, 1.0, s->xw, N, st);
+        apply_with<double>(s, s->outer_op, 0, cd::kApplyResDot, s->xw, s->r, s->bw, nullptr, nullptr, 0.0, 0.0,
+                           s->pdq);
+        cd::launch_finalize(s->pdq, s->nba, s->scal, st);
+        cd::launch_fill<double>(s->scal + 1, 1.0, 3, st);
+        hip_check(hipMemcpyAsync(s->host_scal, s->scal, 4 * sizeof(double), hipMemcpyDeviceToHost, st), "read");
+        return;
+    }
+    cd::launch_fcg_direction<double>(first, s->z, s->pzq, s->nbr, s->scal + 1, s->dd, s->r, s->pdr, s->scal + 3, N,
+                                     st);
+    apply_with<double>(s, s->outer_op, 0, kApplyYDot, s->dd, s->q, nullptr, nullptr, nullptr, 0.0, 0.0, s->pdq);
+    cd::launch_fcg_update<double>(s->pdr, s->nbr, s->pdq, s->nba, s->scal + 1, s->xw, s->r, s->dd, s->q, s->prr,
+                                  s->scal + 2, N, st);
     cd::launch_finalize(s->prr, s->nbr, s->scal, st);
     hip_check(hipMemcpyAsync(s->host_scal, s->scal, 4 * sizeof(double), hipMemcpyDeviceToHost, st), "read");
 }
@@ -1033,8 +1176,10 @@ bool solve_check(cd_solver* s) {
     if (s->prof) prof_flush(s);
     ++S.k;
     const double rr = s->host_scal[0], dq = s->host_scal[1];
-    S.alpha.push_back(s->host_scal[2]);
-    S.beta.push_back(-s->host_scal[3]);  // d = z + beta_cg d_prev
+    if (s->opt.method != CD_METHOD_MIM) {
+        S.alpha.push_back(s->host_scal[2]);
+        S.beta.push_back(-s->host_scal[3]);  // d = z + beta_cg d_prev
+    }
     S.rel = std::sqrt(rr) / S.r0;
     if (!std::isfinite(rr) || !std::isfinite(dq) || !(dq > 0.0)) {
         S.status = CD_EBREAKDOWN;
@@ -1059,7 +1204,7 @@ cd_result solve_finish(cd_solver* s) {
     out.rel_residual = (S.r0 > 0.0) ? S.rel : 0.0;
     cd::launch_copy<double>(s->xw, S.x, N, st);
     if (S.r0 > 0.0) {
-        cd::launch_apply<double>(s->ld64[0].op, kApplyRes, S.x, s->z, S.b, nullptr, nullptr, 0.0, 0.0, nullptr, st);
+        cd::launch_apply<double>(s->outer_op, kApplyRes, S.x, s->z, S.b, nullptr, nullptr, 0.0, 0.0, nullptr, st);
         cd::launch_dot_partial<double, double>(s->z, s->z, N, s->prr, st);
         cd::launch_finalize(s->prr, s->nbr, s->scal + 4, st);
         hip_check(hipMemcpyAsync(s->host_scal + 4, s->scal + 4, sizeof(double), hipMemcpyDeviceToHost, st), "read");
@@ -1103,13 +1248,6 @@ int run(const std::function<void()>& f) {
     }
 }
 
-void need(const cd_solver* s) {
-    if (!s) throw CdError(CD_EINVAL, "null solver handle");
-}
-void need_level(const cd_solver* s, int l) {
-    need(s);
-    if (l < 0 || l >= int(s->lv.size())) throw CdError(CD_EINVAL, "level out of range");
-}
 }  // namespace
 
 extern "C" {
@@ -1164,8 +1302,8 @@ size_t cd_footprint_bytes(const cd_problem* pr, const cd_options* op) {
         for (size_t l = 0; l < tmp.lv.size(); ++l) vw += tmp.lv[l].N * ((l + 1 < tmp.lv.size()) ? 4 : 2);
         const size_t ks = size_t(std::max(tmp.ksteps, 1));
         vw += N * (2 * ks + 5);                             // V (ks+1), Z (ks), w, z, io_in, tmp
-        total = 5 * N * 8                                   // outer r, z, d, q, iterate
-                + (op->method == CD_METHOD_PMIM ? vw * es : 0)  // V-cycle workspace
+        total = (op->method == CD_METHOD_MIM ? 6 : 5) * N * 8  // outer r, z, d, q, iterate (MIM: and b)
+                + (op->method != CD_METHOD_CG ? vw * es : 0)  // V-cycle workspace
                 + size_t(cd::coarse_padded(tmp.Nc)) * cd::coarse_padded(tmp.Nc) * 8  // coarse inverse
                 + (1 << 20);                                 // 1D tables and partial sums
     });
@@ -1220,7 +1358,7 @@ int cd_solve(cd_solver* s, const double* b, double* x, cd_result* res) {
 
 size_t cd_solver_device_bytes(const cd_solver* s) {
     if (!s) return 0;
-    size_t b = s->arena.bytes + (s->hook_arena ? s->hook_arena->bytes : 0);
+    size_t b = s->arena.bytes + (s->hook_arena ? s->hook_arena->bytes : 0) + (s->hook_arena32 ? s->hook_arena32->bytes : 0);
     if (s->stamps) b += size_t(cd_solver::kStampSlots) * (cd::kStampWords + 2) * sizeof(unsigned long long);
     return b;
 }
@@ -1292,40 +1430,24 @@ int cd_apply_f32(cd_solver* s, int level, const float* x, float* y) {
 }
 
 int cd_smooth(cd_solver* s, int level, const double* b, const double* x_in, double* x_out) {
-    return run([&] {
-        need_level(s, level);
-        enter(s);
-        if (level == int(s->lv.size()) - 1) throw CdError(CD_EINVAL, "coarsest level has no smoother");
-        if (s->opt.method != CD_METHOD_PMIM) throw CdError(CD_EINVAL, "no smoother for plain CG");
-        VWork<double>& W = work64(s);
-        auto& Wl = W.lv[level];
-        const size_t n = s->lv[level].N;
-        cd::launch_copy<double>(b, Wl.b, n, s->stream);
-        cd::launch_copy<double>(x_in, Wl.xa, n, s->stream);
-        double* r = chebyshev<double>(s, level, Wl.b, Wl.xa, Wl.xb, false);
-        cd::launch_copy<double>(r, x_out, n, s->stream);
-        hip_check(hipStreamSynchronize(s->stream), "sync");
-    });
+    return run([&] { hook_smooth<double>(s, level, b, x_in, x_out); });
+}
+int cd_smooth_f32(cd_solver* s, int level, const float* b, const float* x_in, float* x_out) {
+    return run([&] { hook_smooth<float>(s, level, b, x_in, x_out); });
 }
 
 int cd_restrict(cd_solver* s, int level, const double* rf, double* rc) {
-    return run([&] {
-        need_level(s, level);
-        enter(s);
-        if (level == int(s->lv.size()) - 1) throw CdError(CD_EINVAL, "coarsest level");
-        cd::launch_restrict<double>(s->ld64[level].xf, s->d, rf, rc, s->stream);
-        hip_check(hipStreamSynchronize(s->stream), "sync");
-    });
+    return run([&] { hook_transfer<double>(s, level, true, rf, rc); });
+}
+int cd_restrict_f32(cd_solver* s, int level, const float* rf, float* rc) {
+    return run([&] { hook_transfer<float>(s, level, true, rf, rc); });
 }
 
 int cd_prolong_add(cd_solver* s, int level, const double* ec, double* xf) {
-    return run([&] {
-        need_level(s, level);
-        enter(s);
-        if (level == int(s->lv.size()) - 1) throw CdError(CD_EINVAL, "coarsest level");
-        cd::launch_prolong_add<double>(s->ld64[level].xf, s->d, ec, xf, s->stream);
-        hip_check(hipStreamSynchronize(s->stream), "sync");
-    });
+    return run([&] { hook_transfer<double>(s, level, false, ec, xf); });
+}
+int cd_prolong_add_f32(cd_solver* s, int level, const float* ec, float* xf) {
+    return run([&] { hook_transfer<float>(s, level, false, ec, xf); });
 }
 
 int cd_tsolve(cd_solver* s, const double* v, double* z) {
@@ -1342,6 +1464,9 @@ int cd_tsolve(cd_solver* s, const double* v, double* z) {
         hip_check(hipStreamSynchronize(s->stream), "sync");
         if (s->prof) prof_flush(s);
     });
+}
+int cd_tsolve_f32(cd_solver* s, const float* v, float* z) {
+    return run([&] { hook_tsolve<float>(s, v, z); });
 }
 
 int cd_tsolve_noalloc(cd_solver* s, const double* v, double* z) {
@@ -1377,7 +1502,7 @@ int cd_precondition(cd_solver* s, const double* r, double* z) {
     return run([&] {
         need(s);
         enter(s);
-        if (s->opt.method != CD_METHOD_PMIM) throw CdError(CD_EINVAL, "plain CG has no preconditioner");
+        if (s->opt.method == CD_METHOD_CG) throw CdError(CD_EINVAL, "plain CG has no preconditioner");
         if (s->lv.size() == 1) {
             cd::launch_coarse_gemv<double>(s->Kinv, s->Nc, s->ldK, r, z, s->stream);
         } else {

@@ -105,6 +105,77 @@ def test_spectral_distribution(d, p, ns, beta):
     assert errs[-1] < errs[0]
 
 
+ANISO = [(2, 2, (5, 8)), (2, 3, (7, 4)), (3, 1, (3, 5, 4)), (3, 2, (3, 4, 6)), (3, 3, (4, 3, 2))]
+
+
+@pytest.mark.parametrize("d,p,ns", ANISO)
+@pytest.mark.parametrize("alpha,beta", [(1.0, 0.1), (0.7, 2.5)])
+def test_anisotropic_literal_equals_kron_apply(d, p, ns, alpha, beta):
+    # n_l = nu_l n (Sec. 5): the literal blocks with per-axis 1D matrices
+    # against the simplified form applied axis by axis
+    K = asm.curl_div_matrix(d, p, ns, alpha, beta)
+    per_axis = [dict(zip("MAS", mt.mass_adv_stiff(nl, p))) for nl in ns]
+    assert K.shape[0] == d * int(np.prod([nl + p - 2 for nl in ns]))
+    x = _rand(K.shape[0], 13)
+    y = asm.kron_apply(per_axis, x, d, alpha, beta)
+    assert np.linalg.norm(K @ x - y) <= 1e-13 * np.linalg.norm(y)
+    # uniform n through the per-axis path is the uniform matrix
+    if len(set(ns)) == 1:
+        assert abs(K - asm.curl_div_matrix(d, p, ns[0], alpha, beta)).max() == 0
+
+
+@pytest.mark.parametrize("d,p,ns", ANISO)
+def test_anisotropic_spd_and_vector_laplacian(d, p, ns):
+    K = asm.curl_div_matrix(d, p, ns, 1.0, 1e-3).toarray()
+    assert np.abs(K - K.T).max() <= 1e-14 * np.abs(K).max()
+    sla.cholesky(K)
+    # alpha = beta: I_d (x) sum_e D_e, D_e = S on axis e and M on the others
+    mats = [mt.mass_adv_stiff(nl, p) for nl in ns]
+    L = 0
+    for e in range(d):
+        X = np.ones((1, 1))
+        for l in range(d):
+            X = np.kron(X, mats[l][2] if l == e else mats[l][0])
+        L = L + X
+    K1 = asm.curl_div_matrix(d, p, ns, 1.3, 1.3).toarray()
+    np.testing.assert_allclose(K1, 1.3 * np.kron(np.eye(d), L), atol=1e-13 * np.abs(K1).max())
+
+
+@pytest.mark.parametrize("d,p,nu,ns", [(2, 3, (1, 2), (10, 20)), (3, 2, (1, 2, 1.5), (4, 6))])
+@pytest.mark.parametrize("beta", [0.5, 0.01])
+def test_anisotropic_spectral_distribution(d, p, nu, ns, beta):
+    # Theorems 5.1 / 5.5 with n_l = nu_l n: eigenvalues of n^{d-2} A against
+    # the sorted samples of f^{p,alpha,beta} with the weights nu on the grid
+    # theta_l = k pi / m_l; the mismatch shrinks with n
+    alpha = 1.0
+    errs = []
+    for n in ns:
+        nl = [int(round(v * n)) for v in nu]
+        K = asm.curl_div_matrix(d, p, nl, alpha, beta).toarray() * n ** (d - 2)
+        ev = np.sort(np.linalg.eigvalsh(K))
+        grids = [np.arange(1, v + p - 1) * np.pi / (v + p - 2) for v in nl]
+        th = np.meshgrid(*grids, indexing="ij")
+        samp = np.sort(np.linalg.eigvalsh(sy.curl_div_symbol(p, alpha, beta, th, nu=nu)).ravel())
+        errs.append(np.median(np.abs(ev - samp)) / samp.max())
+    assert errs[-1] < 0.03
+    assert errs[-1] < errs[0]
+    # the weights matter: the isotropic symbol does not match
+    wrong = np.sort(np.linalg.eigvalsh(sy.curl_div_symbol(p, alpha, beta, th)).ravel())
+    p90 = lambda v: np.percentile(np.abs(ev - v), 90) / samp.max()
+    assert p90(wrong) > 4 * p90(samp)
+
+
+@pytest.mark.parametrize("d,p,ns", [(2, 3, (9, 7)), (3, 2, (4, 5, 6)), (3, 4, (3, 3, 3))])
+def test_sampled_rows_equal_the_full_apply(d, p, ns):
+    # kron_apply_rows (entries one by one, for full-size samples) against the
+    # literal matrix, every row including the boundary ones
+    K = asm.curl_div_matrix(d, p, ns, 1.0, 0.2)
+    per_axis = [dict(zip("MAS", mt.mass_adv_stiff(nl, p))) for nl in ns]
+    x = _rand(K.shape[0], 17)
+    y = asm.kron_apply_rows(per_axis, x, d, 1.0, 0.2, range(K.shape[0]))
+    assert np.abs(y - K @ x).max() <= 1e-13 * np.abs(K @ x).max()
+
+
 @pytest.mark.parametrize("d,p,n", [(2, 2, 8), (2, 4, 6), (3, 2, 4)])
 def test_fast_diagonalization_equals_direct(d, p, n):
     alpha = 1.7

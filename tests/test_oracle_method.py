@@ -175,6 +175,100 @@ def test_solution_matches_direct_solve(d, p, n, beta, transfer):
     assert it < 60
 
 
+@pytest.mark.parametrize("d,p,ns,beta", [(2, 3, (24, 40), 0.05), (3, 2, (8, 12, 16), 0.1), (2, 2, (32, 16), 1.0)])
+def test_anisotropic_solution_matches_direct_solve(d, p, ns, beta):
+    # n_l = nu_l n: every axis is coarsened at every level; the hierarchy
+    # stops when an axis cannot be halved
+    meth = method.Method(d, p, ns, 1.0, beta, coarse_max_dofs=300)
+    assert len(meth.levels) >= 2
+    for L, Lc in zip(meth.levels, meth.levels[1:]):
+        assert all(nc == nl // 2 for nl, nc in zip(L.ns, Lc.ns))
+        assert Lc.K.shape[0] == d * int(np.prod([nl // 2 + p - 2 for nl in L.ns]))
+    b = _rand(meth.K.shape[0], 21)
+    x, it, _ = meth.solve(b, 1e-12)
+    xd = solvers.solve_direct(asm.curl_div_matrix(d, p, ns, 1.0, beta), b)
+    assert np.linalg.norm(x - xd) <= 1e-10 * np.linalg.norm(xd)
+    assert it < 60
+
+
+@pytest.mark.parametrize("d,p,ns,cmax,kind", [(2, 3, (25, 25), 60, "paper"), (2, 2, (4, 64), 10, "none"),
+                                              (3, 2, (7, 8, 6), 30, "paper")])
+def test_odd_and_short_axes_keep_coarsening(d, p, ns, cmax, kind):
+    # an odd n switches its axis to the paper's prolongator (m -> floor(m/2));
+    # an axis with one point stays as it is while the others coarsen
+    meth = method.Method(d, p, ns, 1.0, 0.1, coarse_max_dofs=cmax)
+    C = meth.levels[-1]
+    assert C.K.shape[0] <= cmax or all(m == 1 for m in C.ms)
+    kinds = set()
+    for L, Lc in zip(meth.levels, meth.levels[1:]):
+        for l in range(d):
+            m, mc, n, nc = L.ms[l], Lc.ms[l], L.ns[l], Lc.ns[l]
+            if m == 1:
+                seen = "none"
+                assert mc == 1
+            elif nc is not None:  # knot insertion
+                seen = "knot"
+                assert n % 2 == 0 and nc == n // 2 and mc == nc + p - 2
+            else:  # the paper's prolongator
+                seen = "paper"
+                assert mc == m // 2
+            kinds.add(seen)
+    assert kind in kinds
+    b = _rand(meth.K.shape[0], 23)
+    x, it, _ = meth.solve(b, 1e-12)
+    xd = solvers.solve_direct(asm.curl_div_matrix(d, p, ns, 1.0, 0.1), b)
+    assert np.linalg.norm(x - xd) <= 1e-10 * np.linalg.norm(xd)
+
+
+@pytest.mark.parametrize("variant", ["P_WL", "MIM"])
+@pytest.mark.parametrize("d,p,n,beta", [(2, 3, 16, 0.1), (3, 2, 8, 0.1)])
+def test_pwl_and_mim_solutions_match_direct_solve(variant, d, p, n, beta):
+    meth = method.Method(d, p, n, 1.0, beta, coarse_max_dofs=60, variant=variant)
+    b = _rand(meth.K.shape[0], 25)
+    x, it, hist = meth.solve(b, 1e-11, maxiter=2000)
+    xd = solvers.solve_direct(asm.curl_div_matrix(d, p, n, 1.0, beta), b)
+    assert hist[-1] < 1e-11 * hist[0]
+    assert np.linalg.norm(x - xd) <= 1e-8 * np.linalg.norm(xd)
+    # the outer iteration always uses the system matrix, not the cycle's D
+    assert abs(meth.K - asm.curl_div_matrix(d, p, n, 1.0, beta)).max() == 0
+
+
+def test_pwl_cycle_is_the_pmim_cycle_when_alpha_equals_beta():
+    # alpha = beta: the off-diagonal blocks vanish (weight alpha - beta), D = A,
+    # and without the Krylov post-smoother the two cycles are the same map
+    kw = dict(coarse_max_dofs=60, krylov_steps=0)
+    a = method.Method(2, 3, 16, 0.8, 0.8, variant="P_WL", **kw)
+    b = method.Method(2, 3, 16, 0.8, 0.8, variant="P_MIM", **kw)
+    r = _rand(a.K.shape[0], 26)
+    np.testing.assert_allclose(a.vcycle(r), b.vcycle(r), rtol=1e-13, atol=1e-15)
+
+
+@pytest.mark.parametrize("d,p,n", [(2, 2, 10), (3, 2, 4)])
+def test_pwl_cycle_keeps_components_apart(d, p, n):
+    meth = method.Method(d, p, n, 1.0, 0.05, coarse_max_dofs=30, variant="P_WL")
+    G = meth.K.shape[0] // d
+    for L in meth.levels:
+        Gl = L.K.shape[0] // d
+        for c in range(d):
+            for e in range(d):
+                if c != e:
+                    assert L.K[c * Gl:(c + 1) * Gl, e * Gl:(e + 1) * Gl].nnz == 0
+    r = np.zeros(meth.K.shape[0])
+    r[G:2 * G] = _rand(G, 27)
+    z = meth.vcycle(r)
+    other = np.ones(z.size, bool)
+    other[G:2 * G] = False
+    assert np.abs(z[other]).max() == 0 and np.abs(z[G:2 * G]).max() > 0
+
+
+def test_mim_needs_more_iterations_than_pmim():
+    # the same cycle, with and without Krylov acceleration
+    b = _rand(2 * 17 * 17, 28)
+    it_mim = method.Method(2, 3, 16, 1.0, 0.01, coarse_max_dofs=60, variant="MIM").solve(b, 1e-8)[1]
+    it_pmim = method.Method(2, 3, 16, 1.0, 0.01, coarse_max_dofs=60).solve(b, 1e-8)[1]
+    assert it_mim > it_pmim
+
+
 def test_iterations_flat_in_n_and_growing_as_beta_falls():
     # qualitative behaviour reported in Sec. 6.2
     counts = {}
