@@ -220,6 +220,9 @@ def main():
     ap.add_argument("--serve", type=int, default=32, help="requests of the serving stream to run (0: skip)")
     ap.add_argument("--serve-rate", type=float, default=8.0, help="Poisson arrival rate of the stream, 1/s (0: burst)")
     ap.add_argument("--serve-max-iter", type=int, default=4000)
+    ap.add_argument("--serve-stream", type=int, default=0, metavar="N",
+                    help="run only the full serving workload on N requests: capacity from a burst, Poisson "
+                         "arrivals at 0.5x and 0.9x of it, and the plain FP64 path one at a time")
     ap.add_argument("--batched", type=int, default=8,
                     help="also solve this many right-hand sides of the 2D p=3 n=256 workload at once through the "
                          "continuous-batching server (0: skip)")
@@ -250,6 +253,10 @@ def main():
         copy_calibration(torch)
     if args.only_c4_apply:
         print(json.dumps({"operator_apply_c4": c4_apply(capi, torch, st)}), flush=True)
+        return
+    if args.serve_stream > 0:
+        print(json.dumps({"serving_stream": serve_stream(capi, torch, st, args.serve_stream, args.serve_max_iter,
+                                                         log)}), flush=True)
         return
     if args.only_c4_solve or args.pmc_pass:
         print(json.dumps({"solve_c4": c4_solve(capi, torch, st, args.only_c4_solve or 6,
@@ -390,68 +397,111 @@ def c2_batched(capi, torch, cfg, count, log):
             "note": "all submitted at t=0 to the continuous-batching server; includes solver setup"}
 
 
-def serve_bench(capi, torch, st, count, max_iter, log, rate):
-    """The serving workload: `count` seeded requests of the stream (2D/3D,
-    p in {2,3,4}, n log-uniform, beta log-uniform in [1e-6, 1]) arriving as a
-    Poisson process of `rate` requests per second (0: all at t = 0), served
-    by the continuous-batching mixed-precision server; then the same arrival
-    schedule served one request at a time by the plain FP64 single-solve
-    path.  Latency = completion - arrival; both include solver setup; the
-    right-hand sides are resident in HBM before timing starts."""
+def serve_data(capi, torch, count):
+    """The serving stream's requests with their right-hand sides resident in HBM."""
     import curldiv_inputs as ci
 
-    reqs = ci.serving_stream(count, seed=7, rate=rate if rate > 0 else None)
     data = []
-    for r in reqs:
+    for r in ci.serving_stream(count, seed=7, rate=1.0):
         prob = capi.problem(r["dim"], r["p"], r["n"], r["alpha"], r["beta"])
         b = torch.as_tensor(ci.rhs(r["dim"], r["p"], r["n"], r["seed"])).cuda()
-        data.append((prob, b, torch.zeros_like(b), torch.zeros_like(b), r["arrival"]))
+        data.append({"prob": prob, "b": b, "x": torch.zeros_like(b), "gap1": r["arrival"], "req": r})
     torch.cuda.synchronize()
-    srv = capi.Server(max_active=32)
+    return data
+
+
+def serve_run(capi, data, arrivals, max_iter, max_active=64):
+    """Serve the requests with the continuous-batching mixed-precision server,
+    each submitted at its arrival time (seconds from the start).  Latency =
+    completion - arrival, solver set-up included."""
+    count = len(data)
+    srv = capi.Server(max_active=max_active)
     opt = capi.options(precision=capi.CD_MIXED_FP32, rtol=1e-8, max_iter=max_iter)
-    ticket, done, arrival_of = {}, {}, {}
+    ticket, done = {}, {}
     nxt = 0
+    peak = 0
     t0 = time.perf_counter()
     while len(done) < count:
         now = time.perf_counter() - t0
-        while nxt < count and data[nxt][4] <= now:
-            prob, b, x, _, arr = data[nxt]
-            tk = srv.submit(prob, opt, b.data_ptr(), x.data_ptr())
+        while nxt < count and arrivals[nxt] <= now:
+            tk = srv.submit(data[nxt]["prob"], opt, data[nxt]["b"].data_ptr(), data[nxt]["x"].data_ptr())
             ticket[tk] = nxt
-            arrival_of[nxt] = arr
             nxt += 1
         a, q = srv.step()
+        peak = max(peak, a)
         for c in srv.poll():
             done[ticket[c.ticket]] = (c, time.perf_counter() - t0)
         if a == 0 and q == 0 and nxt < count:
-            time.sleep(max(0.0, data[nxt][4] - (time.perf_counter() - t0)))
+            time.sleep(max(0.0, arrivals[nxt] - (time.perf_counter() - t0)))
     T = time.perf_counter() - t0
     srv.close()
-    lat = [t_done - arrival_of[i] for i, (c, t_done) in done.items()]
-    ok = sum(1 for c, _ in done.values() if c.result.status == capi.CD_OK)
+    lat = [t_done - arrivals[i] for i, (c, t_done) in done.items()]
     its = [c.result.iterations for c, _ in done.values()]
-    log(f"server done in {T:.2f}s; converged {ok}/{count}")
-    ok64, lat64 = 0, []
+    return {"solves_per_s": count / T, "wall_s": T, "converged": sum(1 for c, _ in done.values()
+                                                                     if c.result.status == capi.CD_OK),
+            "p50_ms": 1e3 * percentile(lat, 50), "p99_ms": 1e3 * percentile(lat, 99),
+            "iterations_min_max": [min(its), max(its)], "peak_in_flight": peak,
+            "max_true_rel_residual": max(c.result.true_rel_residual for c, _ in done.values())}
+
+
+def fp64_sequential(capi, data, arrivals, st, max_iter):
+    """The same requests, one at a time, by the plain FP64 single-solve path."""
     t1 = time.perf_counter()
-    for prob, b, _, x, arr in data:
+    lat, ok = [], 0
+    for d, arr in zip(data, arrivals):
         wait = arr - (time.perf_counter() - t1)
         if wait > 0:
             time.sleep(wait)
-        s = capi.Solver(prob, capi.options(rtol=1e-8, max_iter=max_iter), st)
-        r = s.solve(b.data_ptr(), x.data_ptr())
+        s = capi.Solver(d["prob"], capi.options(rtol=1e-8, max_iter=max_iter), st)
+        r = s.solve(d["b"].data_ptr(), d["x"].data_ptr())
         s.close()
-        lat64.append(time.perf_counter() - t1 - arr)
-        ok64 += int(r.status == capi.CD_OK)
-    T64 = time.perf_counter() - t1
+        lat.append(time.perf_counter() - t1 - arr)
+        ok += int(r.status == capi.CD_OK)
+    T = time.perf_counter() - t1
+    return {"solves_per_s": len(data) / T, "wall_s": T, "converged": ok,
+            "p50_ms": 1e3 * percentile(lat, 50), "p99_ms": 1e3 * percentile(lat, 99)}
+
+
+def serve_bench(capi, torch, st, count, max_iter, log, rate):
+    """`count` requests of the serving stream (2D/3D, p in {2,3,4}, n
+    log-uniform, beta log-uniform in [1e-6, 1]) arriving as a Poisson process
+    of `rate` requests per second (0: all at t = 0), served by the
+    continuous-batching server, then the same schedule one request at a time
+    by the plain FP64 single-solve path."""
+    data = serve_data(capi, torch, count)
+    arrivals = [d["gap1"] / rate if rate > 0 else 0.0 for d in data]
+    srv = serve_run(capi, data, arrivals, max_iter)
+    log(f"server: {srv}")
+    seq = fp64_sequential(capi, data, arrivals, st, max_iter)
     mode = (f"Poisson arrivals at {rate:g}/s" if rate > 0 else "burst (all arrive at t=0)") + \
-        ", continuous batching, mixed FP32/FP64, max 32 in flight"
-    return {"requests": count, "mode": mode,
-            "solves_per_s": count / T, "converged": ok, "p50_ms": 1e3 * percentile(lat, 50),
-            "p99_ms": 1e3 * percentile(lat, 99), "iterations_min_max": [min(its), max(its)],
-            "max_iter": max_iter,
-            "fp64_sequential": {"solves_per_s": count / T64, "converged": ok64,
-                                "p50_ms": 1e3 * percentile(lat64, 50), "p99_ms": 1e3 * percentile(lat64, 99)},
-            "speedup_vs_fp64_sequential": T64 / T}
+        ", continuous batching, mixed FP32/FP64, one stream per solve, set-up on a worker thread"
+    out = {"requests": count, "mode": mode, **srv, "max_iter": max_iter, "fp64_sequential": seq,
+           "speedup_vs_fp64_sequential": seq["wall_s"] / srv["wall_s"]}
+    return out
+
+
+def serve_stream(capi, torch, st, count, max_iter, log):
+    """The full serving workload: capacity from a burst of `count` requests,
+    then the same requests arriving as Poisson processes at 0.5x and 0.9x that
+    capacity; the plain FP64 path one request at a time on the burst and on
+    the 0.5x schedule."""
+    data = serve_data(capi, torch, count)
+    out = {"requests": count}
+    burst = serve_run(capi, data, [0.0] * count, max_iter)
+    out["burst"] = burst
+    log(f"stream burst: {burst}")
+    cap = burst["solves_per_s"]
+    for frac in (0.5, 0.9):
+        arr = [d["gap1"] / (frac * cap) for d in data]
+        out[f"poisson_{frac:g}x"] = {"rate_per_s": frac * cap, **serve_run(capi, data, arr, max_iter)}
+        log(f"stream at {frac}x capacity: {out[f'poisson_{frac:g}x']}")
+    out["fp64_sequential_burst"] = fp64_sequential(capi, data, [0.0] * count, st, max_iter)
+    log(f"fp64 sequential burst: {out['fp64_sequential_burst']}")
+    arr = [d["gap1"] / (0.5 * cap) for d in data]
+    out["fp64_sequential_0.5x"] = fp64_sequential(capi, data, arr, st, max_iter)
+    log(f"fp64 sequential at 0.5x: {out['fp64_sequential_0.5x']}")
+    out["speedup_burst_vs_fp64_sequential"] = out["fp64_sequential_burst"]["wall_s"] / burst["wall_s"]
+    return out
 
 
 def copy_calibration(torch, mib=256, reps=5):

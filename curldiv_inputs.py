@@ -31,11 +31,14 @@ def rhs(dim, p, n, seed, dist="uniform"):
     raise ValueError(dist)
 
 
-def serving_stream(count=512, seed=2024, rate=None):
+def serving_stream(count=512, seed=2024, rate=None, round_n=False):
     """Requests of the serving workload: dimension 2/3 with equal probability,
-    p in {2,3,4}, n log-uniform in [32,256] (2D) or [16,96] (3D) rounded to
-    c * 2^k with c in 4..7, beta log-uniform in [1e-6, 1], alpha = 1, and
-    Poisson arrival times (rate requests per second; None = all at t = 0)."""
+    p in {2,3,4}, n log-uniform in [32,256] (2D) or [16,96] (3D) (rounded to
+    the nearest integer; with round_n to the nearest c * 2^k, c in 4..7),
+    beta log-uniform in [1e-6, 1], alpha = 1, and Poisson arrival times (rate
+    requests per second; None = all at t = 0).  The arrival gaps are unit
+    exponentials divided by the rate, so streams of one seed at different
+    rates differ only in their time scale."""
     rng = np.random.default_rng(seed)
     out = []
     t = 0.0
@@ -44,11 +47,15 @@ def serving_stream(count=512, seed=2024, rate=None):
         p = int(rng.integers(2, 5))
         lo, hi = (32, 256) if d == 2 else (16, 96)
         n_raw = float(np.exp(rng.uniform(np.log(lo), np.log(hi))))
-        cands = sorted({c * 2**k for c in range(4, 8) for k in range(0, 8) if lo <= c * 2**k <= hi})
-        n = min(cands, key=lambda v: abs(v - n_raw))
+        if round_n:
+            cands = sorted({c * 2**k for c in range(4, 8) for k in range(0, 8) if lo <= c * 2**k <= hi})
+            n = min(cands, key=lambda v: abs(v - n_raw))
+        else:
+            n = int(round(n_raw))
         beta = float(10.0 ** rng.uniform(-6.0, 0.0))
+        gap = float(rng.exponential(1.0))
         if rate:
-            t += float(rng.exponential(1.0 / rate))
+            t += gap / rate
         out.append({"id": i, "dim": d, "p": p, "n": n, "alpha": 1.0, "beta": beta, "arrival": t,
                     "seed": 10_000 + i})
     return out

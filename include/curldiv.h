@@ -137,8 +137,9 @@ size_t cd_num_dofs(const cd_problem* prob);
 /* CD_OK if (prob, opt) is a valid combination, else CD_EINVAL. */
 int cd_validate(const cd_problem* prob, const cd_options* opt);
 
-/* Device bytes a solver for (prob, opt) allocates (hierarchy, coarse
- * inverse, workspace); used by the server's admission test. */
+/* Device bytes a solver for (prob, opt) needs at its peak (hierarchy,
+ * coarse inverse, workspace, and the set-up's temporary factor and Lanczos
+ * vectors); the server's unit of admission. */
 size_t cd_footprint_bytes(const cd_problem* prob, const cd_options* opt);
 
 /* ---- solver handle ----------------------------------------------------- */
@@ -212,6 +213,19 @@ int cd_tsolve_f32(cd_solver* s, const float* v_dev, float* z_dev);
  * streams run concurrently) race and give undefined results.  The current
  * device must be the handle's device.  Blocks until done. */
 int cd_tsolve_noalloc(cd_solver* s, const double* v_dev, double* z_dev);
+/* The numerical examples of Sec. 6.2 (manufactured solutions):
+ * u = (sin(2 pi g), cos(2 pi g) - 1) in 2D and (sin(2 pi g), cos(2 pi g) - 1,
+ * u_1 + u_2) in 3D, g = prod_i x_i (1 - x_i).  cd_load_vector writes the
+ * Galerkin load vector of f = L_{alpha,beta} u for the handle's problem,
+ * alpha (curl u, curl psi_i) + beta (div u, div psi_i) (the fields vanish on
+ * the boundary), into b_dev (cd_num_dofs doubles, the layout of the system);
+ * cd_l2_error writes ||u - u_h||_{L2((0,1)^d)} for the discrete field u_h
+ * with coefficients x_dev.  Both use (p+3)-point Gauss-Legendre quadrature
+ * per element and direction, run on the GPU in FP64 and allocate their
+ * workspace for the call (3D load vector: about 7 Q^2 m + 6 Q m^2 doubles,
+ * Q = n (p+3), m = n + p - 2). */
+int cd_load_vector(cd_solver* s, double* b_dev);
+int cd_l2_error(cd_solver* s, const double* x_dev, double* err);
 /* z = A_L^{-1} r on the coarsest level, FP64. */
 int cd_coarse_solve(cd_solver* s, const double* r_dev, double* z_dev);
 /* z = one application of the preconditioner (one V-cycle, in the handle's
@@ -256,17 +270,25 @@ int cd_profile_read_tsolve(const cd_solver* s, int fp32, cd_kernel_stats* out);
 /* A server keeps a FIFO of submitted solves and a set of active ones.  Each
  * cd_server_step() admits queued requests while the sum of their footprints
  * (cd_footprint_bytes) stays within the HBM budget and fewer than max_active
- * are in flight, then enqueues one outer iteration of every active solve
- * (each on one of the server's streams, so their kernels overlap on the
- * device) and retires the ones that met their stopping rule.  A request's
- * arithmetic never depends on the others: its result is bitwise the same
- * alone or in a mix.  Callers keep b_dev and x_dev valid until the
- * request's completion has been polled. */
+ * are in flight, handing their set-up (cd_solver_create and the first
+ * residual) to a worker thread of the server, and advances every active
+ * solve whose last outer iteration has finished: stopping test, then the
+ * next iteration is enqueued or the solve retires.  Each solve runs on its
+ * own stream, so the kernels of different solves overlap on the device and
+ * a short solve never waits for a long one.  The call returns as soon as
+ * something progressed (or after about a millisecond without progress).
+ * A request's arithmetic never depends on the others: its result is
+ * bitwise the same alone or in a mix.  A request whose set-up runs out of
+ * device memory while other solves hold it goes back to the head of the
+ * queue.  Callers keep b_dev and x_dev valid until the request's completion
+ * has been polled. */
 typedef struct cd_server cd_server;
 typedef struct {
     size_t hbm_budget_bytes;  /* admission budget; 0 = 80% of the free HBM at creation */
     int max_active;           /* solves in flight at once; 0 = 64 */
-    int num_streams;          /* HIP streams the active solves are spread over; 0 = 4 */
+    int num_streams;          /* 0 (default): one stream per active solve; k in 1..64: a pool
+                                 of k streams shared round robin (solves on one stream
+                                 run one after the other) */
 } cd_server_options;
 typedef struct {
     uint64_t ticket;
@@ -280,7 +302,8 @@ int cd_server_create(const cd_server_options* opt, cd_server** out);
  * its footprint exceeds the whole budget.  *ticket identifies it. */
 int cd_server_submit(cd_server* srv, const cd_problem* prob, const cd_options* opt, const double* b_dev,
                      double* x_dev, uint64_t* ticket);
-/* One scheduling step (blocks until the step's iterations finished). */
+/* One scheduling pass (see above); *n_active counts solves in set-up or
+ * iterating, *n_queued those not admitted yet. */
 int cd_server_step(cd_server* srv, int* n_active, int* n_queued);
 /* Move up to `max` finished solves into out[]; *n_out = how many. */
 int cd_server_poll(cd_server* srv, cd_completion* out, int max, int* n_out);

@@ -14,7 +14,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(HERE, "libcurldiv.so")
-SOURCES = ["csrc/setup.cpp", "csrc/kernels.hip", "csrc/coarse.hip", "csrc/solver.hip"]
+SOURCES = ["csrc/setup.cpp", "csrc/kernels.hip", "csrc/coarse.hip", "csrc/loadvec.hip", "csrc/solver.hip"]
 # the operator kernels: one object per (source, precision, half bandwidth)
 APPLY_SOURCES = ["csrc/apply2d.hip", "csrc/apply3d.hip"]
 APPLY_VARIANTS = [(t, hb) for t in ("double", "float") for hb in range(1, 7)]

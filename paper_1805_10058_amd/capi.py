@@ -91,6 +91,8 @@ SIGNATURES = {
     "cd_tsolve_f32": (_I, [_P, _P, _P]),
     "cd_tsolve_noalloc": (_I, [_P, _P, _P]),
     "cd_coarse_solve": (_I, [_P, _P, _P]),
+    "cd_load_vector": (_I, [_P, _P]),
+    "cd_l2_error": (_I, [_P, _P, ctypes.POINTER(ctypes.c_double)]),
     "cd_precondition": (_I, [_P, _P, _P]),
     "cd_profile_enable": (_I, [_P, _I]),
     "cd_profile_read": (_I, [_P, _I, _I, ctypes.POINTER(cd_kernel_stats)]),
@@ -256,6 +258,14 @@ class Solver:
 
     def tsolve_noalloc(self, v_ptr, z_ptr):
         check(lib().cd_tsolve_noalloc(self._h, ctypes.c_void_p(v_ptr), ctypes.c_void_p(z_ptr)))
+
+    def load_vector(self, b_ptr):
+        check(lib().cd_load_vector(self._h, ctypes.c_void_p(b_ptr)))
+
+    def l2_error(self, x_ptr):
+        e = ctypes.c_double()
+        check(lib().cd_l2_error(self._h, ctypes.c_void_p(x_ptr), ctypes.byref(e)))
+        return e.value
 
     def coarse_solve(self, r_ptr, z_ptr):
         check(lib().cd_coarse_solve(self._h, ctypes.c_void_p(r_ptr), ctypes.c_void_p(z_ptr)))

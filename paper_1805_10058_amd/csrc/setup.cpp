@@ -216,6 +216,34 @@ void assemble_1d(int n, int p, Band& M, Band& A, Band& S) {
     }
 }
 
+QuadAxis quad_axis(int n, int p, int q) {
+    if (p < 1 || p > kMaxP) throw std::runtime_error("degree out of range");
+    QuadAxis Qa;
+    Qa.n = n;
+    Qa.p = p;
+    Qa.q = q;
+    Qa.m = n + p - 2;
+    Qa.Q = n * q;
+    std::vector<double> gt, gw;
+    gauss_legendre(q, gt, gw);
+    const std::vector<double> xi = knots(n, p);
+    Qa.x.resize(Qa.Q);
+    Qa.w.resize(Qa.Q);
+    Qa.f0.resize(Qa.Q);
+    Qa.val.resize(size_t(Qa.Q) * (p + 1));
+    Qa.der.resize(size_t(Qa.Q) * (p + 1));
+    for (int e = 0; e < n; ++e) {
+        const double a = double(e) / n, h = 1.0 / n;
+        for (int t = 0; t < q; ++t) {
+            const int i = e * q + t;
+            Qa.x[i] = a + 0.5 * h * (gt[t] + 1.0);
+            Qa.w[i] = 0.5 * h * gw[t];
+            Qa.f0[i] = bspline_local(xi, p, Qa.x[i], &Qa.val[size_t(i) * (p + 1)], &Qa.der[size_t(i) * (p + 1)]) - 1;
+        }
+    }
+    return Qa;
+}
+
 Prolong knot_insertion(int nf, int p) {
     if (nf % 2) throw std::runtime_error("knot insertion needs an even number of intervals");
     const int nc = nf / 2;

@@ -57,6 +57,18 @@ Prolong identity_prolong(int m);
 // Galerkin product P^T X P.
 Band galerkin(const Band& X, const Prolong& P);
 
+// Quadrature tables of one axis: q-point Gauss-Legendre on each of the n
+// elements (Q = n q points in element order), and at every point the values
+// and first derivatives of the p+1 B-splines nonzero there; f0[a] is the
+// Dirichlet index (full index - 1, so -1 for the dropped first function) of
+// the first of them.
+struct QuadAxis {
+    int n = 0, p = 0, q = 0, m = 0, Q = 0;
+    std::vector<double> x, w, val, der;  // val[a*(p+1) + k], der[a*(p+1) + k]
+    std::vector<int> f0;
+};
+QuadAxis quad_axis(int n, int p, int q);
+
 // Banded LDL^T of T_m(m_{p-1}) (Sec. 6.1): L unit lower with half-bandwidth
 // p-1 stored as l[i*(p-1) + (k-1)] = L(i, i-k), and dinv[i] = 1/D(i).
 struct TFactor {

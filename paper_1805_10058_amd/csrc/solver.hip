@@ -14,9 +14,11 @@
 #include <cmath>
 #include <deque>
 #include <cstring>
+#include <condition_variable>
 #include <functional>
 #include <map>
 #include <mutex>
+#include <thread>
 #include <memory>
 #include <stdexcept>
 #include <string>
@@ -25,6 +27,7 @@
 #include "../../include/curldiv.h"
 #include "coarse.hpp"
 #include "kernels.hpp"
+#include "loadvec.hpp"
 #include "setup.hpp"
 
 // Static device workspace of cd_tsolve_noalloc, the entry point for callers
@@ -1304,7 +1307,9 @@ size_t cd_footprint_bytes(const cd_problem* pr, const cd_options* op) {
         vw += N * (2 * ks + 5);                             // V (ks+1), Z (ks), w, z, io_in, tmp
         total = (op->method == CD_METHOD_MIM ? 6 : 5) * N * 8  // outer r, z, d, q, iterate (MIM: and b)
                 + (op->method != CD_METHOD_CG ? vw * es : 0)  // V-cycle workspace
-                + size_t(cd::coarse_padded(tmp.Nc)) * cd::coarse_padded(tmp.Nc) * 8  // coarse inverse
+                + 2 * size_t(cd::coarse_padded(tmp.Nc)) * cd::coarse_padded(tmp.Nc) * 8  // coarse inverse and,
+                                                                       // during set-up, its factor
+                + (op->method != CD_METHOD_CG ? 4 * N * 8 : 0)      // set-up: Lanczos vectors
                 + (1 << 20);                                 // 1D tables and partial sums
     });
     return rc == CD_OK ? total : 0;
@@ -1489,6 +1494,64 @@ int cd_tsolve_noalloc(cd_solver* s, const double* v, double* z) {
     });
 }
 
+namespace {
+// Quadrature tables of the handle's axes on the device ((p+3)-point Gauss per element).
+struct QuadSet {
+    DevArena ar;
+    cd::QuadDev ax[3]{};
+};
+void make_quad(cd_solver* s, QuadSet& Q) {
+    const int q = s->p + 3;
+    for (int l = 0; l < 3; ++l) {
+        const int nl = (l < s->d) ? s->prob.n[l] : 1;
+        const cd::QuadAxis A = cd::quad_axis(nl, s->p, l < s->d ? q : 1);
+        cd::QuadDev& D = Q.ax[l];
+        D.x = Q.ar.upload(A.x, s->stream);
+        D.w = Q.ar.upload(A.w, s->stream);
+        D.val = Q.ar.upload(A.val, s->stream);
+        D.der = Q.ar.upload(A.der, s->stream);
+        D.f0 = Q.ar.upload(A.f0, s->stream);
+        D.n = A.n;
+        D.p = A.p;
+        D.q = A.q;
+        D.m = A.m;
+        D.Q = A.Q;
+    }
+}
+}  // namespace
+
+int cd_load_vector(cd_solver* s, double* b) {
+    return run([&] {
+        need(s);
+        if (!b) throw CdError(CD_EINVAL, "null vector");
+        enter(s);
+        QuadSet Q;
+        make_quad(s, Q);
+        double* work = Q.ar.alloc<double>(cd::load_vector_work(s->d, Q.ax));
+        cd::launch_load_vector(s->d, Q.ax, s->prob.alpha, s->prob.beta, b, work, s->stream);
+        hip_check(hipStreamSynchronize(s->stream), "sync");
+    });
+}
+
+int cd_l2_error(cd_solver* s, const double* x, double* err) {
+    return run([&] {
+        need(s);
+        if (!x || !err) throw CdError(CD_EINVAL, "null argument");
+        enter(s);
+        QuadSet Q;
+        make_quad(s, Q);
+        double* work = Q.ar.alloc<double>(cd::l2_error_work(s->d, Q.ax));
+        const int np = 1024;
+        double* part = Q.ar.alloc<double>(np + 1);
+        cd::launch_l2_error(s->d, Q.ax, x, work, part, np, s->stream);
+        cd::launch_finalize(part, np, part + np, s->stream);
+        double h = 0.0;
+        hip_check(hipMemcpyAsync(&h, part + np, sizeof(double), hipMemcpyDeviceToHost, s->stream), "read");
+        hip_check(hipStreamSynchronize(s->stream), "sync");
+        *err = std::sqrt(h);
+    });
+}
+
 int cd_coarse_solve(cd_solver* s, const double* r, double* z) {
     return run([&] {
         need(s);
@@ -1576,33 +1639,105 @@ int cd_profile_read_tsolve(const cd_solver* s, int fp32, cd_kernel_stats* out) {
 // =============================== serving loop ===============================
 struct cd_server {
     cd_server_options opt{};
-    std::vector<hipStream_t> streams;
+    std::vector<hipStream_t> streams;  // num_streams > 0: a fixed pool shared round robin
+    std::vector<hipStream_t> free_streams;  // num_streams == 0: one stream per active solve, reused
+    int streams_made = 0;
     struct Req {
-        uint64_t ticket;
-        cd_problem prob;
-        cd_options opt;
-        const double* b;
-        double* x;
-        size_t fp;
-        double t_submit, t_admit;
-        cd_solver* solver;
+        uint64_t ticket = 0;
+        cd_problem prob{};
+        cd_options opt{};
+        const double* b = nullptr;
+        double* x = nullptr;
+        size_t fp = 0;
+        double t_submit = 0, t_admit = 0;
+        cd_solver* solver = nullptr;
+        hipStream_t stream = nullptr;
+        bool own_stream = false;
+        int setup_rc = CD_OK;        // result of the set-up on the worker
+        cd_result early{};          // the result when the set-up already finished the solve
+        bool finished_early = false;
+        bool in_flight = false;     // an outer iteration is enqueued
     };
-    std::deque<Req> queue;
-    std::vector<Req> active;
+    std::deque<std::unique_ptr<Req>> queue;       // submitted, not admitted
+    std::vector<std::unique_ptr<Req>> iterating;  // set up, iterating
     std::deque<cd_completion> done;
-    size_t used = 0;
+    size_t used = 0;  // footprint of the admitted requests
+    int in_setup = 0;
     uint64_t next_ticket = 1;
     uint64_t admitted = 0;
     std::chrono::steady_clock::time_point t0;
     double now() const { return std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count(); }
+
+    // Set-up worker: creates the solvers of admitted requests (host set-up,
+    // uploads, coarse factorisation, eigenvalue bounds, first residual) and
+    // destroys retired ones, on its own thread, so that the scheduling thread
+    // keeps the running solves fed meanwhile.
+    std::thread worker;
+    std::mutex mu;
+    std::condition_variable cv;
+    std::deque<Req*> setup_todo;
+    std::deque<Req*> setup_done;
+    std::deque<cd_solver*> destroy_todo;
+    bool stop = false;
+
+    void work() {
+        for (;;) {
+            Req* r = nullptr;
+            cd_solver* dead = nullptr;
+            {
+                std::unique_lock<std::mutex> lk(mu);
+                cv.wait(lk, [&] { return stop || !setup_todo.empty() || !destroy_todo.empty(); });
+                if (!destroy_todo.empty()) {
+                    dead = destroy_todo.front();
+                    destroy_todo.pop_front();
+                } else if (!setup_todo.empty()) {
+                    r = setup_todo.front();
+                    setup_todo.pop_front();
+                } else {
+                    return;  // stop requested and nothing left
+                }
+            }
+            if (dead) {
+                cd_solver_destroy(dead);
+                continue;
+            }
+            cd_solver* h = nullptr;
+            r->setup_rc = cd_solver_create(&r->prob, &r->opt, r->stream, &h);
+            if (r->setup_rc == CD_OK) {
+                r->solver = h;
+                r->setup_rc = run([&] {
+                    solve_begin(h, r->b, r->x);
+                    if (h->state.done) {  // zero right-hand side: x = 0
+                        r->early = solve_finish(h);
+                        r->finished_early = true;
+                    }
+                });
+            }
+            std::lock_guard<std::mutex> lk(mu);
+            setup_done.push_back(r);
+        }
+    }
+
     ~cd_server() {
-        for (auto& r : active) cd_solver_destroy(r.solver);
+        {
+            std::lock_guard<std::mutex> lk(mu);
+            stop = true;
+        }
+        cv.notify_all();
+        if (worker.joinable()) worker.join();
+        for (auto& r : iterating)
+            if (r->solver) cd_solver_destroy(r->solver);
+        for (Req* r : setup_done) {  // the worker has drained its queues before it returned
+            if (r->solver) cd_solver_destroy(r->solver);
+            delete r;
+        }
         for (hipStream_t st : streams) (void)hipStreamDestroy(st);
+        for (hipStream_t st : free_streams) (void)hipStreamDestroy(st);
     }
 };
 
 namespace {
-void server_complete(cd_server* srv, cd_server::Req& r, const cd_result& res) {
+void server_complete(cd_server* srv, const cd_server::Req& r, const cd_result& res) {
     cd_completion c{};
     c.ticket = r.ticket;
     c.result = res;
@@ -1612,13 +1747,45 @@ void server_complete(cd_server* srv, cd_server::Req& r, const cd_result& res) {
     c.footprint_bytes = r.fp;
     srv->done.push_back(c);
 }
+
+hipStream_t server_take_stream(cd_server* srv, bool* own) {
+    if (!srv->streams.empty()) {
+        *own = false;
+        return srv->streams[srv->admitted % srv->streams.size()];
+    }
+    *own = true;
+    if (!srv->free_streams.empty()) {
+        hipStream_t st = srv->free_streams.back();
+        srv->free_streams.pop_back();
+        return st;
+    }
+    hipStream_t st = nullptr;
+    hip_check(hipStreamCreateWithFlags(&st, hipStreamNonBlocking), "hipStreamCreate");
+    ++srv->streams_made;
+    return st;
+}
+
+// Give a request's resources back (its solver goes to the worker for destruction).
+void server_release(cd_server* srv, cd_server::Req& r) {
+    if (r.solver) {
+        {
+            std::lock_guard<std::mutex> lk(srv->mu);
+            srv->destroy_todo.push_back(r.solver);
+        }
+        srv->cv.notify_one();
+        r.solver = nullptr;
+    }
+    if (r.own_stream && r.stream) srv->free_streams.push_back(r.stream);
+    r.stream = nullptr;
+    srv->used -= r.fp;
+}
 }  // namespace
 
 void cd_server_default_options(cd_server_options* o) {
     if (!o) return;
     o->hbm_budget_bytes = 0;
     o->max_active = 64;
-    o->num_streams = 4;
+    o->num_streams = 0;
 }
 
 int cd_server_create(const cd_server_options* opt, cd_server** out) {
@@ -1634,8 +1801,7 @@ int cd_server_create(const cd_server_options* opt, cd_server** out) {
         cd_server_default_options(&o);
         if (opt) o = *opt;
         if (o.max_active <= 0) o.max_active = 64;
-        if (o.num_streams <= 0) o.num_streams = 4;
-        if (o.num_streams > 16) throw CdError(CD_EINVAL, "num_streams must be <= 16");
+        if (o.num_streams < 0 || o.num_streams > 64) throw CdError(CD_EINVAL, "num_streams must be in 0..64");
         if (o.hbm_budget_bytes == 0) {
             size_t fr = 0, tot = 0;
             hip_check(hipMemGetInfo(&fr, &tot), "hipMemGetInfo");
@@ -1648,6 +1814,7 @@ int cd_server_create(const cd_server_options* opt, cd_server** out) {
             srv->streams.push_back(st);
         }
         srv->t0 = std::chrono::steady_clock::now();
+        srv->worker = std::thread([srv] { srv->work(); });
     });
     if (rc != CD_OK) {
         delete srv;
@@ -1665,70 +1832,106 @@ int cd_server_submit(cd_server* srv, const cd_problem* prob, const cd_options* o
         validate(prob, opt);
         const size_t fp = cd_footprint_bytes(prob, opt);
         if (fp == 0 || fp > srv->opt.hbm_budget_bytes) throw CdError(CD_ENOMEM, "request larger than the server's HBM budget");
-        cd_server::Req r{};
-        r.ticket = srv->next_ticket++;
-        r.prob = *prob;
-        r.opt = *opt;
-        r.b = b;
-        r.x = x;
-        r.fp = fp;
-        r.t_submit = srv->now();
-        r.solver = nullptr;
-        srv->queue.push_back(r);
-        if (ticket) *ticket = r.ticket;
+        auto r = std::make_unique<cd_server::Req>();
+        r->ticket = srv->next_ticket++;
+        r->prob = *prob;
+        r->opt = *opt;
+        r->b = b;
+        r->x = x;
+        r->fp = fp;
+        r->t_submit = srv->now();
+        if (ticket) *ticket = r->ticket;
+        srv->queue.push_back(std::move(r));
     });
 }
 
 int cd_server_step(cd_server* srv, int* n_active, int* n_queued) {
     return run([&] {
         if (!srv) throw CdError(CD_EINVAL, "null server");
-        // admission: FIFO, by footprint and slot count
-        while (!srv->queue.empty() && int(srv->active.size()) < srv->opt.max_active &&
-               srv->used + srv->queue.front().fp <= srv->opt.hbm_budget_bytes) {
-            cd_server::Req r = srv->queue.front();
+        bool progress = false;
+        // 1. solvers the worker has set up: start iterating (or complete)
+        std::deque<cd_server::Req*> ready;
+        {
+            std::lock_guard<std::mutex> lk(srv->mu);
+            ready.swap(srv->setup_done);
+        }
+        for (cd_server::Req* rp : ready) {
+            std::unique_ptr<cd_server::Req> r(rp);
+            --srv->in_setup;
+            progress = true;
+            if (r->setup_rc == CD_ENOMEM && r->solver == nullptr &&
+                (!srv->iterating.empty() || srv->in_setup > 0)) {
+                // the device could not hold it next to the running solves: back to
+                // the head of the queue, admitted again when they have retired
+                server_release(srv, *r);
+                srv->queue.push_front(std::move(r));
+                continue;
+            }
+            if (r->setup_rc != CD_OK || r->finished_early) {
+                cd_result res = r->early;
+                if (r->setup_rc != CD_OK) res.status = r->setup_rc;
+                server_complete(srv, *r, res);
+                server_release(srv, *r);
+                continue;
+            }
+            solve_iterate(r->solver);
+            r->in_flight = true;
+            srv->iterating.push_back(std::move(r));
+        }
+        // 2. admission: FIFO, by footprint and slot count; the set-up runs on the worker
+        while (!srv->queue.empty() && int(srv->iterating.size()) + srv->in_setup < srv->opt.max_active &&
+               srv->used + srv->queue.front()->fp <= srv->opt.hbm_budget_bytes) {
+            std::unique_ptr<cd_server::Req> r = std::move(srv->queue.front());
             srv->queue.pop_front();
-            r.t_admit = srv->now();
-            hipStream_t st = srv->streams[srv->admitted++ % srv->streams.size()];
-            cd_solver* h = nullptr;
-            const int rc = cd_solver_create(&r.prob, &r.opt, st, &h);
-            if (rc != CD_OK) {
-                cd_result res{};
-                res.status = rc;
-                server_complete(srv, r, res);
-                continue;
+            r->t_admit = srv->now();
+            r->stream = server_take_stream(srv, &r->own_stream);
+            ++srv->admitted;
+            srv->used += r->fp;
+            ++srv->in_setup;
+            {
+                std::lock_guard<std::mutex> lk(srv->mu);
+                srv->setup_todo.push_back(r.release());
             }
-            r.solver = h;
-            cd_result res0{};
-            const int rb = run([&] {
-                solve_begin(h, r.b, r.x);
-                if (h->state.done) res0 = solve_finish(h);  // zero right-hand side: x = 0
-            });
-            if (rb != CD_OK || h->state.done) {
-                if (rb != CD_OK) res0.status = rb;
-                server_complete(srv, r, res0);
-                cd_solver_destroy(h);
-                continue;
-            }
-            srv->used += r.fp;
-            srv->active.push_back(r);
+            srv->cv.notify_one();
+            progress = true;
         }
-        // one outer iteration of every active solve, all enqueued before any wait
-        for (auto& r : srv->active) solve_iterate(r.solver);
-        std::vector<cd_server::Req> keep;
-        keep.reserve(srv->active.size());
-        for (auto& r : srv->active) {
-            hip_check(hipEventSynchronize(r.solver->iter_event), "hipEventSynchronize");
-            if (solve_check(r.solver)) {
-                const cd_result res = solve_finish(r.solver);
-                server_complete(srv, r, res);
-                cd_solver_destroy(r.solver);
-                srv->used -= r.fp;
-            } else {
-                keep.push_back(r);
+        // 3. every solve whose last outer iteration has finished: stopping test,
+        //    then retire it or enqueue its next iteration; the others keep running
+        auto pass = [&] {
+            bool any = false;
+            std::vector<std::unique_ptr<cd_server::Req>> keep;
+            keep.reserve(srv->iterating.size());
+            for (auto& r : srv->iterating) {
+                const hipError_t q = hipEventQuery(r->solver->iter_event);
+                if (q == hipErrorNotReady) {
+                    keep.push_back(std::move(r));
+                    continue;
+                }
+                hip_check(q, "hipEventQuery");
+                any = true;
+                if (solve_check(r->solver)) {
+                    const cd_result res = solve_finish(r->solver);
+                    server_complete(srv, *r, res);
+                    server_release(srv, *r);
+                } else {
+                    solve_iterate(r->solver);
+                    keep.push_back(std::move(r));
+                }
+            }
+            srv->iterating.swap(keep);
+            return any;
+        };
+        progress = pass() || progress;
+        // nothing changed: wait briefly for the next iteration or set-up to finish
+        for (int spin = 0; !progress && spin < 200 && (!srv->iterating.empty() || srv->in_setup > 0); ++spin) {
+            std::this_thread::sleep_for(std::chrono::microseconds(5));
+            progress = pass();
+            if (!progress) {
+                std::lock_guard<std::mutex> lk(srv->mu);
+                progress = !srv->setup_done.empty();
             }
         }
-        srv->active.swap(keep);
-        if (n_active) *n_active = int(srv->active.size());
+        if (n_active) *n_active = int(srv->iterating.size()) + srv->in_setup;
         if (n_queued) *n_queued = int(srv->queue.size());
     });
 }
