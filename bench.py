@@ -25,6 +25,34 @@ HBM_PEAK_GBS = 8000.0
 PROF_PERIOD = 8  # outer iterations per timed one in the timed region
 HEADLINE = "c4_3d_p3_n128"
 
+# HBM-side traffic per launch of the level-0 FP32 Chebyshev step at the
+# headline workload: rocprofv3 FETCH_SIZE x 2.000 + WRITE_SIZE x 1.000 (KiB
+# per dispatch, factors from a 256 MiB copy) in runs of
+# `bench.py --pmc-pass --copy-cal`, summarised with the commands in
+# profiles/c4_3d_p3_n128_solve_kernels.txt.  It holds only for the kernel
+# sources it was measured on (their SHA-256 below); after any change to them
+# the line reports null until the counters are taken again.
+CHEB_TRAFFIC = {"fetch_kib": 68922.3, "write_kib": 29750.1, "fetch_factor": 2.000, "write_factor": 1.000,
+                "sources": ["paper_1805_10058_amd/csrc/apply3d.hip", "paper_1805_10058_amd/csrc/apply_common.hpp"],
+                "sha256": "02fbdea0f590f6e8bacb267fd7369a56e2af26ab38aa626964c6e701e44e7fa5"}
+
+
+def cheb_traffic_bytes():
+    """Counted HBM bytes per launch of the roofline kernel, or None when its
+    sources differ from those the counters were taken on."""
+    import hashlib
+    h = hashlib.sha256()
+    try:
+        for f in CHEB_TRAFFIC["sources"]:
+            with open(os.path.join(ROOT, f), "rb") as fh:
+                h.update(fh.read())
+    except OSError:
+        return None
+    if h.hexdigest() != CHEB_TRAFFIC["sha256"]:
+        return None
+    c = CHEB_TRAFFIC
+    return 1024.0 * (c["fetch_kib"] * c["fetch_factor"] + c["write_kib"] * c["write_factor"])
+
 
 def percentile(v, q):
     v = sorted(v)
@@ -195,7 +223,10 @@ def headline(capi, torch, st, steps, warmup):
                                   "rel. residual 1e-8, and the forward error of each is at most kappa_2(A) times "
                                   "its residual"},
         "roofline": {"bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": ach / HBM_PEAK_GBS, "traffic": None,
+                     "frac": ach / HBM_PEAK_GBS, "traffic": cheb_traffic_bytes(),
+                     "traffic_note": "HBM-side bytes per launch from rocprofv3 FETCH_SIZE/WRITE_SIZE runs on the "
+                                     "same kernel sources, calibrated by a 256 MiB copy (null: sources changed "
+                                     "since)",
                      "kernel": "FP32 Chebyshev-step operator apply k_apply3d<float,3,2> on level 0, inside the timed "
                                f"solves (every {PROF_PERIOD}th outer iteration timed by the kernel's own stamps)",
                      "bytes_per_unit": "4 N s per step (read x_k, x_{k-1}, b; write x_{k+1}), N = 6,440,067, s = 4",

@@ -131,7 +131,10 @@ typedef struct {
     double kappa_estimate;      /* Lanczos estimate of the condition number (see above) */
 } cd_result;
 
-/* Number of unknowns d * prod_l (n_l + p - 2); 0 for an invalid problem. */
+/* Number of unknowns of the system: d components (Sec. 4.1 for d = 2,
+ * Sec. 4.2 for d = 3), each the tensor-product spline space with homogeneous
+ * Dirichlet conditions of Sec. 3.1, n_l + p - 2 functions along axis l:
+ * d * prod_l (n_l + p - 2).  0 for an invalid problem (no error code). */
 size_t cd_num_dofs(const cd_problem* prob);
 
 /* CD_OK if (prob, opt) is a valid combination, else CD_EINVAL. */
@@ -145,10 +148,14 @@ size_t cd_footprint_bytes(const cd_problem* prob, const cd_options* opt);
 /* ---- solver handle ----------------------------------------------------- */
 typedef struct cd_solver cd_solver;
 
-/* Set up the hierarchy on the host in FP64 (1D matrices by Gauss
- * quadrature, transfers, Galerkin coarse 1D matrices, banded LDL^T of
- * T_m(m_{p-1}), dense coarse matrix) and on the device (eigenvalue bounds of
- * the smoother, inverse of the coarse matrix).  `stream` is a hipStream_t;
+/* Set up the hierarchy on the host in FP64 (1D matrices M, A, S of
+ * Sec. 3.2 by Gauss quadrature, the prolongators of Sec. 6.1, Galerkin coarse
+ * 1D matrices, banded LDL^T of T_m(m_{p-1}) of Sec. 6.1) and on the device
+ * (dense coarse matrix, its Cholesky factor and inverse, eigenvalue bounds of
+ * the smoother).  *out receives the handle (owned by the caller, released by
+ * cd_solver_destroy); on error *out is NULL and the code is CD_EINVAL (an
+ * invalid problem or option, see cd_validate), CD_ENOMEM (device memory) or
+ * CD_EHIP (another HIP error).  `stream` is a hipStream_t;
  * all later work of the handle is queued on it.  With NULL the handle
  * creates its own non-blocking stream and orders it after the null stream at
  * every entry point (outer iterations are replayed from HIP graphs, which
@@ -178,7 +185,15 @@ int cd_get_matrix(const cd_solver* s, int level, int axis, char which, double* h
  * lanczos_steps Lanczos steps on diag(A_l)^{-1} A_l. */
 int cd_get_lambda(const cd_solver* s, int level, double* lam);
 
-/* y = A_level x in FP64 (level 0 is the system matrix). */
+/* y = A_level x in FP64.  Level 0 is the system matrix of Sec. 4.1 (2D) /
+ * Sec. 4.2 (3D), the block matrix of Kronecker products of the 1D matrices
+ * (for CD_METHOD_PWL the V-cycle's operator, the block-diagonal part D of
+ * Sec. 6.1 eq. diag, on every level; the outer iteration of that method
+ * still multiplies by the full matrix); level l > 0 is the Galerkin operator
+ * P^T A_{l-1} P of the same form.  x_dev, y_dev: device arrays of the level's
+ * unknown count (cd_level_shape), component-major, each component row-major
+ * with the last axis fastest; they must not overlap.  CD_EINVAL for a level
+ * out of range.  Ordered on the handle's stream; blocks until done. */
 int cd_apply(cd_solver* s, int level, const double* x_dev, double* y_dev);
 /* y = A_level x in FP32 with FP32 coefficients. */
 int cd_apply_f32(cd_solver* s, int level, const float* x_dev, float* y_dev);
@@ -228,8 +243,12 @@ int cd_load_vector(cd_solver* s, double* b_dev);
 int cd_l2_error(cd_solver* s, const double* x_dev, double* err);
 /* z = A_L^{-1} r on the coarsest level, FP64. */
 int cd_coarse_solve(cd_solver* s, const double* r_dev, double* z_dev);
-/* z = one application of the preconditioner (one V-cycle, in the handle's
- * precision) to r. */
+/* z = one application of the preconditioner to r: one V-cycle of the
+ * multi-iterative method of Sec. 6.1 (Chebyshev pre- and post-smoothing on
+ * every level, the Krylov post-smoother with the T preconditioner on the
+ * finest level, the exact coarse solve), in the handle's precision, from a
+ * zero start.  r_dev, z_dev: device arrays of cd_num_dofs doubles; they may
+ * not overlap.  Blocks until done. */
 int cd_precondition(cd_solver* s, const double* r_dev, double* z_dev);
 
 /* ---- live kernel timing ------------------------------------------------- */

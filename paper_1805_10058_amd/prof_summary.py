@@ -6,8 +6,8 @@ DIR is a rocprofv3 output directory written with ``--output-format csv``.
 Prints, per kernel, the dispatch count and average duration from
 ``*kernel_stats.csv`` and, when ``*counter_collection.csv`` files are present
 (``--pmc`` runs), the average of every collected counter per dispatch.  With
-``--by-grid`` the dispatches of ``*kernel_trace.csv`` are split by grid size,
-which separates the levels of the multigrid hierarchy.
+``--by-grid`` the dispatches of ``*kernel_trace.csv`` and the counters are
+split by grid size, which separates the levels of the multigrid hierarchy.
 """
 import argparse
 import collections
@@ -43,11 +43,14 @@ def by_grid(d):
                   key=lambda t: -t[4])
 
 
-def counters(d):
+def counters(d, split_grid=False):
     acc = collections.defaultdict(lambda: collections.defaultdict(list))
     for f in glob.glob(os.path.join(d, "**", "*counter_collection.csv"), recursive=True):
         for r in csv.DictReader(open(f)):
-            key = (_short(r.get("Kernel_Name", r.get("Kernel-Name", "?"))), r["Counter_Name"])
+            name = _short(r.get("Kernel_Name", r.get("Kernel-Name", "?")))
+            if split_grid:
+                name = f"{name} grid {r.get('Grid_Size', '?')}"
+            key = (name, r["Counter_Name"])
             acc[key][r.get("Dispatch_Id", r.get("Correlation_Id", ""))].append(float(r["Counter_Value"]))
     res = {}
     for key, per_dispatch in acc.items():
@@ -74,7 +77,7 @@ def main():
         print(f"{'kernel':90s} {'calls':>7s} {'avg_us':>9s} {'total_ms':>9s} {'pct':>6s}")
         for name, calls, avg, tot, pct in ks[:a.top]:
             print(f"{name[:90]:90s} {calls:7d} {avg:9.2f} {tot:9.2f} {pct:6.2f}")
-    cs = counters(a.dir)
+    cs = counters(a.dir, a.by_grid)
     if cs:
         print(f"{'kernel':90s} {'counter':>12s} {'dispatches':>10s} {'avg/dispatch':>14s}")
         for (name, cn), (nd, avg) in sorted(cs.items(), key=lambda kv: (-kv[1][1] * kv[1][0])):
