@@ -32,9 +32,9 @@ HEADLINE = "c4_3d_p3_n128"
 # profiles/c4_3d_p3_n128_solve_kernels.txt.  It holds only for the kernel
 # sources it was measured on (their SHA-256 below); after any change to them
 # the line reports null until the counters are taken again.
-CHEB_TRAFFIC = {"fetch_kib": 68922.3, "write_kib": 29750.1, "fetch_factor": 2.000, "write_factor": 1.000,
+CHEB_TRAFFIC = {"fetch_kib": 71327.2, "write_kib": 30512.6, "fetch_factor": 2.000, "write_factor": 1.000,
                 "sources": ["paper_1805_10058_amd/csrc/apply3d.hip", "paper_1805_10058_amd/csrc/apply_common.hpp"],
-                "sha256": "02fbdea0f590f6e8bacb267fd7369a56e2af26ab38aa626964c6e701e44e7fa5"}
+                "sha256": "2e82bb677ad8f838b13f0d2efef99d984ee54c91477e70bf07355af6b3276b6f"}
 
 
 def cheb_traffic_bytes():

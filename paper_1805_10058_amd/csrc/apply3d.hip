@@ -8,37 +8,47 @@ namespace {
 // ------------------------------------------------------------------------------
 // 3D operator apply.
 //
-// A block of 32 TR threads owns an output tile of TR x (32 - 2HB) columns of
-// the (x2, x3) plane (one output column per thread; the other threads only
-// help with loads and stage A) and the output planes x1 in [o0, o1); it
-// marches over the input planes t = 0, 1, ... (x1 = o0 - HB + t) up to
-// o1 + HB.  Per input plane j:
-//   (A) contract axis 2 (stride m3): M2 x, A2 x, S2 x of the three components
-//       at one position per thread: the tile rows times all 32 tile columns
-//       (LDS tile of the plane with a +-HB halo on both in-plane axes);
-//   (B) contract axis 3 at the thread's column and combine the raw products
-//       with alpha, beta, alpha-beta into W[c][{S,M,A}], the inputs of the
-//       axis-1 contraction of output component c;
-//   (C) scatter W into a ring of 2HB+1 per-plane accumulators in registers:
-//       acc(i) += X1(i, j) W for i in [j-HB, j+HB].
-// After plane j the accumulator of output plane j-HB is complete and goes
+// A block of 32 TR threads (TR/2 waves) owns an output tile of TR rows (x2) by
+// 32 - 2HB columns (x3) of the (x2, x3) plane and the output planes x1 in
+// [o0, o1); it marches over the input planes t = 0, 1, ... (x1 = o0 - HB + t)
+// up to o1 + HB.  Thread (ty, tx) sits at grid row o2 + ty and column
+// o3 - HB + tx: a wave holds two tile rows of 32 columns, of which the middle
+// 32 - 2HB are output columns and the HB on each side their halo.  Per input
+// plane j:
+//   (A) contract axis 2 (rows) at the thread's point: M2 x, A2 x, S2 x of the
+//       three components from the plane's input tile in LDS (rows with a +-HB
+//       halo), with the thread's row of the axis-2 bands in registers (FP32;
+//       in LDS for FP64, whose registers are scarcer);
+//   (B) contract axis 3 (columns): the 2HB + 1 neighbours of a column sit in
+//       the neighbouring lanes of the same wave, and whole-wave lane shifts
+//       (DPP) bring them in, so this stage touches no memory; lanes whose
+//       shifts cross from one tile row into the other are halo lanes, whose
+//       results are discarded.  The raw products combine with alpha, beta and
+//       alpha - beta into W[c][{S, M, A}], the inputs of the axis-1
+//       contraction of output component c;
+//   (C) scatter W into a ring of 2HB + 1 per-plane accumulators in registers:
+//       acc(i) += X1(i, j) W for i in [j - HB, j + HB], with the axis-1
+//       coefficients of plane j (a row of the level's table: X1(j - HB + k, j)
+//       for the three 1D matrices and the diagonal entries of plane j - HB)
+//       read through block-uniform addresses, i.e. into scalar registers.
+// After plane j the accumulator of output plane j - HB is complete and goes
 // through the epilogue.  33 band contractions per point.
 //
-// Software pipeline, one barrier per plane: phase t runs stage A of plane
-// t+1 and stage B of plane t (independent work for the scheduler), stores the
-// prefetched plane t+2 into the input buffer plane t has vacated, and issues
-// the loads of plane t+3.  Input tiles and stage-A results are double
-// buffered in LDS.  The axis-1 coefficients of plane j (the row of the
-// level's table: X1(j-HB+k, j) and the diagonal of plane j-HB) travel with
-// the plane's loads into a ring of 4 rows, so the row a phase reads is never
-// the one a faster wave overwrites in the same phase.  In FP32 the operands
-// of the epilogue (b, x, the previous iterate) are loaded one phase before
-// their plane is emitted; in FP64, whose registers allow fewer waves, at the
-// start of that phase.  The Chebyshev step's diagonal comes from per-thread
-// in-plane factors and the plane's diagonal entries in the table row.
+// Memory: every global access goes through a buffer descriptor of one plane of
+// one component (base and size in scalar registers, built per plane), with a
+// per-thread byte offset fixed for the whole march.  Tile entries outside the
+// grid and the output lanes that are not output points carry an offset past
+// the descriptor's range: their loads return zero and their stores are
+// dropped, with no per-thread address arithmetic or branches.  The loads of
+// plane t + 3 are issued while plane t is computed and stored into LDS in the
+// phase after (double-buffered input tiles, one barrier per plane); the
+// epilogue operands of the next output plane are loaded right after the
+// current one is written.  The Chebyshev step's diagonal comes from per-thread
+// in-plane factors and the plane's diagonal entries in the table row; FP32
+// divides by it through the hardware reciprocal.
 //
 // Accumulator slots: the accumulator of output plane i lives in slot
-// (i - o0 + 2HB + 1) mod (2HB+1).  Every phase reads and clears the slot of
+// (i - o0 + 2HB + 1) mod (2HB + 1).  Every phase reads and clears the slot of
 // the plane it completes, emitted or not, so slots need no range checks: a
 // plane's slot is cleared one phase before its first contribution.
 //
@@ -47,24 +57,54 @@ namespace {
 // different XCDs, so this keeps spatially adjacent tiles, whose halos overlap,
 // on the same XCD and its L2.
 // ------------------------------------------------------------------------------
+constexpr int kDppShl1 = 0x130;         // DPP wave_shl:1, lane l reads lane l + 1
+constexpr int kDppShr1 = 0x138;         // DPP wave_shr:1, lane l reads lane l - 1
+constexpr unsigned kOob = 0xFFFFFFF0u;  // a byte offset past every plane descriptor's range
+constexpr int kRsrcWord3 = 0x00020000;  // descriptor word 3: 32-bit elements, no swizzle
+
+// whole-wave lane shifts; lanes past either end of the wave read zero
+template <int CTRL>
+__device__ inline float lane_shift(float v) {
+    return __builtin_bit_cast(float, __builtin_amdgcn_mov_dpp(__builtin_bit_cast(int, v), CTRL, 0xF, 0xF, true));
+}
+template <int CTRL>
+__device__ inline double lane_shift(double v) {
+    const unsigned long long u = __builtin_bit_cast(unsigned long long, v);
+    const unsigned lo = unsigned(__builtin_amdgcn_mov_dpp(int(unsigned(u)), CTRL, 0xF, 0xF, true));
+    const unsigned hi = unsigned(__builtin_amdgcn_mov_dpp(int(unsigned(u >> 32)), CTRL, 0xF, 0xF, true));
+    return __builtin_bit_cast(double, (static_cast<unsigned long long>(hi) << 32) | lo);
+}
+
+// raw buffer access: offsets at or past `bytes` read zero and drop stores
+__device__ inline __amdgpu_buffer_rsrc_t make_rsrc(const void* base, unsigned bytes) {
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(base), (short)0, int(bytes), kRsrcWord3);
+}
+__device__ inline float buf_load(__amdgpu_buffer_rsrc_t r, unsigned off, float) {
+    return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, off, 0, 0));
+}
+__device__ inline double buf_load(__amdgpu_buffer_rsrc_t r, unsigned off, double) {
+    return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, off, 0, 0));
+}
+__device__ inline void buf_store(float v, __amdgpu_buffer_rsrc_t r, unsigned off) {
+    __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, v), r, off, 0, 0);
+}
+__device__ inline void buf_store(double v, __amdgpu_buffer_rsrc_t r, unsigned off) {
+    using u2 = unsigned __attribute__((ext_vector_type(2)));
+    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u2, v), r, off, 0, 0);
+}
+
 template <typename T, int HB>
 struct Tile3 {
-    static constexpr int TR = k3Rows<T>();  // tile rows (x2)
-    static constexpr int NT = TR * k3E3;    // threads: one stage-A position each
+    static constexpr int TR = k3Rows<T>();          // tile rows (x2)
+    static constexpr int NT = TR * k3E3;            // threads: one point of the tile rows each
     static constexpr int R = 2 * HB + 1;
-    static constexpr int E2 = TR + 2 * HB;  // input rows with the x2 halo
-    static constexpr int NIN = E2 * k3E3;   // input tile of one component
-    static constexpr int NX = 3 * NIN;      // input tile of a plane
-    static constexpr int NLX = (NX + NT - 1) / NT;
-    static constexpr int NC = 3 * R + 2;    // axis-1 table row
-    static constexpr size_t lds_words() {
-        return 2 * size_t(NX) + 2 * 9 * size_t(NT) + 3 * size_t(R) * TR + 4 * size_t(NC);
-    }
-};
-
-template <typename T>
-struct Epi3 {
-    T b[3], x[3], xp[3];
+    static constexpr int E2 = TR + 2 * HB;          // input rows with the x2 halo
+    static constexpr int NIN = E2 * k3E3;           // input tile of one component
+    static constexpr int NX = 3 * NIN;              // input tile of a plane
+    static constexpr int NLC = (NIN + NT - 1) / NT; // tile loads per thread and component
+    static constexpr int NC = 3 * R + 2;            // axis-1 table row
+    static constexpr bool CAREG = sizeof(T) == 4;   // axis-2 band rows in registers
+    static constexpr size_t lds_words() { return 2 * size_t(NX) + (CAREG ? 0 : 3 * size_t(R) * TR); }
 };
 
 template <typename T, int HB, int MODE>
@@ -72,16 +112,14 @@ __global__ __launch_bounds__(k3Rows<T>() * k3E3) void k_apply3d(OpDev<T> op, con
                                                                T* __restrict__ y, const T* __restrict__ b,
                                                                const T* xprev, T* xout, T c1, T c2,
                                                                double* __restrict__ part, int nv, Apply3dGeom g,
-                                                               unsigned long long* stamp) {
+                                                               unsigned long long* stamp, const T* __restrict__ c1g) {
     using Q = Tile3<T, HB>;
     constexpr int TR = Q::TR, NT = Q::NT, R = Q::R, E3 = k3E3, T3 = k3T3(HB);
-    constexpr int NIN = Q::NIN, NX = Q::NX, NLX = Q::NLX, NC = Q::NC, NA = NT;
+    constexpr int NIN = Q::NIN, NX = Q::NX, NLC = Q::NLC, NC = Q::NC;
+    constexpr unsigned S = sizeof(T);
     stamp_begin(stamp);
     extern __shared__ __align__(16) unsigned char smem_raw[];
     T* xs = reinterpret_cast<T*>(smem_raw);  // [2][3][E2][E3] input tiles
-    T* st = xs + 2 * NX;                     // [2][9][TR][E3]: M2x A2x S2x of components 0, 1, 2
-    T* ca = st + 2 * 9 * NA;                 // [3][R][TR] axis-2 band rows of the tile
-    T* rows = ca + 3 * R * TR;               // [4][NC] ring of axis-1 table rows
     const int m1 = op.m[0], m2 = op.m[1], m3 = op.m[2];
     const unsigned PL = unsigned(m2) * m3, G = unsigned(m1) * PL;
     const int xcd = int(blockIdx.x % kXcds), slot = int(blockIdx.x / kXcds);
@@ -92,26 +130,33 @@ __global__ __launch_bounds__(k3Rows<T>() * k3E3) void k_apply3d(OpDev<T> op, con
     const int o0 = (tile / (g.nt2 * g.nt3)) * g.c1len;
     const int o1 = min(o0 + g.c1len, m1);
     const int tid = threadIdx.x;
-    for (int e = tid; e < 3 * R * TR; e += NT) {
-        const int i = e % TR, k = (e / TR) % R, w = e / (TR * R);
-        ca[e] = op.band[1][w][k * m2 + min(o2 + i, m2 - 1)];  // rows past the grid feed unused outputs
-    }
-    // stage-A position of this thread; output column of this thread
-    const int ai = tid / E3, aq = tid % E3;
     const int ty = tid / E3, tx = tid % E3;
-    const int i2 = o2 + ty, i3 = o3 + tx;
-    const bool active = (tx < T3) && (i2 < m2) && (i3 < m3);
-    const int i2c = min(i2, m2 - 1), i3c = min(i3, m3 - 1);
-    T cb[3][R];  // axis-3 band row of the thread's column (zero when inactive)
+    const int i2 = o2 + ty, i3 = o3 - HB + tx;
+    const bool active = (tx >= HB) && (tx < E3 - HB) && (i2 < m2) && (i3 < m3);
+    const int i2c = min(i2, m2 - 1), i3c = min(max(i3, 0), m3 - 1);
+    T car[Q::CAREG ? 3 : 1][Q::CAREG ? R : 1];
+    T* ca = xs + 2 * NX;  // [3][R][TR] when not in registers
+    if constexpr (Q::CAREG) {
+#pragma unroll
+        for (int w = 0; w < 3; ++w)
+#pragma unroll
+            for (int k = 0; k < R; ++k) car[w][k] = op.band[1][w][k * m2 + i2c];
+    } else {
+        for (int e = tid; e < 3 * R * TR; e += NT) {
+            const int i = e % TR, k = (e / TR) % R, w = e / (TR * R);
+            ca[e] = op.band[1][w][k * m2 + min(o2 + i, m2 - 1)];
+        }
+    }
+    T cb[3][R];
 #pragma unroll
     for (int w = 0; w < 3; ++w)
 #pragma unroll
         for (int k = 0; k < R; ++k) cb[w][k] = active ? op.band[2][w][k * m3 + i3] : T(0);
-    // in-plane factors of the diagonal at the thread's output column
     const T dm1 = op.band[1][0][HB * m2 + i2c], ds1 = op.band[1][2][HB * m2 + i2c];
     const T dm2 = op.band[2][0][HB * m3 + i3c], ds2 = op.band[2][2][HB * m3 + i3c];
     const T dmm = dm1 * dm2, dsm = ds1 * dm2, dms = dm1 * ds2;
-    const unsigned pt = unsigned(i2c) * m3 + unsigned(i3c);  // in-plane offset of the output point
+    // byte offset of the output point within a plane; out of range for inactive lanes
+    const unsigned ptb = active ? (unsigned(i2c) * m3 + unsigned(i3c)) * S : kOob;
     T acc[3][R];
 #pragma unroll
     for (int c = 0; c < 3; ++c)
@@ -122,84 +167,91 @@ __global__ __launch_bounds__(k3Rows<T>() * k3E3) void k_apply3d(OpDev<T> op, con
     for (int i = 0; i < apply_ndots<MODE>(); ++i) dots[i] = 0.0;
     const T al = op.alpha, be = op.beta, ab = offdiag_weight(op);
 
-    // loads of one plane: NLX entries of the 3 component tiles per thread
-    // (offsets within a plane of the component stack, the same for every
-    // plane; ~0u outside the grid) and the plane's table row (threads < NC)
-    unsigned loff[NLX];
+    // tile loads: NLC entries per component; in-plane byte offsets (out of range
+    // outside the grid, so those entries read as zero)
+    unsigned loffb[NLC];
 #pragma unroll
-    for (int q = 0; q < NLX; ++q) {
-        const int e = min(tid + q * NT, NX - 1);
-        const int c = e / NIN, rr = e % NIN;
-        const int g2 = o2 - HB + rr / E3, g3 = o3 - HB + rr % E3;
+    for (int q = 0; q < NLC; ++q) {
+        const int e = min(tid + q * NT, NIN - 1);
+        const int g2 = o2 - HB + e / E3, g3 = o3 - HB + e % E3;
         const bool in = g2 >= 0 && g2 < m2 && g3 >= 0 && g3 < m3;
-        loff[q] = in ? unsigned(c) * G + unsigned(g2) * m3 + unsigned(g3) : ~0u;
+        loffb[q] = in ? (unsigned(g2) * m3 + unsigned(g3)) * S : kOob;
     }
-    T v[NLX];
-    T vt = T(0);
-    const T* __restrict__ c1p = op.c1p;
+    T v[3][NLC];
+    auto plane_rsrc = [&](const T* base, int c, int j) {
+        const bool jin = (j >= 0 && j < m1);  // block-uniform
+        return make_rsrc(base + (size_t(c) * G + size_t(jin ? j : 0) * PL), jin ? PL * S : 0u);
+    };
     auto load_plane = [&](int t) {
         const int j = o0 - HB + t;
-        const bool jin = (j >= 0 && j < m1);  // block-uniform
-        const unsigned jo = unsigned(jin ? j : 0) * PL;
 #pragma unroll
-        for (int q = 0; q < NLX; ++q) {
-            const bool in = jin && loff[q] != ~0u;
-            const T val = x[in ? jo + loff[q] : 0u];
-            v[q] = in ? val : T(0);
+        for (int c = 0; c < 3; ++c) {
+            const auto r = plane_rsrc(x, c, j);
+#pragma unroll
+            for (int q = 0; q < NLC; ++q) v[c][q] = buf_load(r, loffb[q], T(0));
         }
-        if (tid < NC) vt = c1p[unsigned(j + HB) * NC + tid];  // rows of planes -HB .. m1+HB-1
     };
     auto store_plane = [&](int t) {
         T* dst = xs + (t & 1) * NX;
 #pragma unroll
-        for (int q = 0; q < NLX; ++q) {
-            const int e = tid + q * NT;
-            if (q + 1 < NLX || e < NX) dst[e] = v[q];
-        }
-        if (tid < NC) rows[(t & 3) * NC + tid] = vt;
+        for (int c = 0; c < 3; ++c)
+#pragma unroll
+            for (int q = 0; q < NLC; ++q) {
+                const int e = tid + q * NT;
+                if ((q + 1) * NT <= NIN || e < NIN) dst[c * NIN + e] = v[c][q];
+            }
     };
     auto live = [&](int t) {
         const int j = o0 - HB + t;
         return j >= 0 && j < m1;
     };
-    auto stage_a = [&](int t) {
+    auto stage_a = [&](int t, T (&sa)[9]) {
         const T* src = xs + (t & 1) * NX;
-        T* dst = st + (t & 1) * 9 * NA;
 #pragma unroll
         for (int c = 0; c < 3; ++c) {
             T aM = T(0), aA = T(0), aS = T(0);
 #pragma unroll
             for (int k = 0; k < R; ++k) {
-                const T xv = src[c * NIN + (ai + k) * E3 + aq];
-                aM += ca[(0 * R + k) * TR + ai] * xv;
-                aA += ca[(1 * R + k) * TR + ai] * xv;
-                aS += ca[(2 * R + k) * TR + ai] * xv;
+                const T xv = src[c * NIN + (ty + k) * E3 + tx];
+                if constexpr (Q::CAREG) {
+                    aM = fma(car[0][k], xv, aM);
+                    aA = fma(car[1][k], xv, aA);
+                    aS = fma(car[2][k], xv, aS);
+                } else {
+                    aM = fma(ca[(0 * R + k) * TR + ty], xv, aM);
+                    aA = fma(ca[(1 * R + k) * TR + ty], xv, aA);
+                    aS = fma(ca[(2 * R + k) * TR + ty], xv, aS);
+                }
             }
-            dst[(3 * c + 0) * NA + tid] = aM;
-            dst[(3 * c + 1) * NA + tid] = aA;
-            dst[(3 * c + 2) * NA + tid] = aS;
+            sa[3 * c + 0] = aM;
+            sa[3 * c + 1] = aA;
+            sa[3 * c + 2] = aS;
         }
     };
-    // epilogue operands at the thread's output point of plane io
-    constexpr bool kPre = (MODE != kApplyYMulti);  // the Krylov basis rows are loaded at the store
-    constexpr bool kAhead = (sizeof(T) == 4);
-    Epi3<T> en{};
+    auto stencil = [&](T val, T (&s)[R]) {
+        s[HB] = val;
+#pragma unroll
+        for (int d = 1; d <= HB; ++d) {
+            s[HB - d] = lane_shift<kDppShr1>(s[HB - d + 1]);
+            s[HB + d] = lane_shift<kDppShl1>(s[HB + d - 1]);
+        }
+    };
+    // epilogue operands of output plane io, loaded one phase before its emit
+    T eb[3], ex[3], ep[3];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) eb[c] = ex[c] = ep[c] = T(0);
+    const bool use_prev = (c1 != T(0) && xprev != nullptr);
     auto epi_load = [&](int io) {
-        if (!kPre || io < o0 || io >= o1 || !active) return;
-        const unsigned base = unsigned(io) * PL + pt;
+        if (io < o0 || io >= o1) return;  // block-uniform
 #pragma unroll
         for (int c = 0; c < 3; ++c) {
-            const unsigned idx = unsigned(c) * G + base;
-            if (MODE == kApplyRes || MODE == kApplyResDot || MODE == kApplyCheb) en.b[c] = b[idx];
-            if (MODE == kApplyCheb) {
-                en.x[c] = x[idx];
-                en.xp[c] = (c1 != T(0) && xprev != nullptr) ? xprev[idx] : T(0);
-            }
-            if (MODE == kApplyYDot) en.x[c] = x[idx];
+            if (MODE == kApplyRes || MODE == kApplyResDot || MODE == kApplyCheb) eb[c] = buf_load(plane_rsrc(b, c, io), ptb, T(0));
+            if (MODE == kApplyCheb || MODE == kApplyYDot) ex[c] = buf_load(plane_rsrc(x, c, io), ptb, T(0));
+            if (MODE == kApplyCheb) ep[c] = use_prev ? buf_load(plane_rsrc(xprev, c, io), ptb, T(0)) : T(0);
         }
     };
 
-    const int TI = (o1 - o0) + 2 * HB;  // input planes of the block
+    const int TI = (o1 - o0) + 2 * HB;
     load_plane(0);
     store_plane(0);
     if (TI > 1) {
@@ -208,47 +260,41 @@ __global__ __launch_bounds__(k3Rows<T>() * k3E3) void k_apply3d(OpDev<T> op, con
     }
     if (TI > 2) load_plane(2);
     __syncthreads();
-    if (live(0)) stage_a(0);
-    __syncthreads();
+    T sa[9];
     for (int t0 = 0; t0 < TI; t0 += R) {
 #pragma unroll
         for (int uu = 0; uu < R; ++uu) {
             const int t = t0 + uu;
-            if (t < TI) {  // block-uniform
+            if (t < TI) {
                 const int j = o0 - HB + t;
-                const int io = j - HB;  // output plane completed in this phase
+                const int io = j - HB;
                 const bool emit = (io >= o0 && io < o1);
-                Epi3<T> ec;
-                if (kAhead) {
-                    ec = en;
-                    epi_load(io + 1);
-                } else {
-                    epi_load(io);
-                    ec = en;
-                }
-                if (t + 1 < TI && live(t + 1)) stage_a(t + 1);
-                const T* row = rows + (t & 3) * NC;
+                if (live(t)) stage_a(t, sa);
+                __syncthreads();  // every wave has read plane t's tile
+                const T* row = c1g + unsigned(o0 + t) * NC;  // table row of plane j
                 if (live(t)) {
-                    const T* sb = st + (t & 1) * 9 * NA;
                     T W[3][3];
                     {
-                        // raw products per input component c: M3(M2x), S3(M2x), A3(M2x), M3(S2x), M3(A2x), A3(A2x)
                         T mm[3], sm[3], am[3], ms[3], ma[3], aa[3];
-                        const int q0 = ty * E3 + tx;
 #pragma unroll
                         for (int c = 0; c < 3; ++c) {
                             mm[c] = sm[c] = am[c] = ms[c] = ma[c] = aa[c] = T(0);
+                            T s[R];
+                            stencil(sa[3 * c + 0], s);
 #pragma unroll
                             for (int k = 0; k < R; ++k) {
-                                const T vM = sb[(3 * c + 0) * NA + q0 + k];
-                                const T vA = sb[(3 * c + 1) * NA + q0 + k];
-                                const T vS = sb[(3 * c + 2) * NA + q0 + k];
-                                mm[c] += cb[0][k] * vM;
-                                sm[c] += cb[2][k] * vM;
-                                if (c != 1) am[c] += cb[1][k] * vM;
-                                ms[c] += cb[0][k] * vS;
-                                if (c != 2) ma[c] += cb[0][k] * vA;
-                                if (c != 0) aa[c] += cb[1][k] * vA;
+                                mm[c] = fma(cb[0][k], s[k], mm[c]);
+                                sm[c] = fma(cb[2][k], s[k], sm[c]);
+                                if (c != 1) am[c] = fma(cb[1][k], s[k], am[c]);
+                            }
+                            stencil(sa[3 * c + 2], s);
+#pragma unroll
+                            for (int k = 0; k < R; ++k) ms[c] = fma(cb[0][k], s[k], ms[c]);
+                            stencil(sa[3 * c + 1], s);
+#pragma unroll
+                            for (int k = 0; k < R; ++k) {
+                                if (c != 2) ma[c] = fma(cb[0][k], s[k], ma[c]);
+                                if (c != 0) aa[c] = fma(cb[1][k], s[k], aa[c]);
                             }
                         }
                         W[0][0] = be * mm[0];
@@ -263,7 +309,7 @@ __global__ __launch_bounds__(k3Rows<T>() * k3E3) void k_apply3d(OpDev<T> op, con
                     }
 #pragma unroll
                     for (int k = 0; k < R; ++k) {
-                        const T cM = row[0 * R + k], cA = row[1 * R + k], cS = row[2 * R + k];  // X1(j-HB+k, j)
+                        const T cM = row[0 * R + k], cA = row[1 * R + k], cS = row[2 * R + k];
                         const int sl = (uu + k + 1) % R;
 #pragma unroll
                         for (int c = 0; c < 3; ++c)
@@ -289,42 +335,47 @@ __global__ __launch_bounds__(k3Rows<T>() * k3E3) void k_apply3d(OpDev<T> op, con
                                 acc[c][r] = T(0);
                             }
                     }
-                    if (emit && active) {
-                        const unsigned base = unsigned(io) * PL + pt;
-                        const T d0m = row[3 * R], d0s = row[3 * R + 1];  // M1, S1 at (io, io)
+                    if (emit) {
+                        const T d0m = row[3 * R], d0s = row[3 * R + 1];
 #pragma unroll
                         for (int c = 0; c < 3; ++c) {
-                            const unsigned idx = unsigned(c) * G + base;
                             if (MODE == kApplyY) {
-                                y[idx] = kx[c];
+                                buf_store(kx[c], plane_rsrc(y, c, io), ptb);
                             } else if (MODE == kApplyRes) {
-                                y[idx] = ec.b[c] - kx[c];
+                                buf_store(eb[c] - kx[c], plane_rsrc(y, c, io), ptb);
                             } else if (MODE == kApplyResDot) {
-                                const T r = ec.b[c] - kx[c];
-                                y[idx] = r;
+                                const T r = eb[c] - kx[c];
+                                buf_store(r, plane_rsrc(y, c, io), ptb);
                                 dots[0] += double(r) * double(r);
                             } else if (MODE == kApplyYDot) {
-                                y[idx] = kx[c];
-                                dots[0] += double(ec.x[c]) * double(kx[c]);
+                                buf_store(kx[c], plane_rsrc(y, c, io), ptb);
+                                dots[0] += double(ex[c]) * double(kx[c]);
                             } else if (MODE == kApplyCheb) {
-                                // diagonal: beta prod(S on axis c, M elsewhere) + alpha sum over the other axes
                                 const T dg = (c == 0 ? be : al) * d0s * dmm + (c == 1 ? be : al) * d0m * dsm +
                                              (c == 2 ? be : al) * d0m * dms;
-                                const T r = ec.b[c] - kx[c];
-                                xout[idx] = ec.x[c] + (c1 * (ec.x[c] - ec.xp[c]) + c2 * r / dg);
-                            } else {  // y = A x with the Krylov-basis dots
-                                y[idx] = kx[c];
+                                const T r = eb[c] - kx[c];
+                                T upd;
+                                if constexpr (sizeof(T) == 4)
+                                    upd = c2 * r * __builtin_amdgcn_rcpf(active ? dg : T(1));
+                                else
+                                    upd = c2 * r / (active ? dg : T(1));
+                                buf_store(ex[c] + (c1 * (ex[c] - ep[c]) + upd), plane_rsrc(xout, c, io), ptb);
+                            } else {
+                                buf_store(kx[c], plane_rsrc(y, c, io), ptb);
+                                if (active) {
+                                    const size_t idx = size_t(c) * G + size_t(io) * PL + size_t(i2c) * m3 + i3c;
 #pragma unroll
-                                for (int i = 0; i < kMaxBasis; ++i)
-                                    if (i < nv) dots[i] += double(b[size_t(i) * (3 * size_t(G)) + idx]) * double(kx[c]);
-                                dots[kMaxBasis] += double(kx[c]) * double(kx[c]);
+                                    for (int i = 0; i < kMaxBasis; ++i)
+                                        if (i < nv) dots[i] += double(b[size_t(i) * (3 * size_t(G)) + idx]) * double(kx[c]);
+                                    dots[kMaxBasis] += double(kx[c]) * double(kx[c]);
+                                }
                             }
                         }
                     }
+                    epi_load(io + 1);
                 }
                 if (t + 2 < TI) store_plane(t + 2);  // into the buffer plane t vacated
                 if (t + 3 < TI) load_plane(t + 3);
-                __syncthreads();
             }
         }
     }
@@ -339,10 +390,13 @@ void launch3d(const OpDev<T>& op, const T* x, T* y, const T* b, T* u, T* xout, T
     const Apply3dGeom g = apply3d_geom(op.m, HB, sizeof(T), op.x1chunk);
     if (size_t(3) * op.m[0] * op.m[1] * op.m[2] >= (size_t(1) << 31))
         throw std::runtime_error("3D operator kernel: too many unknowns for 32-bit offsets");
+    if (size_t(op.m[1]) * op.m[2] * sizeof(T) >= (size_t(1) << 31))
+        throw std::runtime_error("3D operator kernel: a grid plane exceeds the 2 GiB of a buffer descriptor");
     const size_t lds = Q::lds_words() * sizeof(T);
     auto kern = k_apply3d<T, HB, MODE>;
     allow_lds(reinterpret_cast<const void*>(kern), lds);
-    hipLaunchKernelGGL(kern, dim3(g.nblocks), dim3(Q::NT), lds, s, op, x, y, b, u, xout, c1, c2, part, nv, g, stamp);
+    hipLaunchKernelGGL(kern, dim3(g.nblocks), dim3(Q::NT), lds, s, op, x, y, b, u, xout, c1, c2, part, nv, g, stamp,
+                       op.c1p);
 }
 
 }  // namespace

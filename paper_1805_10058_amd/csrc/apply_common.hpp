@@ -19,10 +19,10 @@ constexpr int kT1 = 8, kT2 = 32;  // 2D output tile: kT1 * kT2 = kThreads points
 
 namespace {
 
-// 3D output tile: k3Rows(T) rows (x2) of k3T3(HB) = 32 - 2HB columns (x3),
-// so that the stage-A positions (tile rows times 32 columns) are exactly one
-// per thread: 256-thread blocks of 8 rows in FP32, 128-thread blocks of 4
-// rows in FP64 (whose registers allow half the waves per SIMD).
+// 3D output tile: k3Rows(T) rows (x2) of k3T3(HB) = 32 - 2HB columns (x3);
+// a thread per point of the tile rows times 32 columns (the output columns
+// and their x3 halo): 256-thread blocks of 8 rows in FP32, 128-thread blocks
+// of 4 rows in FP64.
 constexpr int k3E3 = 32;
 __host__ __device__ constexpr int k3T3(int hb) { return k3E3 - 2 * hb; }
 template <typename T>
@@ -32,8 +32,8 @@ __host__ __device__ constexpr int k3Rows() { return sizeof(T) == 4 ? 8 : 4; }
 // ranges of x1 planes.  Blocks march along x1, and each of their input planes
 // costs the in-plane contractions whether or not it is a halo plane, so the x1
 // range is made as long as the device's resident blocks allow: about as many
-// blocks as fit at once (3 per compute unit in FP32, 4 in FP64, from the
-// register footprint of the kernels).
+// blocks as fit at once (4 per compute unit in both precisions, from the
+// register footprint of the kernels: 4 waves per SIMD in FP32, 2 in FP64).
 struct Apply3dGeom {
     int nt2, nt3, c1len, nblocks;
 };
@@ -41,7 +41,7 @@ struct Apply3dGeom {
 // x1chunk > 0 fixes the number of x1 planes per block (the last block of a
 // column takes the remainder).
 inline Apply3dGeom apply3d_geom(const int* m, int hb, size_t elem, int x1chunk = 0) {
-    const int kTargetBlocks = elem == 4 ? 768 : 1024;
+    const int kTargetBlocks = 1024;
     const int rows = elem == 4 ? k3Rows<float>() : k3Rows<double>();
     Apply3dGeom g;
     g.nt2 = (m[1] + rows - 1) / rows;
