@@ -40,6 +40,7 @@ import scipy.sparse as sp
 import scipy.sparse.linalg as spla
 
 from .assembly import curl_div_matrix
+from .symbols import symbol_bound
 from .matrices import mass_adv_stiff, toeplitz_T
 from .transfer import knot_insertion_prolongator, paper_prolongator
 
@@ -75,7 +76,8 @@ class Level:
 
 
 def build_hierarchy(d, p, n, alpha, beta, transfer="knot", coarse_max_dofs=1000,
-                    lanczos_steps=20, nu=3, ratio=30.0, nu_coarse=None, blockdiag=False):
+                    lanczos_steps=20, nu=3, ratio=30.0, nu_coarse=None, blockdiag=False,
+                    bounds="lanczos", safety=1.5):
     """List of Level objects, finest first.  ``n``: intervals of every axis,
     or one count per axis.  Each level coarsens every axis that can be:
     by knot insertion (n -> n/2) while the transfer is "knot" and the axis's
@@ -85,7 +87,10 @@ def build_hierarchy(d, p, n, alpha, beta, transfer="knot", coarse_max_dofs=1000,
     no axis can be coarsened.  blockdiag: every level holds the block-diagonal
     part of its operator (P_WL); the block prolongator keeps it block diagonal,
     so the Galerkin coarse operator of D is the block-diagonal part of the
-    coarse operator."""
+    coarse operator.  bounds="symbol": each smoothed level whose axes all have
+    at least 2p+1 points takes hi = safety x the symbol maximum of
+    diag(K_l)^{-1} K_l (Sec. 5, symbols.symbol_bound); the others, and
+    bounds="lanczos", hi = 1.1 x the Lanczos estimate."""
     ns = [n] * d if np.isscalar(n) else [int(v) for v in n]
     levels = [Level(d, p, ns, alpha, beta, [mass_adv_stiff(nl, p) for nl in ns], blockdiag)]
     if transfer not in ("knot", "paper"):
@@ -113,14 +118,25 @@ def build_hierarchy(d, p, n, alpha, beta, transfer="knot", coarse_max_dofs=1000,
         L.Ps, L.P = Ps, Ps[0]
         cm = [tuple(P.T @ X @ P for X in trip) for P, trip in zip(Ps, L.mats)]
         levels.append(Level(d, p, ncs, alpha, beta, cm, blockdiag))
+    if bounds not in ("lanczos", "symbol"):
+        raise ValueError(bounds)
     for l, L in enumerate(levels[:-1]):
-        L.lam = lanczos_estimate(L, lanczos_steps)
-        L.hi = 1.1 * L.lam
+        if bounds == "symbol" and min(L.ms) >= 2 * p + 1:
+            L.lam = symbol_bound(L.K, d, L.ms, symbol_samples(d))
+            L.hi = safety * L.lam
+        else:
+            L.lam = lanczos_estimate(L, lanczos_steps)
+            L.hi = 1.1 * L.lam
         L.lo = L.hi / ratio
         L.nu = nu if l == 0 or nu_coarse is None else nu_coarse
     C = levels[-1]
     C.coarse_factor = sla.cho_factor(C.K.toarray())
     return levels
+
+
+def symbol_samples(d):
+    """Points per axis of the theta grid of the symbol bound."""
+    return 129 if d == 2 else 33
 
 
 def start_vector(d, m):
@@ -257,12 +273,14 @@ class Method:
     of the preconditioner, ``solve`` the outer flexible CG."""
 
     def __init__(self, d, p, n, alpha, beta, transfer="knot", coarse_max_dofs=1000,
-                 nu=3, ratio=30.0, lanczos_steps=20, krylov_steps=None, nu_coarse=None, variant="P_MIM"):
+                 nu=3, ratio=30.0, lanczos_steps=20, krylov_steps=None, nu_coarse=None, variant="P_MIM",
+                 bounds="lanczos", safety=1.5):
         if variant not in ("P_MIM", "P_WL", "MIM"):
             raise ValueError(variant)
         self.d, self.p, self.n, self.variant = d, p, n, variant
         self.levels = build_hierarchy(d, p, n, alpha, beta, transfer, coarse_max_dofs,
-                                      lanczos_steps, nu, ratio, nu_coarse, blockdiag=(variant == "P_WL"))
+                                      lanczos_steps, nu, ratio, nu_coarse, blockdiag=(variant == "P_WL"),
+                                      bounds=bounds, safety=safety)
         self.krylov_steps = p if krylov_steps is None else krylov_steps
         self.T, self.Tsolve = t_operator(d, p, self.levels[0].ms)
         # the system matrix (the V-cycle of P_WL runs on its block-diagonal part)

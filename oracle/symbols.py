@@ -96,3 +96,44 @@ def grid_gamma(m, d):
     """The uniform grid Gamma = {k pi / m : k = 1..m}^d of Sec. 5.3."""
     t = np.arange(1, m + 1) * np.pi / m
     return np.meshgrid(*([t] * d), indexing="ij")
+
+
+def central_symbol(K, d, ms, thetas):
+    """Symbol of the Toeplitz part of an assembled level operator K (sparse,
+    d components of prod(ms) points each, component-major, last axis fastest):
+    F_ce(theta) = sum_k K[(c, x0), (e, x0 + k)] exp(i k . theta), read off the
+    rows of the central grid point x0 (Sec. 5: for the finest level this is
+    n^{2-d} f^{p,alpha,beta}).  thetas: d arrays of one shape.  Returns an
+    array of shape (..., d, d)."""
+    ms = tuple(int(m) for m in ms)
+    G = int(np.prod(ms))
+    x0 = tuple(m // 2 for m in ms)
+    lin0 = int(np.ravel_multi_index(x0, ms))
+    K = K.tocsr()
+    shape = np.broadcast(*thetas).shape
+    F = np.zeros(shape + (d, d), dtype=np.complex128)
+    for c in range(d):
+        row = K.getrow(c * G + lin0)
+        for col, val in zip(row.indices, row.data):
+            e, rest = divmod(int(col), G)
+            idx = np.unravel_index(rest, ms)
+            phase = sum((int(idx[l]) - x0[l]) * thetas[l] for l in range(d))
+            F[..., c, e] += val * np.exp(1j * phase)
+    return F
+
+
+def symbol_bound(K, d, ms, samples):
+    """max over theta in [0, pi]^d (samples points per axis) of the largest
+    eigenvalue of Dh^{-1/2} F(theta) Dh^{-1/2}, F = central_symbol(K) and Dh
+    its constant diagonal: the symbol's value of lambda_max(diag(K)^{-1} K)
+    away from the boundary."""
+    t = np.linspace(0.0, np.pi, samples)
+    th = np.meshgrid(*([t] * d), indexing="ij")
+    F = central_symbol(K, d, ms, th)
+    G = int(np.prod(ms))
+    x0 = tuple(int(m) // 2 for m in ms)
+    lin0 = int(np.ravel_multi_index(x0, tuple(int(m) for m in ms)))
+    dh = np.array([K[c * G + lin0, c * G + lin0] for c in range(d)])
+    s = 1.0 / np.sqrt(dh)
+    H = F * s[:, None] * s[None, :]
+    return float(np.linalg.eigvalsh(H).max())

@@ -28,6 +28,8 @@ CD_METHOD_MIM = 2
 CD_METHOD_CG = 3
 CD_XFER_KNOT = 0
 CD_XFER_PAPER = 1
+CD_BOUNDS_LANCZOS = 0
+CD_BOUNDS_SYMBOL = 1
 CD_FP64 = 0
 CD_MIXED_FP32 = 1
 
@@ -42,7 +44,9 @@ class cd_options(ctypes.Structure):
                 ("rtol", ctypes.c_double), ("max_iter", ctypes.c_int), ("coarse_max_dofs", ctypes.c_int),
                 ("cheb_degree", ctypes.c_int), ("cheb_ratio", ctypes.c_double), ("lanczos_steps", ctypes.c_int),
                 ("krylov_steps", ctypes.c_int), ("graphs", ctypes.c_int), ("cheb_degree_coarse", ctypes.c_int),
-                ("apply_x1_chunk", ctypes.c_int)]
+                ("apply_x1_chunk", ctypes.c_int),
+                ("eig_bounds", ctypes.c_int),
+                ("bound_safety", ctypes.c_double)]
 
 
 class cd_kernel_stats(ctypes.Structure):
@@ -71,6 +75,8 @@ SIGNATURES = {
     "cd_num_dofs": (ctypes.c_size_t, [ctypes.POINTER(cd_problem)]),
     "cd_validate": (_I, [ctypes.POINTER(cd_problem), ctypes.POINTER(cd_options)]),
     "cd_footprint_bytes": (ctypes.c_size_t, [ctypes.POINTER(cd_problem), ctypes.POINTER(cd_options)]),
+    "cd_symbol_bound": (ctypes.c_int, [ctypes.POINTER(cd_problem), ctypes.POINTER(cd_options), ctypes.c_int,
+                                       ctypes.POINTER(ctypes.c_double)]),
     "cd_solver_create": (_I, [ctypes.POINTER(cd_problem), ctypes.POINTER(cd_options), _P, ctypes.POINTER(_P)]),
     "cd_solver_destroy": (None, [_P]),
     "cd_solve": (_I, [_P, _P, _P, ctypes.POINTER(cd_result)]),
@@ -170,6 +176,12 @@ def footprint_bytes(prob, opt):
 
 def validate(prob, opt):
     return lib().cd_validate(ctypes.byref(prob), ctypes.byref(opt))
+
+
+def symbol_bound(prob, opt, level):
+    lam = ctypes.c_double()
+    check(lib().cd_symbol_bound(ctypes.byref(prob), ctypes.byref(opt), int(level), ctypes.byref(lam)))
+    return lam.value
 
 
 class Solver:

@@ -373,4 +373,100 @@ int recurrence_warmup(const TFactor& F, double tol) {
     return std::min(m, worst + bw + 2);
 }
 
+namespace {
+
+// Largest eigenvalue of a real symmetric matrix of order 1, 2 or 3 (the
+// trigonometric solution of the characteristic cubic for order 3).
+double sym_max_eig(int d, const double a[3][3]) {
+    if (d == 1) return a[0][0];
+    if (d == 2) {
+        const double h = 0.5 * (a[0][0] + a[1][1]), g = 0.5 * (a[0][0] - a[1][1]);
+        return h + std::sqrt(g * g + a[0][1] * a[0][1]);
+    }
+    const double off = a[0][1] * a[0][1] + a[0][2] * a[0][2] + a[1][2] * a[1][2];
+    const double q = (a[0][0] + a[1][1] + a[2][2]) / 3.0;
+    if (off == 0.0) return std::max(a[0][0], std::max(a[1][1], a[2][2]));
+    const double b00 = a[0][0] - q, b11 = a[1][1] - q, b22 = a[2][2] - q;
+    const double p2 = b00 * b00 + b11 * b11 + b22 * b22 + 2.0 * off;
+    const double pp = std::sqrt(p2 / 6.0);
+    // det(B / pp) / 2
+    const double det = b00 * (b11 * b22 - a[1][2] * a[1][2]) - a[0][1] * (a[0][1] * b22 - a[1][2] * a[0][2]) +
+                       a[0][2] * (a[0][1] * a[1][2] - b11 * a[0][2]);
+    double r = det / (2.0 * pp * pp * pp);
+    r = std::min(1.0, std::max(-1.0, r));
+    return q + 2.0 * pp * std::cos(std::acos(r) / 3.0);
+}
+
+}  // namespace
+
+double symbol_lambda_max(int d, const Band* M, const Band* A, const Band* S, double alpha, double beta,
+                         double offw, int samples) {
+    // per axis and sample: Toeplitz symbols of M and S (real: the rows are
+    // symmetric) and of A divided by i (A is skew), from the central row
+    std::vector<double> mr(size_t(d) * samples), sr(size_t(d) * samples), ai(size_t(d) * samples);
+    double m0[3], s0[3];
+    for (int l = 0; l < d; ++l) {
+        const int m = M[l].m;
+        const int hb = std::max(M[l].hb, std::max(A[l].hb, S[l].hb));
+        if (m < 2 * hb + 1) return 0.0;
+        const int i0 = m / 2;
+        m0[l] = M[l].get(i0, i0);
+        s0[l] = S[l].get(i0, i0);
+        for (int t = 0; t < samples; ++t) {
+            const double th = samples > 1 ? M_PI * t / (samples - 1) : 0.0;
+            double vm = 0, vs = 0, va = 0;
+            for (int k = -hb; k <= hb; ++k) {
+                vm += M[l].get(i0, i0 + k) * std::cos(k * th);
+                vs += S[l].get(i0, i0 + k) * std::cos(k * th);
+                va += A[l].get(i0, i0 + k) * std::sin(k * th);
+            }
+            mr[size_t(l) * samples + t] = vm;
+            sr[size_t(l) * samples + t] = vs;
+            ai[size_t(l) * samples + t] = va;
+        }
+    }
+    // constant diagonal of each component block
+    double dh[3];
+    for (int c = 0; c < d; ++c) {
+        dh[c] = 0.0;
+        for (int f = 0; f < d; ++f) {
+            double t = (f == c) ? beta : alpha;
+            for (int l = 0; l < d; ++l) t *= (l == f) ? s0[l] : m0[l];
+            dh[c] += t;
+        }
+        if (!(dh[c] > 0.0)) return 0.0;
+    }
+    double best = 0.0;
+    const int n2 = samples, n3 = d == 3 ? samples : 1;
+    for (int t0 = 0; t0 < samples; ++t0)
+        for (int t1 = 0; t1 < n2; ++t1)
+            for (int t2 = 0; t2 < n3; ++t2) {
+                const int ts[3] = {t0, t1, t2};
+                double vm[3], vs[3], va[3];
+                for (int l = 0; l < d; ++l) {
+                    vm[l] = mr[size_t(l) * samples + ts[l]];
+                    vs[l] = sr[size_t(l) * samples + ts[l]];
+                    va[l] = ai[size_t(l) * samples + ts[l]];
+                }
+                double F[3][3] = {};
+                for (int c = 0; c < d; ++c) {
+                    double v = 0.0;
+                    for (int f = 0; f < d; ++f) {
+                        double t = (f == c) ? beta : alpha;
+                        for (int l = 0; l < d; ++l) t *= (l == f) ? vs[l] : vm[l];
+                        v += t;
+                    }
+                    F[c][c] = v / dh[c];
+                    for (int e = c + 1; e < d; ++e) {
+                        // offw (i a_c)(i a_e) prod of the other axes' M symbols
+                        double t = -offw;
+                        for (int l = 0; l < d; ++l) t *= (l == c || l == e) ? va[l] : vm[l];
+                        F[c][e] = F[e][c] = t / std::sqrt(dh[c] * dh[e]);
+                    }
+                }
+                best = std::max(best, sym_max_eig(d, F));
+            }
+    return best;
+}
+
 }  // namespace cd

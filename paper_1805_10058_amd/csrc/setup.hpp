@@ -57,6 +57,19 @@ Prolong identity_prolong(int m);
 // Galerkin product P^T X P.
 Band galerkin(const Band& X, const Prolong& P);
 
+// Largest eigenvalue of the symbol of diag(K)^{-1} K for a level operator K
+// built from per-axis 1D matrices M[l], A[l], S[l] (l < d) with the block
+// structure of Sec. 4 (diagonal blocks beta S x M x .. + alpha sum of the
+// other S terms; off-diagonal blocks offw times A on the two axes of the pair
+// and M elsewhere): the Toeplitz part of each 1D matrix is read off its
+// central row, the d x d symbol F(theta) of Sec. 5 is formed from the 1D
+// symbols, scaled by its constant diagonal Dh, and the largest eigenvalue of
+// Dh^{-1/2} F Dh^{-1/2} is maximised over theta in {pi k / (s - 1)}^d,
+// k = 0..s-1, s = samples.  Returns 0 when an axis has fewer than 2 hb + 1
+// points (no interior row).
+double symbol_lambda_max(int d, const Band* M, const Band* A, const Band* S, double alpha, double beta,
+                         double offw, int samples);
+
 // Quadrature tables of one axis: q-point Gauss-Legendre on each of the n
 // elements (Q = n q points in element order), and at every point the values
 // and first derivatives of the p+1 B-splines nonzero there; f0[a] is the

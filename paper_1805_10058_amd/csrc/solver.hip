@@ -278,6 +278,10 @@ void validate(const cd_problem* pr, const cd_options* op) {
     if (op->krylov_steps > 7) throw CdError(CD_EINVAL, "krylov_steps must be <= 7");
     if (op->graphs != 0 && op->graphs != 1) throw CdError(CD_EINVAL, "graphs must be 0 or 1");
     if (op->apply_x1_chunk < 0) throw CdError(CD_EINVAL, "apply_x1_chunk must be >= 0");
+    if (op->eig_bounds != CD_BOUNDS_LANCZOS && op->eig_bounds != CD_BOUNDS_SYMBOL)
+        throw CdError(CD_EINVAL, "unknown eig_bounds");
+    if (!(op->bound_safety == 0.0 || (op->bound_safety >= 1.0 && op->bound_safety <= 10.0)))
+        throw CdError(CD_EINVAL, "bound_safety must be 0 or in [1, 10]");
     if (op->coarse_max_dofs < 1 || op->coarse_max_dofs > 8192)
         throw CdError(CD_EINVAL, "coarse_max_dofs must be in 1..8192");
     // the operator kernels use fixed-size LDS tiles (no limit on the grid) and
@@ -916,6 +920,30 @@ double lanczos_kappa(const std::vector<double>& a, const std::vector<double>& b)
 // recurrence restarts from r_i = cos(0.7 i + 0.3) (D-normalised) with
 // beta_{j+1} = 0.  The recurrence coefficients stay on the device until the
 // last step.
+// Smoother bounds from the spectral symbol (Sec. 5) of each smoothed level's
+// Toeplitz part: lam = the symbol maximum of diag^{-1} A_l, hi = safety x lam.
+// Levels without an interior row keep lam = 0 and get the Lanczos bound.
+constexpr double kDefaultBoundSafety = 1.5;
+int symbol_samples(int d) { return d == 2 ? 129 : 33; }
+
+double level_symbol_bound(const cd_solver* s, const LevelHost& H) {
+    const double offw = (s->opt.method == CD_METHOD_PWL) ? 0.0 : s->prob.alpha - s->prob.beta;
+    return cd::symbol_lambda_max(s->d, H.M, H.A, H.S, s->prob.alpha, s->prob.beta, offw, symbol_samples(s->d));
+}
+
+void symbol_bounds(cd_solver* s) {
+    const double safety = s->opt.bound_safety > 0.0 ? s->opt.bound_safety : kDefaultBoundSafety;
+    for (size_t l = 0; l + 1 < s->lv.size(); ++l) {
+        LevelHost& H = s->lv[l];
+        const double lam = level_symbol_bound(s, H);
+        if (lam > 0.0 && std::isfinite(lam)) {
+            H.lam = lam;
+            H.hi = safety * lam;
+            H.lo = H.hi / s->opt.cheb_ratio;
+        }
+    }
+}
+
 void estimate_bounds(cd_solver* s) {
     hipStream_t st = s->stream;
     const int L = int(s->lv.size());
@@ -930,6 +958,7 @@ void estimate_bounds(cd_solver* s) {
     double* coef = tmp.alloc<double>(2 * size_t(ks) + 1);  // alpha[0..ks), beta2[0..ks]
     for (int l = 0; l < L - 1; ++l) {
         LevelHost& H = s->lv[l];
+        if (H.lam > 0.0) continue;  // bound already set from the symbol
         const cd::OpDev<double>& op = s->ld64[l].op;
         const size_t n = H.N;
         std::vector<double> v0(n);
@@ -1055,7 +1084,10 @@ void create(cd_solver* s, const cd_problem* pr, const cd_options* op, void* stre
     void* hp = nullptr;
     hip_check(hipHostMalloc(&hp, 6 * sizeof(double), hipHostMallocDefault), "hipHostMalloc");
     s->host_scal = static_cast<double*>(hp);
-    if (L > 1 && op->method != CD_METHOD_CG) estimate_bounds(s);
+    if (L > 1 && op->method != CD_METHOD_CG) {
+        if (op->eig_bounds == CD_BOUNDS_SYMBOL) symbol_bounds(s);
+        estimate_bounds(s);
+    }
     if (op->method != CD_METHOD_CG) {
         if (op->precision == CD_FP64) {
             s->w64 = make_work<double>(s, s->arena);
@@ -1270,6 +1302,8 @@ void cd_default_options(cd_options* o) {
     o->graphs = 1;
     o->cheb_degree_coarse = 16;
     o->apply_x1_chunk = 0;
+    o->eig_bounds = CD_BOUNDS_LANCZOS;
+    o->bound_safety = 0.0;
 }
 
 size_t cd_num_dofs(const cd_problem* pr) {
@@ -1313,6 +1347,23 @@ size_t cd_footprint_bytes(const cd_problem* pr, const cd_options* op) {
                 + (1 << 20);                                 // 1D tables and partial sums
     });
     return rc == CD_OK ? total : 0;
+}
+
+int cd_symbol_bound(const cd_problem* pr, const cd_options* op, int level, double* lam) {
+    return run([&] {
+        validate(pr, op);
+        if (!lam) throw CdError(CD_EINVAL, "null output pointer");
+        cd_solver tmp;
+        tmp.prob = *pr;
+        tmp.opt = *op;
+        tmp.d = pr->dim;
+        tmp.p = pr->degree;
+        tmp.ksteps = (op->krylov_steps < 0) ? pr->degree : op->krylov_steps;
+        if (tmp.prob.dim == 2) tmp.prob.n[2] = 1;
+        build_host(&tmp);
+        if (level < 0 || level + 1 >= int(tmp.lv.size())) throw CdError(CD_EINVAL, "level has no smoother");
+        *lam = level_symbol_bound(&tmp, tmp.lv[level]);
+    });
 }
 
 int cd_solver_create(const cd_problem* prob, const cd_options* opt, void* stream, cd_solver** out) {

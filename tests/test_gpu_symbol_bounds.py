@@ -1,0 +1,104 @@
+"""Symbol-guided smoother bounds on the GPU (Sec. 5 symbols, Sec. 6.1
+smoother; CD_BOUNDS_SYMBOL): the bound each level's smoother uses, one
+V-cycle entry by entry against the oracle running the same bounds, and whole
+solves against the Lanczos-bounded ones.
+
+Tolerances: the bound is host arithmetic on both sides (1e-13 relative);
+the V-cycle 1e-10 max-norm (FP64) and 1e-3 (FP32), as in
+test_gpu_elementwise, here without sharing any eigenvalue estimate: both
+sides compute the symbol bound themselves.
+"""
+import numpy as np
+import pytest
+
+from tests.gpu_util import dev, empty, gpu_ok, host, stream
+
+pytestmark = pytest.mark.gpu
+
+if not gpu_ok():
+    pytest.skip("no GPU", allow_module_level=True)
+
+import curldiv_inputs as ci  # noqa: E402
+from oracle import method  # noqa: E402
+from paper_1805_10058_amd import capi  # noqa: E402
+
+# every smoothed level has an interior row, so every bound is the symbol's
+CASES = [(2, 3, 64, 0.01, 300), (3, 2, 32, 0.1, 600), (2, 2, (48, 96), 0.1, 500), (3, 3, 16, 1.0, 400)]
+IDS = [f"d{c[0]}p{c[1]}n{c[2]}b{c[3]}" for c in CASES]
+
+
+def _pair(case, precision=capi.CD_FP64):
+    d, p, n, beta, cmax = case
+    opt = capi.options(eig_bounds=capi.CD_BOUNDS_SYMBOL, coarse_max_dofs=cmax, precision=precision)
+    s = capi.Solver(capi.problem(d, p, n, 1.0, beta), opt, stream())
+    m = method.Method(d, p, n, 1.0, beta, coarse_max_dofs=cmax, nu=opt.cheb_degree, ratio=opt.cheb_ratio,
+                      nu_coarse=opt.cheb_degree_coarse, bounds="symbol")
+    return s, m, opt
+
+
+@pytest.mark.parametrize("case", CASES, ids=IDS)
+def test_bounds_are_the_symbol_maxima(case):
+    s, m, opt = _pair(case)
+    prob = capi.problem(case[0], case[1], case[2], 1.0, case[3])
+    assert s.num_levels() == len(m.levels)
+    for l, L in enumerate(m.levels[:-1]):
+        assert min(L.ms) >= 2 * case[1] + 1
+        lam = s.get_lambda(l)
+        assert abs(lam - L.lam) <= 1e-13 * L.lam, (l, lam, L.lam)
+        assert lam == capi.symbol_bound(prob, opt, l)
+        assert L.hi == 1.5 * L.lam
+    s.close()
+
+
+@pytest.mark.parametrize("case", CASES, ids=IDS)
+def test_vcycle_with_symbol_bounds(case):
+    s, m, _ = _pair(case)
+    s32, _, _ = _pair(case, capi.CD_MIXED_FP32)
+    r = np.random.default_rng(71).uniform(-1, 1, m.K.shape[0])
+    ref = m.vcycle(r)
+    rd, z, z32 = dev(r), empty(r.size), empty(r.size)
+    s.precondition(rd.data_ptr(), z.data_ptr())
+    s32.precondition(rd.data_ptr(), z32.data_ptr())
+    scale = np.max(np.abs(ref))
+    assert np.max(np.abs(host(z) - ref)) <= 1e-10 * scale
+    assert np.max(np.abs(host(z32) - ref)) <= 1e-3 * scale
+    s.close()
+    s32.close()
+
+
+def test_short_levels_fall_back_to_lanczos():
+    # 3D p=3 n=16 with a small coarse level: levels with m < 7 per axis have no
+    # interior row and take the Lanczos bound, the same as in Lanczos mode
+    prob = capi.problem(3, 3, 16, 1.0, 0.1)
+    sym = capi.Solver(prob, capi.options(eig_bounds=capi.CD_BOUNDS_SYMBOL, coarse_max_dofs=100), stream())
+    lan = capi.Solver(prob, capi.options(coarse_max_dofs=100), stream())
+    assert sym.num_levels() == lan.num_levels() >= 4
+    fell_back = 0
+    for l in range(sym.num_levels() - 1):
+        m3, _ = sym.level_shape(l)
+        if min(m3) < 7:
+            assert sym.get_lambda(l) == lan.get_lambda(l)
+            fell_back += 1
+        else:
+            assert sym.get_lambda(l) == capi.symbol_bound(prob, capi.options(eig_bounds=1, coarse_max_dofs=100), l)
+    assert fell_back >= 1
+    sym.close()
+    lan.close()
+
+
+@pytest.mark.parametrize("name", ["c2_2d_p3_n256", "c3_3d_p2_n64"])
+def test_solves_with_symbol_bounds(name):
+    d, p, n, alpha, betas, dist, tol = ci.CONFIGS[name]
+    for j, beta in enumerate(betas):
+        prob = capi.problem(d, p, n, alpha, beta)
+        b = dev(ci.rhs(d, p, n, 2000 + j, dist))
+        its = {}
+        for mode in (capi.CD_BOUNDS_LANCZOS, capi.CD_BOUNDS_SYMBOL):
+            s = capi.Solver(prob, capi.options(precision=capi.CD_MIXED_FP32, rtol=tol, eig_bounds=mode), stream())
+            x = empty(b.numel())
+            res = s.solve(b.data_ptr(), x.data_ptr())
+            assert res.status == capi.CD_OK and res.true_rel_residual <= 2 * tol
+            its[mode] = res.iterations
+            s.close()
+        print(f"{name} beta={beta}: iterations Lanczos {its[0]}, symbol {its[1]}")
+        assert its[1] <= 1.5 * its[0] + 2

@@ -66,12 +66,13 @@ def test_default_options():
     assert o.rtol == 1e-8 and o.max_iter == 10000 and o.coarse_max_dofs == 2500
     assert (o.cheb_degree, o.cheb_degree_coarse, o.cheb_ratio, o.lanczos_steps) == (48, 16, 1000.0, 20)
     assert o.krylov_steps < 0 and o.graphs == 1
+    assert o.eig_bounds == capi.CD_BOUNDS_LANCZOS and o.bound_safety == 0.0
 
 
 @pytest.mark.parametrize("field,value", [
     ("cheb_degree", 0), ("cheb_degree", 129), ("cheb_degree_coarse", 129), ("lanczos_steps", 0),
     ("lanczos_steps", 201), ("cheb_ratio", 1.0), ("rtol", 0.0), ("max_iter", 0), ("precision", 7),
-    ("method", 9), ("transfer", 5),
+    ("method", 9), ("transfer", 5), ("eig_bounds", 2), ("bound_safety", 0.5), ("bound_safety", 11.0),
 ])
 def test_invalid_options_are_rejected(field, value):
     prob = capi.problem(2, 3, 32, 1.0, 0.1)
@@ -109,3 +110,35 @@ def test_footprint_grows_with_size_and_precision():
         assert f64 > prev
         prev = f64
     assert capi.footprint_bytes(capi.problem(2, 3, 32, 1.0, 0.1), capi.options(cheb_degree=0)) == 0
+
+
+# The symbol bound is host logic (cd_symbol_bound runs without a device): it
+# must equal the oracle's, which reads the symbol off the central rows of the
+# assembled level operators (oracle/symbols.py, pinned against the paper's
+# symbol in test_oracle_symbol_bound).  Cases: 2D and 3D, both transfers (the
+# paper prolongator's Galerkin levels are not re-discretizations), P_WL (no
+# off-diagonal blocks), an anisotropic grid, and levels too short for an
+# interior row (bound 0, Lanczos takes over).
+@pytest.mark.parametrize("d,p,n,alpha,beta,transfer,method", [
+    (2, 3, 32, 1.0, 0.01, "knot", "P_MIM"), (3, 3, 16, 1.0, 1.0, "knot", "P_MIM"),
+    (3, 2, (8, 12, 16), 1.0, 0.1, "knot", "P_MIM"), (2, 2, 30, 1.0, 0.1, "paper", "P_MIM"),
+    (2, 3, 25, 1.0, 0.1, "knot", "P_WL"), (3, 4, 12, 0.5, 2.0, "knot", "P_MIM"),
+])
+def test_symbol_bound_matches_the_oracle(d, p, n, alpha, beta, transfer, method):
+    from oracle import method as om
+    from oracle import symbols
+    meth = {"P_MIM": capi.CD_METHOD_PMIM, "P_WL": capi.CD_METHOD_PWL}[method]
+    tr = capi.CD_XFER_KNOT if transfer == "knot" else capi.CD_XFER_PAPER
+    opt = capi.options(transfer=tr, method=meth, eig_bounds=capi.CD_BOUNDS_SYMBOL, coarse_max_dofs=60)
+    prob = capi.problem(d, p, n, alpha, beta)
+    levels = om.build_hierarchy(d, p, n, alpha, beta, transfer=transfer, coarse_max_dofs=60,
+                                blockdiag=(method == "P_WL"), lanczos_steps=2)
+    for lvl, L in enumerate(levels[:-1]):
+        got = capi.symbol_bound(prob, opt, lvl)
+        if min(L.ms) < 2 * p + 1:
+            assert got == 0.0
+        else:
+            ref = symbols.symbol_bound(L.K, d, L.ms, om.symbol_samples(d))
+            assert abs(got - ref) <= 1e-13 * ref, (lvl, got, ref)
+    with pytest.raises(capi.CurldivError):
+        capi.symbol_bound(prob, opt, len(levels) - 1)
