@@ -32,9 +32,9 @@ HEADLINE = "c4_3d_p3_n128"
 # profiles/c4_3d_p3_n128_solve_kernels.txt.  It holds only for the kernel
 # sources it was measured on (their SHA-256 below); after any change to them
 # the line reports null until the counters are taken again.
-CHEB_TRAFFIC = {"fetch_kib": 71327.2, "write_kib": 30512.6, "fetch_factor": 2.000, "write_factor": 1.000,
+CHEB_TRAFFIC = {"fetch_kib": 71151.7, "write_kib": 30522.9, "fetch_factor": 2.000, "write_factor": 1.000,
                 "sources": ["paper_1805_10058_amd/csrc/apply3d.hip", "paper_1805_10058_amd/csrc/apply_common.hpp"],
-                "sha256": "2e82bb677ad8f838b13f0d2efef99d984ee54c91477e70bf07355af6b3276b6f"}
+                "sha256": "a340e6d19dd42c39c0601abe200e5a8e92cf11f27d2e8f6c0b5fd9b10a9007ee"}
 
 
 def cheb_traffic_bytes():
@@ -179,6 +179,7 @@ def headline(capi, torch, st, steps, warmup):
                                "GB_s": a.bytes / (a.total_ms * 1e-3) / 1e9 if a.total_ms > 0 else 0.0}
     ts = mixed.profile_read_tsolve(True)
     mixed.profile_enable(False)
+    launches = mixed.graph_launches()[0]
     mixed.close()
 
     # plain FP64 path on the same right-hand sides
@@ -210,6 +211,7 @@ def headline(capi, torch, st, steps, warmup):
                    "dim": d, "degree": p, "n": n, "beta": beta, "solves_per_step": 1},
         "latency_ms": {"p50": 1e3 * percentile(lat, 50), "p99": 1e3 * percentile(lat, 99)},
         "iterations": [r.iterations for r in res],
+        "kernel_launches_per_outer_iteration": launches,
         "max_true_rel_residual": max(r.true_rel_residual for r in res),
         "kappa_estimate": [r.kappa_estimate for r in res],
         "setup_ms": 1e3 * setup_mixed,
@@ -358,16 +360,20 @@ def run_solves(capi, torch, st, name, precision, seeds, **kw):
             res.append((b, r))
     torch.cuda.synchronize()
     T = time.perf_counter() - t0
+    launches = {str(b): s.graph_launches()[0] for b, s in solvers.items()}
     for s in solvers.values():
         s.close()
-    return T, lat, res
+    return T, lat, res, launches
 
 
-def summarize(capi, T, lat, res):
-    return {"solves_per_s": len(lat) / T, "p50_ms": 1e3 * percentile(lat, 50), "p99_ms": 1e3 * percentile(lat, 99),
-            "iterations": {str(b): r.iterations for b, r in res},
-            "converged": sum(1 for _, r in res if r.status == capi.CD_OK), "solves": len(res),
-            "max_true_rel_residual": max(r.true_rel_residual for _, r in res)}
+def summarize(capi, T, lat, res, launches=None):
+    out = {"solves_per_s": len(lat) / T, "p50_ms": 1e3 * percentile(lat, 50), "p99_ms": 1e3 * percentile(lat, 99),
+           "iterations": {str(b): r.iterations for b, r in res},
+           "converged": sum(1 for _, r in res if r.status == capi.CD_OK), "solves": len(res),
+           "max_true_rel_residual": max(r.true_rel_residual for _, r in res)}
+    if launches:
+        out["kernel_launches_per_outer_iteration"] = launches
+    return out
 
 
 def c1_latency(capi, torch, st, reps=100):
@@ -378,9 +384,9 @@ def c1_latency(capi, torch, st, reps=100):
     for graphs in (1, 0):
         # a 32-unknown coarsest level (3 levels), so the solve runs the V-cycle
         # rather than the dense coarse solve alone
-        T, lat, res = run_solves(capi, torch, st, "c1_2d_p2_n16", capi.CD_FP64, list(range(reps)), graphs=graphs,
-                                 coarse_max_dofs=64)
-        out["graph" if graphs else "eager"] = summarize(capi, T, lat, res)
+        T, lat, res, launches = run_solves(capi, torch, st, "c1_2d_p2_n16", capi.CD_FP64, list(range(reps)),
+                                           graphs=graphs, coarse_max_dofs=64)
+        out["graph" if graphs else "eager"] = summarize(capi, T, lat, res, launches if graphs else None)
     out["workload"] = ("2D p=2 n=16 (512 unknowns), alpha=beta=1, FP64, rel. residual 1e-10, one solve at a time, "
                        "3 levels (coarsest 32 unknowns)")
     return out

@@ -208,6 +208,13 @@ int cd_get_matrix(const cd_solver* s, int level, int axis, char which, double* h
  * the symbol maximum of cd_symbol_bound where the level has one. */
 int cd_get_lambda(const cd_solver* s, int level, double* lam);
 
+/* Launches of one outer iteration (a measurement hook): the kernel nodes
+ * (*kernels) and all nodes (*nodes, kernels plus copies) of the HIP graph the
+ * handle captured to replay outer iterations k >= 1; both 0 before a solve
+ * has reached its second iteration or with graphs = 0.  Either pointer may be
+ * NULL. */
+int cd_graph_launches(const cd_solver* s, size_t* kernels, size_t* nodes);
+
 /* y = A_level x in FP64.  Level 0 is the system matrix of Sec. 4.1 (2D) /
  * Sec. 4.2 (3D), the block matrix of Kronecker products of the 1D matrices
  * (for CD_METHOD_PWL the V-cycle's operator, the block-diagonal part D of

@@ -75,6 +75,8 @@ SIGNATURES = {
     "cd_num_dofs": (ctypes.c_size_t, [ctypes.POINTER(cd_problem)]),
     "cd_validate": (_I, [ctypes.POINTER(cd_problem), ctypes.POINTER(cd_options)]),
     "cd_footprint_bytes": (ctypes.c_size_t, [ctypes.POINTER(cd_problem), ctypes.POINTER(cd_options)]),
+    "cd_graph_launches": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_size_t),
+                                         ctypes.POINTER(ctypes.c_size_t)]),
     "cd_symbol_bound": (ctypes.c_int, [ctypes.POINTER(cd_problem), ctypes.POINTER(cd_options), ctypes.c_int,
                                        ctypes.POINTER(ctypes.c_double)]),
     "cd_solver_create": (_I, [ctypes.POINTER(cd_problem), ctypes.POINTER(cd_options), _P, ctypes.POINTER(_P)]),
@@ -230,6 +232,11 @@ class Solver:
         buf = (ctypes.c_double * (rows * cols))()
         check(lib().cd_get_matrix(self._h, level, axis, which.encode(), buf))
         return buf
+
+    def graph_launches(self):
+        k, n = ctypes.c_size_t(), ctypes.c_size_t()
+        check(lib().cd_graph_launches(self._h, ctypes.byref(k), ctypes.byref(n)))
+        return k.value, n.value
 
     def get_lambda(self, level):
         v = ctypes.c_double()

@@ -269,6 +269,20 @@ __global__ __launch_bounds__(k3Rows<T>() * k3E3) void k_apply3d(OpDev<T> op, con
                 const int j = o0 - HB + t;
                 const int io = j - HB;
                 const bool emit = (io >= o0 && io < o1);
+                // Krylov-basis rows of this phase's output plane, loaded before
+                // the contractions so that they hide the loads' latency (FP32 up
+                // to HB = 4; the others have no registers to spare and load
+                // them at the emit)
+                constexpr bool kPreBasis = (MODE == kApplyYMulti) && sizeof(T) == 4 && HB <= 4;
+                T ev[kPreBasis ? kMaxBasis : 1][3];
+                if (kPreBasis && emit) {
+#pragma unroll
+                    for (int i = 0; i < kMaxBasis; ++i)
+#pragma unroll
+                        for (int c = 0; c < 3; ++c)
+                            ev[i][c] = (i < nv) ? buf_load(plane_rsrc(b + size_t(i) * (3 * size_t(G)), c, io), ptb, T(0))
+                                                : T(0);
+                }
                 if (live(t)) stage_a(t, sa);
                 __syncthreads();  // every wave has read plane t's tile
                 const T* row = c1g + unsigned(o0 + t) * NC;  // table row of plane j
@@ -362,13 +376,17 @@ __global__ __launch_bounds__(k3Rows<T>() * k3E3) void k_apply3d(OpDev<T> op, con
                                 buf_store(ex[c] + (c1 * (ex[c] - ep[c]) + upd), plane_rsrc(xout, c, io), ptb);
                             } else {
                                 buf_store(kx[c], plane_rsrc(y, c, io), ptb);
-                                if (active) {
+                                if constexpr (kPreBasis) {
+#pragma unroll
+                                    for (int i = 0; i < kMaxBasis; ++i)
+                                        if (i < nv) dots[i] += double(ev[i][c]) * double(kx[c]);
+                                } else if (active) {
                                     const size_t idx = size_t(c) * G + size_t(io) * PL + size_t(i2c) * m3 + i3c;
 #pragma unroll
                                     for (int i = 0; i < kMaxBasis; ++i)
                                         if (i < nv) dots[i] += double(b[size_t(i) * (3 * size_t(G)) + idx]) * double(kx[c]);
-                                    dots[kMaxBasis] += double(kx[c]) * double(kx[c]);
                                 }
+                                dots[kMaxBasis] += double(kx[c]) * double(kx[c]);
                             }
                         }
                     }

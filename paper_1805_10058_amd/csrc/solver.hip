@@ -221,6 +221,7 @@ struct cd_solver {
     hipGraphExec_t iter_graph = nullptr;  // captured outer iteration k >= 1
     // the same iteration captured with live timing (stamp slots [0, kGraphSlots))
     hipGraphExec_t iter_graph_prof = nullptr;
+    size_t graph_kernels = 0, graph_nodes = 0;  // of iter_graph
     std::vector<ProfRec> prof_graph;
     bool capturing = false, graph_prof_ran = false;
     int prof_period = 1;        // time every prof_period-th outer iteration
@@ -1194,6 +1195,21 @@ void solve_iterate(cd_solver* s) {
             }
             s->capturing = false;
             hip_check(hipStreamEndCapture(st, &g), "hipStreamEndCapture");
+            if (!timed) {
+                size_t nn = 0;
+                if (hipGraphGetNodes(g, nullptr, &nn) == hipSuccess && nn > 0) {
+                    std::vector<hipGraphNode_t> nodes(nn);
+                    size_t nk = 0;
+                    if (hipGraphGetNodes(g, nodes.data(), &nn) == hipSuccess) {
+                        for (size_t i = 0; i < nn; ++i) {
+                            hipGraphNodeType ty;
+                            if (hipGraphNodeGetType(nodes[i], &ty) == hipSuccess && ty == hipGraphNodeTypeKernel) ++nk;
+                        }
+                        s->graph_nodes = nn;
+                        s->graph_kernels = nk;
+                    }
+                }
+            }
             const hipError_t e = hipGraphInstantiate(&exec, g, nullptr, nullptr, 0);
             (void)hipGraphDestroy(g);
             hip_check(e, "hipGraphInstantiate");
@@ -1454,6 +1470,14 @@ int cd_get_matrix(const cd_solver* s, int level, int axis, char which, double* o
         } else {
             throw CdError(CD_EINVAL, "which must be one of M, A, S, T, P");
         }
+    });
+}
+
+int cd_graph_launches(const cd_solver* s, size_t* kernels, size_t* nodes) {
+    return run([&] {
+        if (!s) throw CdError(CD_EINVAL, "null solver");
+        if (kernels) *kernels = s->graph_kernels;
+        if (nodes) *nodes = s->graph_nodes;
     });
 }
 

@@ -312,6 +312,11 @@ def test_graph_replay_equals_eager(case, precision):
         re = s_e.solve(bd.data_ptr(), xe.data_ptr())
         assert rg.iterations == re.iterations and rg.iterations >= 3
         np.testing.assert_array_equal(host(xg), host(xe))
+    # the captured iteration's launch count: the kernels of one outer
+    # iteration (the eager handle captured nothing)
+    kg, ng = s_g.graph_launches()
+    assert 10 <= kg <= ng
+    assert s_e.graph_launches() == (0, 0)
 
 
 @pytest.mark.gpu
