@@ -34,6 +34,11 @@ __host__ __device__ constexpr int k3Rows() { return sizeof(T) == 4 ? 8 : 4; }
 // range is made as long as the device's resident blocks allow: about as many
 // blocks as fit at once (4 per compute unit in both precisions, from the
 // register footprint of the kernels: 4 waves per SIMD in FP32, 2 in FP64).
+// Where that leaves ranges of HB planes or fewer (2 HB halo planes each), the
+// ranges are doubled for HB >= 3: measured in the solves at m = 65 (ranges of
+// 4 instead of 2: 17 instead of 22 us per Chebyshev step) and m = 33 (2
+// instead of 1: 11 instead of 12 us), while at m = 129 halving the blocks to
+// 22-plane ranges costs 10%.
 struct Apply3dGeom {
     int nt2, nt3, c1len, nblocks;
 };
@@ -52,6 +57,12 @@ inline Apply3dGeom apply3d_geom(const int* m, int hb, size_t elem, int x1chunk =
     } else {
         const int nx1 = std::max(1, std::min(m[0], kTargetBlocks / planar));
         g.c1len = (m[0] + nx1 - 1) / nx1;
+        if (hb >= 3 && g.c1len <= hb) {
+            if (g.c1len > 1)
+                g.c1len = std::min(2 * g.c1len, m[0]);
+            else if (m[0] >= 10 * hb)
+                g.c1len = 2;
+        }
     }
     g.nblocks = planar * ((m[0] + g.c1len - 1) / g.c1len);
     return g;
