@@ -401,6 +401,228 @@ __global__ __launch_bounds__(k3Rows<T>() * k3E3) void k_apply3d(OpDev<T> op, con
     stamp_end(stamp);
 }
 
+// ------------------------------------------------------------------------------
+// Short marches: when every block would march over a single output plane
+// (small coarse levels), its 2 HB + 1 input planes are processed side by side
+// instead of one after the other.  A block holds R = 2 HB + 1 groups of
+// 32 TRS threads (TRS tile rows); group g computes stages A and B of input
+// plane io - HB + g exactly as the marching kernel does and leaves W in LDS;
+// then the groups of components 0, 1, 2 sum the axis-1 contributions of the R
+// planes in the marching kernel's order, with the same fused multiply-adds, so
+// A x is bitwise that of the marching kernel (the FP32 Chebyshev update may
+// round its last bit differently), and run the epilogue.  One barrier-separated
+// phase instead of 2 HB + 1.
+// ------------------------------------------------------------------------------
+template <typename T, int HB>
+struct TileS {
+    static constexpr int TR = k3ShortRows<T>();
+    static constexpr int NP = TR * k3E3;            // threads per group
+    static constexpr int R = 2 * HB + 1;            // groups (input planes)
+    static constexpr int NT = R * NP;
+    static constexpr int E2 = TR + 2 * HB;
+    static constexpr int NIN = E2 * k3E3;
+    static constexpr int NX = 3 * NIN;
+    static constexpr int NLC = (NIN + NP - 1) / NP;
+    static constexpr int NC = 3 * R + 2;
+    static constexpr bool CAREG = sizeof(T) == 4;
+    static constexpr size_t lds_words() {
+        return size_t(R) * NX + size_t(R) * 9 * NP + (CAREG ? 0 : 3 * size_t(R) * TR);
+    }
+};
+
+template <typename T, int HB, int MODE>
+__global__ __launch_bounds__((2 * HB + 1) * k3ShortRows<T>() * k3E3) void k_apply3d_short(
+    OpDev<T> op, const T* __restrict__ x, T* __restrict__ y, const T* __restrict__ b, const T* xprev, T* xout, T c1,
+    T c2, Apply3dGeom g, unsigned long long* stamp, const T* __restrict__ c1g) {
+    using Q = TileS<T, HB>;
+    constexpr int TR = Q::TR, NP = Q::NP, R = Q::R, E3 = k3E3, T3 = k3T3(HB);
+    constexpr int NIN = Q::NIN, NX = Q::NX, NLC = Q::NLC, NC = Q::NC;
+    constexpr unsigned S = sizeof(T);
+    stamp_begin(stamp);
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    T* xs = reinterpret_cast<T*>(smem_raw);  // [R][3][E2][E3] input tiles
+    T* ws = xs + size_t(R) * NX;             // [R][9][NP] W of each plane
+    T* ca = ws + size_t(R) * 9 * NP;         // [3][R][TR] when not in registers
+    const int m1 = op.m[0], m2 = op.m[1], m3 = op.m[2];
+    const unsigned PL = unsigned(m2) * m3, G = unsigned(m1) * PL;
+    const int xcd = int(blockIdx.x % kXcds), slot = int(blockIdx.x / kXcds);
+    const int per = g.nblocks / kXcds, rem = g.nblocks % kXcds;
+    const int tile = xcd * per + min(xcd, rem) + slot;
+    const int o2 = (tile % g.nt2) * TR;
+    const int o3 = ((tile / g.nt2) % g.nt3) * T3;
+    const int io = tile / (g.nt2 * g.nt3);  // the block's output plane
+    const int grp = threadIdx.x / NP, tid = threadIdx.x % NP;
+    const int j = io - HB + grp;                 // this group's input plane
+    const bool jlive = (j >= 0 && j < m1);       // uniform within the group
+    const int ty = tid / E3, tx = tid % E3;
+    const int i2 = o2 + ty, i3 = o3 - HB + tx;
+    const bool active = (tx >= HB) && (tx < E3 - HB) && (i2 < m2) && (i3 < m3);
+    const int i2c = min(i2, m2 - 1), i3c = min(max(i3, 0), m3 - 1);
+    const unsigned ptb = active ? (unsigned(i2c) * m3 + unsigned(i3c)) * S : kOob;
+    auto plane_rsrc = [&](const T* base, int c, int jj) {
+        const bool jin = (jj >= 0 && jj < m1);
+        return make_rsrc(base + (size_t(c) * G + size_t(jin ? jj : 0) * PL), jin ? PL * S : 0u);
+    };
+    // epilogue operands (groups 0..2: component grp of the output point)
+    T eb = T(0), ex = T(0), ep = T(0);
+    if (grp < 3) {
+        if (MODE == kApplyRes || MODE == kApplyCheb) eb = buf_load(plane_rsrc(b, grp, io), ptb, T(0));
+        if (MODE == kApplyCheb) {
+            ex = buf_load(plane_rsrc(x, grp, io), ptb, T(0));
+            ep = (c1 != T(0) && xprev != nullptr) ? buf_load(plane_rsrc(xprev, grp, io), ptb, T(0)) : T(0);
+        }
+    }
+    // this group's input tile
+    {
+        T v[3][NLC];
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            const auto r = plane_rsrc(x, c, j);
+#pragma unroll
+            for (int q = 0; q < NLC; ++q) {
+                const int e = min(tid + q * NP, NIN - 1);
+                const int g2 = o2 - HB + e / E3, g3 = o3 - HB + e % E3;
+                const bool in = g2 >= 0 && g2 < m2 && g3 >= 0 && g3 < m3;
+                v[c][q] = buf_load(r, in ? (unsigned(g2) * m3 + unsigned(g3)) * S : kOob, T(0));
+            }
+        }
+        T* dst = xs + size_t(grp) * NX;
+#pragma unroll
+        for (int c = 0; c < 3; ++c)
+#pragma unroll
+            for (int q = 0; q < NLC; ++q) {
+                const int e = tid + q * NP;
+                if ((q + 1) * NP <= NIN || e < NIN) dst[c * NIN + e] = v[c][q];
+            }
+    }
+    T car[Q::CAREG ? 3 : 1][Q::CAREG ? R : 1];
+    if constexpr (Q::CAREG) {
+#pragma unroll
+        for (int w = 0; w < 3; ++w)
+#pragma unroll
+            for (int k = 0; k < R; ++k) car[w][k] = op.band[1][w][k * m2 + i2c];
+    } else {
+        for (int e = threadIdx.x; e < 3 * R * TR; e += Q::NT) {
+            const int i = e % TR, k = (e / TR) % R, w = e / (TR * R);
+            ca[e] = op.band[1][w][k * m2 + min(o2 + i, m2 - 1)];
+        }
+    }
+    T cb[3][R];
+#pragma unroll
+    for (int w = 0; w < 3; ++w)
+#pragma unroll
+        for (int k = 0; k < R; ++k) cb[w][k] = active ? op.band[2][w][k * m3 + i3] : T(0);
+    const T al = op.alpha, be = op.beta, ab = offdiag_weight(op);
+    __syncthreads();
+    if (jlive) {
+        // stage A (axis 2) and stage B (axis 3) of plane j, as in k_apply3d
+        const T* src = xs + size_t(grp) * NX;
+        T sa[9];
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            T aM = T(0), aA = T(0), aS = T(0);
+#pragma unroll
+            for (int k = 0; k < R; ++k) {
+                const T xv = src[c * NIN + (ty + k) * E3 + tx];
+                if constexpr (Q::CAREG) {
+                    aM = fma(car[0][k], xv, aM);
+                    aA = fma(car[1][k], xv, aA);
+                    aS = fma(car[2][k], xv, aS);
+                } else {
+                    aM = fma(ca[(0 * R + k) * TR + ty], xv, aM);
+                    aA = fma(ca[(1 * R + k) * TR + ty], xv, aA);
+                    aS = fma(ca[(2 * R + k) * TR + ty], xv, aS);
+                }
+            }
+            sa[3 * c + 0] = aM;
+            sa[3 * c + 1] = aA;
+            sa[3 * c + 2] = aS;
+        }
+        auto stencil = [&](T val, T (&st)[R]) {
+            st[HB] = val;
+#pragma unroll
+            for (int d = 1; d <= HB; ++d) {
+                st[HB - d] = lane_shift<kDppShr1>(st[HB - d + 1]);
+                st[HB + d] = lane_shift<kDppShl1>(st[HB + d - 1]);
+            }
+        };
+        T mm[3], sm[3], am[3], ms[3], ma[3], aa[3];
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            mm[c] = sm[c] = am[c] = ms[c] = ma[c] = aa[c] = T(0);
+            T st[R];
+            stencil(sa[3 * c + 0], st);
+#pragma unroll
+            for (int k = 0; k < R; ++k) {
+                mm[c] = fma(cb[0][k], st[k], mm[c]);
+                sm[c] = fma(cb[2][k], st[k], sm[c]);
+                if (c != 1) am[c] = fma(cb[1][k], st[k], am[c]);
+            }
+            stencil(sa[3 * c + 2], st);
+#pragma unroll
+            for (int k = 0; k < R; ++k) ms[c] = fma(cb[0][k], st[k], ms[c]);
+            stencil(sa[3 * c + 1], st);
+#pragma unroll
+            for (int k = 0; k < R; ++k) {
+                if (c != 2) ma[c] = fma(cb[0][k], st[k], ma[c]);
+                if (c != 0) aa[c] = fma(cb[1][k], st[k], aa[c]);
+            }
+        }
+        T W[9];
+        W[0] = be * mm[0];
+        W[1] = al * (sm[0] + ms[0]);
+        W[2] = ab * (ma[1] + am[2]);
+        W[3] = al * mm[1];
+        W[4] = al * sm[1] + be * ms[1] + ab * aa[2];
+        W[5] = ab * ma[0];
+        W[6] = al * mm[2];
+        W[7] = be * sm[2] + al * ms[2] + ab * aa[1];
+        W[8] = ab * am[0];
+        T* wd = ws + size_t(grp) * 9 * NP;
+#pragma unroll
+        for (int i = 0; i < 9; ++i) wd[i * NP + tid] = W[i];
+    }
+    __syncthreads();
+    if (grp < 3) {
+        const int c = grp;
+        T kx = T(0);
+#pragma unroll
+        for (int gg = 0; gg < R; ++gg) {
+            const int jj = io - HB + gg;
+            if (jj >= 0 && jj < m1) {  // block-uniform
+                const T* row = c1g + unsigned(jj + HB) * NC;  // table row of plane jj
+                const int k = 2 * HB - gg;                    // X1(io, jj) = row[w R + k]
+                const T* wsrc = ws + size_t(gg) * 9 * NP + size_t(3 * c) * NP + tid;
+                kx = fma(row[2 * R + k], wsrc[0 * NP], kx);
+                kx = fma(row[0 * R + k], wsrc[1 * NP], kx);
+                kx = fma(row[1 * R + k], wsrc[2 * NP], kx);
+            }
+        }
+        const auto rs = (MODE == kApplyCheb) ? plane_rsrc(xout, c, io) : plane_rsrc(y, c, io);
+        if (MODE == kApplyY) {
+            buf_store(kx, rs, ptb);
+        } else if (MODE == kApplyRes) {
+            buf_store(eb - kx, rs, ptb);
+        } else {  // Chebyshev step
+            const T* drow = c1g + unsigned(io + 2 * HB) * NC;  // diagonal entries of plane io
+            const T d0m = drow[3 * R], d0s = drow[3 * R + 1];
+            const T dm1 = op.band[1][0][HB * m2 + i2c], ds1 = op.band[1][2][HB * m2 + i2c];
+            const T dm2 = op.band[2][0][HB * m3 + i3c], ds2 = op.band[2][2][HB * m3 + i3c];
+            const T dmm = dm1 * dm2, dsm = ds1 * dm2, dms = dm1 * ds2;
+            const T dg = (c == 0 ? be : al) * d0s * dmm + (c == 1 ? be : al) * d0m * dsm +
+                         (c == 2 ? be : al) * d0m * dms;
+            const T r = eb - kx;
+            T upd;
+            if constexpr (sizeof(T) == 4)
+                upd = c2 * r * __builtin_amdgcn_rcpf(active ? dg : T(1));
+            else
+                upd = c2 * r / (active ? dg : T(1));
+            buf_store(ex + (c1 * (ex - ep) + upd), rs, ptb);
+        }
+    }
+    stamp_end(stamp);
+}
+
 template <typename T, int HB, int MODE>
 void launch3d(const OpDev<T>& op, const T* x, T* y, const T* b, T* u, T* xout, T c1, T c2, double* part, int nv,
               unsigned long long* stamp, hipStream_t s) {
@@ -410,6 +632,18 @@ void launch3d(const OpDev<T>& op, const T* x, T* y, const T* b, T* u, T* xout, T
         throw std::runtime_error("3D operator kernel: too many unknowns for 32-bit offsets");
     if (size_t(op.m[1]) * op.m[2] * sizeof(T) >= (size_t(1) << 31))
         throw std::runtime_error("3D operator kernel: a grid plane exceeds the 2 GiB of a buffer descriptor");
+    if constexpr (HB <= 3 && (MODE == kApplyY || MODE == kApplyRes || MODE == kApplyCheb)) {
+        const Apply3dGeom gs = apply3d_geom_short(op.m, HB, sizeof(T), op.x1chunk);
+        if (gs.nblocks > 0) {
+            using QS = TileS<T, HB>;
+            const size_t lds = QS::lds_words() * sizeof(T);
+            auto kern = k_apply3d_short<T, HB, MODE>;
+            allow_lds(reinterpret_cast<const void*>(kern), lds);
+            hipLaunchKernelGGL(kern, dim3(gs.nblocks), dim3(QS::NT), lds, s, op, x, y, b, u, xout, c1, c2, gs, stamp,
+                               op.c1p);
+            return;
+        }
+    }
     const size_t lds = Q::lds_words() * sizeof(T);
     auto kern = k_apply3d<T, HB, MODE>;
     allow_lds(reinterpret_cast<const void*>(kern), lds);

@@ -27,6 +27,9 @@ constexpr int k3E3 = 32;
 __host__ __device__ constexpr int k3T3(int hb) { return k3E3 - 2 * hb; }
 template <typename T>
 __host__ __device__ constexpr int k3Rows() { return sizeof(T) == 4 ? 8 : 4; }
+// tile rows of the short-march variant (one wave per group in FP64)
+template <typename T>
+__host__ __device__ constexpr int k3ShortRows() { return sizeof(T) == 4 ? 4 : 2; }
 
 // Launch geometry of the 3D operator kernel: tiles of the (x2, x3) plane times
 // ranges of x1 planes.  Blocks march along x1, and each of their input planes
@@ -65,6 +68,32 @@ inline Apply3dGeom apply3d_geom(const int* m, int hb, size_t elem, int x1chunk =
         }
     }
     g.nblocks = planar * ((m[0] + g.c1len - 1) / g.c1len);
+    return g;
+}
+
+// Geometry of the short-march variant of the 3D kernel (tiles of
+// k3ShortRows rows, one output plane per block, 2 HB + 1 groups of threads):
+// nblocks = 0 when the marching kernel is used instead.  The variant does
+// 2 HB + 1 planes of in-plane work per output plane, the marching kernel with
+// one-plane ranges as much but one plane after another, so it pays where the
+// grid is small enough that latency, not work, sets the time: automatic
+// geometry (x1chunk = 0), HB <= 3, one-plane ranges under the marching rule,
+// and at most 3072 waves in all (measured: 17^3 8.0 against 10.4 us per
+// Chebyshev step in FP32, 7.0 against 12.5 us in FP64; at 33^3 and above the
+// marching kernel is faster).
+inline Apply3dGeom apply3d_geom_short(const int* m, int hb, size_t elem, int x1chunk) {
+    Apply3dGeom g{0, 0, 1, 0};
+    if (x1chunk != 0 || hb > 3) return g;
+    const int rows = elem == 4 ? k3Rows<float>() : k3Rows<double>();
+    const int planar = ((m[1] + rows - 1) / rows) * ((m[2] + k3T3(hb) - 1) / k3T3(hb));
+    if (std::max(1, std::min(m[0], 1024 / planar)) < m[0]) return g;  // ranges of more than one plane
+    const int srows = elem == 4 ? k3ShortRows<float>() : k3ShortRows<double>();
+    const int nt2 = (m[1] + srows - 1) / srows, nt3 = (m[2] + k3T3(hb) - 1) / k3T3(hb);
+    const long waves = long(nt2) * nt3 * m[0] * (2 * hb + 1) * srows / 2;  // 32 srows threads per group
+    if (waves > 3072) return g;
+    g.nt2 = nt2;
+    g.nt3 = nt3;
+    g.nblocks = nt2 * nt3 * m[0];
     return g;
 }
 

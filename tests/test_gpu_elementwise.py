@@ -210,3 +210,25 @@ def test_x1_chunk_solve_matches_automatic(case):
     assert r1.status == capi.CD_OK and r0.status == capi.CD_OK
     assert abs(r1.iterations - r0.iterations) <= 1
     assert maxrel(host(x1), host(x0)) <= 1e-6
+
+
+@pytest.mark.parametrize("d,p,n", [(3, 3, 12), (3, 2, (9, 14, 20)), (3, 1, 10), (3, 3, 16)])
+def test_short_march_variant_matches_marching_kernel(d, p, n):
+    # small grids take the variant of the 3D kernel that processes a block's
+    # 2 HB + 1 input planes side by side (automatic launch geometry); forcing
+    # one-plane ranges selects the marching kernel: y = A x is bitwise the
+    # same, in FP64 and in FP32, on every level
+    prob = capi.problem(d, p, n, 1.0, 0.2)
+    auto = capi.Solver(prob, capi.options(coarse_max_dofs=50), stream())
+    march = capi.Solver(prob, capi.options(coarse_max_dofs=50, apply_x1_chunk=1), stream())
+    rng = np.random.default_rng(47)
+    for l in range(auto.num_levels()):
+        _, nl = auto.level_shape(l)
+        x = rng.uniform(-1, 1, nl)
+        for dt, fn in ((torch.float64, "apply"), (torch.float32, "apply_f32")):
+            xd, ya, ym = dev(x, dt), empty(nl, dt), empty(nl, dt)
+            getattr(auto, fn)(l, xd.data_ptr(), ya.data_ptr())
+            getattr(march, fn)(l, xd.data_ptr(), ym.data_ptr())
+            np.testing.assert_array_equal(host(ya), host(ym))
+    auto.close()
+    march.close()
