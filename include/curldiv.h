@@ -103,9 +103,11 @@ typedef struct {
                              (identical arithmetic); 0: launch every kernel eagerly */
     int cheb_degree_coarse; /* Chebyshev degree on levels >= 1; <= 0 means cheb_degree */
     int apply_x1_chunk;   /* 3D operator kernel: x1 planes each block marches over (the
-                             launch geometry only; results do not depend on it up to
-                             rounding of the per-block partial dot products); 0 = chosen
-                             from the grid size */
+                             launch geometry only; results depend on it only through the
+                             rounding of the per-block partial dot products and, in FP32,
+                             the last bit of a Chebyshev update); 0 = chosen from the grid
+                             size (on small grids: the variant that processes a block's
+                             2p+1 input planes side by side) */
     int eig_bounds;       /* CD_BOUNDS_LANCZOS (default) or CD_BOUNDS_SYMBOL                 */
     double bound_safety;  /* CD_BOUNDS_SYMBOL: hi = bound_safety x symbol maximum; 0 = 1.5
                              (the symbol describes the interior of the spectrum; the boundary
