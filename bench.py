@@ -32,7 +32,7 @@ HEADLINE = "c4_3d_p3_n128"
 # profiles/c4_3d_p3_n128_solve_kernels.txt.  It holds only for the kernel
 # sources it was measured on (their SHA-256 below); after any change to them
 # the line reports null until the counters are taken again.
-CHEB_TRAFFIC = {"fetch_kib": 71480.7, "write_kib": 30443.7, "fetch_factor": 2.000, "write_factor": 1.000,
+CHEB_TRAFFIC = {"fetch_kib": 71394.4, "write_kib": 30446.7, "fetch_factor": 2.000, "write_factor": 1.000,
                 "sources": ["paper_1805_10058_amd/csrc/apply3d.hip", "paper_1805_10058_amd/csrc/apply_common.hpp"],
                 "sha256": "04e794bca3162fd040a077fac732026eb6aad4278ad516fec4a0f028f1fdbee4"}
 
@@ -77,7 +77,7 @@ def cpu_model():
     return platform.processor() or "unknown"
 
 
-def finest_apply_equivalents(opt, p, levels):
+def finest_apply_equivalents(opt, p, levels, coarse_degree):
     """Operator applies of one outer iteration, in units of a finest-level
     apply: on level 0 the Chebyshev steps after the first (the first rides on
     the input conversion), the residual before the coarse correction, the
@@ -88,11 +88,11 @@ def finest_apply_equivalents(opt, p, levels):
     fine = (opt.cheb_degree - 1) + 1 + 1 + p + 1
     coarse = 0.0
     for l in range(1, levels - 1):
-        coarse += (2 * opt.cheb_degree_coarse - 1 + 1) * 8.0 ** (-l)
+        coarse += (2 * coarse_degree - 1 + 1) * 8.0 ** (-l)
     return fine + coarse
 
 
-def cpu_baseline(its_gpu, levels):
+def cpu_baseline(its_gpu, levels, coarse_degree):
     """The oracle's tier-2 Kronecker apply (FP64, one host thread) timed at
     the 3D p=3 n=128 size, times the operator applies one outer iteration of
     the method needs, times the outer iterations the GPU solver took: a
@@ -118,7 +118,7 @@ def cpu_baseline(its_gpu, levels):
             asm.kron_apply({"M": M, "A": A, "S": S}, x, d, alpha, betas[0])
         t_apply = (time.perf_counter() - t0) / reps
     opt = capi.options()
-    per_iter = finest_apply_equivalents(opt, p, levels)
+    per_iter = finest_apply_equivalents(opt, p, levels, coarse_degree)
     t_solve = t_apply * per_iter * its_gpu
     return {"value": 1.0 / t_solve, "unit": "solves/s", "cores": 1, "kind": "oracle",
             "cpu_model": cpu_model(), "host_cores_available": len(os.sched_getaffinity(0)),
@@ -150,6 +150,7 @@ def headline(capi, torch, st, steps, warmup):
     torch.cuda.synchronize()
     setup_mixed = time.perf_counter() - t0
     levels = mixed.num_levels()
+    coarse_degree = mixed.coarse_degree()
     # live timing on from the warm-up on, so that the timed region replays
     # graphs captured (with their timing nodes) before it
     mixed.profile_enable(True, PROF_PERIOD)
@@ -180,6 +181,7 @@ def headline(capi, torch, st, steps, warmup):
     ts = mixed.profile_read_tsolve(True)
     mixed.profile_enable(False)
     launches = mixed.graph_launches()[0]
+    mixed_degree0 = mixed.get_smoother(0)[0]
     mixed.close()
 
     # plain FP64 path on the same right-hand sides
@@ -212,6 +214,9 @@ def headline(capi, torch, st, steps, warmup):
         "latency_ms": {"p50": 1e3 * percentile(lat, 50), "p99": 1e3 * percentile(lat, 99)},
         "iterations": [r.iterations for r in res],
         "kernel_launches_per_outer_iteration": launches,
+        "smoother": {"degree_finest": mixed_degree0, "degree_coarse": coarse_degree, "note": "default options: "
+                     "the coarse-level degree is chosen from beta / alpha (32 below 1e-5, 16 above)"},
+        "coarse_degree": coarse_degree,
         "max_true_rel_residual": max(r.true_rel_residual for r in res),
         "kappa_estimate": [r.kappa_estimate for r in res],
         "setup_ms": 1e3 * setup_mixed,
@@ -332,7 +337,7 @@ def main():
 
     if not args.no_cpu_baseline:
         log("timing the oracle on the host")
-        out["cpu_baseline"] = cpu_baseline(int(percentile(out["iterations"], 50)), levels)
+        out["cpu_baseline"] = cpu_baseline(int(percentile(out["iterations"], 50)), levels, out["coarse_degree"])
     print(json.dumps(out), flush=True)
 
 

@@ -101,7 +101,13 @@ typedef struct {
     int krylov_steps;     /* finest post-smoothing GMRES steps; < 0 means p  */
     int graphs;           /* 1: replay outer iterations from a captured HIP graph
                              (identical arithmetic); 0: launch every kernel eagerly */
-    int cheb_degree_coarse; /* Chebyshev degree on levels >= 1; <= 0 means cheb_degree */
+    int cheb_degree_coarse; /* Chebyshev degree on levels >= 1; 0 means cheb_degree; < 0 (the
+                             default) chooses from the problem: 16 when beta >= 1e-5 alpha,
+                             32 below (small beta leaves the smoother a branch of the
+                             spectrum it damps slowly, and the cheap coarse levels are where
+                             more steps pay: measured at 3D p=3 n=128 beta = 1e-6, 379
+                             outer iterations with 16, 238 with 32, 1.84 against 1.47 s per
+                             solve; at beta >= 1e-4, 16 is faster) */
     int apply_x1_chunk;   /* 3D operator kernel: x1 planes each block marches over (the
                              launch geometry only; results depend on it only through the
                              rounding of the per-block partial dot products and, in FP32,
@@ -117,8 +123,8 @@ typedef struct {
 
 /* Fill *opt with the defaults: P_MIM, knot insertion, FP64, rtol 1e-8,
  * max_iter 10000, coarse_max_dofs 2500, cheb_degree 48, cheb_ratio 1000,
- * lanczos_steps 20, krylov_steps = p, graphs 1, cheb_degree_coarse 16,
- * apply_x1_chunk 0.  The
+ * lanczos_steps 20, krylov_steps = p, graphs 1, cheb_degree_coarse -1 (16,
+ * or 32 when beta < 1e-5 alpha), apply_x1_chunk 0, eig_bounds Lanczos.  The
  * smoother settings were chosen by measured solve rate on 2D and 3D
  * problems; a wide interval needs the eigenvalue bound to cover the top of
  * the spectrum, which the Lanczos estimate times 1.1 does on every tested
@@ -216,6 +222,11 @@ int cd_get_lambda(const cd_solver* s, int level, double* lam);
  * has reached its second iteration or with graphs = 0.  Either pointer may be
  * NULL. */
 int cd_graph_launches(const cd_solver* s, size_t* kernels, size_t* nodes);
+
+/* The smoother of `level` (a level above the coarsest): Chebyshev degree and
+ * interval [lo, hi] on diag(A_l)^{-1} A_l, as the handle resolved them from
+ * its options and the eigenvalue bound.  Any output pointer may be NULL. */
+int cd_get_smoother(const cd_solver* s, int level, int* degree, double* lo, double* hi);
 
 /* y = A_level x in FP64.  Level 0 is the system matrix of Sec. 4.1 (2D) /
  * Sec. 4.2 (3D), the block matrix of Kronecker products of the 1D matrices

@@ -75,6 +75,8 @@ SIGNATURES = {
     "cd_num_dofs": (ctypes.c_size_t, [ctypes.POINTER(cd_problem)]),
     "cd_validate": (_I, [ctypes.POINTER(cd_problem), ctypes.POINTER(cd_options)]),
     "cd_footprint_bytes": (ctypes.c_size_t, [ctypes.POINTER(cd_problem), ctypes.POINTER(cd_options)]),
+    "cd_get_smoother": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, ctypes.POINTER(ctypes.c_int),
+                                       ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double)]),
     "cd_graph_launches": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_size_t),
                                          ctypes.POINTER(ctypes.c_size_t)]),
     "cd_symbol_bound": (ctypes.c_int, [ctypes.POINTER(cd_problem), ctypes.POINTER(cd_options), ctypes.c_int,
@@ -232,6 +234,15 @@ class Solver:
         buf = (ctypes.c_double * (rows * cols))()
         check(lib().cd_get_matrix(self._h, level, axis, which.encode(), buf))
         return buf
+
+    def get_smoother(self, level):
+        deg, lo, hi = ctypes.c_int(), ctypes.c_double(), ctypes.c_double()
+        check(lib().cd_get_smoother(self._h, level, ctypes.byref(deg), ctypes.byref(lo), ctypes.byref(hi)))
+        return deg.value, lo.value, hi.value
+
+    def coarse_degree(self):
+        """The Chebyshev degree of the levels below the finest (None with one smoothed level)."""
+        return self.get_smoother(1)[0] if self.num_levels() > 2 else None
 
     def graph_launches(self):
         k, n = ctypes.c_size_t(), ctypes.c_size_t()

@@ -638,7 +638,7 @@ T* chebyshev(cd_solver* s, int l, const T* b, T* x, T* other, bool from_zero, bo
     const double theta = 0.5 * (L.hi + L.lo), delta = 0.5 * (L.hi - L.lo);
     const double sigma = theta / delta;
     double rho = 1.0 / sigma;
-    const int nu = (l > 0 && s->opt.cheb_degree_coarse > 0) ? s->opt.cheb_degree_coarse : s->opt.cheb_degree;
+    const int nu = (l > 0) ? s->opt.cheb_degree_coarse : s->opt.cheb_degree;  // resolved in create
     T* cur = x;
     T* nxt = other;
     const T* prev = nullptr;  // x_{k-1}; nullptr: zero
@@ -948,6 +948,9 @@ void symbol_bounds(cd_solver* s) {
 void estimate_bounds(cd_solver* s) {
     hipStream_t st = s->stream;
     const int L = int(s->lv.size());
+    bool any = false;  // a smoothed level without a bound from the symbol
+    for (int l = 0; l < L - 1; ++l) any = any || !(s->lv[l].lam > 0.0);
+    if (!any) return;
     const int ks = s->opt.lanczos_steps;
     DevArena tmp;
     double* qa = tmp.alloc<double>(s->N);
@@ -1013,10 +1016,21 @@ void estimate_bounds(cd_solver* s) {
     }
 }
 
+// Chebyshev degree on the levels below the finest: 0 = the finest level's;
+// < 0 = from the problem (more coarse-level smoothing for small beta / alpha,
+// where the outer iteration count grows; measured, see cd_options).
+constexpr double kSmallBeta = 1e-5;
+int resolve_coarse_degree(const cd_problem& pr, const cd_options& o) {
+    if (o.cheb_degree_coarse > 0) return o.cheb_degree_coarse;
+    if (o.cheb_degree_coarse == 0) return o.cheb_degree;
+    return (pr.beta < kSmallBeta * pr.alpha) ? 32 : 16;
+}
+
 void create(cd_solver* s, const cd_problem* pr, const cd_options* op, void* stream) {
     validate(pr, op);
     s->prob = *pr;
     s->opt = *op;
+    s->opt.cheb_degree_coarse = resolve_coarse_degree(*pr, *op);
     if (s->prob.dim == 2) s->prob.n[2] = 1;
     s->stream = static_cast<hipStream_t>(stream);
     if (!s->stream) {
@@ -1316,7 +1330,7 @@ void cd_default_options(cd_options* o) {
     o->lanczos_steps = 20;
     o->krylov_steps = -1;
     o->graphs = 1;
-    o->cheb_degree_coarse = 16;
+    o->cheb_degree_coarse = -1;
     o->apply_x1_chunk = 0;
     o->eig_bounds = CD_BOUNDS_LANCZOS;
     o->bound_safety = 0.0;
@@ -1470,6 +1484,16 @@ int cd_get_matrix(const cd_solver* s, int level, int axis, char which, double* o
         } else {
             throw CdError(CD_EINVAL, "which must be one of M, A, S, T, P");
         }
+    });
+}
+
+int cd_get_smoother(const cd_solver* s, int level, int* degree, double* lo, double* hi) {
+    return run([&] {
+        if (!s) throw CdError(CD_EINVAL, "null solver");
+        if (level < 0 || level + 1 >= int(s->lv.size())) throw CdError(CD_EINVAL, "level has no smoother");
+        if (degree) *degree = (level == 0) ? s->opt.cheb_degree : s->opt.cheb_degree_coarse;
+        if (lo) *lo = s->lv[level].lo;
+        if (hi) *hi = s->lv[level].hi;
     });
 }
 

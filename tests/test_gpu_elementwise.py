@@ -76,8 +76,7 @@ def setup(case, precision=capi.CD_FP64):
         opt = capi.options(transfer=tr, coarse_max_dofs=cmax, precision=precision, apply_x1_chunk=chunk)
         s = capi.Solver(capi.problem(d, p, n, 1.0, beta), opt, stream())
         m = method.Method(d, p, n, 1.0, beta, transfer=xfer, coarse_max_dofs=cmax, nu=opt.cheb_degree,
-                          ratio=opt.cheb_ratio, lanczos_steps=opt.lanczos_steps,
-                          nu_coarse=opt.cheb_degree_coarse if opt.cheb_degree_coarse > 0 else None)
+                          ratio=opt.cheb_ratio, lanczos_steps=opt.lanczos_steps, nu_coarse=s.coarse_degree())
         # both sides estimate the smoother's eigenvalue bound independently (checked
         # below); the oracle then takes the GPU's estimate so that the smoother and
         # V-cycle comparisons measure the kernels' arithmetic, not the last bits of

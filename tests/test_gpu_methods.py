@@ -36,7 +36,7 @@ def make(variant, d, p, n, beta, transfer="paper", cmax=None, **kw):
     s = capi.Solver(capi.problem(d, p, n, 1.0, beta), opt, stream())
     m = method.Method(d, p, n, 1.0, beta, transfer=transfer, coarse_max_dofs=cmax, nu=opt.cheb_degree,
                       ratio=opt.cheb_ratio, lanczos_steps=opt.lanczos_steps,
-                      nu_coarse=opt.cheb_degree_coarse if opt.cheb_degree_coarse > 0 else None, variant=variant)
+                      nu_coarse=s.coarse_degree(), variant=variant)
     for l, L in enumerate(m.levels[:-1]):  # the same eigenvalue bounds on both sides (see test_gpu_elementwise)
         lam = s.get_lambda(l)
         assert abs(lam - L.lam) <= 1e-9 * L.lam

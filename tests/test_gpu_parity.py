@@ -50,7 +50,7 @@ def setup_case(case, precision=capi.CD_FP64, **kw):
         m = method.Method(d, p, n, 1.0, beta, transfer=xfer, coarse_max_dofs=cmax,
                           nu=opt.cheb_degree, ratio=opt.cheb_ratio, lanczos_steps=opt.lanczos_steps,
                           krylov_steps=None if opt.krylov_steps < 0 else opt.krylov_steps,
-                          nu_coarse=opt.cheb_degree_coarse if opt.cheb_degree_coarse > 0 else None)
+                          nu_coarse=s.coarse_degree())
         _cache[key] = (s, m)
     return _cache[key]
 
@@ -362,7 +362,7 @@ def test_alpha_not_one(case):
     opt = capi.options(coarse_max_dofs=200, rtol=1e-12)
     s = capi.Solver(capi.problem(d, p, n, alpha, beta), opt, stream())
     m = method.Method(d, p, n, alpha, beta, coarse_max_dofs=200, nu=opt.cheb_degree,
-                      nu_coarse=opt.cheb_degree_coarse if opt.cheb_degree_coarse > 0 else None,
+                      nu_coarse=s.coarse_degree(),
                       ratio=opt.cheb_ratio, lanczos_steps=opt.lanczos_steps)
     assert s.num_levels() == len(m.levels)
     rng = np.random.default_rng(23)

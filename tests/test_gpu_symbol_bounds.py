@@ -32,7 +32,7 @@ def _pair(case, precision=capi.CD_FP64):
     opt = capi.options(eig_bounds=capi.CD_BOUNDS_SYMBOL, coarse_max_dofs=cmax, precision=precision)
     s = capi.Solver(capi.problem(d, p, n, 1.0, beta), opt, stream())
     m = method.Method(d, p, n, 1.0, beta, coarse_max_dofs=cmax, nu=opt.cheb_degree, ratio=opt.cheb_ratio,
-                      nu_coarse=opt.cheb_degree_coarse, bounds="symbol")
+                      nu_coarse=s.coarse_degree(), bounds="symbol")
     return s, m, opt
 
 

@@ -64,7 +64,7 @@ def test_default_options():
     o = capi.options()
     assert (o.method, o.transfer, o.precision) == (capi.CD_METHOD_PMIM, capi.CD_XFER_KNOT, capi.CD_FP64)
     assert o.rtol == 1e-8 and o.max_iter == 10000 and o.coarse_max_dofs == 2500
-    assert (o.cheb_degree, o.cheb_degree_coarse, o.cheb_ratio, o.lanczos_steps) == (48, 16, 1000.0, 20)
+    assert (o.cheb_degree, o.cheb_degree_coarse, o.cheb_ratio, o.lanczos_steps) == (48, -1, 1000.0, 20)
     assert o.krylov_steps < 0 and o.graphs == 1
     assert o.eig_bounds == capi.CD_BOUNDS_LANCZOS and o.bound_safety == 0.0
 
