@@ -83,6 +83,12 @@ typedef struct {
                               hi = bound_safety x the symbol's maximum of diag^{-1} A_l (levels with an
                               axis shorter than 2p+1 points fall back to Lanczos)               */
 
+#define CD_APPLY3D_AUTO 0   /* 3D operator kernel variant chosen from the level's grid size      */
+#define CD_APPLY3D_MARCH 1  /* blocks march over their x1 range one input plane at a time      */
+#define CD_APPLY3D_SHORT 2  /* one output plane per block, its 2p+1 input planes side by side
+                              (p <= 3; the marching kernel otherwise)                       */
+#define CD_APPLY3D_GROUP 3  /* four thread groups per block take four input planes at a time  */
+
 #define CD_FP64 0          /* every step in FP64                                              */
 #define CD_MIXED_FP32 1    /* V-cycle (smoother, transfers, level operators, T-solves, GMRES
                               vectors) in FP32; outer residual, Krylov inner products and the
@@ -108,23 +114,29 @@ typedef struct {
                              more steps pay: measured at 3D p=3 n=128 beta = 1e-6, 379
                              outer iterations with 16, 238 with 32, 1.84 against 1.47 s per
                              solve; at beta >= 1e-4, 16 is faster) */
-    int apply_x1_chunk;   /* 3D operator kernel: x1 planes each block marches over (the
-                             launch geometry only; results depend on it only through the
-                             rounding of the per-block partial dot products and, in FP32,
-                             the last bit of a Chebyshev update); 0 = chosen from the grid
-                             size (on small grids: the variant that processes a block's
-                             2p+1 input planes side by side) */
+    int apply_x1_chunk;   /* 3D operator kernel: x1 planes each block covers (the launch
+                             geometry only; results depend on it only through the rounding
+                             of the per-block partial dot products and, in FP32, the last
+                             bit of a Chebyshev update); 0 = chosen from the grid size.
+                             Applies to the marching and grouped-march variants            */
     int eig_bounds;       /* CD_BOUNDS_LANCZOS (default) or CD_BOUNDS_SYMBOL                 */
     double bound_safety;  /* CD_BOUNDS_SYMBOL: hi = bound_safety x symbol maximum; 0 = 1.5
                              (the symbol describes the interior of the spectrum; the boundary
                              rows of diag^{-1} A put outliers up to 1.42x above it in 3D,
                              1.23x in 2D, on the operators measured)                        */
+    int apply3d_kernel;   /* CD_APPLY3D_*: variant of the 3D operator kernel for y = A x, the
+                             residual and the Chebyshev step (the kernels with fused dot
+                             products always march); every variant sums each output entry's
+                             terms in the same order, so A x does not depend on it.  A fixed
+                             apply_x1_chunk implies CD_APPLY3D_MARCH under AUTO.  Default
+                             AUTO.                                                          */
 } cd_options;
 
 /* Fill *opt with the defaults: P_MIM, knot insertion, FP64, rtol 1e-8,
  * max_iter 10000, coarse_max_dofs 2500, cheb_degree 48, cheb_ratio 1000,
  * lanczos_steps 20, krylov_steps = p, graphs 1, cheb_degree_coarse -1 (16,
- * or 32 when beta < 1e-5 alpha), apply_x1_chunk 0, eig_bounds Lanczos.  The
+ * or 32 when beta < 1e-5 alpha), apply_x1_chunk 0, eig_bounds Lanczos,
+ * apply3d_kernel AUTO.  The
  * smoother settings were chosen by measured solve rate on 2D and 3D
  * problems; a wide interval needs the eigenvalue bound to cover the top of
  * the spectrum, which the Lanczos estimate times 1.1 does on every tested

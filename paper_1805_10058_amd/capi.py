@@ -30,6 +30,10 @@ CD_XFER_KNOT = 0
 CD_XFER_PAPER = 1
 CD_BOUNDS_LANCZOS = 0
 CD_BOUNDS_SYMBOL = 1
+CD_APPLY3D_AUTO = 0
+CD_APPLY3D_MARCH = 1
+CD_APPLY3D_SHORT = 2
+CD_APPLY3D_GROUP = 3
 CD_FP64 = 0
 CD_MIXED_FP32 = 1
 
@@ -46,7 +50,8 @@ class cd_options(ctypes.Structure):
                 ("krylov_steps", ctypes.c_int), ("graphs", ctypes.c_int), ("cheb_degree_coarse", ctypes.c_int),
                 ("apply_x1_chunk", ctypes.c_int),
                 ("eig_bounds", ctypes.c_int),
-                ("bound_safety", ctypes.c_double)]
+                ("bound_safety", ctypes.c_double),
+                ("apply3d_kernel", ctypes.c_int)]
 
 
 class cd_kernel_stats(ctypes.Structure):

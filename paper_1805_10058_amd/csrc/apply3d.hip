@@ -1,6 +1,7 @@
 // 3D curl-div operator apply (sum factorization), one object per (precision,
 // half bandwidth): compiled with -DCD_T=<float|double> -DCD_HB=<1..6>.
 #include "apply_common.hpp"
+#include "curldiv.h"
 
 namespace cd {
 namespace {
@@ -91,6 +92,24 @@ __device__ inline void buf_store(float v, __amdgpu_buffer_rsrc_t r, unsigned off
 __device__ inline void buf_store(double v, __amdgpu_buffer_rsrc_t r, unsigned off) {
     using u2 = unsigned __attribute__((ext_vector_type(2)));
     __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u2, v), r, off, 0, 0);
+}
+
+// W[c][{S, M, A}] from the axis-2/axis-3 products of one plane, shared by
+// every variant.  The three-term sums are written as explicit fused
+// multiply-adds: left to the compiler, their contraction was seen to differ
+// between kernels (FP64, p = 6), and every variant must round alike.
+template <typename T>
+__device__ inline void combine_w(const T (&mm)[3], const T (&sm)[3], const T (&am)[3], const T (&ms)[3],
+                                 const T (&ma)[3], const T (&aa)[3], T al, T be, T ab, T (&W)[9]) {
+    W[0] = be * mm[0];
+    W[1] = al * (sm[0] + ms[0]);
+    W[2] = ab * (ma[1] + am[2]);
+    W[3] = al * mm[1];
+    W[4] = fma(ab, aa[2], fma(be, ms[1], al * sm[1]));
+    W[5] = ab * ma[0];
+    W[6] = al * mm[2];
+    W[7] = fma(ab, aa[1], fma(al, ms[2], be * sm[2]));
+    W[8] = ab * am[0];
 }
 
 template <typename T, int HB>
@@ -311,15 +330,10 @@ __global__ __launch_bounds__(k3Rows<T>() * k3E3) void k_apply3d(OpDev<T> op, con
                                 if (c != 0) aa[c] = fma(cb[1][k], s[k], aa[c]);
                             }
                         }
-                        W[0][0] = be * mm[0];
-                        W[0][1] = al * (sm[0] + ms[0]);
-                        W[0][2] = ab * (ma[1] + am[2]);
-                        W[1][0] = al * mm[1];
-                        W[1][1] = al * sm[1] + be * ms[1] + ab * aa[2];
-                        W[1][2] = ab * ma[0];
-                        W[2][0] = al * mm[2];
-                        W[2][1] = be * sm[2] + al * ms[2] + ab * aa[1];
-                        W[2][2] = ab * am[0];
+                        T w9[9];
+                        combine_w(mm, sm, am, ms, ma, aa, al, be, ab, w9);
+#pragma unroll
+                        for (int i = 0; i < 9; ++i) W[i / 3][i % 3] = w9[i];
                     }
 #pragma unroll
                     for (int k = 0; k < R; ++k) {
@@ -451,7 +465,10 @@ __global__ __launch_bounds__((2 * HB + 1) * k3ShortRows<T>() * k3E3) void k_appl
     const int o2 = (tile % g.nt2) * TR;
     const int o3 = ((tile / g.nt2) % g.nt3) * T3;
     const int io = tile / (g.nt2 * g.nt3);  // the block's output plane
-    const int grp = threadIdx.x / NP, tid = threadIdx.x % NP;
+    // a group is whole waves (NP is a multiple of 64): its index is wave-uniform,
+    // and read into a scalar register so that plane descriptors and table rows
+    // built from it stay scalar
+    const int grp = __builtin_amdgcn_readfirstlane(int(threadIdx.x) / NP), tid = threadIdx.x % NP;
     const int j = io - HB + grp;                 // this group's input plane
     const bool jlive = (j >= 0 && j < m1);       // uniform within the group
     const int ty = tid / E3, tx = tid % E3;
@@ -569,15 +586,7 @@ __global__ __launch_bounds__((2 * HB + 1) * k3ShortRows<T>() * k3E3) void k_appl
             }
         }
         T W[9];
-        W[0] = be * mm[0];
-        W[1] = al * (sm[0] + ms[0]);
-        W[2] = ab * (ma[1] + am[2]);
-        W[3] = al * mm[1];
-        W[4] = al * sm[1] + be * ms[1] + ab * aa[2];
-        W[5] = ab * ma[0];
-        W[6] = al * mm[2];
-        W[7] = be * sm[2] + al * ms[2] + ab * aa[1];
-        W[8] = ab * am[0];
+        combine_w(mm, sm, am, ms, ma, aa, al, be, ab, W);
         T* wd = ws + size_t(grp) * 9 * NP;
 #pragma unroll
         for (int i = 0; i < 9; ++i) wd[i * NP + tid] = W[i];
@@ -623,27 +632,314 @@ __global__ __launch_bounds__((2 * HB + 1) * k3ShortRows<T>() * k3E3) void k_appl
     stamp_end(stamp);
 }
 
+// ------------------------------------------------------------------------------
+// Grouped marches: a block of G groups of 32 TRS threads (TRS tile rows) owns
+// an output tile and a range [o0, o1) of x1 planes, like the marching kernel,
+// but takes its input planes G at a time.  In phase p, group g computes
+// stages A and B of input plane o0 - HB + G p + g and leaves its W in a ring
+// of G + 2 HB planes in LDS; after a barrier, group g sums the axis-1
+// contributions of output plane o0 - 2 HB + G p + g from the ring, in the
+// marching kernel's order and with the same fused multiply-adds (A x is
+// bitwise that of the marching kernel), and runs the epilogue.  A range of L
+// planes costs L + 2 HB planes of in-plane work and L sums, where the marching
+// kernel pays L + 2 HB of both; G groups per block let the ranges be G times
+// longer at the same number of waves, so the halo planes weigh less.  Input
+// tiles of the next phase and the epilogue operands of the next output plane
+// are loaded while the current phase computes; two barriers per phase.
+// ------------------------------------------------------------------------------
+template <typename T, int HB>
+struct TileG {
+    static constexpr int TR = k3ShortRows<T>();
+    static constexpr int NP = TR * k3E3;              // threads per group
+    static constexpr int GR = k3Groups;               // groups: input planes per phase
+    static constexpr int NT = GR * NP;
+    static constexpr int R = 2 * HB + 1;
+    static constexpr int RING = GR + 2 * HB;          // W planes held
+    static constexpr int E2 = TR + 2 * HB;
+    static constexpr int NIN = E2 * k3E3;
+    static constexpr int NX = 3 * NIN;
+    static constexpr int NLC = (NIN + NP - 1) / NP;
+    static constexpr int NC = 3 * R + 2;
+    static constexpr bool CAREG = sizeof(T) == 4;
+    static constexpr size_t lds_words() {
+        return size_t(GR) * NX + size_t(RING) * 9 * NP + (CAREG ? 0 : 3 * size_t(R) * TR);
+    }
+};
+
+template <typename T, int HB, int MODE>
+__global__ __launch_bounds__(k3Groups * k3ShortRows<T>() * k3E3) void k_apply3d_group(
+    OpDev<T> op, const T* __restrict__ x, T* __restrict__ y, const T* __restrict__ b, const T* xprev, T* xout, T c1,
+    T c2, Apply3dGeom g, unsigned long long* stamp, const T* __restrict__ c1g) {
+    using Q = TileG<T, HB>;
+    constexpr int TR = Q::TR, NP = Q::NP, GR = Q::GR, R = Q::R, RING = Q::RING, E3 = k3E3, T3 = k3T3(HB);
+    constexpr int NIN = Q::NIN, NX = Q::NX, NLC = Q::NLC, NC = Q::NC;
+    constexpr unsigned S = sizeof(T);
+    stamp_begin(stamp);
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    T* xs = reinterpret_cast<T*>(smem_raw);  // [GR][3][E2][E3] input tiles, one per group
+    T* ws = xs + size_t(GR) * NX;            // [RING][9][NP] W of the ring's planes
+    T* ca = ws + size_t(RING) * 9 * NP;      // [3][R][TR] when not in registers
+    const int m1 = op.m[0], m2 = op.m[1], m3 = op.m[2];
+    const unsigned PL = unsigned(m2) * m3, G = unsigned(m1) * PL;
+    const int xcd = int(blockIdx.x % kXcds), slot = int(blockIdx.x / kXcds);
+    const int per = g.nblocks / kXcds, rem = g.nblocks % kXcds;
+    const int tile = xcd * per + min(xcd, rem) + slot;
+    const int o2 = (tile % g.nt2) * TR;
+    const int o3 = ((tile / g.nt2) % g.nt3) * T3;
+    const int o0 = (tile / (g.nt2 * g.nt3)) * g.c1len;
+    const int o1 = min(o0 + g.c1len, m1);
+    // a group is whole waves (NP is a multiple of 64): its index is wave-uniform,
+    // and read into a scalar register so that plane descriptors, table rows and
+    // ring slots built from it stay scalar
+    const int grp = __builtin_amdgcn_readfirstlane(int(threadIdx.x) / NP), tid = threadIdx.x % NP;
+    const int ty = tid / E3, tx = tid % E3;
+    const int i2 = o2 + ty, i3 = o3 - HB + tx;
+    const bool active = (tx >= HB) && (tx < E3 - HB) && (i2 < m2) && (i3 < m3);
+    const int i2c = min(i2, m2 - 1), i3c = min(max(i3, 0), m3 - 1);
+    const unsigned ptb = active ? (unsigned(i2c) * m3 + unsigned(i3c)) * S : kOob;
+    auto plane_rsrc = [&](const T* base, int c, int jj) {
+        const bool jin = (jj >= 0 && jj < m1);
+        return make_rsrc(base + (size_t(c) * G + size_t(jin ? jj : 0) * PL), jin ? PL * S : 0u);
+    };
+    T car[Q::CAREG ? 3 : 1][Q::CAREG ? R : 1];
+    if constexpr (Q::CAREG) {
+#pragma unroll
+        for (int w = 0; w < 3; ++w)
+#pragma unroll
+            for (int k = 0; k < R; ++k) car[w][k] = op.band[1][w][k * m2 + i2c];
+    } else {
+        for (int e = threadIdx.x; e < 3 * R * TR; e += Q::NT) {
+            const int i = e % TR, k = (e / TR) % R, w = e / (TR * R);
+            ca[e] = op.band[1][w][k * m2 + min(o2 + i, m2 - 1)];
+        }
+    }
+    T cb[3][R];
+#pragma unroll
+    for (int w = 0; w < 3; ++w)
+#pragma unroll
+        for (int k = 0; k < R; ++k) cb[w][k] = active ? op.band[2][w][k * m3 + i3] : T(0);
+    T dmm = T(0), dsm = T(0), dms = T(0);
+    if (MODE == kApplyCheb) {
+        const T dm1 = op.band[1][0][HB * m2 + i2c], ds1 = op.band[1][2][HB * m2 + i2c];
+        const T dm2 = op.band[2][0][HB * m3 + i3c], ds2 = op.band[2][2][HB * m3 + i3c];
+        dmm = dm1 * dm2;
+        dsm = ds1 * dm2;
+        dms = dm1 * ds2;
+    }
+    const T al = op.alpha, be = op.beta, ab = offdiag_weight(op);
+
+    // this thread's entries of its group's input tile (offsets out of range outside the grid)
+    unsigned loffb[NLC];
+#pragma unroll
+    for (int q = 0; q < NLC; ++q) {
+        const int e = min(tid + q * NP, NIN - 1);
+        const int g2 = o2 - HB + e / E3, g3 = o3 - HB + e % E3;
+        const bool in = g2 >= 0 && g2 < m2 && g3 >= 0 && g3 < m3;
+        loffb[q] = in ? (unsigned(g2) * m3 + unsigned(g3)) * S : kOob;
+    }
+    T v[3][NLC];
+    auto load_plane = [&](int jj) {
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            const auto r = plane_rsrc(x, c, jj);
+#pragma unroll
+            for (int q = 0; q < NLC; ++q) v[c][q] = buf_load(r, loffb[q], T(0));
+        }
+    };
+    T eb[3], ex[3], ep[3];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) eb[c] = ex[c] = ep[c] = T(0);
+    const bool use_prev = (c1 != T(0) && xprev != nullptr);
+    auto epi_load = [&](int io) {
+        if (io < o0 || io >= o1) return;
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            if (MODE == kApplyRes || MODE == kApplyCheb) eb[c] = buf_load(plane_rsrc(b, c, io), ptb, T(0));
+            if (MODE == kApplyCheb) {
+                ex[c] = buf_load(plane_rsrc(x, c, io), ptb, T(0));
+                ep[c] = use_prev ? buf_load(plane_rsrc(xprev, c, io), ptb, T(0)) : T(0);
+            }
+        }
+    };
+    auto stencil = [&](T val, T (&st)[R]) {
+        st[HB] = val;
+#pragma unroll
+        for (int d = 1; d <= HB; ++d) {
+            st[HB - d] = lane_shift<kDppShr1>(st[HB - d + 1]);
+            st[HB + d] = lane_shift<kDppShl1>(st[HB + d - 1]);
+        }
+    };
+
+    const int TI = (o1 - o0) + 2 * HB;  // input planes of the range
+    const int NPH = (TI + GR - 1) / GR;  // phases
+    load_plane(o0 - HB + grp);
+    epi_load(o0 - 2 * HB + grp);
+    T* xg = xs + size_t(grp) * NX;
+    for (int ph = 0; ph < NPH; ++ph) {
+        const int t = ph * GR + grp;  // this group's input plane index in the range
+        const int j = o0 - HB + t;
+        const bool jlive = t < TI && j >= 0 && j < m1;
+#pragma unroll
+        for (int c = 0; c < 3; ++c)
+#pragma unroll
+            for (int q = 0; q < NLC; ++q) {
+                const int e = tid + q * NP;
+                if ((q + 1) * NP <= NIN || e < NIN) xg[c * NIN + e] = v[c][q];
+            }
+        if (t + GR < TI) load_plane(j + GR);  // the next phase's tile
+        __syncthreads();                      // (1) tiles of the phase in LDS
+        if (jlive) {
+            T sa[9];
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+                T aM = T(0), aA = T(0), aS = T(0);
+#pragma unroll
+                for (int k = 0; k < R; ++k) {
+                    const T xv = xg[c * NIN + (ty + k) * E3 + tx];
+                    if constexpr (Q::CAREG) {
+                        aM = fma(car[0][k], xv, aM);
+                        aA = fma(car[1][k], xv, aA);
+                        aS = fma(car[2][k], xv, aS);
+                    } else {
+                        aM = fma(ca[(0 * R + k) * TR + ty], xv, aM);
+                        aA = fma(ca[(1 * R + k) * TR + ty], xv, aA);
+                        aS = fma(ca[(2 * R + k) * TR + ty], xv, aS);
+                    }
+                }
+                sa[3 * c + 0] = aM;
+                sa[3 * c + 1] = aA;
+                sa[3 * c + 2] = aS;
+            }
+            T mm[3], sm[3], am[3], ms[3], ma[3], aa[3];
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+                mm[c] = sm[c] = am[c] = ms[c] = ma[c] = aa[c] = T(0);
+                T st[R];
+                stencil(sa[3 * c + 0], st);
+#pragma unroll
+                for (int k = 0; k < R; ++k) {
+                    mm[c] = fma(cb[0][k], st[k], mm[c]);
+                    sm[c] = fma(cb[2][k], st[k], sm[c]);
+                    if (c != 1) am[c] = fma(cb[1][k], st[k], am[c]);
+                }
+                stencil(sa[3 * c + 2], st);
+#pragma unroll
+                for (int k = 0; k < R; ++k) ms[c] = fma(cb[0][k], st[k], ms[c]);
+                stencil(sa[3 * c + 1], st);
+#pragma unroll
+                for (int k = 0; k < R; ++k) {
+                    if (c != 2) ma[c] = fma(cb[0][k], st[k], ma[c]);
+                    if (c != 0) aa[c] = fma(cb[1][k], st[k], aa[c]);
+                }
+            }
+            T W[9];
+            combine_w(mm, sm, am, ms, ma, aa, al, be, ab, W);
+            T* wd = ws + size_t(t % RING) * 9 * NP + tid;
+#pragma unroll
+            for (int i = 0; i < 9; ++i) wd[i * NP] = W[i];
+        }
+        __syncthreads();  // (2) W of the phase's planes in the ring
+        const int io = o0 - 2 * HB + t;  // this group's output plane
+        if (io >= o0 && io < o1) {
+            T kx[3] = {T(0), T(0), T(0)};
+#pragma unroll
+            for (int gg = 0; gg < R; ++gg) {
+                const int jj = io - HB + gg;
+                if (jj >= 0 && jj < m1) {
+                    const T* row = c1g + unsigned(jj + HB) * NC;  // table row of plane jj
+                    const int k = 2 * HB - gg;                    // X1(io, jj) = row[w R + k]
+                    const T cM = row[0 * R + k], cA = row[1 * R + k], cS = row[2 * R + k];
+                    const T* wsrc = ws + size_t((t - 2 * HB + gg) % RING) * 9 * NP + tid;
+#pragma unroll
+                    for (int c = 0; c < 3; ++c) {
+                        kx[c] = fma(cS, wsrc[(3 * c + 0) * NP], kx[c]);
+                        kx[c] = fma(cM, wsrc[(3 * c + 1) * NP], kx[c]);
+                        kx[c] = fma(cA, wsrc[(3 * c + 2) * NP], kx[c]);
+                    }
+                }
+            }
+            const T* drow = c1g + unsigned(io + 2 * HB) * NC;  // diagonal entries of plane io
+            const T d0m = drow[3 * R], d0s = drow[3 * R + 1];
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+                if (MODE == kApplyY) {
+                    buf_store(kx[c], plane_rsrc(y, c, io), ptb);
+                } else if (MODE == kApplyRes) {
+                    buf_store(eb[c] - kx[c], plane_rsrc(y, c, io), ptb);
+                } else {  // Chebyshev step
+                    const T dg = (c == 0 ? be : al) * d0s * dmm + (c == 1 ? be : al) * d0m * dsm +
+                                 (c == 2 ? be : al) * d0m * dms;
+                    const T r = eb[c] - kx[c];
+                    T upd;
+                    if constexpr (sizeof(T) == 4)
+                        upd = c2 * r * __builtin_amdgcn_rcpf(active ? dg : T(1));
+                    else
+                        upd = c2 * r / (active ? dg : T(1));
+                    buf_store(ex[c] + (c1 * (ex[c] - ep[c]) + upd), plane_rsrc(xout, c, io), ptb);
+                }
+            }
+        }
+        epi_load(io + GR);  // the next phase's output plane
+    }
+    stamp_end(stamp);
+}
+
+// The variant for one launch: the caller's choice, else the short-march
+// variant on small grids (apply3d_geom_short), the grouped march where the
+// marching kernel's ranges would be short (apply3d_prefer_group) and the
+// marching kernel otherwise.  Kernels with fused dot products always march.
+template <typename T, int HB, int MODE>
+int apply3d_variant(const OpDev<T>& op) {
+    constexpr bool kPlain = (MODE == kApplyY || MODE == kApplyRes || MODE == kApplyCheb);
+    if (!kPlain) return CD_APPLY3D_MARCH;
+    int v = op.variant;
+    if (v == CD_APPLY3D_AUTO) {
+        if (op.x1chunk != 0) return CD_APPLY3D_MARCH;
+        if (apply3d_geom_short(op.m, HB, sizeof(T), 0).nblocks > 0)
+            v = CD_APPLY3D_SHORT;
+        else if (apply3d_prefer_group(op.m, HB, sizeof(T)))
+            v = CD_APPLY3D_GROUP;
+        else
+            v = CD_APPLY3D_MARCH;
+    }
+    if (v == CD_APPLY3D_SHORT && HB > 3) v = CD_APPLY3D_MARCH;
+    return v;
+}
+
 template <typename T, int HB, int MODE>
 void launch3d(const OpDev<T>& op, const T* x, T* y, const T* b, T* u, T* xout, T c1, T c2, double* part, int nv,
               unsigned long long* stamp, hipStream_t s) {
-    using Q = Tile3<T, HB>;
-    const Apply3dGeom g = apply3d_geom(op.m, HB, sizeof(T), op.x1chunk);
     if (size_t(3) * op.m[0] * op.m[1] * op.m[2] >= (size_t(1) << 31))
         throw std::runtime_error("3D operator kernel: too many unknowns for 32-bit offsets");
     if (size_t(op.m[1]) * op.m[2] * sizeof(T) >= (size_t(1) << 31))
         throw std::runtime_error("3D operator kernel: a grid plane exceeds the 2 GiB of a buffer descriptor");
-    if constexpr (HB <= 3 && (MODE == kApplyY || MODE == kApplyRes || MODE == kApplyCheb)) {
-        const Apply3dGeom gs = apply3d_geom_short(op.m, HB, sizeof(T), op.x1chunk);
-        if (gs.nblocks > 0) {
-            using QS = TileS<T, HB>;
-            const size_t lds = QS::lds_words() * sizeof(T);
-            auto kern = k_apply3d_short<T, HB, MODE>;
+    const int variant = apply3d_variant<T, HB, MODE>(op);
+    if constexpr (MODE == kApplyY || MODE == kApplyRes || MODE == kApplyCheb) {
+        if constexpr (HB <= 3) {
+            if (variant == CD_APPLY3D_SHORT) {
+                using QS = TileS<T, HB>;
+                const Apply3dGeom gs = apply3d_geom_short(op.m, HB, sizeof(T), 0, true);
+                const size_t lds = QS::lds_words() * sizeof(T);
+                auto kern = k_apply3d_short<T, HB, MODE>;
+                allow_lds(reinterpret_cast<const void*>(kern), lds);
+                hipLaunchKernelGGL(kern, dim3(gs.nblocks), dim3(QS::NT), lds, s, op, x, y, b, u, xout, c1, c2, gs,
+                                   stamp, op.c1p);
+                return;
+            }
+        }
+        if (variant == CD_APPLY3D_GROUP) {
+            using QG = TileG<T, HB>;
+            const Apply3dGeom gg = apply3d_geom_group(op.m, HB, sizeof(T), op.x1chunk);
+            const size_t lds = QG::lds_words() * sizeof(T);
+            auto kern = k_apply3d_group<T, HB, MODE>;
             allow_lds(reinterpret_cast<const void*>(kern), lds);
-            hipLaunchKernelGGL(kern, dim3(gs.nblocks), dim3(QS::NT), lds, s, op, x, y, b, u, xout, c1, c2, gs, stamp,
+            hipLaunchKernelGGL(kern, dim3(gg.nblocks), dim3(QG::NT), lds, s, op, x, y, b, u, xout, c1, c2, gg, stamp,
                                op.c1p);
             return;
         }
     }
+    using Q = Tile3<T, HB>;
+    const Apply3dGeom g = apply3d_geom(op.m, HB, sizeof(T), op.x1chunk);
     const size_t lds = Q::lds_words() * sizeof(T);
     auto kern = k_apply3d<T, HB, MODE>;
     allow_lds(reinterpret_cast<const void*>(kern), lds);

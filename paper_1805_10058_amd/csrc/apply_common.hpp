@@ -81,20 +81,57 @@ inline Apply3dGeom apply3d_geom(const int* m, int hb, size_t elem, int x1chunk =
 // and at most 3072 waves in all (measured: 17^3 8.0 against 10.4 us per
 // Chebyshev step in FP32, 7.0 against 12.5 us in FP64; at 33^3 and above the
 // marching kernel is faster).
-inline Apply3dGeom apply3d_geom_short(const int* m, int hb, size_t elem, int x1chunk) {
+// With force, the geometry regardless of the rule (for HB <= 3).
+inline Apply3dGeom apply3d_geom_short(const int* m, int hb, size_t elem, int x1chunk, bool force = false) {
     Apply3dGeom g{0, 0, 1, 0};
     if (x1chunk != 0 || hb > 3) return g;
     const int rows = elem == 4 ? k3Rows<float>() : k3Rows<double>();
     const int planar = ((m[1] + rows - 1) / rows) * ((m[2] + k3T3(hb) - 1) / k3T3(hb));
-    if (std::max(1, std::min(m[0], 1024 / planar)) < m[0]) return g;  // ranges of more than one plane
+    if (!force && std::max(1, std::min(m[0], 1024 / planar)) < m[0]) return g;  // ranges of more than one plane
     const int srows = elem == 4 ? k3ShortRows<float>() : k3ShortRows<double>();
     const int nt2 = (m[1] + srows - 1) / srows, nt3 = (m[2] + k3T3(hb) - 1) / k3T3(hb);
     const long waves = long(nt2) * nt3 * m[0] * (2 * hb + 1) * srows / 2;  // 32 srows threads per group
-    if (waves > 3072) return g;
+    if (!force && waves > 3072) return g;
     g.nt2 = nt2;
     g.nt3 = nt3;
     g.nblocks = nt2 * nt3 * m[0];
     return g;
+}
+
+// Grouped-march variant of the 3D kernel: k3Groups groups of 32 k3ShortRows
+// threads per block, each taking one input plane per phase.  Ranges are set
+// from a target number of waves in all (what fits at once: 4 per SIMD in
+// FP32, 2 in FP64), then lengthened so that the range and its 2 HB halo
+// planes fill whole phases.
+constexpr int k3Groups = 4;
+// x1chunk > 0 fixes the range length instead.
+inline Apply3dGeom apply3d_geom_group(const int* m, int hb, size_t elem, int x1chunk) {
+    const int waves = elem == 4 ? 4096 : 2048;  // FP64: 2 waves per SIMD fit (registers)
+    Apply3dGeom g{0, 0, 1, 0};
+    const int srows = elem == 4 ? k3ShortRows<float>() : k3ShortRows<double>();
+    const int wpb = k3Groups * srows / 2;  // waves per block
+    g.nt2 = (m[1] + srows - 1) / srows;
+    g.nt3 = (m[2] + k3T3(hb) - 1) / k3T3(hb);
+    const int planar = g.nt2 * g.nt3;
+    const int nx1 = std::max(1, std::min(m[0], waves / wpb / planar));
+    const int len = (m[0] + nx1 - 1) / nx1;
+    const int phases = (len + 2 * hb + k3Groups - 1) / k3Groups;
+    g.c1len = x1chunk > 0 ? std::min(x1chunk, m[0]) : std::min(m[0], phases * k3Groups - 2 * hb);
+    g.nblocks = planar * ((m[0] + g.c1len - 1) / g.c1len);
+    return g;
+}
+
+// Whether the grouped march beats the marching kernel on a grid: where the
+// marching kernel's ranges are short, its halo planes dominate and the
+// grouped march's longer ranges pay for its LDS exchange of W.  Measured per
+// Chebyshev step (FP32): p=3, m = 33 (marching ranges of 2) 11.4 against
+// 13.3 us; m = 65 (ranges of 4) 21.3 against 20.6; m = 129 (11) 59 against
+// 55; p=2, m = 64 and 32, 13.8 / 9.0 against 14.8 / 10.2; p=4, m = 66 and
+// below 12-22 against 16-27.  FP64 gains up to ranges of HB + 1: p=3,
+// m = 65, 23.4 against 28.1 us.
+inline bool apply3d_prefer_group(const int* m, int hb, size_t elem) {
+    const int len = apply3d_geom(m, hb, elem, 0).c1len;
+    return len < m[0] && len <= hb + (elem == 8 ? 1 : 0);
 }
 
 // Partial dot products an operator kernel accumulates per thread.

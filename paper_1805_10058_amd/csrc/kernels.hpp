@@ -23,6 +23,7 @@ struct OpDev {
     int m[3];   // unknowns per axis (m[2] = 1 in 2D)
     int hb;     // half bandwidth (= p on every level)
     int x1chunk;  // 3D kernel: x1 planes per block (0: chosen from the grid size)
+    int variant;  // 3D kernel: CD_APPLY3D_* (0: chosen from the grid size)
     int blockdiag;  // 1: the block-diagonal part D of the operator (off-diagonal blocks dropped)
     int dim;
     T alpha, beta;

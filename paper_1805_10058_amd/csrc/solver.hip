@@ -283,6 +283,8 @@ void validate(const cd_problem* pr, const cd_options* op) {
         throw CdError(CD_EINVAL, "unknown eig_bounds");
     if (!(op->bound_safety == 0.0 || (op->bound_safety >= 1.0 && op->bound_safety <= 10.0)))
         throw CdError(CD_EINVAL, "bound_safety must be 0 or in [1, 10]");
+    if (op->apply3d_kernel < CD_APPLY3D_AUTO || op->apply3d_kernel > CD_APPLY3D_GROUP)
+        throw CdError(CD_EINVAL, "unknown apply3d_kernel");
     if (op->coarse_max_dofs < 1 || op->coarse_max_dofs > 8192)
         throw CdError(CD_EINVAL, "coarse_max_dofs must be in 1..8192");
     // the operator kernels use fixed-size LDS tiles (no limit on the grid) and
@@ -370,6 +372,7 @@ cd::OpDev<T> make_op(cd_solver* s, const LevelHost& L, hipStream_t st) {
     op.dim = s->d;
     op.hb = s->p;
     op.x1chunk = s->opt.apply_x1_chunk;
+    op.variant = s->opt.apply3d_kernel;
     op.blockdiag = (s->opt.method == CD_METHOD_PWL) ? 1 : 0;  // P_WL cycles on D (Sec. 6.1, eq. diag)
     op.alpha = T(s->prob.alpha);
     op.beta = T(s->prob.beta);
@@ -1334,6 +1337,7 @@ void cd_default_options(cd_options* o) {
     o->apply_x1_chunk = 0;
     o->eig_bounds = CD_BOUNDS_LANCZOS;
     o->bound_safety = 0.0;
+    o->apply3d_kernel = CD_APPLY3D_AUTO;
 }
 
 size_t cd_num_dofs(const cd_problem* pr) {

@@ -37,43 +37,56 @@ if not gpu_ok():
 from oracle import method  # noqa: E402
 from paper_1805_10058_amd import capi  # noqa: E402
 
-# (dim, p, n, beta, transfer, coarse_max, x1 chunk of the 3D kernel; 0 = automatic)
+# (dim, p, n, beta, transfer, coarse_max, x1 chunk of the 3D kernel (0 =
+# automatic), 3D kernel variant)
 CASES = [
-    (2, 2, 40, 0.05, "knot", 100, 0),
-    (2, 3, 64, 1e-2, "knot", 300, 0),
-    (2, 4, 24, 0.5, "paper", 80, 0),
-    (3, 2, 20, 0.1, "knot", 500, 3),
-    (3, 3, 16, 0.01, "knot", 700, 3),
-    (3, 3, 16, 0.01, "knot", 700, 5),
-    (3, 4, 10, 1.0, "paper", 600, 4),
-    (3, 6, 8, 0.3, "knot", 2000, 3),
-    (3, 2, 20, 0.1, "knot", 500, 0),
+    (2, 2, 40, 0.05, "knot", 100, 0, "auto"),
+    (2, 3, 64, 1e-2, "knot", 300, 0, "auto"),
+    (2, 4, 24, 0.5, "paper", 80, 0, "auto"),
+    (3, 2, 20, 0.1, "knot", 500, 3, "auto"),
+    (3, 3, 16, 0.01, "knot", 700, 3, "auto"),
+    (3, 3, 16, 0.01, "knot", 700, 5, "auto"),
+    (3, 4, 10, 1.0, "paper", 600, 4, "auto"),
+    (3, 6, 8, 0.3, "knot", 2000, 3, "auto"),
+    (3, 2, 20, 0.1, "knot", 500, 0, "auto"),
     # n_l = nu_l n (anisotropic grids), an odd n (its axis coarsens with the
     # paper's prolongator), and an axis that stops at one point
-    (2, 3, (24, 40), 0.05, "knot", 300, 0),
-    (3, 2, (8, 12, 16), 0.1, "knot", 500, 3),
-    (2, 3, 25, 0.1, "knot", 60, 0),
-    (3, 2, (7, 8, 6), 0.2, "knot", 30, 2),
-    (2, 2, (4, 64), 0.3, "knot", 10, 0),
+    (2, 3, (24, 40), 0.05, "knot", 300, 0, "auto"),
+    (3, 2, (8, 12, 16), 0.1, "knot", 500, 3, "auto"),
+    (2, 3, 25, 0.1, "knot", 60, 0, "auto"),
+    (3, 2, (7, 8, 6), 0.2, "knot", 30, 2, "auto"),
+    (2, 2, (4, 64), 0.3, "knot", 10, 0, "auto"),
+    # the grouped-march variant of the 3D kernel: its own geometry, one range
+    # over the whole x1 axis (several phases, the last one partly idle),
+    # ragged ranges, p = 6 and an anisotropic grid
+    (3, 3, 16, 0.01, "knot", 700, 0, "group"),
+    (3, 3, 16, 0.01, "knot", 700, 17, "group"),
+    (3, 2, 20, 0.1, "knot", 500, 7, "group"),
+    (3, 4, 10, 1.0, "paper", 600, 0, "group"),
+    (3, 6, 8, 0.3, "knot", 2000, 0, "group"),
+    (3, 2, (8, 12, 16), 0.1, "knot", 500, 0, "group"),
 ]
+KERNELS = {"auto": capi.CD_APPLY3D_AUTO, "march": capi.CD_APPLY3D_MARCH, "short": capi.CD_APPLY3D_SHORT,
+           "group": capi.CD_APPLY3D_GROUP}
 
 
 def _nid(n):
     return "x".join(map(str, n)) if isinstance(n, tuple) else str(n)
 
 
-IDS = [f"d{c[0]}p{c[1]}n{_nid(c[2])}b{c[3]}{c[4]}x{c[6]}" for c in CASES]
+IDS = [f"d{c[0]}p{c[1]}n{_nid(c[2])}b{c[3]}{c[4]}x{c[6]}{'' if c[7] == 'auto' else c[7]}" for c in CASES]
 U64, U32 = 2.0 ** -53, 2.0 ** -24
 
 _cache = {}
 
 
 def setup(case, precision=capi.CD_FP64):
-    d, p, n, beta, xfer, cmax, chunk = case
+    d, p, n, beta, xfer, cmax, chunk, kern = case
     key = (case, precision)
     if key not in _cache:
         tr = capi.CD_XFER_KNOT if xfer == "knot" else capi.CD_XFER_PAPER
-        opt = capi.options(transfer=tr, coarse_max_dofs=cmax, precision=precision, apply_x1_chunk=chunk)
+        opt = capi.options(transfer=tr, coarse_max_dofs=cmax, precision=precision, apply_x1_chunk=chunk,
+                           apply3d_kernel=KERNELS[kern])
         s = capi.Solver(capi.problem(d, p, n, 1.0, beta), opt, stream())
         m = method.Method(d, p, n, 1.0, beta, transfer=xfer, coarse_max_dofs=cmax, nu=opt.cheb_degree,
                           ratio=opt.cheb_ratio, lanczos_steps=opt.lanczos_steps, nu_coarse=s.coarse_degree())
@@ -192,7 +205,8 @@ def test_vcycle_entrywise(case):
     assert err <= 1e-3
 
 
-CHUNKED = [(c, i) for c, i in zip(CASES, IDS) if c[0] == 3 and c[6] > 0 and not isinstance(c[2], tuple)]
+CHUNKED = [(c, i) for c, i in zip(CASES, IDS)
+           if c[0] == 3 and c[6] > 0 and c[7] == "auto" and not isinstance(c[2], tuple)]
 
 
 @pytest.mark.parametrize("case", [c for c, _ in CHUNKED], ids=[i for _, i in CHUNKED])
@@ -200,7 +214,7 @@ def test_x1_chunk_solve_matches_automatic(case):
     # the launch geometry changes only the per-block partial sums of the dot
     # products: solves agree to the solver tolerance and take the same count
     s, m = setup(case)
-    auto = case[:6] + (0,)
+    auto = case[:6] + (0, "auto")
     s0, _ = setup(auto)
     b = np.random.default_rng(46).uniform(-1, 1, m.K.shape[0])
     bd, x1, x0 = dev(b), empty(b.size), empty(b.size)
@@ -231,3 +245,40 @@ def test_short_march_variant_matches_marching_kernel(d, p, n):
             np.testing.assert_array_equal(host(ya), host(ym))
     auto.close()
     march.close()
+
+
+@pytest.mark.parametrize("d,p,n,chunk", [(3, 3, 12, 0), (3, 2, (9, 14, 20), 0), (3, 1, 10, 0), (3, 3, 16, 0),
+                                         (3, 3, 16, 5), (3, 4, (10, 7, 12), 0), (3, 6, 8, 0), (3, 2, 34, 0)])
+def test_apply3d_variants_agree(d, p, n, chunk):
+    # every variant of the 3D kernel (marching, short-march, grouped march)
+    # sums each output entry's terms in the same order: y = A x bitwise equal
+    # on every level in FP64 and FP32; the Chebyshev smoother within the
+    # rounding of its update (the FP32 step may round its last bit
+    # differently, and 48 steps pass that on)
+    prob = capi.problem(d, p, n, 1.0, 0.2)
+    solvers = {k: capi.Solver(prob, capi.options(coarse_max_dofs=50, apply_x1_chunk=chunk, apply3d_kernel=v),
+                              stream())
+               for k, v in (("march", capi.CD_APPLY3D_MARCH), ("short", capi.CD_APPLY3D_SHORT),
+                            ("group", capi.CD_APPLY3D_GROUP), ("auto", capi.CD_APPLY3D_AUTO))}
+    ref = solvers["march"]
+    rng = np.random.default_rng(48)
+    for l in range(ref.num_levels()):
+        _, nl = ref.level_shape(l)
+        x, b = rng.uniform(-1, 1, nl), rng.uniform(-1, 1, nl)
+        for dt, fn, sm, tol in ((torch.float64, "apply", "smooth", 1e-13), (torch.float32, "apply_f32", "smooth_f32", 1e-5)):
+            xd, bd = dev(x, dt), dev(b, dt)
+            ym, zm = empty(nl, dt), empty(nl, dt)
+            getattr(ref, fn)(l, xd.data_ptr(), ym.data_ptr())
+            if l < ref.num_levels() - 1:
+                getattr(ref, sm)(l, bd.data_ptr(), xd.data_ptr(), zm.data_ptr())
+            for k, s in solvers.items():
+                if k == "march":
+                    continue
+                y, z = empty(nl, dt), empty(nl, dt)
+                getattr(s, fn)(l, xd.data_ptr(), y.data_ptr())
+                np.testing.assert_array_equal(host(y), host(ym), err_msg=f"{k} level {l} {dt}")
+                if l < ref.num_levels() - 1:
+                    getattr(s, sm)(l, bd.data_ptr(), xd.data_ptr(), z.data_ptr())
+                    assert maxrel(host(z), host(zm)) <= tol, (k, l, dt)
+    for s in solvers.values():
+        s.close()

@@ -67,12 +67,14 @@ def test_default_options():
     assert (o.cheb_degree, o.cheb_degree_coarse, o.cheb_ratio, o.lanczos_steps) == (48, -1, 1000.0, 20)
     assert o.krylov_steps < 0 and o.graphs == 1
     assert o.eig_bounds == capi.CD_BOUNDS_LANCZOS and o.bound_safety == 0.0
+    assert o.apply3d_kernel == capi.CD_APPLY3D_AUTO and o.apply_x1_chunk == 0
 
 
 @pytest.mark.parametrize("field,value", [
     ("cheb_degree", 0), ("cheb_degree", 129), ("cheb_degree_coarse", 129), ("lanczos_steps", 0),
     ("lanczos_steps", 201), ("cheb_ratio", 1.0), ("rtol", 0.0), ("max_iter", 0), ("precision", 7),
     ("method", 9), ("transfer", 5), ("eig_bounds", 2), ("bound_safety", 0.5), ("bound_safety", 11.0),
+    ("apply3d_kernel", -1), ("apply3d_kernel", 4), ("apply_x1_chunk", -1),
 ])
 def test_invalid_options_are_rejected(field, value):
     prob = capi.problem(2, 3, 32, 1.0, 0.1)
