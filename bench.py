@@ -32,9 +32,9 @@ HEADLINE = "c4_3d_p3_n128"
 # profiles/c4_3d_p3_n128_solve_kernels.txt.  It holds only for the kernel
 # sources it was measured on (their SHA-256 below); after any change to them
 # the line reports null until the counters are taken again.
-CHEB_TRAFFIC = {"fetch_kib": 71878.5, "write_kib": 30394.9, "fetch_factor": 2.000, "write_factor": 1.000,
+CHEB_TRAFFIC = {"fetch_kib": 71601.7, "write_kib": 30418.7, "fetch_factor": 2.000, "write_factor": 1.000,
                 "sources": ["paper_1805_10058_amd/csrc/apply3d.hip", "paper_1805_10058_amd/csrc/apply_common.hpp"],
-                "sha256": "33c246119bf3c84e3d1063a039b51cf8fa433a5b2e5e03e34f4d4938ea05a08e"}
+                "sha256": "340a17641eb6538cf09ee60b1f2b4cac5c0763dd384aa21d79be6058c2687e85"}
 
 
 def cheb_traffic_bytes():

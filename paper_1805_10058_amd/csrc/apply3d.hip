@@ -447,7 +447,7 @@ struct TileS {
 template <typename T, int HB, int MODE>
 __global__ __launch_bounds__((2 * HB + 1) * k3ShortRows<T>() * k3E3) void k_apply3d_short(
     OpDev<T> op, const T* __restrict__ x, T* __restrict__ y, const T* __restrict__ b, const T* xprev, T* xout, T c1,
-    T c2, Apply3dGeom g, unsigned long long* stamp, const T* __restrict__ c1g) {
+    T c2, Apply3dGeom g, unsigned long long* stamp, const T* __restrict__ c1r) {
     using Q = TileS<T, HB>;
     constexpr int TR = Q::TR, NP = Q::NP, R = Q::R, E3 = k3E3, T3 = k3T3(HB);
     constexpr int NIN = Q::NIN, NX = Q::NX, NLC = Q::NLC, NC = Q::NC;
@@ -594,17 +594,16 @@ __global__ __launch_bounds__((2 * HB + 1) * k3ShortRows<T>() * k3E3) void k_appl
     __syncthreads();
     if (grp < 3) {
         const int c = grp;
+        const T* orow = c1r + unsigned(io) * NC;  // axis-1 row of output plane io
         T kx = T(0);
 #pragma unroll
         for (int gg = 0; gg < R; ++gg) {
             const int jj = io - HB + gg;
-            if (jj >= 0 && jj < m1) {  // block-uniform
-                const T* row = c1g + unsigned(jj + HB) * NC;  // table row of plane jj
-                const int k = 2 * HB - gg;                    // X1(io, jj) = row[w R + k]
+            if (jj >= 0 && jj < m1) {  // block-uniform; X1(io, jj) = orow[w R + gg]
                 const T* wsrc = ws + size_t(gg) * 9 * NP + size_t(3 * c) * NP + tid;
-                kx = fma(row[2 * R + k], wsrc[0 * NP], kx);
-                kx = fma(row[0 * R + k], wsrc[1 * NP], kx);
-                kx = fma(row[1 * R + k], wsrc[2 * NP], kx);
+                kx = fma(orow[2 * R + gg], wsrc[0 * NP], kx);
+                kx = fma(orow[0 * R + gg], wsrc[1 * NP], kx);
+                kx = fma(orow[1 * R + gg], wsrc[2 * NP], kx);
             }
         }
         const auto rs = (MODE == kApplyCheb) ? plane_rsrc(xout, c, io) : plane_rsrc(y, c, io);
@@ -613,8 +612,7 @@ __global__ __launch_bounds__((2 * HB + 1) * k3ShortRows<T>() * k3E3) void k_appl
         } else if (MODE == kApplyRes) {
             buf_store(eb - kx, rs, ptb);
         } else {  // Chebyshev step
-            const T* drow = c1g + unsigned(io + 2 * HB) * NC;  // diagonal entries of plane io
-            const T d0m = drow[3 * R], d0s = drow[3 * R + 1];
+            const T d0m = orow[3 * R], d0s = orow[3 * R + 1];  // diagonal entries of plane io
             const T dm1 = op.band[1][0][HB * m2 + i2c], ds1 = op.band[1][2][HB * m2 + i2c];
             const T dm2 = op.band[2][0][HB * m3 + i3c], ds2 = op.band[2][2][HB * m3 + i3c];
             const T dmm = dm1 * dm2, dsm = ds1 * dm2, dms = dm1 * ds2;
@@ -637,15 +635,21 @@ __global__ __launch_bounds__((2 * HB + 1) * k3ShortRows<T>() * k3E3) void k_appl
 // an output tile and a range [o0, o1) of x1 planes, like the marching kernel,
 // but takes its input planes G at a time.  In phase p, group g computes
 // stages A and B of input plane o0 - HB + G p + g and leaves its W in a ring
-// of G + 2 HB planes in LDS; after a barrier, group g sums the axis-1
-// contributions of output plane o0 - 2 HB + G p + g from the ring, in the
-// marching kernel's order and with the same fused multiply-adds (A x is
-// bitwise that of the marching kernel), and runs the epilogue.  A range of L
-// planes costs L + 2 HB planes of in-plane work and L sums, where the marching
-// kernel pays L + 2 HB of both; G groups per block let the ranges be G times
-// longer at the same number of waves, so the halo planes weigh less.  Input
-// tiles of the next phase and the epilogue operands of the next output plane
-// are loaded while the current phase computes; two barriers per phase.
+// of W planes in LDS; after a barrier, group g sums the axis-1 contributions
+// of output plane o0 - 2 HB + G p + g from the ring, in the marching kernel's
+// order and with the same fused multiply-adds (A x is bitwise that of the
+// marching kernel), and runs the epilogue.  A range of L planes costs L + 2 HB
+// planes of in-plane work and L sums, where the marching kernel pays L + 2 HB
+// of both; G groups per block let the ranges be G times longer at the same
+// number of waves, so the halo planes weigh less.
+//
+// One barrier per phase: every lane loads the 2 HB + 1 input rows of stage A
+// at its own column straight from the caches (no shared input tile), one
+// phase ahead, and the ring holds 2 G + 2 HB planes, so that the W a group
+// writes in phase p + 1 never lands on a plane another group may still read
+// for phase p (phases p and p + 1 touch 2 G + 2 HB consecutive planes;
+// phase p + 2 starts after the barrier of p + 1, which every wave reaches only
+// after its phase-p sums).
 // ------------------------------------------------------------------------------
 template <typename T, int HB>
 struct TileG {
@@ -654,30 +658,25 @@ struct TileG {
     static constexpr int GR = k3Groups;               // groups: input planes per phase
     static constexpr int NT = GR * NP;
     static constexpr int R = 2 * HB + 1;
-    static constexpr int RING = GR + 2 * HB;          // W planes held
-    static constexpr int E2 = TR + 2 * HB;
-    static constexpr int NIN = E2 * k3E3;
-    static constexpr int NX = 3 * NIN;
-    static constexpr int NLC = (NIN + NP - 1) / NP;
+    static constexpr int RING = 2 * GR + 2 * HB;      // W planes held
     static constexpr int NC = 3 * R + 2;
-    static constexpr bool CAREG = sizeof(T) == 4;
-    static constexpr size_t lds_words() {
-        return size_t(GR) * NX + size_t(RING) * 9 * NP + (CAREG ? 0 : 3 * size_t(R) * TR);
-    }
+    // axis-2 band rows in registers in FP32 up to HB = 3; above, they would
+    // push the kernel past 128 VGPRs (3 waves per SIMD instead of 4)
+    static constexpr bool CAREG = sizeof(T) == 4 && HB <= 3;
+    static constexpr size_t lds_words() { return size_t(RING) * 9 * NP + (CAREG ? 0 : 3 * size_t(R) * TR); }
 };
 
 template <typename T, int HB, int MODE>
-__global__ __launch_bounds__(k3Groups * k3ShortRows<T>() * k3E3) void k_apply3d_group(
+__global__ __launch_bounds__(k3Groups * k3ShortRows<T>() * k3E3) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 && HB <= 4 ? 4 : 1))) void k_apply3d_group(
     OpDev<T> op, const T* __restrict__ x, T* __restrict__ y, const T* __restrict__ b, const T* xprev, T* xout, T c1,
-    T c2, Apply3dGeom g, unsigned long long* stamp, const T* __restrict__ c1g) {
+    T c2, Apply3dGeom g, unsigned long long* stamp, const T* __restrict__ c1r) {
     using Q = TileG<T, HB>;
     constexpr int TR = Q::TR, NP = Q::NP, GR = Q::GR, R = Q::R, RING = Q::RING, E3 = k3E3, T3 = k3T3(HB);
-    constexpr int NIN = Q::NIN, NX = Q::NX, NLC = Q::NLC, NC = Q::NC;
+    constexpr int NC = Q::NC;
     constexpr unsigned S = sizeof(T);
     stamp_begin(stamp);
     extern __shared__ __align__(16) unsigned char smem_raw[];
-    T* xs = reinterpret_cast<T*>(smem_raw);  // [GR][3][E2][E3] input tiles, one per group
-    T* ws = xs + size_t(GR) * NX;            // [RING][9][NP] W of the ring's planes
+    T* ws = reinterpret_cast<T*>(smem_raw);  // [RING][9][NP] W of the ring's planes
     T* ca = ws + size_t(RING) * 9 * NP;      // [3][R][TR] when not in registers
     const int m1 = op.m[0], m2 = op.m[1], m3 = op.m[2];
     const unsigned PL = unsigned(m2) * m3, G = unsigned(m1) * PL;
@@ -728,22 +727,22 @@ __global__ __launch_bounds__(k3Groups * k3ShortRows<T>() * k3E3) void k_apply3d_
     }
     const T al = op.alpha, be = op.beta, ab = offdiag_weight(op);
 
-    // this thread's entries of its group's input tile (offsets out of range outside the grid)
-    unsigned loffb[NLC];
+    // the 2 HB + 1 input rows of stage A at this lane's column (offsets out of
+    // range outside the grid, so those entries read as zero)
+    unsigned roff[R];
 #pragma unroll
-    for (int q = 0; q < NLC; ++q) {
-        const int e = min(tid + q * NP, NIN - 1);
-        const int g2 = o2 - HB + e / E3, g3 = o3 - HB + e % E3;
-        const bool in = g2 >= 0 && g2 < m2 && g3 >= 0 && g3 < m3;
-        loffb[q] = in ? (unsigned(g2) * m3 + unsigned(g3)) * S : kOob;
+    for (int k = 0; k < R; ++k) {
+        const int r = i2 - HB + k;
+        const bool in = r >= 0 && r < m2 && i3 >= 0 && i3 < m3;
+        roff[k] = in ? (unsigned(r) * m3 + unsigned(i3)) * S : kOob;
     }
-    T v[3][NLC];
-    auto load_plane = [&](int jj) {
+    T xin[3][R];
+    auto load_in = [&](int jj) {
 #pragma unroll
         for (int c = 0; c < 3; ++c) {
             const auto r = plane_rsrc(x, c, jj);
 #pragma unroll
-            for (int q = 0; q < NLC; ++q) v[c][q] = buf_load(r, loffb[q], T(0));
+            for (int k = 0; k < R; ++k) xin[c][k] = buf_load(r, roff[k], T(0));
         }
     };
     T eb[3], ex[3], ep[3];
@@ -772,30 +771,31 @@ __global__ __launch_bounds__(k3Groups * k3ShortRows<T>() * k3E3) void k_apply3d_
 
     const int TI = (o1 - o0) + 2 * HB;  // input planes of the range
     const int NPH = (TI + GR - 1) / GR;  // phases
-    load_plane(o0 - HB + grp);
+    load_in(o0 - HB + grp);
     epi_load(o0 - 2 * HB + grp);
-    T* xg = xs + size_t(grp) * NX;
+    if constexpr (!Q::CAREG) __syncthreads();  // the axis-2 band rows are in LDS
     for (int ph = 0; ph < NPH; ++ph) {
         const int t = ph * GR + grp;  // this group's input plane index in the range
         const int j = o0 - HB + t;
         const bool jlive = t < TI && j >= 0 && j < m1;
+        const int io = o0 - 2 * HB + t;  // this group's output plane
+        const bool emit = io >= o0 && io < o1;
+        // the axis-1 row of the output plane, read early so that its scalar
+        // loads are in flight during stages A and B
+        T oc[NC];
+        if (emit) {
+            const T* orow = c1r + unsigned(io) * NC;
 #pragma unroll
-        for (int c = 0; c < 3; ++c)
-#pragma unroll
-            for (int q = 0; q < NLC; ++q) {
-                const int e = tid + q * NP;
-                if ((q + 1) * NP <= NIN || e < NIN) xg[c * NIN + e] = v[c][q];
-            }
-        if (t + GR < TI) load_plane(j + GR);  // the next phase's tile
-        __syncthreads();                      // (1) tiles of the phase in LDS
+            for (int i = 0; i < NC; ++i) oc[i] = orow[i];
+        }
+        T sa[9];
         if (jlive) {
-            T sa[9];
 #pragma unroll
             for (int c = 0; c < 3; ++c) {
                 T aM = T(0), aA = T(0), aS = T(0);
 #pragma unroll
                 for (int k = 0; k < R; ++k) {
-                    const T xv = xg[c * NIN + (ty + k) * E3 + tx];
+                    const T xv = xin[c][k];
                     if constexpr (Q::CAREG) {
                         aM = fma(car[0][k], xv, aM);
                         aA = fma(car[1][k], xv, aA);
@@ -810,6 +810,9 @@ __global__ __launch_bounds__(k3Groups * k3ShortRows<T>() * k3E3) void k_apply3d_
                 sa[3 * c + 1] = aA;
                 sa[3 * c + 2] = aS;
             }
+        }
+        if (t + GR < TI) load_in(j + GR);  // the next phase's rows, into the registers stage A freed
+        if (jlive) {
             T mm[3], sm[3], am[3], ms[3], ma[3], aa[3];
 #pragma unroll
             for (int c = 0; c < 3; ++c) {
@@ -838,17 +841,14 @@ __global__ __launch_bounds__(k3Groups * k3ShortRows<T>() * k3E3) void k_apply3d_
 #pragma unroll
             for (int i = 0; i < 9; ++i) wd[i * NP] = W[i];
         }
-        __syncthreads();  // (2) W of the phase's planes in the ring
-        const int io = o0 - 2 * HB + t;  // this group's output plane
-        if (io >= o0 && io < o1) {
+        __syncthreads();  // W of the phase's planes in the ring
+        if (emit) {
             T kx[3] = {T(0), T(0), T(0)};
 #pragma unroll
             for (int gg = 0; gg < R; ++gg) {
                 const int jj = io - HB + gg;
-                if (jj >= 0 && jj < m1) {
-                    const T* row = c1g + unsigned(jj + HB) * NC;  // table row of plane jj
-                    const int k = 2 * HB - gg;                    // X1(io, jj) = row[w R + k]
-                    const T cM = row[0 * R + k], cA = row[1 * R + k], cS = row[2 * R + k];
+                if (jj >= 0 && jj < m1) {  // X1(io, jj) = oc[w R + gg]
+                    const T cM = oc[0 * R + gg], cA = oc[1 * R + gg], cS = oc[2 * R + gg];
                     const T* wsrc = ws + size_t((t - 2 * HB + gg) % RING) * 9 * NP + tid;
 #pragma unroll
                     for (int c = 0; c < 3; ++c) {
@@ -858,8 +858,7 @@ __global__ __launch_bounds__(k3Groups * k3ShortRows<T>() * k3E3) void k_apply3d_
                     }
                 }
             }
-            const T* drow = c1g + unsigned(io + 2 * HB) * NC;  // diagonal entries of plane io
-            const T d0m = drow[3 * R], d0s = drow[3 * R + 1];
+            const T d0m = oc[3 * R], d0s = oc[3 * R + 1];  // diagonal entries of plane io
 #pragma unroll
             for (int c = 0; c < 3; ++c) {
                 if (MODE == kApplyY) {
@@ -923,7 +922,7 @@ void launch3d(const OpDev<T>& op, const T* x, T* y, const T* b, T* u, T* xout, T
                 auto kern = k_apply3d_short<T, HB, MODE>;
                 allow_lds(reinterpret_cast<const void*>(kern), lds);
                 hipLaunchKernelGGL(kern, dim3(gs.nblocks), dim3(QS::NT), lds, s, op, x, y, b, u, xout, c1, c2, gs,
-                                   stamp, op.c1p);
+                                   stamp, op.c1r);
                 return;
             }
         }
@@ -934,7 +933,7 @@ void launch3d(const OpDev<T>& op, const T* x, T* y, const T* b, T* u, T* xout, T
             auto kern = k_apply3d_group<T, HB, MODE>;
             allow_lds(reinterpret_cast<const void*>(kern), lds);
             hipLaunchKernelGGL(kern, dim3(gg.nblocks), dim3(QG::NT), lds, s, op, x, y, b, u, xout, c1, c2, gg, stamp,
-                               op.c1p);
+                               op.c1r);
             return;
         }
     }

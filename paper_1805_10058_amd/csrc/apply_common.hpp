@@ -124,14 +124,15 @@ inline Apply3dGeom apply3d_geom_group(const int* m, int hb, size_t elem, int x1c
 // Whether the grouped march beats the marching kernel on a grid: where the
 // marching kernel's ranges are short, its halo planes dominate and the
 // grouped march's longer ranges pay for its LDS exchange of W.  Measured per
-// Chebyshev step (FP32): p=3, m = 33 (marching ranges of 2) 11.4 against
-// 13.3 us; m = 65 (ranges of 4) 21.3 against 20.6; m = 129 (11) 59 against
-// 55; p=2, m = 64 and 32, 13.8 / 9.0 against 14.8 / 10.2; p=4, m = 66 and
-// below 12-22 against 16-27.  FP64 gains up to ranges of HB + 1: p=3,
-// m = 65, 23.4 against 28.1 us.
+// FP32 Chebyshev step (grouped against marching): p=3, m = 33 (marching
+// ranges of 2) 11.1 against 13.4 us, m = 65 (ranges of 4) 19.9 against
+// 20.7, m = 129 (ranges of 11) 56.5 against 55.3 at best; p=2, m = 64, 48 and
+// 32: 13.5 / 10.9 / 8.3 against 14.8 / 13.0 / 10.2, m = 96 (ranges of 5) a
+// tie; p=4, m = 66 and 34: 22.8 / 14.1 against 27.5 / 20.6, m = 98 (ranges
+// of 6) a tie.  FP64, p=3, m = 65: 23.8 against 28.1 us.
 inline bool apply3d_prefer_group(const int* m, int hb, size_t elem) {
     const int len = apply3d_geom(m, hb, elem, 0).c1len;
-    return len < m[0] && len <= hb + (elem == 8 ? 1 : 0);
+    return len < m[0] && len <= hb + 1;
 }
 
 // Partial dot products an operator kernel accumulates per thread.

@@ -20,6 +20,10 @@ struct OpDev {
     // in [-hb, m[0]+hb): X(j-hb+k, j) for X = M, A, S and k < 2hb+1, then
     // M(j-hb, j-hb) and S(j-hb, j-hb); zero where an index leaves [0, m[0])
     const T* c1p;
+    // the same entries by output plane, one row of 3(2hb+1)+2 per plane i in
+    // [0, m[0]): X(i, i-hb+g) for X = M, A, S and g < 2hb+1, then M(i, i) and
+    // S(i, i) (the variants of the 3D kernel that sum one output plane at a time)
+    const T* c1r;
     int m[3];   // unknowns per axis (m[2] = 1 in 2D)
     int hb;     // half bandwidth (= p on every level)
     int x1chunk;  // 3D kernel: x1 planes per block (0: chosen from the grid size)

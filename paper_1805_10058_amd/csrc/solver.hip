@@ -408,6 +408,15 @@ cd::OpDev<T> make_op(cd_solver* s, const LevelHost& L, hipStream_t st) {
             row[3 * R + 1] = at(2, j - hb, j - hb);
         }
         op.c1p = s->arena.upload(convert<T>(tab), st);
+        std::vector<double> rows(size_t(m0) * NC, 0.0);
+        for (int i = 0; i < m0; ++i) {
+            double* row = rows.data() + size_t(i) * NC;
+            for (int w = 0; w < 3; ++w)
+                for (int g = 0; g < R; ++g) row[w * R + g] = at(w, i, i - hb + g);
+            row[3 * R] = at(0, i, i);
+            row[3 * R + 1] = at(2, i, i);
+        }
+        op.c1r = s->arena.upload(convert<T>(rows), st);
     }
     if (s->d == 2) {  // unused third axis: a 1x1 identity band keeps pointers valid
         std::vector<double> id(2 * s->p + 1, 0.0);
