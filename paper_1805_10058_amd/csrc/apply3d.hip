@@ -308,24 +308,33 @@ __global__ __launch_bounds__(k3Rows<T>() * k3E3) void k_apply3d(OpDev<T> op, con
                 if (live(t)) {
                     T W[3][3];
                     {
+                        // each chain starts with a product: a zero start costs a
+                        // register per chain (fma(a, b, 0) differs from a * b in
+                        // the sign of a zero product), and the first neighbour's
+                        // lane shift folds into it; every variant keeps this order
                         T mm[3], sm[3], am[3], ms[3], ma[3], aa[3];
 #pragma unroll
                         for (int c = 0; c < 3; ++c) {
-                            mm[c] = sm[c] = am[c] = ms[c] = ma[c] = aa[c] = T(0);
                             T s[R];
                             stencil(sa[3 * c + 0], s);
+                            mm[c] = cb[0][0] * s[0];
+                            sm[c] = cb[2][0] * s[0];
+                            am[c] = c != 1 ? cb[1][0] * s[0] : T(0);
 #pragma unroll
-                            for (int k = 0; k < R; ++k) {
+                            for (int k = 1; k < R; ++k) {
                                 mm[c] = fma(cb[0][k], s[k], mm[c]);
                                 sm[c] = fma(cb[2][k], s[k], sm[c]);
                                 if (c != 1) am[c] = fma(cb[1][k], s[k], am[c]);
                             }
                             stencil(sa[3 * c + 2], s);
+                            ms[c] = cb[0][0] * s[0];
 #pragma unroll
-                            for (int k = 0; k < R; ++k) ms[c] = fma(cb[0][k], s[k], ms[c]);
+                            for (int k = 1; k < R; ++k) ms[c] = fma(cb[0][k], s[k], ms[c]);
                             stencil(sa[3 * c + 1], s);
+                            ma[c] = c != 2 ? cb[0][0] * s[0] : T(0);
+                            aa[c] = c != 0 ? cb[1][0] * s[0] : T(0);
 #pragma unroll
-                            for (int k = 0; k < R; ++k) {
+                            for (int k = 1; k < R; ++k) {
                                 if (c != 2) ma[c] = fma(cb[0][k], s[k], ma[c]);
                                 if (c != 0) aa[c] = fma(cb[1][k], s[k], aa[c]);
                             }
@@ -566,21 +575,26 @@ __global__ __launch_bounds__((2 * HB + 1) * k3ShortRows<T>() * k3E3) void k_appl
         T mm[3], sm[3], am[3], ms[3], ma[3], aa[3];
 #pragma unroll
         for (int c = 0; c < 3; ++c) {
-            mm[c] = sm[c] = am[c] = ms[c] = ma[c] = aa[c] = T(0);
             T st[R];
             stencil(sa[3 * c + 0], st);
+            mm[c] = cb[0][0] * st[0];
+            sm[c] = cb[2][0] * st[0];
+            am[c] = c != 1 ? cb[1][0] * st[0] : T(0);
 #pragma unroll
-            for (int k = 0; k < R; ++k) {
+            for (int k = 1; k < R; ++k) {
                 mm[c] = fma(cb[0][k], st[k], mm[c]);
                 sm[c] = fma(cb[2][k], st[k], sm[c]);
                 if (c != 1) am[c] = fma(cb[1][k], st[k], am[c]);
             }
             stencil(sa[3 * c + 2], st);
+            ms[c] = cb[0][0] * st[0];
 #pragma unroll
-            for (int k = 0; k < R; ++k) ms[c] = fma(cb[0][k], st[k], ms[c]);
+            for (int k = 1; k < R; ++k) ms[c] = fma(cb[0][k], st[k], ms[c]);
             stencil(sa[3 * c + 1], st);
+            ma[c] = c != 2 ? cb[0][0] * st[0] : T(0);
+            aa[c] = c != 0 ? cb[1][0] * st[0] : T(0);
 #pragma unroll
-            for (int k = 0; k < R; ++k) {
+            for (int k = 1; k < R; ++k) {
                 if (c != 2) ma[c] = fma(cb[0][k], st[k], ma[c]);
                 if (c != 0) aa[c] = fma(cb[1][k], st[k], aa[c]);
             }
@@ -816,21 +830,26 @@ __global__ __launch_bounds__(k3Groups * k3ShortRows<T>() * k3E3) __attribute__((
             T mm[3], sm[3], am[3], ms[3], ma[3], aa[3];
 #pragma unroll
             for (int c = 0; c < 3; ++c) {
-                mm[c] = sm[c] = am[c] = ms[c] = ma[c] = aa[c] = T(0);
                 T st[R];
                 stencil(sa[3 * c + 0], st);
+                mm[c] = cb[0][0] * st[0];
+                sm[c] = cb[2][0] * st[0];
+                am[c] = c != 1 ? cb[1][0] * st[0] : T(0);
 #pragma unroll
-                for (int k = 0; k < R; ++k) {
+                for (int k = 1; k < R; ++k) {
                     mm[c] = fma(cb[0][k], st[k], mm[c]);
                     sm[c] = fma(cb[2][k], st[k], sm[c]);
                     if (c != 1) am[c] = fma(cb[1][k], st[k], am[c]);
                 }
                 stencil(sa[3 * c + 2], st);
+                ms[c] = cb[0][0] * st[0];
 #pragma unroll
-                for (int k = 0; k < R; ++k) ms[c] = fma(cb[0][k], st[k], ms[c]);
+                for (int k = 1; k < R; ++k) ms[c] = fma(cb[0][k], st[k], ms[c]);
                 stencil(sa[3 * c + 1], st);
+                ma[c] = c != 2 ? cb[0][0] * st[0] : T(0);
+                aa[c] = c != 0 ? cb[1][0] * st[0] : T(0);
 #pragma unroll
-                for (int k = 0; k < R; ++k) {
+                for (int k = 1; k < R; ++k) {
                     if (c != 2) ma[c] = fma(cb[0][k], st[k], ma[c]);
                     if (c != 0) aa[c] = fma(cb[1][k], st[k], aa[c]);
                 }
