@@ -108,12 +108,16 @@ typedef struct {
     int graphs;           /* 1: replay outer iterations from a captured HIP graph
                              (identical arithmetic); 0: launch every kernel eagerly */
     int cheb_degree_coarse; /* Chebyshev degree on levels >= 1; 0 means cheb_degree; < 0 (the
-                             default) chooses from the problem: 16 when beta >= 1e-5 alpha,
-                             32 below (small beta leaves the smoother a branch of the
-                             spectrum it damps slowly, and the cheap coarse levels are where
-                             more steps pay: measured at 3D p=3 n=128 beta = 1e-6, 379
-                             outer iterations with 16, 238 with 32, 1.84 against 1.47 s per
-                             solve; at beta >= 1e-4, 16 is faster) */
+                             default) chooses from beta / alpha: 8 at 1e-2 and above, 16
+                             from 1e-5 to 1e-2, 32 below (small beta leaves the smoother a
+                             branch of the spectrum it damps slowly, and the cheap coarse
+                             levels are where more steps pay; at large beta the outer
+                             iteration count does not move and fewer steps are faster).
+                             Measured, mixed precision, solve times with 8 / 16 / 32:
+                             3D p=3 n=128 beta = 1e-6 379 iterations with 16, 238 with 32
+                             (1.84 against 1.47 s); beta = 1e-4 51 / 32 iterations with
+                             8 / 16 (210 / 150 ms); 2D p=3 n=256 beta = 1 2.4 / 3.0 ms,
+                             3D p=2 n=64 beta = 1 and 1e-2 4.1 / 4.8 and 6.1 / 7.2 ms */
     int apply_x1_chunk;   /* 3D operator kernel: x1 planes each block covers (the launch
                              geometry only; results depend on it only through the rounding
                              of the per-block partial dot products and, in FP32, the last
@@ -134,8 +138,8 @@ typedef struct {
 
 /* Fill *opt with the defaults: P_MIM, knot insertion, FP64, rtol 1e-8,
  * max_iter 10000, coarse_max_dofs 2500, cheb_degree 48, cheb_ratio 1000,
- * lanczos_steps 20, krylov_steps = p, graphs 1, cheb_degree_coarse -1 (16,
- * or 32 when beta < 1e-5 alpha), apply_x1_chunk 0, eig_bounds Lanczos,
+ * lanczos_steps 20, krylov_steps = p, graphs 1, cheb_degree_coarse -1 (8, 16
+ * or 32 from beta / alpha), apply_x1_chunk 0, eig_bounds Lanczos,
  * apply3d_kernel AUTO.  The
  * smoother settings were chosen by measured solve rate on 2D and 3D
  * problems; a wide interval needs the eigenvalue bound to cover the top of

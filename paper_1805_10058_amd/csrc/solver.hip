@@ -1031,11 +1031,16 @@ void estimate_bounds(cd_solver* s) {
 // Chebyshev degree on the levels below the finest: 0 = the finest level's;
 // < 0 = from the problem (more coarse-level smoothing for small beta / alpha,
 // where the outer iteration count grows; measured, see cd_options).
-constexpr double kSmallBeta = 1e-5;
+// Default Chebyshev degree below the finest level, from beta / alpha: the
+// smaller beta, the more of the spectrum the smoother damps slowly and the
+// more the cheap coarse levels' extra steps pay (measured solve times in the
+// options' documentation).
+constexpr double kSmallBeta = 1e-5, kLargeBeta = 1e-2;
 int resolve_coarse_degree(const cd_problem& pr, const cd_options& o) {
     if (o.cheb_degree_coarse > 0) return o.cheb_degree_coarse;
     if (o.cheb_degree_coarse == 0) return o.cheb_degree;
-    return (pr.beta < kSmallBeta * pr.alpha) ? 32 : 16;
+    if (pr.beta < kSmallBeta * pr.alpha) return 32;
+    return (pr.beta < kLargeBeta * pr.alpha) ? 16 : 8;
 }
 
 void create(cd_solver* s, const cd_problem* pr, const cd_options* op, void* stream) {

@@ -166,6 +166,23 @@ def test_vcycle(case):
     assert relerr(host(z), m.vcycle(r)) <= 1e-10
 
 
+@pytest.mark.parametrize("alpha,beta,expect", [(1.0, 1.0, 8), (2.0, 0.05, 8), (1.0, 5e-3, 16), (1.0, 1e-5, 16),
+                                                (10.0, 1.1e-4, 16), (10.0, 9e-5, 32), (1.0, 1e-6, 32)])
+def test_default_coarse_degree_follows_beta_over_alpha(alpha, beta, expect):
+    # cheb_degree_coarse < 0 resolves from beta / alpha at creation: 8 from
+    # 1e-2 up, 16 from 1e-5 to 1e-2, 32 below; the finest level keeps cheb_degree
+    s = capi.Solver(capi.problem(2, 2, 16, alpha, beta), capi.options(coarse_max_dofs=40), stream())
+    assert s.num_levels() > 2
+    assert s.coarse_degree() == expect
+    assert s.get_smoother(0)[0] == 48
+    s.close()
+    for set_to, got in ((0, 48), (5, 5)):
+        s = capi.Solver(capi.problem(2, 2, 16, alpha, beta), capi.options(coarse_max_dofs=40, cheb_degree_coarse=set_to),
+                        stream())
+        assert s.coarse_degree() == got
+        s.close()
+
+
 @pytest.mark.parametrize("case", [CASES[2], CASES[4], CASES[7]], ids=[IDS[2], IDS[4], IDS[7]])
 def test_vcycle_light_smoothing_one_degree_everywhere(case):
     # cheb_degree_coarse = 0 keeps the finest level's degree on every level
