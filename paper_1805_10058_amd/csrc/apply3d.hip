@@ -112,6 +112,45 @@ __device__ inline void combine_w(const T (&mm)[3], const T (&sm)[3], const T (&a
     W[8] = ab * am[0];
 }
 
+// The Chebyshev step's diagonal at one point, for the three components:
+// diag_c = fd[c] d0s + fe[c] d0m, with d0m and d0s the axis-1 mass and
+// stiffness diagonal entries of the point's x1 plane (the diagonal of the
+// Kronecker sum, blocks on the diagonal only).  Lanes that are not output
+// points get fd = 0, fe = 1, a positive diagonal whose results are dropped.
+template <typename T>
+struct ChebDiag {
+    T fd[3], fe[3];
+};
+template <typename T, int HB>
+__device__ inline void cheb_diag_one(const OpDev<T>& op, int c, int i2c, int i3c, bool active, T& fd, T& fe) {
+    const int m2 = op.m[1], m3 = op.m[2];
+    const T dm1 = op.band[1][0][HB * m2 + i2c], ds1 = op.band[1][2][HB * m2 + i2c];
+    const T dm2 = op.band[2][0][HB * m3 + i3c], ds2 = op.band[2][2][HB * m3 + i3c];
+    const T dmm = dm1 * dm2, dsm = ds1 * dm2, dms = dm1 * ds2;
+    const T al = op.alpha, be = op.beta;
+    fd = active ? (c == 0 ? be : al) * dmm : T(0);
+    fe = active ? fma(c == 1 ? be : al, dsm, (c == 2 ? be : al) * dms) : T(1);
+}
+template <typename T, int HB>
+__device__ inline ChebDiag<T> cheb_diag(const OpDev<T>& op, int i2c, int i3c, bool active) {
+    ChebDiag<T> d;
+#pragma unroll
+    for (int c = 0; c < 3; ++c) cheb_diag_one<T, HB>(op, c, i2c, i3c, active, d.fd[c], d.fe[c]);
+    return d;
+}
+// x_{k+1} = x_k + c1 (x_k - x_{k-1}) + c2 (b - A x_k) / diag at one entry
+template <typename T>
+__device__ inline T cheb_update(T xk, T xp, T bv, T kx, T fd, T fe, T d0m, T d0s, T c1, T c2) {
+    const T dg = fma(fd, d0s, fe * d0m);
+    const T r = bv - kx;
+    T upd;
+    if constexpr (sizeof(T) == 4)
+        upd = c2 * r * __builtin_amdgcn_rcpf(dg);
+    else
+        upd = c2 * r / dg;
+    return xk + (c1 * (xk - xp) + upd);
+}
+
 template <typename T, int HB>
 struct Tile3 {
     static constexpr int TR = k3Rows<T>();          // tile rows (x2)
@@ -171,9 +210,7 @@ __global__ __launch_bounds__(k3Rows<T>() * k3E3) void k_apply3d(OpDev<T> op, con
     for (int w = 0; w < 3; ++w)
 #pragma unroll
         for (int k = 0; k < R; ++k) cb[w][k] = active ? op.band[2][w][k * m3 + i3] : T(0);
-    const T dm1 = op.band[1][0][HB * m2 + i2c], ds1 = op.band[1][2][HB * m2 + i2c];
-    const T dm2 = op.band[2][0][HB * m3 + i3c], ds2 = op.band[2][2][HB * m3 + i3c];
-    const T dmm = dm1 * dm2, dsm = ds1 * dm2, dms = dm1 * ds2;
+    const ChebDiag<T> cd = cheb_diag<T, HB>(op, i2c, i3c, active);
     // byte offset of the output point within a plane; out of range for inactive lanes
     const unsigned ptb = active ? (unsigned(i2c) * m3 + unsigned(i3c)) * S : kOob;
     T acc[3][R];
@@ -388,15 +425,8 @@ __global__ __launch_bounds__(k3Rows<T>() * k3E3) void k_apply3d(OpDev<T> op, con
                                 buf_store(kx[c], plane_rsrc(y, c, io), ptb);
                                 dots[0] += double(ex[c]) * double(kx[c]);
                             } else if (MODE == kApplyCheb) {
-                                const T dg = (c == 0 ? be : al) * d0s * dmm + (c == 1 ? be : al) * d0m * dsm +
-                                             (c == 2 ? be : al) * d0m * dms;
-                                const T r = eb[c] - kx[c];
-                                T upd;
-                                if constexpr (sizeof(T) == 4)
-                                    upd = c2 * r * __builtin_amdgcn_rcpf(active ? dg : T(1));
-                                else
-                                    upd = c2 * r / (active ? dg : T(1));
-                                buf_store(ex[c] + (c1 * (ex[c] - ep[c]) + upd), plane_rsrc(xout, c, io), ptb);
+                                buf_store(cheb_update(ex[c], ep[c], eb[c], kx[c], cd.fd[c], cd.fe[c], d0m, d0s, c1, c2),
+                                          plane_rsrc(xout, c, io), ptb);
                             } else {
                                 buf_store(kx[c], plane_rsrc(y, c, io), ptb);
                                 if constexpr (kPreBasis) {
@@ -627,18 +657,9 @@ __global__ __launch_bounds__((2 * HB + 1) * k3ShortRows<T>() * k3E3) void k_appl
             buf_store(eb - kx, rs, ptb);
         } else {  // Chebyshev step
             const T d0m = orow[3 * R], d0s = orow[3 * R + 1];  // diagonal entries of plane io
-            const T dm1 = op.band[1][0][HB * m2 + i2c], ds1 = op.band[1][2][HB * m2 + i2c];
-            const T dm2 = op.band[2][0][HB * m3 + i3c], ds2 = op.band[2][2][HB * m3 + i3c];
-            const T dmm = dm1 * dm2, dsm = ds1 * dm2, dms = dm1 * ds2;
-            const T dg = (c == 0 ? be : al) * d0s * dmm + (c == 1 ? be : al) * d0m * dsm +
-                         (c == 2 ? be : al) * d0m * dms;
-            const T r = eb - kx;
-            T upd;
-            if constexpr (sizeof(T) == 4)
-                upd = c2 * r * __builtin_amdgcn_rcpf(active ? dg : T(1));
-            else
-                upd = c2 * r / (active ? dg : T(1));
-            buf_store(ex + (c1 * (ex - ep) + upd), rs, ptb);
+            T fd, fe;
+            cheb_diag_one<T, HB>(op, c, i2c, i3c, active, fd, fe);
+            buf_store(cheb_update(ex, ep, eb, kx, fd, fe, d0m, d0s, c1, c2), rs, ptb);
         }
     }
     stamp_end(stamp);
@@ -731,14 +752,7 @@ __global__ __launch_bounds__(k3Groups * k3ShortRows<T>() * k3E3) __attribute__((
     for (int w = 0; w < 3; ++w)
 #pragma unroll
         for (int k = 0; k < R; ++k) cb[w][k] = active ? op.band[2][w][k * m3 + i3] : T(0);
-    T dmm = T(0), dsm = T(0), dms = T(0);
-    if (MODE == kApplyCheb) {
-        const T dm1 = op.band[1][0][HB * m2 + i2c], ds1 = op.band[1][2][HB * m2 + i2c];
-        const T dm2 = op.band[2][0][HB * m3 + i3c], ds2 = op.band[2][2][HB * m3 + i3c];
-        dmm = dm1 * dm2;
-        dsm = ds1 * dm2;
-        dms = dm1 * ds2;
-    }
+    const ChebDiag<T> cd = cheb_diag<T, HB>(op, i2c, i3c, active);
     const T al = op.alpha, be = op.beta, ab = offdiag_weight(op);
 
     // the 2 HB + 1 input rows of stage A at this lane's column (offsets out of
@@ -885,15 +899,8 @@ __global__ __launch_bounds__(k3Groups * k3ShortRows<T>() * k3E3) __attribute__((
                 } else if (MODE == kApplyRes) {
                     buf_store(eb[c] - kx[c], plane_rsrc(y, c, io), ptb);
                 } else {  // Chebyshev step
-                    const T dg = (c == 0 ? be : al) * d0s * dmm + (c == 1 ? be : al) * d0m * dsm +
-                                 (c == 2 ? be : al) * d0m * dms;
-                    const T r = eb[c] - kx[c];
-                    T upd;
-                    if constexpr (sizeof(T) == 4)
-                        upd = c2 * r * __builtin_amdgcn_rcpf(active ? dg : T(1));
-                    else
-                        upd = c2 * r / (active ? dg : T(1));
-                    buf_store(ex[c] + (c1 * (ex[c] - ep[c]) + upd), plane_rsrc(xout, c, io), ptb);
+                    buf_store(cheb_update(ex[c], ep[c], eb[c], kx[c], cd.fd[c], cd.fe[c], d0m, d0s, c1, c2),
+                              plane_rsrc(xout, c, io), ptb);
                 }
             }
         }
