@@ -32,9 +32,9 @@ HEADLINE = "c4_3d_p3_n128"
 # profiles/c4_3d_p3_n128_solve_kernels.txt.  It holds only for the kernel
 # sources it was measured on (their SHA-256 below); after any change to them
 # the line reports null until the counters are taken again.
-CHEB_TRAFFIC = {"fetch_kib": 71353.1, "write_kib": 30539.4, "fetch_factor": 2.000, "write_factor": 1.000,
+CHEB_TRAFFIC = {"fetch_kib": 71376.4, "write_kib": 30660.0, "fetch_factor": 2.000, "write_factor": 1.000,
                 "sources": ["paper_1805_10058_amd/csrc/apply3d.hip", "paper_1805_10058_amd/csrc/apply_common.hpp"],
-                "sha256": "3bcb6dc15f2c3a65be6410e42f9f5fde769ae68664b8f1ca1a556d33d3514c37"}
+                "sha256": "9b37aa47d8ff3da93f72ea8b6e08bb3f7b9a4234efd163c915e25cfda757964e"}
 
 
 def cheb_traffic_bytes():
