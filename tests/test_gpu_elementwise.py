@@ -248,7 +248,8 @@ def test_short_march_variant_matches_marching_kernel(d, p, n):
 
 
 @pytest.mark.parametrize("d,p,n,chunk", [(3, 3, 12, 0), (3, 2, (9, 14, 20), 0), (3, 1, 10, 0), (3, 3, 16, 0),
-                                         (3, 3, 16, 5), (3, 4, (10, 7, 12), 0), (3, 6, 8, 0), (3, 2, 34, 0)])
+                                         (3, 3, 16, 5), (3, 4, (10, 7, 12), 0), (3, 5, (9, 11, 8), 0), (3, 6, 8, 0),
+                                         (3, 2, 34, 0)])
 def test_apply3d_variants_agree(d, p, n, chunk):
     # every variant of the 3D kernel (marching, short-march, grouped march)
     # sums each output entry's terms in the same order: y = A x bitwise equal
