@@ -269,6 +269,9 @@ def main():
     ap.add_argument("--only-c4-solve", type=int, default=0, metavar="MAX_ITER",
                     help="run only one mixed solve of the headline workload, cut at MAX_ITER outer iterations "
                          "(a short program for profiling)")
+    ap.add_argument("--only-c2-solve", action="store_true",
+                    help="run only three mixed solves of the 2D p=3 n=256 workload at beta = 1e-4 (a short "
+                         "program for profiling)")
     ap.add_argument("--pmc-pass", action="store_true",
                     help="only run 6 eager outer iterations of the headline mixed solve (and --copy-cal): a short "
                          "program for the HBM byte counters of the V-cycle kernels")
@@ -295,6 +298,9 @@ def main():
     if args.serve_stream > 0:
         print(json.dumps({"serving_stream": serve_stream(capi, torch, st, args.serve_stream, args.serve_max_iter,
                                                          log)}), flush=True)
+        return
+    if args.only_c2_solve:
+        print(json.dumps({"solve_c2": c2_solve(capi, torch, st)}), flush=True)
         return
     if args.only_c4_solve or args.pmc_pass:
         print(json.dumps({"solve_c4": c4_solve(capi, torch, st, args.only_c4_solve or 6,
@@ -611,6 +617,33 @@ def c4_solve(capi, torch, st, max_iter, graphs=1, bounds=0):
     out = {"unknowns": N, "beta": betas[0], "levels": s.num_levels(), "iterations": r.iterations,
            "status": r.status, "true_rel_residual": r.true_rel_residual, "setup_ms": 1e3 * (t1 - t0),
            "solve_s": t2 - t1, "ms_per_iteration": 1e3 * (t2 - t1) / max(r.iterations, 1)}
+    s.close()
+    return out
+
+
+def c2_solve(capi, torch, st, solves=3):
+    """Mixed-precision solves of the 2D p=3 n=256 workload at its small beta
+    (1e-4, uniform right-hand side, rel. residual 1e-8), from the captured
+    graph after a first solve: iterations, launches and time per solve."""
+    import curldiv_inputs as ci
+
+    d, p, n, alpha, betas, dist, tol = ci.CONFIGS["c2_2d_p3_n256"]
+    beta = min(betas)
+    N = ci.num_dofs(d, p, n)
+    b = torch.as_tensor(ci.rhs(d, p, n, 0, dist)).cuda()
+    x = torch.zeros(N, dtype=torch.float64, device="cuda")
+    s = capi.Solver(capi.problem(d, p, n, alpha, beta), capi.options(precision=capi.CD_MIXED_FP32, rtol=tol), st)
+    s.solve(b.data_ptr(), x.data_ptr())
+    torch.cuda.synchronize()
+    ts = []
+    for _ in range(solves):
+        t0 = time.perf_counter()
+        r = s.solve(b.data_ptr(), x.data_ptr())
+        torch.cuda.synchronize()
+        ts.append(time.perf_counter() - t0)
+    out = {"unknowns": N, "beta": beta, "levels": s.num_levels(), "iterations": r.iterations, "status": r.status,
+           "kernel_launches_per_outer_iteration": s.graph_launches()[0],
+           "ms_per_solve": [1e3 * t for t in ts], "ms_per_iteration": 1e3 * min(ts) / max(r.iterations, 1)}
     s.close()
     return out
 
