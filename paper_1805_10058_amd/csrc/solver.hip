@@ -1028,13 +1028,10 @@ void estimate_bounds(cd_solver* s) {
     }
 }
 
-// Chebyshev degree on the levels below the finest: 0 = the finest level's;
-// < 0 = from the problem (more coarse-level smoothing for small beta / alpha,
-// where the outer iteration count grows; measured, see cd_options).
-// Default Chebyshev degree below the finest level, from beta / alpha: the
-// smaller beta, the more of the spectrum the smoother damps slowly and the
-// more the cheap coarse levels' extra steps pay (measured solve times in the
-// options' documentation).
+// Chebyshev degree on the levels below the finest: > 0 as given, 0 = the
+// finest level's, < 0 = from beta / alpha: the smaller beta, the more of the
+// spectrum the smoother damps slowly and the more the cheap coarse levels'
+// extra steps pay (measured solve times in the options' documentation).
 constexpr double kSmallBeta = 1e-5, kLargeBeta = 1e-2;
 int resolve_coarse_degree(const cd_problem& pr, const cd_options& o) {
     if (o.cheb_degree_coarse > 0) return o.cheb_degree_coarse;
